@@ -1,0 +1,280 @@
+"""The batched per-subdomain clip-and-verify pipeline, the slope adjoint and
+Adam (FP64 oracle).
+
+Steps, for one property whose root planes were cached by ``crown.root_pass``
+and a batch of subdomains (input box + activation split list each):
+
+a1 split -> input halfspace (eqs. 9-10 of the activation-BaB section): the
+   branch z_j >= 0 gives  -Ahi_j x - chi_j <= 0  (because z_j <= Ahi_j x + chi_j);
+   the branch z_j <= 0 gives  Alo_j x + clo_j <= 0 (because z_j >= Alo_j x + clo_j).
+a2 relaxed clipping of the box (Thm 3.2 / Alg. 2, or Alg. 3).
+a3 re-concretization of every cached plane over the clipped box (the
+   "re-concretize cached linear constraints over the shrunk box" step of the
+   relaxed-clipping section), intersected with the root bounds; a split
+   neuron is fixed to its branch (l >= 0 for z >= 0, u <= 0 for z <= 0) as
+   in Alg. 5, where children fix each split neuron's regime.
+a4 (optional) complete clipping of unstable intermediate neurons: the cached
+   lower plane (and the negated upper plane) are the objectives, the split
+   halfspaces the constraints (Alg. 1).
+a5 CROWN backward pass for the objective rows with the per-subdomain bounds.
+a6 concretization of the final plane over the clipped box (Lemma A.2).
+a7 complete clipping of each final plane against the subdomain's split
+   halfspaces (Alg. 1, one pass); lb <- max(lb, result).
+
+A subdomain is infeasible if a2 finds an empty constraint (or lo > hi), a3/a4
+leave some neuron with l > u, or a7 finds a constraint empty over the clipped
+box; its bounds are +inf.  It is verified if infeasible or every objective
+row has lb > 0 (MinPool conjunction, appendix on Boolean properties).
+
+The slope step (a8): the gradient of sum(lb) after a7 with respect to the
+alpha of every unstable lower-line entry, holding the a7 multipliers fixed
+(Danskin), followed by projected Adam ascent (the experimental settings use
+Adam on alpha with lr 0.1, 20 iterations, optional decay 0.98).
+
+Readings taken:
+* Intermediate bounds are intersected with the root bounds, and split
+  neurons are fixed to their branch (the 2-D toy example leaves the split
+  neuron unfixed to show clipping alone; ``Config.split_fix=False`` gives
+  that behaviour).
+* Optimised alpha is one value per (subdomain, objective row, neuron), the
+  loss is the sum of the rows' bounds (separable per row).  Root planes use a
+  fixed alpha (0.5).
+* At a kink of the final dual (a coefficient of A + beta^T G that is zero up
+  to rounding, which happens at the breakpoint chosen by a7) the subgradient
+  uses the box midpoint for that coordinate: any point of [lo_j, hi_j] is a
+  valid subgradient there; the midpoint is the symmetric choice.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import relaxed as rx
+from . import complete as cc
+from . import crown
+from .box import f64, concretize_min, concretize_min_shared, concretize_max_shared
+
+KINK_REL = 2.0 ** -40
+
+
+@dataclass
+class Config:
+    relaxed: str = "parallel"        # "parallel" | "sequential" | "none"
+    reconcretize: bool = True        # a3
+    split_fix: bool = True
+    complete_intermediate: bool = False  # a4
+    complete_final: bool = True      # a7
+    ca_passes: int = 1
+    alpha: float = 0.5
+
+
+def split_constraints(root, neuron, sign, count):
+    """a1: halfspaces G x + h <= 0 of each subdomain's splits (eqs. 9-10).
+    neuron/sign: [B, kmax]; count: [B].  Returns (G [B,k,n0], h [B,k],
+    active [B,k])."""
+    A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
+    B, k = neuron.shape
+    active = np.arange(k)[None, :] < np.asarray(count)[:, None]
+    idx = np.where(active, neuron, 0)
+    neg = (np.asarray(sign) < 0)[..., None]
+    G = np.where(neg, A_lo[idx], -A_hi[idx])
+    h = np.where(neg[..., 0], c_lo[idx], -c_hi[idx])
+    G = np.where(active[..., None], G, 0.0)
+    h = np.where(active, h, 0.0)
+    return G, h, active
+
+
+def reconcretize(root, lo, hi):
+    """a3 without the fixes: bounds of every hidden neuron over each box.
+    Returns (l [B, N], u [B, N])."""
+    A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
+    return concretize_min_shared(A_lo, c_lo, lo, hi), concretize_max_shared(A_hi, c_hi, lo, hi)
+
+
+def fix_bounds(root, l, u, neuron, sign, count, split_fix=True):
+    """Intersect with the root bounds and fix split neurons to their branch.
+    Returns (l, u, empty [B]) where empty marks some l > u."""
+    _, _, _, _, l0, u0 = root.stacked()
+    l = np.maximum(l, l0[None])
+    u = np.minimum(u, u0[None])
+    if split_fix:
+        B, k = neuron.shape
+        for s in range(k):
+            act = s < np.asarray(count)
+            b = np.nonzero(act)[0]
+            j = neuron[b, s]
+            pos = sign[b, s] > 0
+            l[b[pos], j[pos]] = np.maximum(l[b[pos], j[pos]], 0.0)
+            u[b[~pos], j[~pos]] = np.minimum(u[b[~pos], j[~pos]], 0.0)
+    return l, u, np.any(l > u, axis=-1)
+
+
+def complete_intermediate(root, l, u, G, h, active, lo, hi, passes=1):
+    """a4: complete clipping of every unstable neuron's cached lower plane
+    (tightens l) and negated upper plane (tightens u).  Returns (l, u, empty)."""
+    A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
+    l, u = l.copy(), u.copy()
+    empty = np.zeros(l.shape[0], bool)
+    for b in range(l.shape[0]):
+        js = np.nonzero((l[b] < 0.0) & (u[b] > 0.0))[0]
+        if js.size == 0 or not active[b].any():
+            continue
+        R = js.size
+        Gr = np.broadcast_to(G[b], (R,) + G[b].shape)
+        hr = np.broadcast_to(h[b], (R,) + h[b].shape)
+        ar = np.broadcast_to(active[b], (R,) + active[b].shape)
+        lor = np.broadcast_to(lo[b], (R, lo.shape[1]))
+        hir = np.broadcast_to(hi[b], (R, hi.shape[1]))
+        Ll, _, inf1 = cc.coord_ascent(A_lo[js], c_lo[js], Gr, hr, lor, hir, ar, passes)
+        Lu, _, inf2 = cc.coord_ascent(-A_hi[js], -c_hi[js], Gr, hr, lor, hir, ar, passes)
+        l[b, js] = np.maximum(l[b, js], Ll)
+        u[b, js] = np.minimum(u[b, js], -Lu)
+        empty[b] = bool(inf1.any() or inf2.any())
+    return l, u, empty | np.any(l > u, axis=-1)
+
+
+def split_layers(net_layers, flat):
+    """Cut [B, N] concatenated hidden quantities into per-layer arrays."""
+    out, off = [], 0
+    for W, _ in net_layers[:-1]:
+        n = W.shape[0]
+        out.append(flat[:, off:off + n])
+        off += n
+    return out
+
+
+def final_clip(A, c, G, h, active, lo, hi, passes=1):
+    """a7 for a batch: rows (b, m) of A [B, M, n] / c [B, M] against the
+    constraints of subdomain b.  Returns (L [B, M], beta [B, M, k], empty [B])."""
+    B, M, n = A.shape
+    k = G.shape[1]
+    rep = lambda x: np.repeat(x, M, axis=0)
+    L, beta, inf = cc.coord_ascent(A.reshape(B * M, n), c.reshape(B * M), rep(G), rep(h),
+                                   rep(lo), rep(hi), rep(active), passes)
+    return L.reshape(B, M), beta.reshape(B, M, k), inf.reshape(B, M).any(-1)
+
+
+def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=None):
+    """Steps a1-a7 for a batch of subdomains; returns a dict of every
+    intermediate result.  ``layers``: dense (W, b) list; lo/hi: [B, n0];
+    alpha: None (use cfg.alpha) or per-layer [B, M, n_i] arrays."""
+    lo, hi = f64(lo), f64(hi)
+    out = {}
+    G, h, act = split_constraints(root, neuron, sign, count)
+    if cfg.relaxed == "parallel":
+        lo2, hi2, inf_a2 = rx.clip_parallel(G, h, lo, hi, act)
+    elif cfg.relaxed == "sequential":
+        lo2, hi2, inf_a2 = rx.clip_sequential(G, h, lo, hi, act)
+    else:
+        lo2, hi2, inf_a2 = lo.copy(), hi.copy(), np.zeros(lo.shape[0], bool)
+    out.update(G=G, h=h, active=act, lo=lo2, hi=hi2, infeasible_clip=inf_a2)
+    # bounds are computed on the clipped box; an empty box keeps its values
+    if cfg.reconcretize:
+        l, u = reconcretize(root, lo2, hi2)
+    else:
+        _, _, _, _, l0, u0 = root.stacked()
+        l = np.broadcast_to(l0, (lo.shape[0], l0.size)).copy()
+        u = np.broadcast_to(u0, (lo.shape[0], u0.size)).copy()
+    l, u, emp3 = fix_bounds(root, l, u, neuron, sign, count, cfg.split_fix)
+    out.update(l_a3=l.copy(), u_a3=u.copy(), empty_a3=emp3)
+    emp4 = np.zeros_like(emp3)
+    if cfg.complete_intermediate:
+        l, u, emp4 = complete_intermediate(root, l, u, G, h, act, lo2, hi2, cfg.ca_passes)
+    out.update(l=l, u=u, empty_a4=emp4)
+    a = cfg.alpha if alpha is None else alpha
+    A, c = crown.backward(layers, C, t, split_layers(layers, l), split_layers(layers, u), a)
+    lb0 = concretize_min(A, c, lo2, hi2)
+    out.update(A=A, c=c, lb_unclipped=lb0.copy())
+    emp7 = np.zeros_like(emp3)
+    lb = lb0
+    if cfg.complete_final and G.shape[1] > 0:
+        L, beta, emp7 = final_clip(A, c, G, h, act, lo2, hi2, cfg.ca_passes)
+        lb = np.maximum(lb0, L)
+        out["beta"] = beta
+    infeasible = inf_a2 | emp3 | emp4 | emp7
+    lb = np.where(infeasible[:, None], np.inf, lb)
+    out.update(lb=lb, infeasible=infeasible, empty_a7=emp7,
+               verified=infeasible | np.all(lb > 0.0, axis=-1))
+    return out
+
+
+# ------------------------------------------------------------- slopes (a8)
+
+def bound_and_grad(layers, C, t, l_list, u_list, alpha, lo, hi, G, h, active,
+                   complete=True, passes=1):
+    """Post-a7 bound of every row and its gradient with respect to alpha.
+
+    alpha: list of [B, M, n_i] (one per hidden layer).  The multipliers of a7
+    are held fixed (Danskin), so the bound is min over the box of
+    (A + beta^T G).x + c + beta^T h and its derivative with respect to A is
+    the minimising corner x* (midpoint at zero coefficients).  The adjoint
+    then runs the CROWN recursion backwards:
+        Omega_bar_k = Psi_bar_k W_k^T + b_k,   Psi_bar_0 = x*
+        Psi_bar_{k+1} = Omega_bar_k * slope_k + intercept_k
+        dlb/dalpha_k = Omega_bar_k * Psi_{k+1}   on lower-line entries.
+    Returns (lb [B, M], grads list, beta or None, infeasible rows [B])."""
+    lo, hi = f64(lo), f64(hi)
+    A, c, psis = crown.backward(layers, C, t, l_list, u_list, alpha, trace=True)
+    B, M, n = A.shape
+    beta = None
+    if complete and G.shape[1] > 0:
+        L, beta, emp = final_clip(A, c, G, h, active, lo, hi, passes)
+        Af = A + np.einsum("bmk,bkn->bmn", beta, G)
+        cf = c + np.einsum("bmk,bk->bm", beta, h)
+    else:
+        emp = np.zeros(B, bool)
+        Af, cf = A, c
+    lb = concretize_min(Af, cf, lo, hi)
+    scale = np.abs(A)
+    if beta is not None:
+        scale = scale + np.einsum("bmk,bkn->bmn", beta, np.abs(G))
+    kink = np.abs(Af) <= KINK_REL * scale
+    xstar = np.where(kink, (lo[:, None, :] + hi[:, None, :]) / 2.0,
+                     np.where(Af > 0.0, lo[:, None, :], hi[:, None, :]))
+    grads = [None] * (len(layers) - 1)
+    Psi_bar = xstar
+    for kk in range(len(layers) - 1):
+        W, b = layers[kk]
+        Om_bar = Psi_bar @ W.T + b
+        l = f64(l_list[kk])[:, None, :]
+        u = f64(u_list[kk])[:, None, :]
+        slope, icpt, mask = crown.relu_relaxation(l, u, psis[kk], alpha[kk])
+        grads[kk] = np.where(mask, Om_bar * psis[kk], 0.0)
+        Psi_bar = Om_bar * slope + icpt
+    for kk in range(len(grads)):
+        grads[kk] = np.where(emp[:, None, None], 0.0, grads[kk])
+    lb = np.where(emp[:, None], np.inf, lb)
+    return lb, grads, beta, emp
+
+
+def adam_ascent(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One projected Adam ascent step (Kingma & Ba; bias-corrected moments),
+    then clamp to [0, 1].  Returns (param, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    param = np.clip(param + lr * mh / (np.sqrt(vh) + eps), 0.0, 1.0)
+    return param, m, v
+
+
+def alpha_opt(layers, C, t, l_list, u_list, lo, hi, G, h, active, steps=20,
+              lr=0.1, alpha0=0.5, decay=1.0, complete=True, passes=1):
+    """a8 repeated: ``steps`` iterations of (bound, gradient, Adam) starting
+    from alpha0 everywhere.  Returns (best lb over the iterations [B, M],
+    per-iteration lb list, final alpha list)."""
+    B = lo.shape[0]
+    M = C.shape[0]
+    alpha = [np.full((B, M, W.shape[0]), alpha0) for W, _ in layers[:-1]]
+    ms = [np.zeros_like(a) for a in alpha]
+    vs = [np.zeros_like(a) for a in alpha]
+    best = np.full((B, M), -np.inf)
+    hist = []
+    for s in range(1, steps + 1):
+        lb, grads, _, _ = bound_and_grad(layers, C, t, l_list, u_list, alpha, lo, hi,
+                                         G, h, active, complete, passes)
+        hist.append(lb)
+        best = np.maximum(best, lb)
+        lr_s = lr * decay ** (s - 1)
+        for kk in range(len(alpha)):
+            alpha[kk], ms[kk], vs[kk] = adam_ascent(alpha[kk], grads[kk], ms[kk], vs[kk], s, lr_s)
+    return best, hist, alpha

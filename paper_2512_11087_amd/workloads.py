@@ -1,0 +1,311 @@
+"""Seeded synthetic inputs for the clip-and-verify hot path.
+
+This module is shared by the GPU path, the CPU oracle, the tests and the
+benchmark.  It only draws random numbers and arranges them into arrays: it
+holds none of the bounding or clipping arithmetic.  Every array it returns is
+float32 (or an integer type); a consumer that computes in float64 widens the
+float32 values exactly.
+
+Workload shapes follow the paper's settings where it states them: He-normal
+ReLU networks, l-infinity input boxes (CIFAR radius 2/255 from the experiments
+section), activation split constraints drawn as (layer, neuron, sign) triples,
+and margin specifications ``e_y - e_j`` with a zero threshold (appendix on
+specification matrices).  The paper's benchmark models and datasets are not
+available; these synthetic inputs stand in for them.
+
+Seeds: weights 0, box centres 1, splits 2, soundness samples 3, property
+sizes 4 (each generator takes its seed explicitly).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+SEED_WEIGHTS = 0
+SEED_CENTRES = 1
+SEED_SPLITS = 2
+SEED_SAMPLES = 3
+SEED_SIZES = 4
+
+
+@dataclass
+class Layer:
+    """One affine layer.  ``kind`` is ``"linear"`` (W: [out, in]) or
+    ``"conv"`` (W: [oc, ic, kh, kw] with stride/pad and the input shape)."""
+
+    kind: str
+    W: np.ndarray
+    b: np.ndarray
+    stride: int = 1
+    pad: int = 0
+    in_shape: tuple = ()   # (C, H, W) for conv
+    out_shape: tuple = ()  # (C, H, W) for conv
+
+    @property
+    def n_in(self) -> int:
+        if self.kind == "linear":
+            return int(self.W.shape[1])
+        return int(np.prod(self.in_shape))
+
+    @property
+    def n_out(self) -> int:
+        if self.kind == "linear":
+            return int(self.W.shape[0])
+        return int(np.prod(self.out_shape))
+
+
+@dataclass
+class Network:
+    """A feed-forward ReLU network: ReLU after every layer but the last."""
+
+    layers: List[Layer]
+
+    @property
+    def n_in(self) -> int:
+        return self.layers[0].n_in
+
+    @property
+    def n_out(self) -> int:
+        return self.layers[-1].n_out
+
+    @property
+    def hidden_sizes(self) -> List[int]:
+        return [ly.n_out for ly in self.layers[:-1]]
+
+    @property
+    def hidden_offsets(self) -> List[int]:
+        """Global index of the first neuron of each hidden layer."""
+        off, acc = [], 0
+        for n in self.hidden_sizes:
+            off.append(acc)
+            acc += n
+        return off
+
+    @property
+    def n_hidden(self) -> int:
+        return int(sum(self.hidden_sizes))
+
+
+def he_mlp(widths: Sequence[int], seed: int = SEED_WEIGHTS,
+           bias: str = "zero") -> Network:
+    """ReLU MLP with He-normal weights N(0, 2/fan_in), drawn in layer order,
+    row-major [out, in].  ``bias`` is ``"zero"`` or ``"uniform"``
+    (U[-0.1, 0.1], a correctness-only variant exercising the bias path)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for n_in, n_out in zip(widths[:-1], widths[1:]):
+        W = rng.normal(0.0, np.sqrt(2.0 / n_in), size=(n_out, n_in))
+        layers.append(Layer("linear", W.astype(np.float32), np.zeros(n_out, np.float32)))
+    if bias == "uniform":
+        for ly in layers:
+            ly.b = rng.uniform(-0.1, 0.1, size=ly.b.shape).astype(np.float32)
+    return Network(layers)
+
+
+def he_cnn(in_shape, convs, fcs, seed: int = SEED_WEIGHTS,
+           bias: str = "zero") -> Network:
+    """CNN: ``convs`` is a list of (out_ch, k, stride, pad); ``fcs`` a list of
+    output widths of the linear layers after flattening (C, H, W order)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    c, h, w = in_shape
+    for oc, k, s, p in convs:
+        fan_in = c * k * k
+        W = rng.normal(0.0, np.sqrt(2.0 / fan_in), size=(oc, c, k, k))
+        ho = (h + 2 * p - k) // s + 1
+        wo = (w + 2 * p - k) // s + 1
+        layers.append(Layer("conv", W.astype(np.float32), np.zeros(oc, np.float32),
+                            stride=s, pad=p, in_shape=(c, h, w), out_shape=(oc, ho, wo)))
+        c, h, w = oc, ho, wo
+    n = c * h * w
+    for n_out in fcs:
+        W = rng.normal(0.0, np.sqrt(2.0 / n), size=(n_out, n))
+        layers.append(Layer("linear", W.astype(np.float32), np.zeros(n_out, np.float32)))
+        n = n_out
+    if bias == "uniform":
+        for ly in layers:
+            ly.b = rng.uniform(-0.1, 0.1, size=ly.b.shape).astype(np.float32)
+    return Network(layers)
+
+
+def box_around(centre: np.ndarray, eps: float, clip: Optional[tuple] = None):
+    """Input box [centre - eps, centre + eps], optionally intersected with
+    [clip[0], clip[1]]; returned as float32 (lo, hi)."""
+    c = np.asarray(centre, np.float64)
+    lo, hi = c - eps, c + eps
+    if clip is not None:
+        lo = np.maximum(lo, clip[0])
+        hi = np.minimum(hi, clip[1])
+    return lo.astype(np.float32), hi.astype(np.float32)
+
+
+def centres(n: int, count: int, low: float, high: float, seed: int = SEED_CENTRES):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(low, high, size=(count, n))
+
+
+def forward(net: Network, x: np.ndarray) -> np.ndarray:
+    """Plain float64 forward pass (used to pick labels and to draw soundness
+    samples).  ``x``: [S, n_in] -> [S, n_out]."""
+    h = np.asarray(x, np.float64)
+    for i, ly in enumerate(net.layers):
+        h = affine(ly, h)
+        if i < len(net.layers) - 1:
+            h = np.maximum(h, 0.0)
+    return h
+
+
+def affine(ly: Layer, h: np.ndarray) -> np.ndarray:
+    """Apply one layer to a batch of flat inputs [S, n_in] in float64."""
+    W = ly.W.astype(np.float64)
+    b = ly.b.astype(np.float64)
+    if ly.kind == "linear":
+        return h @ W.T + b
+    c, hh, ww = ly.in_shape
+    oc, ho, wo = ly.out_shape
+    k = W.shape[2]
+    S = h.shape[0]
+    x = h.reshape(S, c, hh, ww)
+    xp = np.zeros((S, c, hh + 2 * ly.pad, ww + 2 * ly.pad))
+    xp[:, :, ly.pad:ly.pad + hh, ly.pad:ly.pad + ww] = x
+    out = np.zeros((S, oc, ho, wo))
+    for di in range(k):
+        for dj in range(k):
+            patch = xp[:, :, di:di + ly.stride * ho:ly.stride, dj:dj + ly.stride * wo:ly.stride]
+            out += np.einsum("sihw,oi->sohw", patch, W[:, :, di, dj])
+    out += b[None, :, None, None]
+    return out.reshape(S, -1)
+
+
+def pre_activations(net: Network, x: np.ndarray) -> np.ndarray:
+    """Concatenated hidden pre-activations z^(1..L-1) at points x: [S, n_hidden]."""
+    h = np.asarray(x, np.float64)
+    zs = []
+    for i, ly in enumerate(net.layers[:-1]):
+        z = affine(ly, h)
+        zs.append(z)
+        h = np.maximum(z, 0.0)
+    return np.concatenate(zs, axis=1) if zs else np.zeros((x.shape[0], 0))
+
+
+def margin_spec(n_out: int, label: int):
+    """Specification rows e_y - e_j for j != y, threshold 0 (float32)."""
+    rows = []
+    for j in range(n_out):
+        if j != label:
+            r = np.zeros(n_out)
+            r[label], r[j] = 1.0, -1.0
+            rows.append(r)
+    C = np.asarray(rows, np.float32)
+    return C, np.zeros(C.shape[0], np.float32)
+
+
+def identity_spec(n_out: int):
+    return np.eye(n_out, dtype=np.float32), np.zeros(n_out, np.float32)
+
+
+@dataclass
+class Splits:
+    """Per-subdomain activation split lists, padded to ``kmax``.
+
+    ``neuron``: [B, kmax] int32 global hidden-neuron index (-1 = unused slot),
+    ``sign``:   [B, kmax] int8, +1 for the branch z >= 0, -1 for z <= 0,
+    ``count``:  [B] int32 number of used slots (used slots come first)."""
+
+    neuron: np.ndarray
+    sign: np.ndarray
+    count: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return int(self.neuron.shape[0])
+
+    @property
+    def kmax(self) -> int:
+        return int(self.neuron.shape[1])
+
+
+def draw_splits(B: int, counts: np.ndarray, candidates: np.ndarray,
+                seed: int = SEED_SPLITS, kmax: Optional[int] = None) -> Splits:
+    """For each subdomain b, ``counts[b]`` distinct neurons drawn uniformly
+    from ``candidates`` (global indices), each with sign +-1 (p = 1/2)."""
+    rng = np.random.default_rng(seed)
+    counts = np.asarray(counts, np.int32)
+    if kmax is None:
+        kmax = int(counts.max()) if B else 0
+    kmax = max(int(kmax), 1)
+    neuron = np.full((B, kmax), -1, np.int32)
+    sign = np.zeros((B, kmax), np.int8)
+    cand = np.asarray(candidates, np.int64)
+    for b in range(B):
+        k = int(counts[b])
+        if k == 0:
+            continue
+        sel = rng.choice(cand.size, size=k, replace=False)
+        neuron[b, :k] = cand[sel]
+        sign[b, :k] = np.where(rng.random(k) < 0.5, 1, -1)
+    return Splits(neuron, sign, counts.copy())
+
+
+def splits_from_points(net: Network, x: np.ndarray, counts: np.ndarray,
+                       candidates: np.ndarray, seed: int = SEED_SPLITS,
+                       kmax: Optional[int] = None) -> Splits:
+    """Split lists whose signs agree with the activation pattern of point
+    x[b]: so x[b] is a feasible point of subdomain b (soundness tests)."""
+    sp = draw_splits(x.shape[0], counts, candidates, seed, kmax)
+    z = pre_activations(net, x)
+    for b in range(sp.B):
+        k = int(sp.count[b])
+        idx = sp.neuron[b, :k]
+        sp.sign[b, :k] = np.where(z[b, idx] >= 0.0, 1, -1)
+    return sp
+
+
+# ---------------------------------------------------------------- configs
+
+@dataclass
+class Workload:
+    """One synthetic property: network, root box, specification and a batch
+    of subdomains (boxes + split lists)."""
+
+    name: str
+    net: Network
+    lo0: np.ndarray
+    hi0: np.ndarray
+    C: np.ndarray
+    t: np.ndarray
+    B: int
+    split_counts: np.ndarray
+    alpha0: float = 0.5
+    extra: dict = field(default_factory=dict)
+
+
+def tiny_mlp(B: int = 1024, seed: int = SEED_WEIGHTS) -> Workload:
+    """ReLU MLP 5-50x6-5 (zero biases), box = centre U[-1,1]^5 +- 0.05,
+    k ~ U{1..8} splits over all hidden neurons, objective = the 5 outputs."""
+    net = he_mlp([5] + [50] * 6 + [5], seed)
+    c = centres(5, 1, -1.0, 1.0)[0]
+    lo, hi = box_around(c, 0.05)
+    C, t = identity_spec(5)
+    counts = np.random.default_rng(SEED_SIZES).integers(1, 9, size=B).astype(np.int32)
+    return Workload("mlp5-50x6-5", net, lo, hi, C, t, B, counts)
+
+
+def mnist_mlp(B: int = 16384, widths=(784,) + (256,) * 6 + (10,),
+              k: int = 4, seed: int = SEED_WEIGHTS, name="mlp784-256x6-10") -> Workload:
+    """ReLU MLP 784-256x6-10, centre U[0,1]^784, eps 0.02 clipped to [0,1],
+    ``k`` splits per subdomain, 9 margin objectives (label = argmax f(centre))."""
+    net = he_mlp(list(widths), seed)
+    c = centres(widths[0], 1, 0.0, 1.0)[0]
+    lo, hi = box_around(c, 0.02, clip=(0.0, 1.0))
+    label = int(np.argmax(forward(net, c[None, :].astype(np.float32))[0]))
+    C, t = margin_spec(widths[-1], label)
+    counts = np.full(B, k, np.int32)
+    return Workload(name, net, lo, hi, C, t, B, counts, extra={"label": label})
+
+
+def alpha_mlp(B: int = 8192, seed: int = SEED_WEIGHTS) -> Workload:
+    """ReLU MLP 784-1024x4-10, 6 splits per subdomain (slope optimisation)."""
+    return mnist_mlp(B, (784,) + (1024,) * 4 + (10,), 6, seed, "mlp784-1024x4-10")
