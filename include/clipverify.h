@@ -1,0 +1,239 @@
+/*
+ * clipverify.h - C ABI of the MI355X (gfx950) clip-and-verify hot path.
+ *
+ * Batched evaluation, over many branch-and-bound subdomains at once, of
+ * CROWN-style linear bound propagation together with linear-constraint
+ * driven domain clipping (Clip-and-Verify, arXiv 2512.11087).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Floating-point data crossing the ABI is IEEE float32, row-major and
+ *   contiguous.  Internally every sum and product is evaluated in float64
+ *   and every bound written back as float32 is rounded outward (lower
+ *   bounds down, upper bounds up) after subtracting a rigorous bound on the
+ *   float64 rounding error, so a float32 result is never tighter than the
+ *   exact real-arithmetic value it stands for.
+ * - A "box" is a pair lo[n], hi[n] (lo <= x <= hi).  Constraints are
+ *   G x + h <= 0 (the form of Thm 3.1 / Thm 3.2 / Alg. 1).
+ * - Pointers named in "device" are device (HBM) pointers owned by the
+ *   caller; the library never frees them.  Pointers named "host" are read
+ *   during the call only.  Handles (cv_net, cv_root) own their device
+ *   memory until destroyed.
+ * - Every call that takes a hipStream_t enqueues its kernels on that
+ *   stream and returns without synchronising.  Argument and shape checks
+ *   happen before anything is enqueued; a failed check returns an error
+ *   and enqueues nothing.  A HIP error from an enqueue returns CV_E_HIP and
+ *   is kept for cv_last_hip_error().
+ * - Calls that need scratch memory take a caller-provided device workspace
+ *   (ws, ws_bytes) whose minimum size is reported by the matching
+ *   *_workspace function; hot calls never allocate.
+ * - Infeasibility is not an error: an infeasible subdomain gets flag 1 and
+ *   +inf lower bounds (case 1 of the proof of Thm 3.1).
+ * - Handles are immutable after creation: concurrent calls on different
+ *   streams may share them; calls sharing one workspace must not overlap.
+ */
+#ifndef CLIPVERIFY_H
+#define CLIPVERIFY_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CV_OK = 0,
+  CV_E_INVALID = -1,     /* null pointer / invalid value (e.g. alpha outside [0,1]) */
+  CV_E_SHAPE = -2,       /* sizes inconsistent with the handle or each other */
+  CV_E_UNSUPPORTED = -3, /* valid request this build does not implement */
+  CV_E_WORKSPACE = -4,   /* ws_bytes smaller than the reported requirement */
+  CV_E_HIP = -5,         /* a HIP runtime call failed (see cv_last_hip_error) */
+  CV_E_NOMEM = -6        /* device allocation inside a create call failed */
+} cv_status;
+
+const char* cv_status_string(cv_status s);
+/* Last HIP error code recorded by this thread (hipSuccess = 0). */
+int cv_last_hip_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int cv_version(void);
+
+/* ------------------------------------------------------------- network */
+
+enum { CV_LINEAR = 0, CV_CONV2D = 1 };
+
+/* One affine layer; a ReLU follows every layer except the last.
+ * Linear: W host [out_features, in_features], b host [out_features].
+ * Conv2d: W host [out_c, in_c, kernel, kernel], b host [out_c], cross-
+ * correlation with zero padding; activations are flattened (c, h, w). */
+typedef struct {
+  int kind;
+  int in_features, out_features;
+  int in_c, in_h, in_w, out_c, out_h, out_w, kernel, stride, pad;
+  const float* W;
+  const float* b;
+} cv_layer_desc;
+
+typedef struct cv_net_s* cv_net;
+
+/* Copies the weights to the current device.  n_layers >= 1.
+ * Conv layers return CV_E_UNSUPPORTED in this build. */
+cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out);
+cv_status cv_net_destroy(cv_net net);
+/* Host outputs: input dim, output dim, total hidden neurons, layer count. */
+cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_layers);
+
+/* ---------------------------------------------------------- root state */
+
+typedef struct cv_root_s* cv_root;
+
+/* Root pass (once per property): CROWN bounds and planes of every hidden
+ * neuron over the root box, cached for reuse by every subdomain (the
+ * initial bounding pass of the activation-BaB section / Alg. 5,
+ * Get_Constraints).  Layer-1 planes are W1, b1; for a deeper neuron the
+ * lower plane is CROWN with objective +e_j on the cut network and the
+ * upper plane the negation of CROWN with objective -e_j (Lemma A.3 and the
+ * plane recursion of appendix A.3), with the fixed slope alpha0 in [0,1]
+ * for unstable neurons.  Planes are stored float32 with intercepts moved
+ * outward so that they remain valid planes.
+ * lo0, hi0: device [n_in].  Synchronises `stream` before returning. */
+cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
+                         hipStream_t stream, cv_root* out);
+cv_status cv_root_destroy(cv_root root);
+/* Device outputs [n_hidden]: root pre-activation bounds (global neuron
+ * order = layer by layer). */
+cv_status cv_root_bounds(cv_root root, float* l0, float* u0, hipStream_t stream);
+/* Device outputs: A_lo, A_hi [n_hidden, n_in], c_lo, c_hi [n_hidden]:
+ * z_j >= A_lo[j].x + c_lo[j] and z_j <= A_hi[j].x + c_hi[j] on the root box. */
+cv_status cv_root_planes(cv_root root, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
+                         hipStream_t stream);
+/* Host output: number of root-unstable neurons (l0 < 0 < u0). */
+cv_status cv_root_unstable_count(cv_root root, int* count);
+
+/* --------------------------------------------------------- constraints */
+
+/* The linear constraints of each subdomain, in one of two forms.
+ * Split form (neuron != NULL; needs a cv_root): slot k of subdomain b is the
+ * activation split (neuron[b,k], sign[b,k]) on a hidden neuron, turned into
+ * an input halfspace with the cached root planes (eqs. 9-10): sign -1
+ * (branch z <= 0) gives A_lo[j].x + c_lo[j] <= 0, sign +1 (branch z >= 0)
+ * gives -A_hi[j].x - c_hi[j] <= 0.
+ * Dense form (neuron == NULL): slot k of subdomain b is G[b,k,:].x + h[b,k] <= 0.
+ * Slots k < count[b] are used (count == NULL: all kmax).  All device. */
+typedef struct {
+  int kmax;
+  const int32_t* count;  /* [B] or NULL */
+  const int32_t* neuron; /* [B, kmax] global hidden-neuron index */
+  const int8_t* sign;    /* [B, kmax] +1 / -1 */
+  const float* G;        /* [B, kmax, n] */
+  const float* h;        /* [B, kmax] */
+} cv_constraints;
+
+enum { CV_CLIP_PARALLEL = 0, CV_CLIP_SEQUENTIAL = 1 };
+
+/* Relaxed clipping of each subdomain's box.  For each subdomain b and each used
+ * constraint k, m = min over the box of G_k x + h_k; if m > 0 the box is
+ * empty.  Otherwise coordinate i is tightened to lo_i - m/G_ki (upper bound,
+ * G_ki > 0) or hi_i - m/G_ki (lower bound, G_ki < 0): the closed form of
+ * Thm 3.2.  CV_CLIP_PARALLEL applies every constraint to the original box
+ * and keeps the tightest value (Alg. 2); CV_CLIP_SEQUENTIAL applies them in
+ * slot order to the box left by the previous one (Alg. 3).
+ * root: required for the split form, else may be NULL.
+ * lo, hi: device [B, n] in/out.  infeasible: device [B] uint8 out, 1 when
+ * some constraint is certainly empty over the box or lo > hi afterwards.
+ * B == 0 is a no-op. */
+cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons,
+                          float* lo, float* hi, uint8_t* infeasible, int mode,
+                          hipStream_t stream);
+
+/* Re-concretization of the cached planes over each subdomain's box (the
+ * relaxed-clipping section: all intermediate bounds are re-concretized
+ * over the clipped box without a new bound-propagation pass):
+ *   l_j = min over box of A_lo[j].x + c_lo[j],  u_j = max of A_hi[j].x + c_hi[j]
+ * for every root-unstable neuron j, intersected with the root bounds;
+ * root-stable neurons keep their root bounds.  Split neurons are then fixed
+ * to their branch (l_j = max(l_j, 0) for +1, u_j = min(u_j, 0) for -1).
+ * splits: split form or NULL.  l, u: device [B, n_hidden] out.
+ * infeasible: device [B] in/out (OR-ed with "some neuron has l > u").
+ * With complete != 0 the bounds of every neuron still unstable are then
+ * tightened by complete clipping (Alg. 1, `passes` passes) of its lower and
+ * negated upper plane against the subdomain's split halfspaces. */
+cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
+                               const cv_constraints* splits, int complete, int passes,
+                               float* l, float* u, uint8_t* infeasible,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+/* Workspace bytes of cv_concretize_planes (0 unless complete != 0). */
+cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes);
+
+/* Concretization of linear functions over boxes (Lemma A.2), optionally
+ * with complete clipping.  Row p of subdomain b is A[b,p,:].x + c[b,p]
+ * (A_shared != 0: A[p,:], c[p] for every b).  Without constraints
+ * (cons == NULL) lb[b,p] = min over the box.  With constraints, lb[b,p] is
+ * max(that, D(beta)) where beta comes from `passes` passes of coordinate
+ * ascent over the multipliers (Alg. 1): each step maximises the 1-D dual of
+ * Thm 3.1 exactly by locating, among the breakpoints -a_j/g_j, the one where
+ * the supergradient changes sign.  An empty constraint gives lb = +inf and
+ * infeasible[b] = 1.  ub (optional) gets the maximum without constraints.
+ * beta (optional) device [B, P, kmax] gets the multipliers.
+ * lo, hi: device [B, n].  lb, ub: device [B, P].  infeasible: [B] or NULL. */
+cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A_shared,
+                        const float* c, const float* lo, const float* hi,
+                        const cv_constraints* cons, int passes, float* lb, float* ub,
+                        float* beta, uint8_t* infeasible, hipStream_t stream);
+
+/* CROWN backward bound propagation for the objective rows C y + t
+ * (specification matrix and threshold) of every subdomain, the
+ * concretization of the resulting input plane over the box and,
+ * when cons != NULL, complete clipping of that plane against the
+ * subdomain's constraints (lb = the larger of the two).
+ * Starting from Omega = C, each linear layer maps Omega to Psi = Omega W and
+ * adds Omega b to the intercept; each ReLU neuron uses the relaxation of
+ * Lemma A.3 chosen by the sign of Psi: slope 1 (l >= 0), 0 (u <= 0), alpha
+ * (unstable, Psi >= 0) or the upper line u/(u-l)(z-l) (unstable, Psi < 0).
+ * C: device [M, n_out], t: device [M].  l, u: device [B, n_hidden]
+ * (per-subdomain pre-activation bounds, e.g. from cv_concretize_planes).
+ * alpha: device [B, M, n_hidden] in [0,1] or NULL (alpha_default for all).
+ * lo, hi: device [B, n_in], inside the root box of `root` (the root's bounds
+ * feed the rigorous rounding-error bounds; l, u must lie inside the root
+ * bounds, as cv_concretize_planes guarantees).  infeasible: device [B]
+ * in/out or NULL: flagged subdomains get +inf; complete clipping sets the
+ * flag when a constraint is empty over the box.
+ * Outputs (device): lb [B, M]; A_out [B, M, n_in] or NULL (the input plane,
+ * rounded to float32); c_out [B, M] or NULL (its intercept, moved down by
+ * the rounding error bound so that A_out, c_out is a valid plane).
+ * ws: workspace of at least cv_bound_propagate_workspace(...) bytes. */
+cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const float* t,
+                             const float* l, const float* u, const float* alpha,
+                             float alpha_default, const float* lo, const float* hi,
+                             uint8_t* infeasible, cv_root root,
+                             const cv_constraints* cons, int passes,
+                             float* lb, float* A_out, float* c_out,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+cv_status cv_bound_propagate_workspace(cv_net net, int B, int M, size_t* bytes);
+
+/* One slope-optimisation step.  Computes the bound of cv_bound_propagate
+ * (with complete clipping when cons != NULL) at the current alpha into lb,
+ * then the gradient of sum(lb) with respect to every alpha entry that
+ * selects a lower line (unstable neuron, Psi >= 0), holding the complete-
+ * clipping multipliers fixed, by a hand-written adjoint of the backward
+ * pass; then, when lr > 0, one projected Adam ascent step (bias-corrected
+ * moments with beta1, beta2, eps; `step` >= 1 is the 1-based step index)
+ * on alpha, clamped to [0,1].
+ * alpha, adam_m, adam_v: device [B, M, n_hidden] in/out (adam_* may be NULL
+ * when lr == 0).  grad: device [B, M, n_hidden] out or NULL.
+ * ws: at least cv_alpha_step_workspace(...) bytes. */
+cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t,
+                        const float* l, const float* u, float* alpha,
+                        const float* lo, const float* hi, uint8_t* infeasible,
+                        cv_root root, const cv_constraints* cons, int passes,
+                        float* adam_m, float* adam_v, int step, float lr,
+                        float beta1, float beta2, float eps,
+                        float* lb, float* grad, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLIPVERIFY_H */

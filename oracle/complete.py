@@ -32,10 +32,20 @@ Readings taken:
 * Coefficients g_j = 0 give no breakpoint (key +inf, weight 0).
 * Among equal maximisers the smallest beta is reported; the optimum value is
   unique and is what callers compare.
+* Near-ties: a supergradient within TIE_REL * sum_j |g_j| max(|lo_j|, |hi_j|)
+  of zero counts as zero, so the smallest near-maximiser is taken.  Relaxed
+  clipping followed by complete clipping with the same constraint makes the
+  dual exactly flat on [0, q] (the clipped coordinate's weight equals -m);
+  without a tolerance the choice inside that flat segment, and with it every
+  later coordinate-ascent step, would be decided by rounding.  Any beta >= 0
+  stays a valid bound; for one constraint the loss is at most the tolerance
+  times the step in beta.
 """
 import numpy as np
 
 from .box import f64, concretize_min
+
+TIE_REL = 2.0 ** -18
 
 
 def dual_value(a, c, g, h, lo, hi, beta):
@@ -92,17 +102,18 @@ def single_sort(a, c, g, h, lo, hi):
     qs = np.take_along_axis(q, order, -1)
     es = np.take_along_axis(e, order, -1)
     base = (g * xh).sum(-1) + h
+    tol = TIE_REL * (np.abs(g) * np.maximum(np.abs(lo), np.abs(hi))).sum(-1)
     cum = np.cumsum(es, axis=-1)                   # sum_{j<=i}
     total = cum[..., -1:] if es.shape[-1] else np.zeros(base.shape + (1,))
     sg = base[..., None] + (total - cum) - cum      # right supergradient
     before_first = base + total[..., 0]
     m = base - total[..., 0]
     infeas = m > 0.0
-    nonpos = sg <= 0.0
+    nonpos = sg <= tol[..., None]
     has = nonpos.any(-1)
     istar = np.argmax(nonpos, axis=-1)
     q_star = np.take_along_axis(qs, istar[..., None], -1)[..., 0] if qs.shape[-1] else np.zeros(base.shape)
-    beta = np.where(before_first <= 0.0, 0.0, np.where(has, np.maximum(q_star, 0.0), 0.0))
+    beta = np.where(before_first <= tol, 0.0, np.where(has, np.maximum(q_star, 0.0), 0.0))
     beta = np.where(infeas, 0.0, beta)
     L = dual_value(a, c, g, h, lo, hi, beta)
     L = np.where(infeas, np.inf, L)

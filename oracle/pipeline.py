@@ -4,30 +4,30 @@ Adam (FP64 oracle).
 Steps, for one property whose root planes were cached by ``crown.root_pass``
 and a batch of subdomains (input box + activation split list each):
 
-a1 split -> input halfspace (eqs. 9-10 of the activation-BaB section): the
+(1) split -> input halfspace (eqs. 9-10 of the activation-BaB section): the
    branch z_j >= 0 gives  -Ahi_j x - chi_j <= 0  (because z_j <= Ahi_j x + chi_j);
    the branch z_j <= 0 gives  Alo_j x + clo_j <= 0 (because z_j >= Alo_j x + clo_j).
-a2 relaxed clipping of the box (Thm 3.2 / Alg. 2, or Alg. 3).
-a3 re-concretization of every cached plane over the clipped box (the
+(2) relaxed clipping of the box (Thm 3.2 / Alg. 2, or Alg. 3).
+(3) re-concretization of every cached plane over the clipped box (the
    "re-concretize cached linear constraints over the shrunk box" step of the
    relaxed-clipping section), intersected with the root bounds; a split
    neuron is fixed to its branch (l >= 0 for z >= 0, u <= 0 for z <= 0) as
    in Alg. 5, where children fix each split neuron's regime.
-a4 (optional) complete clipping of unstable intermediate neurons: the cached
+(4) (optional) complete clipping of unstable intermediate neurons: the cached
    lower plane (and the negated upper plane) are the objectives, the split
    halfspaces the constraints (Alg. 1).
-a5 CROWN backward pass for the objective rows with the per-subdomain bounds.
-a6 concretization of the final plane over the clipped box (Lemma A.2).
-a7 complete clipping of each final plane against the subdomain's split
+(5) CROWN backward pass for the objective rows with the per-subdomain bounds.
+(6) concretization of the final plane over the clipped box (Lemma A.2).
+(7) complete clipping of each final plane against the subdomain's split
    halfspaces (Alg. 1, one pass); lb <- max(lb, result).
 
-A subdomain is infeasible if a2 finds an empty constraint (or lo > hi), a3/a4
-leave some neuron with l > u, or a7 finds a constraint empty over the clipped
+A subdomain is infeasible if (2) finds an empty constraint (or lo > hi), (3)/(4)
+leave some neuron with l > u, or (7) finds a constraint empty over the clipped
 box; its bounds are +inf.  It is verified if infeasible or every objective
 row has lb > 0 (MinPool conjunction, appendix on Boolean properties).
 
-The slope step (a8): the gradient of sum(lb) after a7 with respect to the
-alpha of every unstable lower-line entry, holding the a7 multipliers fixed
+The slope step (8): the gradient of sum(lb) after (7) with respect to the
+alpha of every unstable lower-line entry, holding the (7) multipliers fixed
 (Danskin), followed by projected Adam ascent (the experimental settings use
 Adam on alpha with lr 0.1, 20 iterations, optional decay 0.98).
 
@@ -40,7 +40,7 @@ Readings taken:
   loss is the sum of the rows' bounds (separable per row).  Root planes use a
   fixed alpha (0.5).
 * At a kink of the final dual (a coefficient of A + beta^T G that is zero up
-  to rounding, which happens at the breakpoint chosen by a7) the subgradient
+  to rounding, which happens at the breakpoint chosen by (7)) the subgradient
   uses the box midpoint for that coordinate: any point of [lo_j, hi_j] is a
   valid subgradient there; the midpoint is the symmetric choice.
 """
@@ -59,16 +59,16 @@ KINK_REL = 2.0 ** -40
 @dataclass
 class Config:
     relaxed: str = "parallel"        # "parallel" | "sequential" | "none"
-    reconcretize: bool = True        # a3
+    reconcretize: bool = True        # step (3)
     split_fix: bool = True
-    complete_intermediate: bool = False  # a4
-    complete_final: bool = True      # a7
+    complete_intermediate: bool = False  # step (4)
+    complete_final: bool = True      # step (7)
     ca_passes: int = 1
     alpha: float = 0.5
 
 
 def split_constraints(root, neuron, sign, count):
-    """a1: halfspaces G x + h <= 0 of each subdomain's splits (eqs. 9-10).
+    """Step (1): halfspaces G x + h <= 0 of each subdomain's splits (eqs. 9-10).
     neuron/sign: [B, kmax]; count: [B].  Returns (G [B,k,n0], h [B,k],
     active [B,k])."""
     A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
@@ -84,7 +84,7 @@ def split_constraints(root, neuron, sign, count):
 
 
 def reconcretize(root, lo, hi):
-    """a3 without the fixes: bounds of every hidden neuron over each box.
+    """Step (3) without the fixes: bounds of every hidden neuron over each box.
     Returns (l [B, N], u [B, N])."""
     A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
     return concretize_min_shared(A_lo, c_lo, lo, hi), concretize_max_shared(A_hi, c_hi, lo, hi)
@@ -109,7 +109,7 @@ def fix_bounds(root, l, u, neuron, sign, count, split_fix=True):
 
 
 def complete_intermediate(root, l, u, G, h, active, lo, hi, passes=1):
-    """a4: complete clipping of every unstable neuron's cached lower plane
+    """Step (4): complete clipping of every unstable neuron's cached lower plane
     (tightens l) and negated upper plane (tightens u).  Returns (l, u, empty)."""
     A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
     l, u = l.copy(), u.copy()
@@ -143,7 +143,7 @@ def split_layers(net_layers, flat):
 
 
 def final_clip(A, c, G, h, active, lo, hi, passes=1):
-    """a7 for a batch: rows (b, m) of A [B, M, n] / c [B, M] against the
+    """Step (7) for a batch: rows (b, m) of A [B, M, n] / c [B, M] against the
     constraints of subdomain b.  Returns (L [B, M], beta [B, M, k], empty [B])."""
     B, M, n = A.shape
     k = G.shape[1]
@@ -154,19 +154,19 @@ def final_clip(A, c, G, h, active, lo, hi, passes=1):
 
 
 def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=None):
-    """Steps a1-a7 for a batch of subdomains; returns a dict of every
+    """Steps (1)-(7) for a batch of subdomains; returns a dict of every
     intermediate result.  ``layers``: dense (W, b) list; lo/hi: [B, n0];
     alpha: None (use cfg.alpha) or per-layer [B, M, n_i] arrays."""
     lo, hi = f64(lo), f64(hi)
     out = {}
     G, h, act = split_constraints(root, neuron, sign, count)
     if cfg.relaxed == "parallel":
-        lo2, hi2, inf_a2 = rx.clip_parallel(G, h, lo, hi, act)
+        lo2, hi2, inf_clip = rx.clip_parallel(G, h, lo, hi, act)
     elif cfg.relaxed == "sequential":
-        lo2, hi2, inf_a2 = rx.clip_sequential(G, h, lo, hi, act)
+        lo2, hi2, inf_clip = rx.clip_sequential(G, h, lo, hi, act)
     else:
-        lo2, hi2, inf_a2 = lo.copy(), hi.copy(), np.zeros(lo.shape[0], bool)
-    out.update(G=G, h=h, active=act, lo=lo2, hi=hi2, infeasible_clip=inf_a2)
+        lo2, hi2, inf_clip = lo.copy(), hi.copy(), np.zeros(lo.shape[0], bool)
+    out.update(G=G, h=h, active=act, lo=lo2, hi=hi2, infeasible_clip=inf_clip)
     # bounds are computed on the clipped box; an empty box keeps its values
     if cfg.reconcretize:
         l, u = reconcretize(root, lo2, hi2)
@@ -174,36 +174,36 @@ def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=Non
         _, _, _, _, l0, u0 = root.stacked()
         l = np.broadcast_to(l0, (lo.shape[0], l0.size)).copy()
         u = np.broadcast_to(u0, (lo.shape[0], u0.size)).copy()
-    l, u, emp3 = fix_bounds(root, l, u, neuron, sign, count, cfg.split_fix)
-    out.update(l_a3=l.copy(), u_a3=u.copy(), empty_a3=emp3)
-    emp4 = np.zeros_like(emp3)
+    l, u, emp_r = fix_bounds(root, l, u, neuron, sign, count, cfg.split_fix)
+    out.update(l_reconc=l.copy(), u_reconc=u.copy(), empty_reconc=emp_r)
+    emp_n = np.zeros_like(emp_r)
     if cfg.complete_intermediate:
-        l, u, emp4 = complete_intermediate(root, l, u, G, h, act, lo2, hi2, cfg.ca_passes)
-    out.update(l=l, u=u, empty_a4=emp4)
+        l, u, emp_n = complete_intermediate(root, l, u, G, h, act, lo2, hi2, cfg.ca_passes)
+    out.update(l=l, u=u, empty_neurons=emp_n)
     a = cfg.alpha if alpha is None else alpha
     A, c = crown.backward(layers, C, t, split_layers(layers, l), split_layers(layers, u), a)
     lb0 = concretize_min(A, c, lo2, hi2)
     out.update(A=A, c=c, lb_unclipped=lb0.copy())
-    emp7 = np.zeros_like(emp3)
+    emp_f = np.zeros_like(emp_r)
     lb = lb0
     if cfg.complete_final and G.shape[1] > 0:
-        L, beta, emp7 = final_clip(A, c, G, h, act, lo2, hi2, cfg.ca_passes)
+        L, beta, emp_f = final_clip(A, c, G, h, act, lo2, hi2, cfg.ca_passes)
         lb = np.maximum(lb0, L)
         out["beta"] = beta
-    infeasible = inf_a2 | emp3 | emp4 | emp7
+    infeasible = inf_clip | emp_r | emp_n | emp_f
     lb = np.where(infeasible[:, None], np.inf, lb)
-    out.update(lb=lb, infeasible=infeasible, empty_a7=emp7,
+    out.update(lb=lb, infeasible=infeasible, empty_final=emp_f,
                verified=infeasible | np.all(lb > 0.0, axis=-1))
     return out
 
 
-# ------------------------------------------------------------- slopes (a8)
+# ---------------------------------------------------------- slopes, step (8)
 
 def bound_and_grad(layers, C, t, l_list, u_list, alpha, lo, hi, G, h, active,
                    complete=True, passes=1):
-    """Post-a7 bound of every row and its gradient with respect to alpha.
+    """Post-(7) bound of every row and its gradient with respect to alpha.
 
-    alpha: list of [B, M, n_i] (one per hidden layer).  The multipliers of a7
+    alpha: list of [B, M, n_i] (one per hidden layer).  The multipliers of (7)
     are held fixed (Danskin), so the bound is min over the box of
     (A + beta^T G).x + c + beta^T h and its derivative with respect to A is
     the minimising corner x* (midpoint at zero coefficients).  The adjoint
@@ -259,7 +259,7 @@ def adam_ascent(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 def alpha_opt(layers, C, t, l_list, u_list, lo, hi, G, h, active, steps=20,
               lr=0.1, alpha0=0.5, decay=1.0, complete=True, passes=1):
-    """a8 repeated: ``steps`` iterations of (bound, gradient, Adam) starting
+    """Step (8) repeated: ``steps`` iterations of (bound, gradient, Adam) starting
     from alpha0 everywhere.  Returns (best lb over the iterations [B, M],
     per-iteration lb list, final alpha list)."""
     B = lo.shape[0]

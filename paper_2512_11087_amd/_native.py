@@ -1,0 +1,102 @@
+"""ctypes view of libclipverify.so (the C ABI declared in include/clipverify.h).
+
+Loading fails loudly: there is no fallback implementation.  Build the
+library first with ``python -m paper_2512_11087_amd.build``.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libclipverify.so")
+
+CV_LINEAR, CV_CONV2D = 0, 1
+CV_CLIP_PARALLEL, CV_CLIP_SEQUENTIAL = 0, 1
+
+STATUS = {0: "CV_OK", -1: "CV_E_INVALID", -2: "CV_E_SHAPE", -3: "CV_E_UNSUPPORTED",
+          -4: "CV_E_WORKSPACE", -5: "CV_E_HIP", -6: "CV_E_NOMEM"}
+
+# every function the header declares (checked by the CPU test suite)
+EXPORTS = [
+    "cv_status_string", "cv_last_hip_error", "cv_version",
+    "cv_net_create", "cv_net_destroy", "cv_net_info",
+    "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
+    "cv_root_unstable_count",
+    "cv_clip_domains", "cv_concretize_planes", "cv_concretize_planes_workspace",
+    "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
+    "cv_alpha_step", "cv_alpha_step_workspace",
+]
+
+
+class LayerDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("in_features", C.c_int), ("out_features", C.c_int),
+                ("in_c", C.c_int), ("in_h", C.c_int), ("in_w", C.c_int),
+                ("out_c", C.c_int), ("out_h", C.c_int), ("out_w", C.c_int),
+                ("kernel", C.c_int), ("stride", C.c_int), ("pad", C.c_int),
+                ("W", C.c_void_p), ("b", C.c_void_p)]
+
+
+class Constraints(C.Structure):
+    _fields_ = [("kmax", C.c_int), ("count", C.c_void_p), ("neuron", C.c_void_p),
+                ("sign", C.c_void_p), ("G", C.c_void_p), ("h", C.c_void_p)]
+
+
+class CvError(RuntimeError):
+    def __init__(self, fn, status, hip):
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)}"
+                         + (f" (hip error {hip})" if status == -5 else ""))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libclipverify is not built ({LIB_PATH} missing); "
+                           "run `python -m paper_2512_11087_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, I, F, S, V = C.c_void_p, C.c_int, C.c_float, C.c_size_t, None
+    sig = {
+        "cv_status_string": (C.c_char_p, [I]),
+        "cv_last_hip_error": (I, []),
+        "cv_version": (I, []),
+        "cv_net_create": (I, [P, I, P]),
+        "cv_net_destroy": (I, [P]),
+        "cv_net_info": (I, [P, P, P, P, P]),
+        "cv_root_create": (I, [P, P, P, F, P, P]),
+        "cv_root_destroy": (I, [P]),
+        "cv_root_bounds": (I, [P, P, P, P]),
+        "cv_root_planes": (I, [P, P, P, P, P, P]),
+        "cv_root_unstable_count": (I, [P, P]),
+        "cv_clip_domains": (I, [P, I, I, P, P, P, P, I, P]),
+        "cv_concretize_planes": (I, [P, I, P, P, P, I, I, P, P, P, P, S, P]),
+        "cv_concretize_planes_workspace": (I, [P, I, I, P]),
+        "cv_concretize": (I, [P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),
+        "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, I, P, P, P, P, S, P]),
+        "cv_bound_propagate_workspace": (I, [P, I, I, P]),
+        "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, P, P, P, P, P, I, P, P, I, F, F, F, F,
+                              P, P, P, S, P]),
+        "cv_alpha_step_workspace": (I, [P, I, I, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(fn_name, status):
+    if status != 0:
+        raise CvError(fn_name, status, lib().cv_last_hip_error())
+
+
+def call(name, *args):
+    """Call a cv_* function and raise CvError on a non-zero status."""
+    st = getattr(lib(), name)(*args)
+    check(name, st)
+    return st

@@ -1,0 +1,240 @@
+"""Python binding of libclipverify: argument marshalling only.
+
+Tensors are torch CUDA (HIP) tensors; every call enqueues on the current
+torch stream.  The names follow the C ABI (cv_clip_domains ->
+``clip_domains`` ...).  All arithmetic happens in the HIP library.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    """Device pointer of a contiguous tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f32(t, dev=None):
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32))
+    t = t.to(device=dev or "cuda", dtype=torch.float32)
+    return t.contiguous()
+
+
+class Net:
+    """A ReLU network (linear layers; ReLU after every layer but the last).
+    ``layers``: list of (W [out, in], b [out]) float32 arrays."""
+
+    def __init__(self, layers):
+        self._keep = []
+        descs = (N.LayerDesc * len(layers))()
+        for i, (W, b) in enumerate(layers):
+            W = np.ascontiguousarray(W, dtype=np.float32)
+            b = np.ascontiguousarray(b, dtype=np.float32)
+            self._keep += [W, b]
+            descs[i].kind = N.CV_LINEAR
+            descs[i].in_features = W.shape[1]
+            descs[i].out_features = W.shape[0]
+            descs[i].W = W.ctypes.data
+            descs[i].b = b.ctypes.data
+        h = C.c_void_p()
+        N.call("cv_net_create", descs, len(layers), C.byref(h))
+        self.handle = h
+        self._keep = []
+        a, o, nh, nl = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        N.call("cv_net_info", h, C.byref(a), C.byref(o), C.byref(nh), C.byref(nl))
+        self.n_in, self.n_out, self.n_hidden, self.n_layers = a.value, o.value, nh.value, nl.value
+        self.hidden_sizes = [np.asarray(W).shape[0] for W, _ in layers[:-1]]
+
+    @classmethod
+    def from_network(cls, net):
+        """From an object with ``.layers`` of (kind, W, b) (linear only)."""
+        for ly in net.layers:
+            if ly.kind != "linear":
+                raise NotImplementedError("conv layers are not supported by this build")
+        return cls([(ly.W, ly.b) for ly in net.layers])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and N._lib is not None:
+            N._lib.cv_net_destroy(h)
+            self.handle = None
+
+
+class Root:
+    """Root bounds and cached planes of a property (root box lo0, hi0)."""
+
+    def __init__(self, net, lo0, hi0, alpha0=0.5):
+        self.net = net
+        self.lo0, self.hi0 = _f32(lo0), _f32(hi0)
+        h = C.c_void_p()
+        N.call("cv_root_create", net.handle, _p(self.lo0), _p(self.hi0), float(alpha0), _stream(),
+               C.byref(h))
+        self.handle = h
+        cnt = C.c_int()
+        N.call("cv_root_unstable_count", h, C.byref(cnt))
+        self.n_unstable = cnt.value
+
+    def bounds(self):
+        l0 = torch.empty(self.net.n_hidden, device="cuda")
+        u0 = torch.empty_like(l0)
+        N.call("cv_root_bounds", self.handle, _p(l0), _p(u0), _stream())
+        return l0, u0
+
+    def planes(self):
+        n, d = self.net.n_hidden, self.net.n_in
+        A_lo = torch.empty(n, d, device="cuda")
+        A_hi = torch.empty_like(A_lo)
+        c_lo = torch.empty(n, device="cuda")
+        c_hi = torch.empty_like(c_lo)
+        N.call("cv_root_planes", self.handle, _p(A_lo), _p(c_lo), _p(A_hi), _p(c_hi), _stream())
+        return A_lo, c_lo, A_hi, c_hi
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and N._lib is not None:
+            N._lib.cv_root_destroy(h)
+            self.handle = None
+
+
+class Constraints:
+    """Per-subdomain constraints: ``splits(neuron, sign, count)`` (activation
+    splits resolved with a Root's planes) or ``dense(G, h, count)``."""
+
+    def __init__(self, kmax, count=None, neuron=None, sign=None, G=None, h=None):
+        self.kmax = int(kmax)
+        self.count, self.neuron, self.sign, self.G, self.h = count, neuron, sign, G, h
+        self.struct = N.Constraints(self.kmax, _p(count), _p(neuron), _p(sign), _p(G), _p(h))
+
+    @classmethod
+    def splits(cls, neuron, sign, count=None):
+        neuron = torch.as_tensor(neuron).to("cuda", torch.int32).contiguous()
+        sign = torch.as_tensor(sign).to("cuda", torch.int8).contiguous()
+        if count is not None:
+            count = torch.as_tensor(count).to("cuda", torch.int32).contiguous()
+        return cls(neuron.shape[1], count, neuron, sign)
+
+    @classmethod
+    def dense(cls, G, h, count=None):
+        G, h = _f32(G), _f32(h)
+        if count is not None:
+            count = torch.as_tensor(count).to("cuda", torch.int32).contiguous()
+        return cls(G.shape[1], count, None, None, G, h)
+
+    def ref(self):
+        return C.byref(self.struct)
+
+
+def _cref(cons):
+    return None if cons is None else cons.ref()
+
+
+class Workspace:
+    """Grow-only device scratch buffer handed to the library."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+def clip_domains(root, lo, hi, cons, mode="parallel", infeasible=None):
+    """Relaxed clipping of boxes lo/hi [B, n] in place; returns the
+    infeasible flags [B] (uint8)."""
+    B, n = lo.shape
+    if infeasible is None:
+        infeasible = torch.empty(B, dtype=torch.uint8, device="cuda")
+    m = N.CV_CLIP_SEQUENTIAL if mode == "sequential" else N.CV_CLIP_PARALLEL
+    N.call("cv_clip_domains", root.handle if root is not None else None, B, n, _cref(cons),
+           _p(lo), _p(hi), _p(infeasible), m, _stream())
+    return infeasible
+
+
+def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infeasible=None,
+                      l=None, u=None, ws=None):
+    """Bounds [B, n_hidden] of every hidden neuron over each box from the
+    cached planes; returns (l, u, infeasible)."""
+    B = lo.shape[0]
+    nh = root.net.n_hidden
+    l = torch.empty(B, nh, device="cuda") if l is None else l
+    u = torch.empty(B, nh, device="cuda") if u is None else u
+    if infeasible is None:
+        infeasible = torch.zeros(B, dtype=torch.uint8, device="cuda")
+    need = C.c_size_t()
+    N.call("cv_concretize_planes_workspace", root.handle, B, int(bool(complete)), C.byref(need))
+    buf = None
+    if need.value:
+        buf = (ws or Workspace()).get(need.value)
+    N.call("cv_concretize_planes", root.handle, B, _p(lo), _p(hi), _cref(splits),
+           int(bool(complete)), int(passes), _p(l), _p(u), _p(infeasible), _p(buf),
+           need.value, _stream())
+    return l, u, infeasible
+
+
+def concretize(A, c, lo, hi, cons=None, passes=1, root=None, shared=False, want_ub=False,
+               want_beta=False, infeasible=None):
+    """min (and optionally max) of A x + c over each box, with complete
+    clipping against ``cons`` when given.  A: [B, P, n] or [P, n] (shared)."""
+    B, n = lo.shape
+    P = A.shape[-2]
+    lb = torch.empty(B, P, device="cuda")
+    ub = torch.empty(B, P, device="cuda") if want_ub else None
+    beta = torch.empty(B, P, max(cons.kmax, 1), device="cuda") if (want_beta and cons) else None
+    N.call("cv_concretize", root.handle if root is not None else None, B, P, n, _p(A),
+           int(bool(shared)), _p(c), _p(lo), _p(hi), _cref(cons), int(passes), _p(lb), _p(ub),
+           _p(beta), _p(infeasible), _stream())
+    return lb, ub, beta
+
+
+def bound_propagate(net, root, C_, t, l, u, lo, hi, alpha=None, alpha_default=0.5,
+                    infeasible=None, cons=None, passes=1, want_plane=False, ws=None):
+    """CROWN bound of the objective rows C y + t for every subdomain (with
+    complete clipping when ``cons`` is given).  Returns lb [B, M] and, with
+    ``want_plane``, the input plane (A [B, M, n_in], c [B, M])."""
+    B = lo.shape[0]
+    M = C_.shape[0]
+    lb = torch.empty(B, M, device="cuda")
+    A = torch.empty(B, M, net.n_in, device="cuda") if want_plane else None
+    c = torch.empty(B, M, device="cuda") if want_plane else None
+    need = C.c_size_t()
+    N.call("cv_bound_propagate_workspace", net.handle, B, M, C.byref(need))
+    buf = (ws or Workspace()).get(need.value)
+    N.call("cv_bound_propagate", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha),
+           float(alpha_default), _p(lo), _p(hi), _p(infeasible), root.handle, _cref(cons),
+           int(passes), _p(lb), _p(A), _p(c), _p(buf), need.value, _stream())
+    return (lb, A, c) if want_plane else lb
+
+
+def alpha_step(net, root, C_, t, l, u, alpha, lo, hi, infeasible=None, cons=None, passes=1,
+               adam_m=None, adam_v=None, step=1, lr=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
+               want_grad=False, ws=None):
+    """Bound at the current alpha [B, M, n_hidden] and its gradient, then
+    (lr > 0) one Adam ascent step on alpha in place.  Returns (lb, grad)."""
+    B = lo.shape[0]
+    M = C_.shape[0]
+    lb = torch.empty(B, M, device="cuda")
+    grad = torch.empty_like(alpha) if want_grad else None
+    need = C.c_size_t()
+    N.call("cv_alpha_step_workspace", net.handle, B, M, C.byref(need))
+    buf = (ws or Workspace()).get(need.value)
+    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
+           _p(hi), _p(infeasible), root.handle, _cref(cons), int(passes), _p(adam_m),
+           _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
+           _p(grad), _p(buf), need.value, _stream())
+    return lb, grad

@@ -1,0 +1,610 @@
+// C ABI of libclipverify: handles, argument validation, workspace layout
+// and the host-side sequencing of the kernels (all work is enqueued on the
+// caller's stream; only the create calls synchronise).
+#include <math.h>
+#include <string.h>
+#include <algorithm>
+#include <vector>
+
+#include "../../include/clipverify.h"
+#include "cv_common.h"
+#include "cv_internal.h"
+
+#define CV_VERSION 10000
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+cv_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return CV_E_HIP;
+}
+#define CV_HIP(x)                                  \
+  do {                                             \
+    hipError_t e__ = (x);                          \
+    if (e__ != hipSuccess) return hip_fail(e__);   \
+  } while (0)
+
+// Bump allocator over a caller workspace (256-byte aligned slices).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* p) : base((char*)p) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+template <class T>
+cv_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return CV_OK;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) return CV_E_NOMEM;
+  return CV_OK;
+}
+
+// Workspace of one backward pass (rows R = B*M, objective rows M).
+struct Bwd {
+  double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
+  float* trace;
+};
+
+size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, bool trace,
+                  void* ws, Bwd* w) {
+  Carve cv(ws);
+  int nmax = 1, ntmax = 1;
+  for (int i = 1; i < T; ++i) nmax = std::max(nmax, net->n[i]);
+  for (int i = 0; i < T; ++i) ntmax = std::max(ntmax, gemm_ntiles(net->n[i]));
+  Bwd x{};
+  x.Om0 = cv.take<double>((size_t)R * nmax);
+  x.Om1 = cv.take<double>((size_t)R * nmax);
+  x.Ax = keepAx ? cv.take<double>((size_t)R * net->n[0]) : nullptr;
+  x.part = cv.take<double>((size_t)R * ntmax * 3);
+  x.rowc = cv.take<double>(R);
+  x.rowerr = cv.take<double>(R);
+  x.rowcabs = cv.take<double>(R);
+  x.psiT = cv.take<double>((size_t)M * net->n[T - 1]);
+  x.c0 = cv.take<double>(M);
+  x.e0 = cv.take<double>(M);
+  x.cabs0 = cv.take<double>(M);
+  x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
+  if (w) *w = x;
+  return cv.off + 256;
+}
+
+// CROWN backward pass through layers T..1 of `net` for rows r = (b, m):
+// objective C (M x n_T) on z_T, then concretization over each box.  Leaves
+// the intercept and the plane's error bound in w.rowc / w.rowerr and, when
+// w.Ax is set, the input plane in w.Ax.
+cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B, int M,
+                       const float* C, const float* t, const float* l, const float* u,
+                       const float* alpha, double alpha_def, const float* lo, const float* hi,
+                       const uint8_t* infeasible, const Bwd& w, float* lb, float* A_out,
+                       float* c_out, hipStream_t s) {
+  const int R = B * M;
+  const int Nh = net->n_hidden;
+  const int nP = net->n[T - 1];
+  CV_HIP(launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
+                    w.psiT, w.c0, w.e0, w.cabs0, s));
+  // ReLU of hidden layer T-1 (array index T-2)
+  CV_HIP(launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
+                          alpha_def, net->b[T - 2], root->wrel[T - 2], w.Om0, w.trace, w.rowc,
+                          w.rowerr, w.rowcabs, s));
+  double* cur = w.Om0;
+  double* nxt = w.Om1;
+  for (int i = T - 1; i >= 2; --i) {
+    const int K = net->n[i], N = net->n[i - 1];
+    CV_HIP(launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
+                             alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
+    CV_HIP(launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
+    std::swap(cur, nxt);
+  }
+  const int n0 = net->n[0];
+  CV_HIP(launch_gemm_final(R, net->n[1], n0, cur, net->W[0], M, lo, hi, root->X0, w.Ax, A_out,
+                           w.part, s));
+  CV_HIP(launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
+                         root->gamma_big, infeasible, lb, c_out, s));
+  return CV_OK;
+}
+
+cv_status resolve_cons(const cv_root_s* root, const cv_constraints* c, CvCons* out) {
+  memset(out, 0, sizeof(*out));
+  if (!c) return CV_OK;
+  if (c->kmax < 0) return CV_E_SHAPE;
+  out->kmax = c->kmax;
+  out->count = c->count;
+  if (c->kmax == 0) return CV_OK;
+  if (c->neuron) {
+    if (!root) return CV_E_INVALID;
+    if (!c->sign) return CV_E_INVALID;
+    out->neuron = c->neuron;
+    out->sign = c->sign;
+    out->A_lo = root->A_lo;
+    out->A_hi = root->A_hi;
+    out->c_lo = root->c_lo;
+    out->c_hi = root->c_hi;
+    out->nplanes = root->N;
+  } else {
+    if (!c->G || !c->h) return CV_E_INVALID;
+    out->G = c->G;
+    out->h = c->h;
+  }
+  return CV_OK;
+}
+
+bool finite01(float a) { return a >= 0.0f && a <= 1.0f; }
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char* cv_status_string(cv_status s) {
+  switch (s) {
+    case CV_OK: return "ok";
+    case CV_E_INVALID: return "invalid argument";
+    case CV_E_SHAPE: return "inconsistent shape";
+    case CV_E_UNSUPPORTED: return "unsupported";
+    case CV_E_WORKSPACE: return "workspace too small";
+    case CV_E_HIP: return "HIP runtime error";
+    case CV_E_NOMEM: return "device allocation failed";
+  }
+  return "unknown status";
+}
+
+int cv_last_hip_error(void) { return g_last_hip; }
+int cv_version(void) { return CV_VERSION; }
+
+cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) {
+  if (!layers || !out) return CV_E_INVALID;
+  *out = nullptr;
+  if (n_layers < 2) return CV_E_UNSUPPORTED;  // at least one hidden ReLU layer
+  if (n_layers > CV_MAX_LAYERS) return CV_E_UNSUPPORTED;
+  for (int i = 0; i < n_layers; ++i) {
+    const cv_layer_desc& d = layers[i];
+    if (d.kind == CV_CONV2D) return CV_E_UNSUPPORTED;
+    if (d.kind != CV_LINEAR) return CV_E_INVALID;
+    if (d.in_features <= 0 || d.out_features <= 0 || !d.W || !d.b) return CV_E_INVALID;
+    if (i > 0 && d.in_features != layers[i - 1].out_features) return CV_E_SHAPE;
+  }
+  cv_net_s* net = new cv_net_s();
+  net->L = n_layers;
+  net->n[0] = layers[0].in_features;
+  int acc = 0;
+  for (int i = 0; i < n_layers; ++i) {
+    const cv_layer_desc& d = layers[i];
+    const int no = d.out_features, ni = d.in_features;
+    net->n[i + 1] = no;
+    net->W[i] = net->Wt[i] = net->b[i] = nullptr;
+    std::vector<float> W(d.W, d.W + (size_t)no * ni), Wt((size_t)no * ni), bb(d.b, d.b + no);
+    for (int r = 0; r < no; ++r)
+      for (int c = 0; c < ni; ++c) Wt[(size_t)c * no + r] = W[(size_t)r * ni + c];
+    if (dev_alloc(&net->W[i], W.size()) || dev_alloc(&net->Wt[i], Wt.size()) ||
+        dev_alloc(&net->b[i], bb.size())) {
+      cv_net_destroy(net);
+      return CV_E_NOMEM;
+    }
+    if (hipMemcpy(net->W[i], W.data(), W.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->Wt[i], Wt.data(), Wt.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->b[i], bb.data(), bb.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      cv_net_destroy(net);
+      return hip_fail(hipGetLastError());
+    }
+    net->hW.push_back(W);
+    net->hb.push_back(bb);
+    if (i < n_layers - 1) {
+      net->off[i] = acc;
+      acc += no;
+      net->nmax_hidden = std::max(net->nmax_hidden, no);
+    }
+  }
+  net->n_hidden = acc;
+  *out = net;
+  return CV_OK;
+}
+
+cv_status cv_net_destroy(cv_net net) {
+  if (!net) return CV_OK;
+  for (int i = 0; i < net->L; ++i) {
+    if (net->W[i]) (void)hipFree(net->W[i]);
+    if (net->Wt[i]) (void)hipFree(net->Wt[i]);
+    if (net->b[i]) (void)hipFree(net->b[i]);
+  }
+  delete net;
+  return CV_OK;
+}
+
+cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_layers) {
+  if (!net) return CV_E_INVALID;
+  if (n_in) *n_in = net->n[0];
+  if (n_out) *n_out = net->n[net->L];
+  if (n_hidden) *n_hidden = net->n_hidden;
+  if (n_layers) *n_layers = net->L;
+  return CV_OK;
+}
+
+cv_status cv_root_destroy(cv_root r) {
+  if (!r) return CV_OK;
+  float* fs[] = {r->A_lo, r->A_hi, r->c_lo, r->c_hi, r->l0, r->u0, r->lo0, r->hi0, r->P, r->cP};
+  for (float* p : fs)
+    if (p) (void)hipFree(p);
+  if (r->X0) (void)hipFree(r->X0);
+  if (r->eP) (void)hipFree(r->eP);
+  if (r->uidx) (void)hipFree(r->uidx);
+  if (r->sidx) (void)hipFree(r->sidx);
+  for (int i = 0; i < CV_MAX_LAYERS; ++i) {
+    if (r->vgemm[i]) (void)hipFree(r->vgemm[i]);
+    if (r->wrel[i]) (void)hipFree(r->wrel[i]);
+  }
+  delete r;
+  return CV_OK;
+}
+
+cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
+                         hipStream_t s, cv_root* out) {
+  if (!net || !lo0 || !hi0 || !out) return CV_E_INVALID;
+  if (!finite01(alpha0)) return CV_E_INVALID;
+  *out = nullptr;
+  const int n0 = net->n[0], N = net->n_hidden, L = net->L;
+  cv_root_s* r = new cv_root_s();
+  for (int i = 0; i < CV_MAX_LAYERS; ++i) r->vgemm[i] = r->wrel[i] = nullptr;
+  r->net = net;
+  r->n0 = n0;
+  r->N = N;
+  r->alpha0 = alpha0;
+  cv_status st = CV_OK;
+  auto fail = [&](cv_status e) {
+    cv_root_destroy(r);
+    return e;
+  };
+  if ((st = dev_alloc(&r->A_lo, (size_t)N * n0)) || (st = dev_alloc(&r->A_hi, (size_t)N * n0)) ||
+      (st = dev_alloc(&r->c_lo, N)) || (st = dev_alloc(&r->c_hi, N)) ||
+      (st = dev_alloc(&r->l0, N)) || (st = dev_alloc(&r->u0, N)) ||
+      (st = dev_alloc(&r->lo0, n0)) || (st = dev_alloc(&r->hi0, n0)) ||
+      (st = dev_alloc(&r->X0, n0)))
+    return fail(st);
+  // root box and |x| bound
+  std::vector<float> hlo(n0), hhi(n0);
+  if (hipMemcpyAsync(hlo.data(), lo0, n0 * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hhi.data(), hi0, n0 * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(hip_fail(hipGetLastError()));
+  for (int j = 0; j < n0; ++j)
+    if (!(hlo[j] <= hhi[j])) return fail(CV_E_INVALID);
+  std::vector<double> hX0(n0);
+  for (int j = 0; j < n0; ++j) hX0[j] = std::max(fabs((double)hlo[j]), fabs((double)hhi[j]));
+  if (hipMemcpy(r->lo0, hlo.data(), n0 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(r->hi0, hhi.data(), n0 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(r->X0, hX0.data(), n0 * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(hip_fail(hipGetLastError()));
+  int kmax_dot = 2 * n0 + 2;
+  for (int i = 0; i <= L; ++i) kmax_dot = std::max(kmax_dot, net->n[i] + 2);
+  r->gamma_big = cv_gamma(kmax_dot);
+
+  std::vector<float> hl0(N), hu0(N);
+  std::vector<double> H(hX0);  // bound on |input| of the current layer
+  auto upload_vec = [&](double** dst, const std::vector<double>& v) -> cv_status {
+    cv_status e = dev_alloc(dst, v.size());
+    if (e) return e;
+    if (hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return hip_fail(hipGetLastError());
+    return CV_OK;
+  };
+  // vgemm of layer i (1-based) from the bound H on its input
+  auto make_vgemm = [&](int i) -> cv_status {
+    const int no = net->n[i], ni = net->n[i - 1];
+    std::vector<double> v(no);
+    const std::vector<float>& W = net->hW[i - 1];
+    const std::vector<float>& b = net->hb[i - 1];
+    for (int k = 0; k < no; ++k) {
+      double s_ = fabs((double)b[k]);
+      for (int j = 0; j < ni; ++j) s_ += fabs((double)W[(size_t)k * ni + j]) * H[j];
+      v[k] = s_ * (1.0 + 1e-12);
+    }
+    return upload_vec(&r->vgemm[i - 1], v);
+  };
+  // after hidden layer i's root bounds are known: wrel_i and the next H
+  auto finish_layer = [&](int i) -> cv_status {
+    const int no = net->n[i], off = net->off[i - 1];
+    if (hipMemcpy(hl0.data() + off, r->l0 + off, no * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hu0.data() + off, r->u0 + off, no * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(hipGetLastError());
+    std::vector<double> vg(no), wr(no);
+    if (hipMemcpy(vg.data(), r->vgemm[i - 1], no * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(hipGetLastError());
+    H.assign(no, 0.0);
+    for (int k = 0; k < no; ++k) {
+      const double lz = hl0[off + k], uz = hu0[off + k];
+      wr[k] = std::max(fabs(lz), fabs(uz)) + vg[k];
+      H[k] = std::max(uz, 0.0);
+    }
+    return upload_vec(&r->wrel[i - 1], wr);
+  };
+
+  // hidden layer 1: planes are W1, b1 exactly
+  const int n1 = net->n[1];
+  if ((st = make_vgemm(1))) return fail(st);
+  if (hipMemcpyAsync(r->A_lo, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(r->A_hi, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(r->c_lo, net->b[0], n1 * 4, hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(r->c_hi, net->b[0], n1 * 4, hipMemcpyDeviceToDevice, s))
+    return fail(hip_fail(hipGetLastError()));
+  if (launch_concretize_rows(n1, n0, r->A_lo, r->c_lo, r->lo0, r->hi0, 0, r->l0, s) ||
+      launch_concretize_rows(n1, n0, r->A_hi, r->c_hi, r->lo0, r->hi0, 1, r->u0, s) ||
+      hipStreamSynchronize(s))
+    return fail(hip_fail(hipGetLastError()));
+  if ((st = finish_layer(1))) return fail(st);
+
+  // deeper hidden layers: CROWN with objectives +I (lower) and -I (upper)
+  void* ws = nullptr;
+  float *Cdev = nullptr, *tdev = nullptr, *lbtmp = nullptr;
+  auto cleanup = [&]() {
+    if (ws) (void)hipFree(ws);
+    if (Cdev) (void)hipFree(Cdev);
+    if (tdev) (void)hipFree(tdev);
+    if (lbtmp) (void)hipFree(lbtmp);
+  };
+  for (int i = 2; i <= L - 1; ++i) {
+    const int ni = net->n[i], off = net->off[i - 1];
+    if ((st = make_vgemm(i))) { cleanup(); return fail(st); }
+    Bwd w;
+    const size_t bytes = bwd_layout(net, i, ni, ni, true, false, nullptr, nullptr);
+    if (ws) (void)hipFree(ws);
+    ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) { cleanup(); return fail(CV_E_NOMEM); }
+    bwd_layout(net, i, ni, ni, true, false, ws, &w);
+    if (Cdev) (void)hipFree(Cdev);
+    if (tdev) (void)hipFree(tdev);
+    if (lbtmp) (void)hipFree(lbtmp);
+    Cdev = tdev = lbtmp = nullptr;
+    if (dev_alloc(&Cdev, (size_t)ni * ni) || dev_alloc(&tdev, ni) || dev_alloc(&lbtmp, ni)) {
+      cleanup();
+      return fail(CV_E_NOMEM);
+    }
+    std::vector<float> I((size_t)ni * ni, 0.0f), z(ni, 0.0f);
+    for (int side = 0; side < 2; ++side) {
+      for (int k = 0; k < ni; ++k) I[(size_t)k * ni + k] = side ? -1.0f : 1.0f;
+      if (hipMemcpy(Cdev, I.data(), I.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(tdev, z.data(), ni * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        cleanup();
+        return fail(hip_fail(hipGetLastError()));
+      }
+      st = backward_run(net, r, i, 1, ni, Cdev, tdev, r->l0, r->u0, nullptr, alpha0, r->lo0,
+                        r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
+      if (st) { cleanup(); return fail(st); }
+      float* Adst = (side ? r->A_hi : r->A_lo) + (size_t)off * n0;
+      float* cdst = (side ? r->c_hi : r->c_lo) + off;
+      if (launch_root_store_planes(ni, n0, w.Ax, w.rowc, w.rowerr, r->X0, side, Adst, cdst, s)) {
+        cleanup();
+        return fail(hip_fail(hipGetLastError()));
+      }
+    }
+    if (launch_concretize_rows(ni, n0, r->A_lo + (size_t)off * n0, r->c_lo + off, r->lo0, r->hi0,
+                               0, r->l0 + off, s) ||
+        launch_concretize_rows(ni, n0, r->A_hi + (size_t)off * n0, r->c_hi + off, r->lo0, r->hi0,
+                               1, r->u0 + off, s) ||
+        hipStreamSynchronize(s)) {
+      cleanup();
+      return fail(hip_fail(hipGetLastError()));
+    }
+    if ((st = finish_layer(i))) { cleanup(); return fail(st); }
+  }
+  cleanup();
+  if ((st = make_vgemm(L))) return fail(st);
+
+  // unstable / stable lists and the packed plane matrix
+  std::vector<int32_t> us, ss;
+  for (int j = 0; j < N; ++j) (hl0[j] < 0.0f && hu0[j] > 0.0f ? us : ss).push_back(j);
+  r->U = (int)us.size();
+  if ((st = dev_alloc(&r->uidx, us.size())) || (st = dev_alloc(&r->sidx, ss.size())) ||
+      (st = dev_alloc(&r->P, (size_t)2 * n0 * 2 * r->U)) || (st = dev_alloc(&r->cP, 2 * r->U)) ||
+      (st = dev_alloc(&r->eP, 2 * r->U)))
+    return fail(st);
+  if ((!us.empty() && hipMemcpy(r->uidx, us.data(), us.size() * 4, hipMemcpyHostToDevice)) ||
+      (!ss.empty() && hipMemcpy(r->sidx, ss.data(), ss.size() * 4, hipMemcpyHostToDevice)))
+    return fail(hip_fail(hipGetLastError()));
+  if (launch_build_P(n0, r->U, r->uidx, r->A_lo, r->A_hi, r->c_lo, r->c_hi, r->X0, r->P, r->cP,
+                     r->eP, s) ||
+      hipStreamSynchronize(s))
+    return fail(hip_fail(hipGetLastError()));
+  *out = r;
+  return CV_OK;
+}
+
+cv_status cv_root_bounds(cv_root r, float* l0, float* u0, hipStream_t s) {
+  if (!r || !l0 || !u0) return CV_E_INVALID;
+  CV_HIP(hipMemcpyAsync(l0, r->l0, (size_t)r->N * 4, hipMemcpyDeviceToDevice, s));
+  CV_HIP(hipMemcpyAsync(u0, r->u0, (size_t)r->N * 4, hipMemcpyDeviceToDevice, s));
+  return CV_OK;
+}
+
+cv_status cv_root_planes(cv_root r, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
+                         hipStream_t s) {
+  if (!r || !A_lo || !c_lo || !A_hi || !c_hi) return CV_E_INVALID;
+  const size_t na = (size_t)r->N * r->n0 * 4, nc = (size_t)r->N * 4;
+  CV_HIP(hipMemcpyAsync(A_lo, r->A_lo, na, hipMemcpyDeviceToDevice, s));
+  CV_HIP(hipMemcpyAsync(A_hi, r->A_hi, na, hipMemcpyDeviceToDevice, s));
+  CV_HIP(hipMemcpyAsync(c_lo, r->c_lo, nc, hipMemcpyDeviceToDevice, s));
+  CV_HIP(hipMemcpyAsync(c_hi, r->c_hi, nc, hipMemcpyDeviceToDevice, s));
+  return CV_OK;
+}
+
+cv_status cv_root_unstable_count(cv_root r, int* count) {
+  if (!r || !count) return CV_E_INVALID;
+  *count = r->U;
+  return CV_OK;
+}
+
+cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons, float* lo,
+                          float* hi, uint8_t* infeasible, int mode, hipStream_t s) {
+  if (B < 0 || n <= 0) return CV_E_SHAPE;
+  if (mode != CV_CLIP_PARALLEL && mode != CV_CLIP_SEQUENTIAL) return CV_E_INVALID;
+  if (B == 0) return CV_OK;
+  if (!cons || !lo || !hi || !infeasible) return CV_E_INVALID;
+  if (n > 4096) return CV_E_UNSUPPORTED;
+  if (cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
+  CvCons c;
+  cv_status st = resolve_cons(root, cons, &c);
+  if (st) return st;
+  CV_HIP(launch_clip(B, n, c, lo, hi, infeasible, mode, s));
+  return CV_OK;
+}
+
+cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes) {
+  if (!root || !bytes || B < 0) return CV_E_INVALID;
+  *bytes = complete ? (size_t)B * root->U * 2 * sizeof(float) + 256 : 0;
+  return CV_OK;
+}
+
+cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
+                               const cv_constraints* splits, int complete, int passes, float* l,
+                               float* u, uint8_t* infeasible, void* ws, size_t ws_bytes,
+                               hipStream_t s) {
+  if (!root || B < 0) return CV_E_INVALID;
+  if (B == 0) return CV_OK;
+  if (!lo || !hi || !l || !u || !infeasible) return CV_E_INVALID;
+  if (splits && splits->kmax > 0 && (!splits->neuron || !splits->sign)) return CV_E_INVALID;
+  if (complete && passes < 1) return CV_E_INVALID;
+  size_t need = 0;
+  cv_concretize_planes_workspace(root, B, complete, &need);
+  if (complete && ws_bytes < need) return CV_E_WORKSPACE;
+  if (complete && root->n0 > 1024) return CV_E_UNSUPPORTED;
+  CvCons sp;
+  cv_status st = resolve_cons(root, splits, &sp);
+  if (st) return st;
+  const int Nh = root->N, U = root->U;
+  CV_HIP(launch_fill_stable(B, Nh, Nh - U, root->sidx, root->l0, root->u0, l, u, s));
+  CV_HIP(launch_gemm_planes(B, root->n0, U, lo, hi, root->P, root->cP, root->eP, root->uidx,
+                            root->l0, root->u0, Nh, l, u, s));
+  if (splits && splits->kmax > 0) CV_HIP(launch_split_fix(B, Nh, sp, l, u, infeasible, s));
+  if (complete && splits && splits->kmax > 0 && U > 0) {
+    float* Ltmp = Carve(ws).take<float>((size_t)B * U * 2);
+    CV_HIP(launch_ca_neurons(B, U, root->n0, root->uidx, root->A_lo, root->c_lo, root->A_hi,
+                             root->c_hi, sp, passes, lo, hi, l, u, Nh, infeasible, Ltmp, s));
+    CV_HIP(launch_merge_neurons(B, U, root->uidx, Nh, Ltmp, l, u, infeasible, s));
+  }
+  return CV_OK;
+}
+
+cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A_shared,
+                        const float* c, const float* lo, const float* hi,
+                        const cv_constraints* cons, int passes, float* lb, float* ub, float* beta,
+                        uint8_t* infeasible, hipStream_t s) {
+  if (B < 0 || P < 0 || n <= 0) return CV_E_SHAPE;
+  if ((long long)B * P == 0) return CV_OK;
+  if (!A || !c || !lo || !hi || !lb) return CV_E_INVALID;
+  if (n > 1024) return CV_E_UNSUPPORTED;
+  if (cons && passes < 1) return CV_E_INVALID;
+  if (cons && cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
+  if (beta && !cons) return CV_E_INVALID;
+  CvCons cc;
+  cv_status st = resolve_cons(root, cons, &cc);
+  if (st) return st;
+  CV_HIP(launch_ca_generic(B, P, n, A, A_shared, c, lo, hi, cons ? &cc : nullptr, passes, lb, ub,
+                           beta, infeasible, s));
+  return CV_OK;
+}
+
+static cv_status check_prop(cv_net net, cv_root root, int B, int M, const float* C, const float* t,
+                            const float* l, const float* u, const float* lo, const float* hi,
+                            const float* lb) {
+  if (!net || !root || B < 0 || M <= 0) return CV_E_INVALID;
+  if (root->net != net) return CV_E_INVALID;
+  if (B == 0) return CV_OK;
+  if (!C || !t || !l || !u || !lo || !hi || !lb) return CV_E_INVALID;
+  if (net->n[0] > 1024) return CV_E_UNSUPPORTED;
+  return CV_OK;
+}
+
+cv_status cv_bound_propagate_workspace(cv_net net, int B, int M, size_t* bytes) {
+  if (!net || !bytes || B < 0 || M <= 0) return CV_E_INVALID;
+  *bytes = bwd_layout(net, net->L, (long long)B * M, M, true, false, nullptr, nullptr);
+  return CV_OK;
+}
+
+cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const float* t,
+                             const float* l, const float* u, const float* alpha,
+                             float alpha_default, const float* lo, const float* hi,
+                             uint8_t* infeasible, cv_root root, const cv_constraints* cons,
+                             int passes, float* lb, float* A_out, float* c_out, void* ws,
+                             size_t ws_bytes, hipStream_t s) {
+  cv_status st = check_prop(net, root, B, M, C, t, l, u, lo, hi, lb);
+  if (st || B == 0) return st;
+  if (!alpha && !finite01(alpha_default)) return CV_E_INVALID;
+  if (cons && passes < 1) return CV_E_INVALID;
+  if ((A_out == nullptr) != (c_out == nullptr)) return CV_E_INVALID;
+  size_t need = 0;
+  cv_bound_propagate_workspace(net, B, M, &need);
+  if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
+  CvCons cc;
+  if ((st = resolve_cons(root, cons, &cc))) return st;
+  Bwd w;
+  bwd_layout(net, net->L, (long long)B * M, M, true, false, ws, &w);
+  st = backward_run(net, root, net->L, B, M, C, t, l, u, alpha, alpha_default, lo, hi, infeasible,
+                    w, lb, A_out, c_out, s);
+  if (st) return st;
+  if (cons && cons->kmax > 0)
+    CV_HIP(launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
+                          infeasible, lb, nullptr, 0, s));
+  return CV_OK;
+}
+
+cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes) {
+  if (!net || !bytes || B < 0 || M <= 0) return CV_E_INVALID;
+  *bytes = bwd_layout(net, net->L, (long long)B * M, M, true, true, nullptr, nullptr);
+  return CV_OK;
+}
+
+cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t, const float* l,
+                        const float* u, float* alpha, const float* lo, const float* hi,
+                        uint8_t* infeasible, cv_root root, const cv_constraints* cons, int passes,
+                        float* adam_m, float* adam_v, int step, float lr, float beta1, float beta2,
+                        float eps, float* lb, float* grad, void* ws, size_t ws_bytes,
+                        hipStream_t s) {
+  cv_status st = check_prop(net, root, B, M, C, t, l, u, lo, hi, lb);
+  if (st || B == 0) return st;
+  if (!alpha) return CV_E_INVALID;
+  if (cons && passes < 1) return CV_E_INVALID;
+  if (lr < 0.0f || !(lr == lr)) return CV_E_INVALID;
+  if (lr > 0.0f) {
+    if (!adam_m || !adam_v || step < 1) return CV_E_INVALID;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+      return CV_E_INVALID;
+  }
+  size_t need = 0;
+  cv_alpha_step_workspace(net, B, M, &need);
+  if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
+  CvCons cc;
+  if ((st = resolve_cons(root, cons, &cc))) return st;
+  Bwd w;
+  const int R = B * M;
+  bwd_layout(net, net->L, R, M, true, true, ws, &w);
+  st = backward_run(net, root, net->L, B, M, C, t, l, u, alpha, 0.0, lo, hi, infeasible, w, lb,
+                    nullptr, nullptr, s);
+  if (st) return st;
+  // complete clipping (or plain concretization) leaves the minimising corner
+  // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane
+  CvCons none{};
+  CV_HIP(launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes < 1 ? 1 : passes,
+                        w.Ax, w.rowc, w.rowerr, lo, hi, infeasible, lb, nullptr, 1, s));
+  const double dlr = lr;
+  double* cur = w.Ax;
+  double* bufs[2] = {w.Om0, w.Om1};
+  for (int k = 1; k <= net->L - 1; ++k) {
+    const int K = net->n[k - 1], N = net->n[k];
+    double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
+    CV_HIP(launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
+                               net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
+                               adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
+                               s));
+    cur = out;
+  }
+  return CV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Host-side internals of libclipverify: handle layouts and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+
+#define CV_MAX_LAYERS 32
+
+struct cv_net_s {
+  int L = 0;                  // number of affine layers
+  int n[CV_MAX_LAYERS + 1];   // n[0] input dim, n[i] output dim of layer i (1-based)
+  float* W[CV_MAX_LAYERS];    // device, layer i at index i-1: [n_i, n_{i-1}]
+  float* Wt[CV_MAX_LAYERS];   // device transposes [n_{i-1}, n_i]
+  float* b[CV_MAX_LAYERS];    // device [n_i]
+  int off[CV_MAX_LAYERS];     // global offset of hidden layer i (index i-1)
+  int n_hidden = 0;
+  int nmax_hidden = 0;
+  std::vector<std::vector<float>> hW, hb;  // host copies (root set-up)
+};
+
+struct cv_root_s {
+  cv_net_s* net = nullptr;
+  int n0 = 0, N = 0, U = 0;
+  float alpha0 = 0.5f;
+  float *A_lo = nullptr, *A_hi = nullptr, *c_lo = nullptr, *c_hi = nullptr;  // [N, n0], [N]
+  float *l0 = nullptr, *u0 = nullptr;                                        // [N]
+  float *lo0 = nullptr, *hi0 = nullptr;                                      // [n0]
+  double* X0 = nullptr;                       // [n0] max(|lo0|, |hi0|)
+  double* vgemm[CV_MAX_LAYERS];               // layer i: |W_i| H_{i-1} + |b_i|  [n_i]
+  double* wrel[CV_MAX_LAYERS];                // hidden layer i: max(|l0|,|u0|) + vgemm_i  [n_i]
+  double gamma_big = 0.0;                     // error factor of one backward pass
+  // re-concretization of cached planes: unstable neurons, packed plane matrix P [2 n0, 2U]
+  int32_t* uidx = nullptr;                    // [U] global index of each root-unstable neuron
+  int32_t* sidx = nullptr;                    // [N - U] root-stable neurons
+  float* P = nullptr;                         // [2 n0, 2U]
+  float* cP = nullptr;                        // [2U] intercepts (lower | upper)
+  double* eP = nullptr;                       // [2U] rigorous error bound per column
+};
+
+// ----------------------------------------------------------- launchers
+// All return hipError_t of the launch.
+
+struct CvCons {  // device view of cv_constraints (resolved)
+  int kmax;
+  const int32_t* count;
+  const int32_t* neuron;
+  const int8_t* sign;
+  const float* G;
+  const float* h;
+  const float* A_lo; const float* A_hi; const float* c_lo; const float* c_hi;  // split form
+  int nplanes;  // rows of the plane table; split slots with other indices are ignored
+};
+
+// Number of used slots of subdomain b, clamped to [0, kmax].
+__device__ __forceinline__ int cons_count(const CvCons& c, int b) {
+  int k = c.count ? c.count[b] : c.kmax;
+  return k < 0 ? 0 : (k > c.kmax ? c.kmax : k);
+}
+
+hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, uint8_t* infeasible,
+                       int mode, hipStream_t s);
+
+// backward pass building blocks
+hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
+                      const float* b, const double* vT, double* psiT, double* c0, double* e0,
+                      double* cabs0, hipStream_t s);
+hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
+                            const double* c0, const double* e0, const double* cabs0,
+                            const float* l, const float* u, const float* alpha, double alpha_def,
+                            const float* bprev, const double* wrel, double* Om, float* trace,
+                            double* rowc, double* rowerr, double* rowcabs, hipStream_t s);
+hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
+                             int off, const float* l, const float* u, const float* alpha,
+                             double alpha_def, const float* bprev, const double* wrel,
+                             double* Om_out, float* trace, double* part, hipStream_t s);
+hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
+                         double* rowcabs, hipStream_t s);
+hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W, int M,
+                             const float* lo, const float* hi, const double* X0, double* Ax,
+                             float* A_out, double* part, hipStream_t s);
+int gemm_ntiles(int N);
+hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const double* rowc,
+                           double* rowerr, const double* rowcabs, double gamma_big,
+                           const uint8_t* infeasible, float* lb, float* c_out, hipStream_t s);
+hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
+                               const float* b, int M, int Nh, int off, const float* l,
+                               const float* u, float* alpha, double alpha_def,
+                               const float* trace, const uint8_t* infeasible, float* grad,
+                               float* adam_m, float* adam_v, double lr, double b1, double b2,
+                               double eps, int step, double* Psibar_out, hipStream_t s);
+
+// re-concretization of the cached planes
+hipError_t launch_fill_stable(int B, int Nh, int nS, const int32_t* sidx, const float* l0,
+                              const float* u0, float* l, float* u, hipStream_t s);
+hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float* hi,
+                              const float* P, const float* cP, const double* eP,
+                              const int32_t* uidx, const float* l0, const float* u0, int Nh,
+                              float* l, float* u, hipStream_t s);
+hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float* u,
+                            uint8_t* infeasible, hipStream_t s);
+
+// complete clipping (coordinate ascent over the 1-D duals)
+hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
+                          const double* rowc, const double* rowerr, const float* lo,
+                          const float* hi, uint8_t* infeasible, float* lb, float* beta_out,
+                          int write_xstar, hipStream_t s);
+hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, const float* c,
+                             const float* lo, const float* hi, const CvCons* cons, int passes,
+                             float* lb, float* ub, float* beta_out, uint8_t* infeasible,
+                             hipStream_t s);
+hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
+                             const float* c_lo, const float* A_hi, const float* c_hi,
+                             const CvCons& cons, int passes, const float* lo, const float* hi,
+                             const float* l, const float* u, int Nh, const uint8_t* infeasible,
+                             float* Ltmp, hipStream_t s);
+hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const float* Ltmp,
+                                float* l, float* u, uint8_t* infeasible, hipStream_t s);
+
+// root set-up helpers
+hipError_t launch_root_store_planes(int rows, int n0, const double* Ax, const double* rowc,
+                                    const double* rowerr, const double* X0, int negate,
+                                    float* A_dst, float* c_dst, hipStream_t s);
+hipError_t launch_concretize_rows(int rows, int n0, const float* A, const float* c,
+                                  const float* lo, const float* hi, int upper, float* out,
+                                  hipStream_t s);
+hipError_t launch_build_P(int n0, int U, const int32_t* uidx, const float* A_lo, const float* A_hi,
+                          const float* c_lo, const float* c_hi, const double* X0, float* P,
+                          float* cP, double* eP, hipStream_t s);

@@ -1,0 +1,426 @@
+// Complete clipping: lower bound of a.x + c over box ∩ {G x + h <= 0} by
+// coordinate ascent over the Lagrange multipliers (Alg. 1, eq. 4).  Each
+// step maximises the 1-D dual of Thm 3.1 for one constraint g.x + h <= 0
+// with the other multipliers fixed:
+//   D(beta) = min_box (a' + beta g).x + c' + beta h  (concave, piecewise linear)
+// Its slope just right of beta is  m + sum_{q_j > beta} w_j,  where
+// m = min_box(g.x + h), q_j = -a'_j / g_j are the breakpoints and
+// w_j = |g_j| (hi_j - lo_j).  So beta* = 0 when the slope at 0+ is <= 0, else
+// beta* is the breakpoint q* where the slope changes sign: the smallest
+// positive breakpoint with  sum_{q_j > q*} w_j <= -m  (a weighted quantile).
+// m > 0 means the constraint is empty over the box (+inf).  Supergradients
+// within a small tolerance of zero count as zero, so near-ties between
+// maximisers go to the smallest one.
+//
+// GPU mapping: one wave64 per problem; lane L owns coordinates L, L+64, ...
+// (EPL per lane) and keeps a', its absolute scale and the breakpoints in
+// registers.  The weighted quantile is found without sorting by bisection
+// over the float64 bit patterns of the breakpoints (positive doubles order
+// like their bit patterns): each round picks the largest breakpoint at or
+// below the midpoint and tests it with two wave-wide sums; a hit ends the
+// search and otherwise the bit range halves, so at most 63 rounds are needed
+// and about log2(#breakpoints) are typical.
+//
+// The returned bound D(beta) is valid for any beta >= 0 (weak duality); it is
+// evaluated in float64, moved down by a rigorous bound on its rounding (and by
+// the error bound of the objective plane itself) and rounded down to float32.
+#include "cv_common.h"
+#include "cv_internal.h"
+
+namespace {
+
+constexpr int CA_KMAX = 64;
+
+__device__ __forceinline__ void cons_row(const CvCons& c, int b, int k, int n, const float*& row,
+                                         float& scale, double& h) {
+  const size_t s = (size_t)b * c.kmax + k;
+  if (c.neuron) {
+    const int j = c.neuron[s];
+    if (j < 0 || j >= c.nplanes) {  // not a hidden neuron: slot ignored
+      row = nullptr;
+      scale = 0.0f;
+      h = 0.0;
+      return;
+    }
+    if (c.sign[s] < 0) {
+      row = c.A_lo + (size_t)j * n;
+      scale = 1.0f;
+      h = (double)c.c_lo[j];
+    } else {
+      row = c.A_hi + (size_t)j * n;
+      scale = -1.0f;
+      h = -(double)c.c_hi[j];
+    }
+  } else {
+    row = c.G + s * n;
+    scale = 1.0f;
+    h = (double)c.h[s];
+  }
+}
+
+template <int EPL>
+__device__ double ca_select(const double (&q)[EPL], const double (&g)[EPL], const float (&xl)[EPL],
+                            const float (&xh)[EPL], uint32_t cand, double S) {
+  double qmax = -INFINITY, qmin = INFINITY;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e)
+    if ((cand >> e) & 1u) {
+      qmax = fmax(qmax, q[e]);
+      qmin = fmin(qmin, q[e]);
+    }
+  qmax = wave_max(qmax);
+  qmin = wave_min(qmin);
+  auto above = [&](double p, double& wg, double& wge) {
+    wg = 0.0;
+    wge = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if ((cand >> e) & 1u) {
+        const double w = fabs(g[e]) * ((double)xh[e] - (double)xl[e]);
+        if (q[e] > p) wg += w;
+        if (q[e] >= p) wge += w;
+      }
+    wg = wave_sum(wg);
+    wge = wave_sum(wge);
+  };
+  double wg, wge;
+  above(qmin, wg, wge);
+  if (wg <= S) return qmin;
+  above(qmax, wg, wge);
+  if (wge > S) return qmax;
+  double lo_v = qmin, hi_v = qmax;  // W(> lo_v) > S,  W(>= hi_v) <= S
+  for (int it = 0; it < 80; ++it) {
+    const unsigned long long blo = (unsigned long long)__double_as_longlong(lo_v);
+    const unsigned long long bhi = (unsigned long long)__double_as_longlong(hi_v);
+    if (bhi - blo <= 1ull) break;
+    const double mv = __longlong_as_double((long long)(blo + (bhi - blo) / 2ull));
+    double p = -INFINITY;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if (((cand >> e) & 1u) && q[e] > lo_v && q[e] <= mv) p = fmax(p, q[e]);
+    p = wave_max(p);
+    if (p == -INFINITY) {
+      lo_v = mv;
+      continue;
+    }
+    above(p, wg, wge);
+    if (wg <= S && wge > S) return p;
+    if (wg > S) lo_v = mv;
+    else hi_v = p;
+  }
+  return hi_v;
+}
+
+// One problem on one wave.  a: objective coefficients (lane-strided), c its
+// intercept; on return a holds a + beta^T G.  Returns the rigorous float64
+// lower bound (before the final float32 rounding) or +inf when empty.
+template <int EPL>
+__device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_in,
+                          const float* lo_b, const float* hi_b, const CvCons* cons, int b,
+                          int passes, bool& empty, float* beta_out, double* xstar,
+                          double* beta) {
+  float xl[EPL], xh[EPL];
+  double sc[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int j = lane + 64 * e;
+    const bool in = j < n;
+    xl[e] = in ? lo_b[j] : 0.0f;
+    xh[e] = in ? hi_b[j] : 0.0f;
+    sc[e] = fabs(a[e]);
+  }
+  double cabs = fabs(c);
+  const int cnt = cons ? cons_count(*cons, b) : 0;
+  // beta: this wave's slice of LDS (all lanes hold and write equal values)
+  for (int k = 0; k < cnt; ++k) beta[k] = 0.0;
+  empty = false;
+  for (int pass = 0; pass < passes && !empty; ++pass) {
+    for (int k = 0; k < cnt; ++k) {
+      const float* row;
+      float scale;
+      double h;
+      cons_row(*cons, b, k, n, row, scale, h);
+      if (!row) continue;
+      double g[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int j = lane + 64 * e;
+        g[e] = (j < n) ? (double)(scale * row[j]) : 0.0;
+      }
+      if (beta[k] != 0.0) {  // later passes: drop this constraint's own multiplier
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) a[e] -= beta[k] * g[e];
+        c -= beta[k] * h;
+      }
+      double m = 0.0, em = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        m += fmin(g[e] * (double)xl[e], g[e] * (double)xh[e]);
+        em += fabs(g[e]) * fabs_max(xl[e], xh[e]);
+      }
+      m = wave_sum(m) + h;
+      em = wave_sum(em);
+      if (m - cv_gamma(n + 1) * (em + fabs(h)) * CV_ERR_SLACK > 0.0) {
+        empty = true;
+        break;
+      }
+      // slopes within 2^-18 sum_j |g_j| max(|lo_j|,|hi_j|) of zero count as
+      // zero: near-ties go to the smaller multiplier (the dual is exactly flat
+      // on [0, q] after relaxed clipping by the same constraint)
+      const double S = -m + 3.814697265625e-06 * em;
+      double q[EPL];
+      uint32_t cand = 0;
+      double wpos = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        q[e] = 0.0;
+        if (g[e] != 0.0) {
+          q[e] = -a[e] / g[e];
+          const double w = fabs(g[e]) * ((double)xh[e] - (double)xl[e]);
+          if (q[e] > 0.0 && w > 0.0) {
+            cand |= 1u << e;
+            wpos += w;
+          }
+        }
+      }
+      wpos = wave_sum(wpos);
+      double bk = 0.0;
+      if (wpos > S) bk = ca_select<EPL>(q, g, xl, xh, cand, S);
+      beta[k] = bk;
+      if (bk != 0.0) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          a[e] += bk * g[e];
+          sc[e] += bk * fabs(g[e]);
+        }
+        c += bk * h;
+        cabs += bk * fabs(h);
+      }
+    }
+  }
+  if (empty) return INFINITY;
+  double d = 0.0, E = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
+    E += sc[e] * fabs_max(xl[e], xh[e]);
+  }
+  d = wave_sum(d) + c;
+  E = wave_sum(E);
+  const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (E + cabs) + e_in) * CV_ERR_SLACK;
+  if (beta_out && lane == 0)
+    for (int k = 0; k < cons->kmax; ++k) beta_out[k] = k < cnt ? (float)beta[k] : 0.0f;
+  if (xstar) {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int j = lane + 64 * e;
+      if (j < n) {
+        const bool kink = fabs(a[e]) <= 9.094947017729282e-13 * sc[e];  // 2^-40
+        xstar[j] = kink ? 0.5 * ((double)xl[e] + (double)xh[e])
+                        : (a[e] > 0.0 ? (double)xl[e] : (double)xh[e]);
+      }
+    }
+  }
+  return d - err;
+}
+
+// Final planes: rows r = (b, m) of the backward pass output.
+template <int EPL>
+__global__ __launch_bounds__(256) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
+                                                 double* Ax, const double* __restrict__ rowc,
+                                                 const double* __restrict__ rowerr,
+                                                 const float* __restrict__ lo,
+                                                 const float* __restrict__ hi, uint8_t* infeasible,
+                                                 float* lb, float* beta_out, int write_xstar) {
+  __shared__ double sbeta[4 * CA_KMAX];
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  const int b = r / M;
+  double* arow = Ax + (size_t)r * n;
+  if (infeasible && infeasible[b]) {
+    if (lane == 0) lb[r] = INFINITY;
+    return;
+  }
+  double a[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int j = lane + 64 * e;
+    a[e] = j < n ? arow[j] : 0.0;
+  }
+  bool empty;
+  const double L = ca_core<EPL>(lane, n, a, rowc[r], rowerr[r], lo + (size_t)b * n, hi + (size_t)b * n,
+                                &cons, b, passes, empty,
+                                beta_out ? beta_out + (size_t)r * cons.kmax : nullptr,
+                                write_xstar ? arow : nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX);
+  if (lane == 0) {
+    if (empty) {
+      lb[r] = INFINITY;
+      if (infeasible) infeasible[b] = 1;
+    } else {
+      lb[r] = fmaxf(lb[r], rd32(L));
+    }
+  }
+}
+
+// Generic: row p of subdomain b, float32 plane; also the plain minimum and
+// (optionally) the maximum over the box.
+template <int EPL>
+__global__ __launch_bounds__(256) void k_ca_generic(int B, int P, int n, const float* __restrict__ A,
+                                                    int A_shared, const float* __restrict__ cv,
+                                                    const float* __restrict__ lo,
+                                                    const float* __restrict__ hi, CvCons cons,
+                                                    int has_cons, int passes, float* lb, float* ub,
+                                                    float* beta_out, uint8_t* infeasible) {
+  __shared__ double sbeta[4 * CA_KMAX];
+  const int lane = threadIdx.x & 63;
+  const long long pid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pid >= (long long)B * P) return;
+  const int b = (int)(pid / P), p = (int)(pid % P);
+  const size_t arow = A_shared ? (size_t)p : (size_t)pid;
+  const float* ap = A + arow * n;
+  const double c = (double)cv[arow];
+  const float* lb_ = lo + (size_t)b * n;
+  const float* hb_ = hi + (size_t)b * n;
+  double a[EPL];
+  double dmin = 0.0, dmax = 0.0, ea = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int j = lane + 64 * e;
+    a[e] = j < n ? (double)ap[j] : 0.0;
+    if (j < n) {
+      const double x0 = (double)lb_[j], x1 = (double)hb_[j];
+      dmin += fmin(a[e] * x0, a[e] * x1);
+      dmax += fmax(a[e] * x0, a[e] * x1);
+      ea += fabs(a[e]) * fmax(fabs(x0), fabs(x1));
+    }
+  }
+  dmin = wave_sum(dmin);
+  dmax = wave_sum(dmax);
+  ea = wave_sum(ea);
+  const double e0 = cv_gamma(n + 1) * (ea + fabs(c)) * CV_ERR_SLACK;
+  float out = rd32(dmin + c - e0);
+  bool empty = false;
+  if (has_cons) {
+    const double L = ca_core<EPL>(lane, n, a, c, 0.0, lb_, hb_, &cons, b, passes, empty,
+                                  beta_out ? beta_out + (size_t)pid * cons.kmax : nullptr, nullptr,
+                                  sbeta + (threadIdx.x >> 6) * CA_KMAX);
+    if (!empty) out = fmaxf(out, rd32(L));
+  }
+  if (lane == 0) {
+    lb[pid] = empty ? INFINITY : out;
+    if (ub) ub[pid] = ru32(dmax + c + e0);
+    if (empty && infeasible) infeasible[b] = 1;
+  }
+}
+
+// Intermediate neurons: lower plane (side 0) and negated upper plane (side 1) of every
+// root-unstable neuron still unstable in subdomain b.
+template <int EPL>
+__global__ __launch_bounds__(256) void k_ca_neurons(int B, int U, int n, const int32_t* __restrict__ uidx,
+                                                    const float* __restrict__ A_lo,
+                                                    const float* __restrict__ c_lo,
+                                                    const float* __restrict__ A_hi,
+                                                    const float* __restrict__ c_hi, CvCons cons,
+                                                    int passes, const float* __restrict__ lo,
+                                                    const float* __restrict__ hi,
+                                                    const float* __restrict__ l,
+                                                    const float* __restrict__ u, int Nh,
+                                                    const uint8_t* __restrict__ infeasible,
+                                                    float* Ltmp) {
+  __shared__ double sbeta[4 * CA_KMAX];
+  const int lane = threadIdx.x & 63;
+  const long long pid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pid >= (long long)B * U * 2) return;
+  const int side = (int)(pid & 1);
+  const long long bc = pid >> 1;
+  const int b = (int)(bc / U), q = (int)(bc % U);
+  const int j = uidx[q];
+  const float lj = l[(size_t)b * Nh + j], uj = u[(size_t)b * Nh + j];
+  if ((infeasible && infeasible[b]) || !(lj < 0.0f && uj > 0.0f)) {
+    if (lane == 0) Ltmp[pid] = -INFINITY;
+    return;
+  }
+  const float* ap = (side ? A_hi : A_lo) + (size_t)j * n;
+  const double c = side ? -(double)c_hi[j] : (double)c_lo[j];
+  double a[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int jj = lane + 64 * e;
+    a[e] = jj < n ? (side ? -(double)ap[jj] : (double)ap[jj]) : 0.0;
+  }
+  bool empty;
+  const double L = ca_core<EPL>(lane, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n, &cons, b,
+                                passes, empty, nullptr, nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX);
+  if (lane == 0) Ltmp[pid] = empty ? INFINITY : rd32(L);
+}
+
+int epl_for(int n) {
+  const int e = (n + 63) / 64;
+  if (e <= 1) return 1;
+  if (e <= 2) return 2;
+  if (e <= 4) return 4;
+  if (e <= 8) return 8;
+  if (e <= 13) return 13;
+  if (e <= 16) return 16;
+  return -1;
+}
+
+#define CV_DISPATCH_EPL(n, CALL)          \
+  switch (epl_for(n)) {                   \
+    case 1: { constexpr int E = 1; CALL; } break;   \
+    case 2: { constexpr int E = 2; CALL; } break;   \
+    case 4: { constexpr int E = 4; CALL; } break;   \
+    case 8: { constexpr int E = 8; CALL; } break;   \
+    case 13: { constexpr int E = 13; CALL; } break; \
+    case 16: { constexpr int E = 16; CALL; } break; \
+    default: return hipErrorInvalidValue;           \
+  }
+
+}  // namespace
+
+hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
+                          const double* rowc, const double* rowerr, const float* lo,
+                          const float* hi, uint8_t* infeasible, float* lb, float* beta_out,
+                          int write_xstar, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
+  dim3 grid((R + 3) / 4);
+  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_rows<E>), grid, dim3(256), 0, s, R, M, n, cons, passes,
+                                        Ax, rowc, rowerr, lo, hi, infeasible, lb, beta_out,
+                                        write_xstar));
+  return hipGetLastError();
+}
+
+hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, const float* c,
+                             const float* lo, const float* hi, const CvCons* cons, int passes,
+                             float* lb, float* ub, float* beta_out, uint8_t* infeasible,
+                             hipStream_t s) {
+  const long long tot = (long long)B * P;
+  if (tot <= 0) return hipSuccess;
+  CvCons cc{};
+  if (cons) {
+    cc = *cons;
+    if (cc.kmax > CA_KMAX) return hipErrorInvalidValue;
+  }
+  dim3 grid((unsigned)((tot + 3) / 4));
+  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_generic<E>), grid, dim3(256), 0, s, B, P, n, A,
+                                        A_shared, c, lo, hi, cc, cons ? 1 : 0, passes, lb, ub,
+                                        beta_out, infeasible));
+  return hipGetLastError();
+}
+
+hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
+                             const float* c_lo, const float* A_hi, const float* c_hi,
+                             const CvCons& cons, int passes, const float* lo, const float* hi,
+                             const float* l, const float* u, int Nh, const uint8_t* infeasible,
+                             float* Ltmp, hipStream_t s) {
+  const long long tot = (long long)B * U * 2;
+  if (tot <= 0) return hipSuccess;
+  if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((tot + 3) / 4));
+  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_neurons<E>), grid, dim3(256), 0, s, B, U, n, uidx, A_lo,
+                                        c_lo, A_hi, c_hi, cons, passes, lo, hi, l, u, Nh,
+                                        infeasible, Ltmp));
+  return hipGetLastError();
+}

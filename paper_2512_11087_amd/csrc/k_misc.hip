@@ -1,0 +1,335 @@
+// Small kernels of the backward pass and of the root set-up: the shared top
+// layer, the first relaxation, row-state accumulation, final rounding,
+// split fixes, and the packing of the cached planes.
+#include "cv_common.h"
+#include "cv_internal.h"
+
+namespace {
+
+// Psi_T = C W_T (shared by all subdomains), c0 = t + C b_T and the error
+// weight e0 = |C| vT, one workgroup per objective row m.
+__global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float* __restrict__ C,
+                                             const float* __restrict__ t,
+                                             const float* __restrict__ W,
+                                             const float* __restrict__ b,
+                                             const double* __restrict__ vT, double* psiT,
+                                             double* c0, double* e0, double* cabs0) {
+  const int m = blockIdx.x;
+  const float* crow = C + (size_t)m * nT;
+  for (int j = threadIdx.x; j < nP; j += blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < nT; ++k) acc += (double)crow[k] * (double)W[(size_t)k * nP + j];
+    psiT[(size_t)m * nP + j] = acc;
+  }
+  if (threadIdx.x < 64) {
+    double cb = 0.0, ea = 0.0;
+    for (int k = threadIdx.x; k < nT; k += 64) {
+      cb += (double)crow[k] * (double)b[k];
+      ea += fabs((double)crow[k]) * vT[k];
+    }
+    cb = wave_sum(cb);
+    ea = wave_sum(ea);
+    if (threadIdx.x == 0) {
+      c0[m] = (double)t[m] + cb;
+      e0[m] = ea;
+      cabs0[m] = fabs((double)t[m]) + fabs(cb);
+    }
+  }
+}
+
+// First relaxation (ReLU of layer T-1) of every row r = (b, m): one wave
+// per row.  Writes Omega_{T-1} and initialises the row state.
+__global__ __launch_bounds__(256) void k_relax_top(
+    int R, int M, int nP, int Nh, int off, const double* __restrict__ psiT,
+    const double* __restrict__ c0, const double* __restrict__ e0, const double* __restrict__ cabs0,
+    const float* __restrict__ l, const float* __restrict__ u, const float* __restrict__ alpha,
+    double alpha_def, const float* __restrict__ bprev, const double* __restrict__ wrel,
+    double* Om, float* trace, double* rowc, double* rowerr, double* rowcabs) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  const int b = r / M, m = r % M;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int j = lane; j < nP; j += 64) {
+    const double psi = psiT[(size_t)m * nP + j];
+    const size_t bi = (size_t)b * Nh + off + j;
+    const size_t ri = (size_t)r * Nh + off + j;
+    const double al = alpha ? (double)alpha[ri] : alpha_def;
+    const Relax rl = relu_relax(psi, l[bi], u[bi], al);
+    const double om = psi * rl.s;
+    Om[(size_t)r * nP + j] = om;
+    if (trace) trace[ri] = trace32(psi);
+    s1 += psi * rl.t;
+    s2 += om * (double)bprev[j];
+    s3 += fabs(psi) * wrel[j];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  s3 = wave_sum(s3);
+  if (lane == 0) {
+    rowc[r] = c0[m] + s1 + s2;
+    rowerr[r] = e0[m] + s3;
+    rowcabs[r] = cabs0[m] + fabs(s1) + fabs(s2);
+  }
+}
+
+__global__ void k_rowacc(int R, int ntiles, const double* __restrict__ part, double* rowc,
+                         double* rowerr, double* rowcabs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const double* p = part + ((size_t)r * ntiles + t) * 3;
+    s1 += p[0];
+    s2 += p[1];
+    s3 += p[2];
+  }
+  rowc[r] += s1 + s2;
+  rowerr[r] += s3;
+  rowcabs[r] += fabs(s1) + fabs(s2);
+}
+
+// lb = c + sum_j min(A_j lo_j, A_j hi_j), moved down by the rigorous error
+// bound, rounded down to float32.  rowerr becomes the error bound of the
+// plane (A, c) itself (used by complete clipping); c_out (optional) is c moved
+// down by that bound and by the float32 rounding of A.
+__global__ void k_finalize(int R, int M, int ntiles, const double* __restrict__ part,
+                           const double* __restrict__ rowc, double* rowerr,
+                           const double* __restrict__ rowcabs, double gamma_big,
+                           const uint8_t* __restrict__ infeasible, float* lb, float* c_out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double slb = 0.0, sabs = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const double* p = part + ((size_t)r * ntiles + t) * 2;
+    slb += p[0];
+    sabs += p[1];
+  }
+  const double c = rowc[r];
+  const double eplane = (gamma_big * (rowerr[r] + sabs) + 4.0 * CV_U64 * 16.0 * rowcabs[r]) * CV_ERR_SLACK;
+  const double v = c + slb;
+  const double err = eplane + 8.0 * CV_U64 * (fabs(c) + fabs(slb));
+  const bool dead = infeasible && infeasible[r / M];
+  lb[r] = dead ? INFINITY : rd32(v - err);
+  rowerr[r] = eplane;
+  if (c_out) c_out[r] = rd32(c - eplane - 1.2e-7 * sabs);
+}
+
+__global__ void k_fill_stable(int B, int Nh, int nS, const int32_t* __restrict__ sidx,
+                              const float* __restrict__ l0, const float* __restrict__ u0,
+                              float* l, float* u) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * nS) return;
+  const int b = (int)(i / nS), q = (int)(i % nS);
+  const int j = sidx[q];
+  l[(size_t)b * Nh + j] = l0[j];
+  u[(size_t)b * Nh + j] = u0[j];
+}
+
+// Split neurons are fixed to their branch; l > u marks the subdomain empty.
+__global__ void k_split_fix(int B, int Nh, CvCons sp, float* l, float* u, uint8_t* infeasible) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * sp.kmax) return;
+  const int b = i / sp.kmax, k = i % sp.kmax;
+  if (k >= cons_count(sp, b)) return;
+  const int j = sp.neuron[(size_t)b * sp.kmax + k];
+  if (j < 0 || j >= Nh) return;
+  const size_t bi = (size_t)b * Nh + j;
+  if (sp.sign[(size_t)b * sp.kmax + k] > 0) l[bi] = fmaxf(l[bi], 0.0f);
+  else u[bi] = fminf(u[bi], 0.0f);
+  if (l[bi] > u[bi]) infeasible[b] = 1;
+}
+
+// Complete-clipping results of intermediate neurons: l <- max(l, L_lo),
+// u <- min(u, -L_up); an empty result marks the subdomain.
+__global__ void k_merge_neurons(int B, int U, const int32_t* __restrict__ uidx, int Nh,
+                                const float* __restrict__ Ltmp, float* l, float* u,
+                                uint8_t* infeasible) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * U) return;
+  const int b = (int)(i / U), c = (int)(i % U);
+  const int j = uidx[c];
+  const float Ll = Ltmp[i * 2], Lu = Ltmp[i * 2 + 1];
+  const size_t bi = (size_t)b * Nh + j;
+  if (Ll == INFINITY || Lu == INFINITY) { infeasible[b] = 1; return; }
+  l[bi] = fmaxf(l[bi], Ll);
+  u[bi] = fminf(u[bi], -Lu);
+  if (l[bi] > u[bi]) infeasible[b] = 1;
+}
+
+// Root set-up: the float64 plane (A, c) of a row with error bound e becomes a
+// float32 plane that is still valid: A32 = nearest(A) and the intercept moves
+// outward by e + sum |A32 - A| X0 (bounded by 2^-24 sum |A32| X0).
+// negate != 0 stores (-A, -c) moved up instead (upper planes from -I).
+__global__ __launch_bounds__(64) void k_root_store(int rows, int n0, const double* __restrict__ Ax,
+                                                   const double* __restrict__ rowc,
+                                                   const double* __restrict__ rowerr,
+                                                   const double* __restrict__ X0, int negate,
+                                                   float* A_dst, float* c_dst) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  double sa = 0.0;
+  for (int j = lane; j < n0; j += 64) {
+    const double a = Ax[(size_t)r * n0 + j];
+    const float f = negate ? (float)(-a) : (float)a;
+    A_dst[(size_t)r * n0 + j] = f;
+    sa += fabs((double)f) * X0[j];
+  }
+  sa = wave_sum(sa);
+  if (lane == 0) {
+    const double e = (rowerr[r] + 1.2e-7 * sa) * CV_ERR_SLACK;
+    const double c = rowc[r];
+    c_dst[r] = negate ? ru32(-c + e) : rd32(c - e);
+  }
+}
+
+// min (upper = 0) or max (upper = 1) of A[r].x + c[r] over one box, rounded
+// outward after a rigorous float64 error bound.
+__global__ __launch_bounds__(64) void k_concretize_rows(int rows, int n0, const float* __restrict__ A,
+                                                        const float* __restrict__ c,
+                                                        const float* __restrict__ lo,
+                                                        const float* __restrict__ hi, int upper,
+                                                        float* out) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s = 0.0, e = 0.0;
+  for (int j = lane; j < n0; j += 64) {
+    const double a = (double)A[(size_t)r * n0 + j];
+    const double x0 = (double)lo[j], x1 = (double)hi[j];
+    s += upper ? fmax(a * x0, a * x1) : fmin(a * x0, a * x1);
+    e += fabs(a) * fmax(fabs(x0), fabs(x1));
+  }
+  s = wave_sum(s);
+  e = wave_sum(e);
+  if (lane == 0) {
+    const double cc = (double)c[r];
+    const double err = (cv_gamma(n0 + 1) * (e + fabs(cc))) * CV_ERR_SLACK;
+    out[r] = upper ? ru32(s + cc + err) : rd32(s + cc - err);
+  }
+}
+
+// Packed plane matrix for the re-concretization GEMM.  Column q < U is the
+// lower plane of neuron uidx[q]: rows [0, n0) hold A_lo^+ (multiplying lo),
+// rows [n0, 2 n0) hold A_lo^- (multiplying hi).  Column U + q is the upper
+// plane: A_hi^- against lo, A_hi^+ against hi.  eP is the rigorous error
+// bound of the float64 evaluation (products of float32 values are exact).
+__global__ __launch_bounds__(64) void k_build_P(int n0, int U, const int32_t* __restrict__ uidx,
+                                                const float* __restrict__ A_lo,
+                                                const float* __restrict__ A_hi,
+                                                const float* __restrict__ c_lo,
+                                                const float* __restrict__ c_hi,
+                                                const double* __restrict__ X0, float* P, float* cP,
+                                                double* eP) {
+  const int q = blockIdx.x;  // 0 .. 2U-1
+  const int lane = threadIdx.x;
+  const bool up = q >= U;
+  const int j = uidx[up ? q - U : q];
+  const float* a = (up ? A_hi : A_lo) + (size_t)j * n0;
+  const size_t ld = (size_t)2 * U;
+  double e = 0.0;
+  for (int k = lane; k < n0; k += 64) {
+    const float v = a[k];
+    const float pos = v > 0.0f ? v : 0.0f, neg = v < 0.0f ? v : 0.0f;
+    P[(size_t)k * ld + q] = up ? neg : pos;
+    P[(size_t)(k + n0) * ld + q] = up ? pos : neg;
+    e += fabs((double)v) * X0[k];
+  }
+  e = wave_sum(e);
+  if (lane == 0) {
+    const float cc = up ? c_hi[j] : c_lo[j];
+    cP[q] = cc;
+    eP[q] = cv_gamma(2 * n0 + 2) * (e + fabs((double)cc)) * CV_ERR_SLACK;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
+                      const float* b, const double* vT, double* psiT, double* c0, double* e0,
+                      double* cabs0, hipStream_t s) {
+  hipLaunchKernelGGL(k_top, dim3(M), dim3(256), 0, s, M, nT, nP, C, t, W, b, vT, psiT, c0, e0, cabs0);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
+                            const double* c0, const double* e0, const double* cabs0,
+                            const float* l, const float* u, const float* alpha, double alpha_def,
+                            const float* bprev, const double* wrel, double* Om, float* trace,
+                            double* rowc, double* rowerr, double* rowcabs, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relax_top, dim3((R + 3) / 4), dim3(256), 0, s, R, M, nP, Nh, off, psiT, c0,
+                     e0, cabs0, l, u, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
+                     rowcabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
+                         double* rowcabs, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rowacc, dim3((R + 255) / 256), dim3(256), 0, s, R, ntiles, part, rowc,
+                     rowerr, rowcabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const double* rowc,
+                           double* rowerr, const double* rowcabs, double gamma_big,
+                           const uint8_t* infeasible, float* lb, float* c_out, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((R + 255) / 256), dim3(256), 0, s, R, M, ntiles, part, rowc,
+                     rowerr, rowcabs, gamma_big, infeasible, lb, c_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_stable(int B, int Nh, int nS, const int32_t* sidx, const float* l0,
+                              const float* u0, float* l, float* u, hipStream_t s) {
+  const size_t tot = (size_t)B * nS;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_stable, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, Nh,
+                     nS, sidx, l0, u0, l, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float* u,
+                            uint8_t* infeasible, hipStream_t s) {
+  const int tot = B * splits.kmax;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_fix, dim3((tot + 255) / 256), dim3(256), 0, s, B, Nh, splits, l, u,
+                     infeasible);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const float* Ltmp,
+                                float* l, float* u, uint8_t* infeasible, hipStream_t s) {
+  const size_t tot = (size_t)B * U;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_neurons, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, U,
+                     uidx, Nh, Ltmp, l, u, infeasible);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_store_planes(int rows, int n0, const double* Ax, const double* rowc,
+                                    const double* rowerr, const double* X0, int negate,
+                                    float* A_dst, float* c_dst, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_root_store, dim3(rows), dim3(64), 0, s, rows, n0, Ax, rowc, rowerr, X0,
+                     negate, A_dst, c_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_concretize_rows(int rows, int n0, const float* A, const float* c,
+                                  const float* lo, const float* hi, int upper, float* out,
+                                  hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_concretize_rows, dim3(rows), dim3(64), 0, s, rows, n0, A, c, lo, hi, upper,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_P(int n0, int U, const int32_t* uidx, const float* A_lo, const float* A_hi,
+                          const float* c_lo, const float* c_hi, const double* X0, float* P,
+                          float* cP, double* eP, hipStream_t s) {
+  if (U <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_P, dim3(2 * U), dim3(64), 0, s, n0, U, uidx, A_lo, A_hi, c_lo, c_hi,
+                     X0, P, cP, eP);
+  return hipGetLastError();
+}

@@ -1,0 +1,119 @@
+"""The batched clip-and-verify pass over one property, sequenced on the
+device through the C ABI:
+
+  split halfspaces + relaxed clipping     (clip_domains)
+  re-concretization of cached planes      (concretize_planes)
+  CROWN backward + concretization
+  + complete clipping of the final plane  (bound_propagate)
+  slope optimisation                      (alpha_step, repeated)
+
+Every step is a HIP kernel; this module only allocates device buffers and
+orders the calls on the current stream.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import api
+
+
+@dataclass
+class PassConfig:
+    clip: str = "parallel"          # "parallel" | "sequential" | "none"
+    complete_intermediate: bool = False
+    complete_final: bool = True
+    passes: int = 1
+    alpha: float = 0.5
+
+
+class Property:
+    """A network, root box and specification resident on the device."""
+
+    def __init__(self, layers, lo0, hi0, C, t, alpha0=0.5):
+        self.net = api.Net(layers)
+        self.root = api.Root(self.net, lo0, hi0, alpha0)
+        self.C = api._f32(C)
+        self.t = api._f32(t)
+        self.M = self.C.shape[0]
+        self.ws = api.Workspace()
+        self.ws2 = api.Workspace()
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls([(ly.W, ly.b) for ly in w.net.layers], w.lo0, w.hi0, w.C, w.t, w.alpha0)
+
+    def boxes(self, B):
+        lo = self.root.lo0.expand(B, -1).contiguous()
+        hi = self.root.hi0.expand(B, -1).contiguous()
+        return lo, hi
+
+
+@dataclass
+class Batch:
+    lo: torch.Tensor
+    hi: torch.Tensor
+    splits: api.Constraints
+
+
+def make_batch(prop, neuron, sign, count, lo=None, hi=None):
+    B = neuron.shape[0]
+    if lo is None:
+        lo, hi = prop.boxes(B)
+    return Batch(lo, hi, api.Constraints.splits(neuron, sign, count))
+
+
+def plain_pass(prop, batch, cfg=PassConfig(), out=None):
+    """One pass of the hot path over a batch; boxes are clipped in place.
+    Returns dict(infeasible, l, u, lb)."""
+    B = batch.lo.shape[0]
+    out = out if out is not None else {}
+    if cfg.clip != "none":
+        inf = api.clip_domains(prop.root, batch.lo, batch.hi, batch.splits, cfg.clip,
+                               infeasible=out.get("infeasible"))
+    else:
+        inf = out.get("infeasible")
+        if inf is None:
+            inf = torch.zeros(B, dtype=torch.uint8, device="cuda")
+        else:
+            inf.zero_()
+    l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, batch.splits,
+                                      cfg.complete_intermediate, cfg.passes, inf,
+                                      out.get("l"), out.get("u"), prop.ws2)
+    cons = batch.splits if cfg.complete_final else None
+    lb = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
+                             None, cfg.alpha, inf, cons, cfg.passes, ws=prop.ws)
+    out.update(infeasible=inf, l=l, u=u, lb=lb)
+    return out
+
+
+def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0=0.5,
+              complete=True, passes=1, state=None):
+    """Slope optimisation: ``steps`` x (bound, adjoint, Adam).  Returns the
+    best bound over the iterations [B, M] and the final alpha."""
+    B = batch.lo.shape[0]
+    M, nh = prop.M, prop.net.n_hidden
+    if state is None:
+        state = {}
+    alpha = state.get("alpha")
+    if alpha is None:
+        alpha = torch.full((B, M, nh), alpha0, device="cuda")
+        m = torch.zeros_like(alpha)
+        v = torch.zeros_like(alpha)
+        state.update(alpha=alpha, m=m, v=v)
+    else:
+        alpha.fill_(alpha0)
+        state["m"].zero_()
+        state["v"].zero_()
+    best = state.get("best")
+    if best is None:
+        best = torch.empty(B, M, device="cuda")
+        state["best"] = best
+    best.fill_(-float("inf"))
+    cons = batch.splits if complete else None
+    for s in range(1, steps + 1):
+        lb, _ = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha, batch.lo,
+                               batch.hi, infeasible, cons, passes, state["m"], state["v"], s,
+                               lr * decay ** (s - 1), ws=prop.ws)
+        torch.maximum(best, lb, out=best)
+    return best, alpha

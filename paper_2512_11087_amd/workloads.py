@@ -309,3 +309,45 @@ def mnist_mlp(B: int = 16384, widths=(784,) + (256,) * 6 + (10,),
 def alpha_mlp(B: int = 8192, seed: int = SEED_WEIGHTS) -> Workload:
     """ReLU MLP 784-1024x4-10, 6 splits per subdomain (slope optimisation)."""
     return mnist_mlp(B, (784,) + (1024,) * 4 + (10,), 6, seed, "mlp784-1024x4-10")
+
+
+def random_boxes_and_constraints(B: int, n: int, k: int, seed: int, width=0.5,
+                                 p_zero_coef=0.1, p_flat=0.05, slack=0.5, nnz=8):
+    """Random boxes [B, n] and dense constraints G [B, k, n], h [B, k] with
+    ragged counts.  Half of the constraint rows have only ``nnz`` nonzero
+    coefficients (so that clipping and empty intersections stay frequent in
+    high dimension), the rest are dense with a fraction of exact zeros; each
+    passes near a random point of the box (``slack`` scales the offset); a
+    fraction of coordinates has zero width (degenerate cases).  float32."""
+    rng = np.random.default_rng(seed)
+    lo = rng.uniform(-1.0, 1.0, (B, n))
+    hi = lo + rng.uniform(0.0, width, (B, n))
+    flat = rng.random((B, n)) < p_flat
+    hi[flat] = lo[flat]
+    G = rng.normal(size=(B, k, n))
+    G[rng.random((B, k, n)) < p_zero_coef] = 0.0
+    sparse = rng.random((B, k)) < 0.5
+    if n > nnz:
+        keep = np.argsort(rng.random((B, k, n)), axis=-1) < nnz
+        G = np.where(sparse[..., None] & ~keep, 0.0, G)
+    xs = rng.uniform(lo, hi)
+    scale = np.sqrt(np.where(sparse, min(n, nnz), n)) * width
+    h = -np.einsum("bkn,bn->bk", G, xs) + rng.normal(0.0, 1.0, (B, k)) * slack * scale
+    count = rng.integers(0, k + 1, B).astype(np.int32)
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return f(lo), f(hi), f(G), f(h), count
+
+
+def random_planes(B: int, P: int, n: int, seed: int):
+    """Random objective planes A [B, P, n], c [B, P] (float32)."""
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(B, P, n))
+    A[rng.random((B, P, n)) < 0.05] = 0.0
+    c = rng.normal(size=(B, P)) * np.sqrt(n)
+    return np.ascontiguousarray(A, np.float32), np.ascontiguousarray(c, np.float32)
+
+
+def random_alpha(B: int, M: int, n_hidden: int, seed: int):
+    """Slopes in [0, 1] for every (subdomain, objective row, hidden neuron)."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(0.0, 1.0, (B, M, n_hidden)), np.float32)

@@ -1,0 +1,347 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle on
+the same seeded inputs, plus directional soundness checks.
+
+Kernel-level tests feed both sides identical float32 inputs, so the GPU
+result must equal the oracle's within the parity band AND lie on the safe
+side of it (a clipped box never smaller, a lower bound never larger than the
+exact value, up to the oracle's own float64 rounding).  Pipeline tests
+compare the whole pass; their inputs to intermediate steps (cached planes,
+intermediate bounds) are computed by each side independently.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import complete, crown, pipeline as opipe, relaxed  # noqa: E402
+from paper_2512_11087_amd import api, pipeline as gpipe, workloads as wl  # noqa: E402
+from helpers import OracleProp, assert_close, subset_splits  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DIR = 1e-12   # slack for the oracle's own float64 rounding in directional checks
+
+
+def T(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ relaxed clip
+
+@pytest.mark.parametrize("n", [5, 37, 784])
+@pytest.mark.parametrize("mode", ["parallel", "sequential"])
+def test_clip_dense_matches_oracle_and_contains_it(n, mode):
+    B, k = 300, 6
+    lo, hi, G, h, count = wl.random_boxes_and_constraints(B, n, k, seed=20 + n)
+    lo_t, hi_t = T(lo), T(hi)
+    cons = api.Constraints.dense(G, h, count)
+    inf = H(api.clip_domains(None, lo_t, hi_t, cons, mode))
+    sync()
+    act = np.arange(k)[None, :] < count[:, None]
+    fn = relaxed.clip_parallel if mode == "parallel" else relaxed.clip_sequential
+    olo, ohi, oinf = fn(G, h, lo, hi, act)
+    assert np.array_equal(inf.astype(bool), oinf), "infeasible flags differ"
+    assert 0 < oinf.sum() < B
+    glo, ghi = H(lo_t).astype(np.float64), H(hi_t).astype(np.float64)
+    fe = ~oinf
+    scale = np.maximum(np.abs(olo[fe]), 1.0)
+    assert np.all(glo[fe] <= olo[fe] + DIR * scale), "GPU lower bound tighter than exact"
+    assert np.all(ghi[fe] >= ohi[fe] - DIR * np.maximum(np.abs(ohi[fe]), 1.0))
+    assert_close(glo[fe], olo[fe], 1e-6, "lo")
+    assert_close(ghi[fe], ohi[fe], 1e-6, "hi")
+    assert (glo[fe] > lo[fe]).any() and (ghi[fe] < hi[fe]).any()   # something was clipped
+
+
+# ------------------------------------------------- concretize / complete clip
+
+@pytest.mark.parametrize("n", [5, 130, 784])
+def test_concretize_and_complete_clip_match_oracle(n):
+    B, P, k = 97, 3, 5
+    lo, hi, G, h, count = wl.random_boxes_and_constraints(B, n, k, seed=40 + n, slack=0.2)
+    A, c = wl.random_planes(B, P, n, seed=41 + n)
+    lb, ub, _ = api.concretize(T(A), T(c), T(lo), T(hi), want_ub=True)
+    cons = api.Constraints.dense(G, h, count)
+    inf = torch.zeros(B, dtype=torch.uint8, device="cuda")
+    lbc, _, beta = api.concretize(T(A), T(c), T(lo), T(hi), cons, want_beta=True, infeasible=inf)
+    sync()
+    from oracle import box
+    olb = box.concretize_min(A, c, lo, hi)
+    oub = box.concretize_max(A, c, lo, hi)
+    sc = (np.abs(A) * np.maximum(np.abs(lo), np.abs(hi))[:, None, :]).sum(-1) + np.abs(c)
+    assert np.all(H(lb) <= olb + DIR * sc) and np.all(H(ub) >= oub - DIR * sc)
+    assert_close(H(lb), olb, 1e-6, "lb")
+    assert_close(H(ub), oub, 1e-6, "ub")
+    act = np.arange(k)[None, :] < count[:, None]
+    rep = lambda x: np.repeat(x, P, axis=0)
+    L, obeta, oinf = complete.coord_ascent(A.reshape(B * P, n), c.reshape(B * P), rep(G), rep(h),
+                                           rep(lo), rep(hi), rep(act))
+    L = np.maximum(L.reshape(B, P), olb)
+    oinf = oinf.reshape(B, P).any(-1)
+    assert np.array_equal(H(inf).astype(bool), oinf)
+    fe = ~oinf
+    g = H(lbc)
+    assert np.all(np.isinf(g[oinf]))
+    assert np.all(g[fe] <= L[fe] + DIR * sc[fe]), "complete clip above the exact dual value"
+    assert_close(g[fe], L[fe], 1e-6, "complete clip")
+    assert (L[fe] > olb[fe] + 1e-6).any()      # clipping tightened something
+    # multipliers: where the oracle's is unique the GPU finds the same one
+    gb = H(beta).reshape(B * P, k)
+    ob = obeta
+    keep = np.repeat(fe, P)
+    assert_close(gb[keep], ob[keep], 1e-5, "beta")
+
+
+def test_complete_clip_single_constraint_is_exact_lp():
+    # one constraint: Thm 3.1 says the dual optimum equals the LP optimum
+    from oracle import exact
+    B, P, n, k = 40, 1, 6, 1
+    lo, hi, G, h, _ = wl.random_boxes_and_constraints(B, n, k, seed=7, slack=0.3)
+    A, c = wl.random_planes(B, P, n, seed=8)
+    cons = api.Constraints.dense(G, h, np.ones(B, np.int32))
+    lbc, _, _ = api.concretize(T(A), T(c), T(lo), T(hi), cons)
+    g = H(lbc)[:, 0]
+    for b in range(B):
+        v = exact.lp_vertices(A[b, 0], c[b, 0], G[b], h[b], lo[b], hi[b])[0]
+        if np.isinf(v):
+            assert np.isinf(g[b])
+        else:
+            assert g[b] <= v + 1e-9 and g[b] == pytest.approx(v, rel=1e-6, abs=1e-6)
+
+
+# ---------------------------------------------------------------- root pass
+
+@pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(8), lambda: wl.mnist_mlp(8)],
+                         ids=["mlp5-50x6-5", "mlp784-256x6-10"])
+def test_root_pass_matches_oracle_and_is_sound(make):
+    w = make()
+    op = OracleProp(w)
+    prop = gpipe.Property.from_workload(w)
+    l0, u0 = prop.root.bounds()
+    A_lo, c_lo, A_hi, c_hi = prop.root.planes()
+    sync()
+    assert_close(H(l0), op.l0, 1e-5, "root l")
+    assert_close(H(u0), op.u0, 1e-5, "root u")
+    oA_lo, oc_lo, oA_hi, oc_hi, _, _ = op.root.stacked()
+    X = np.maximum(np.abs(w.lo0), np.abs(w.hi0)).astype(np.float64)
+    rs = np.abs(oA_lo) @ X + np.abs(oc_lo) + 1.0
+    assert np.all(np.abs(H(A_lo) - oA_lo) @ X <= 1e-5 * rs)
+    assert np.all(np.abs(H(c_lo) - oc_lo) <= 1e-5 * rs)
+    assert np.all(np.abs(H(c_hi) - oc_hi) <= 1e-5 * (np.abs(oA_hi) @ X + np.abs(oc_hi) + 1.0))
+    assert prop.root.n_unstable == int(((op.l0 < 0) & (op.u0 > 0)).sum())
+    # planes and bounds hold at sampled points of the root box
+    rng = np.random.default_rng(wl.SEED_SAMPLES)
+    x = rng.uniform(w.lo0, w.hi0, size=(4000, w.net.n_in))
+    z = wl.pre_activations(w.net, x)
+    assert np.all(z >= H(l0)) and np.all(z <= H(u0))
+    assert np.all(x @ H(A_lo).astype(np.float64).T + H(c_lo) <= z + 1e-9 * np.abs(z).max())
+    assert np.all(x @ H(A_hi).astype(np.float64).T + H(c_hi) >= z - 1e-9 * np.abs(z).max())
+
+
+# ------------------------------------------------------------- whole pass
+
+def run_both(w, sp, cfg_g, cfg_o, op=None):
+    op = op or OracleProp(w)
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, cfg_g)
+    sync()
+    ref = op.run(sp, cfg=cfg_o)
+    return prop, batch, out, ref, op
+
+
+def compare_pass(out, batch, ref, op, rel=1e-5):
+    ginf = H(out["infeasible"]).astype(bool)
+    oinf = ref["infeasible"]
+    assert not (ginf & ~oinf).any(), "GPU pruned a subdomain the oracle keeps"
+    assert (ginf == oinf).mean() > 0.999
+    fe = ~oinf & ~ginf
+    assert_close(H(batch.lo)[fe], ref["lo"][fe], 1e-5, "clipped lo")
+    assert_close(H(batch.hi)[fe], ref["hi"][fe], 1e-5, "clipped hi")
+    unst = op.unstable()
+    assert_close(H(out["l"])[fe][:, unst], ref["l"][fe][:, unst], rel, "l")
+    assert_close(H(out["u"])[fe][:, unst], ref["u"][fe][:, unst], rel, "u")
+    glb = H(out["lb"])
+    assert np.all(np.isinf(glb[ginf]))
+    return assert_close(glb[fe], ref["lb"][fe], rel, "lb")
+
+
+@pytest.mark.parametrize("mode", ["parallel", "sequential"])
+def test_pass_tiny_matches_oracle(mode):
+    w = wl.tiny_mlp(1024)
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts, np.arange(w.net.n_hidden))
+    cfg_g = gpipe.PassConfig(clip=mode, complete_intermediate=True)
+    cfg_o = opipe.Config(relaxed=mode, complete_intermediate=True)
+    prop, batch, out, ref, _ = run_both(w, sp, cfg_g, cfg_o, op)
+    compare_pass(out, batch, ref, op)
+    assert ref["infeasible"].any() and not ref["infeasible"].all()
+
+
+def test_pass_mnist_matches_oracle():
+    w = wl.mnist_mlp(B=517)            # ragged: not a multiple of any tile
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(), opipe.Config(), op)
+    compare_pass(out, batch, ref, op)
+
+
+def test_pass_biased_net_matches_oracle():
+    w = wl.tiny_mlp(256)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 0, bias="uniform")
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts[:256], np.arange(w.net.n_hidden))
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(complete_intermediate=True),
+                                        opipe.Config(complete_intermediate=True), op)
+    compare_pass(out, batch, ref, op)
+
+
+def test_pass_sound_on_sampled_points_of_each_subdomain():
+    w = wl.tiny_mlp(256)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 1, bias="uniform")
+    rng = np.random.default_rng(wl.SEED_SAMPLES)
+    anchors = rng.uniform(w.lo0, w.hi0, size=(256, 5))
+    sp = wl.splits_from_points(w.net, anchors, w.split_counts[:256], np.arange(w.net.n_hidden))
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig(complete_intermediate=True))
+    sync()
+    assert not H(out["infeasible"]).any()
+    x = np.concatenate([anchors[:, None], rng.uniform(w.lo0, w.hi0, (256, 3000, 5))], 1)
+    z = wl.pre_activations(w.net, x.reshape(-1, 5)).reshape(256, -1, w.net.n_hidden)
+    y = wl.forward(w.net, x.reshape(-1, 5)).reshape(256, -1, 5) @ w.C.T.astype(np.float64) + w.t
+    lo, hi, l, u, lb = H(batch.lo), H(batch.hi), H(out["l"]), H(out["u"]), H(out["lb"])
+    for b in range(256):
+        k = sp.count[b]
+        idx, sg = sp.neuron[b, :k], sp.sign[b, :k]
+        feas = np.all(np.where(sg > 0, z[b][:, idx] >= 0, z[b][:, idx] <= 0), axis=1)
+        assert feas[0]
+        assert np.all(x[b][feas] >= lo[b]) and np.all(x[b][feas] <= hi[b])
+        assert np.all(z[b][feas] >= l[b]) and np.all(z[b][feas] <= u[b])
+        assert np.all(y[b][feas] >= lb[b])
+
+
+# ------------------------------------------------------------------ slopes
+
+def test_alpha_gradient_matches_oracle():
+    w = wl.tiny_mlp(64)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 2, bias="uniform")
+    op = OracleProp(w)
+    sp = wl.draw_splits(64, w.split_counts[:64], np.arange(w.net.n_hidden))
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(), opipe.Config(), op)
+    alpha = wl.random_alpha(64, 5, w.net.n_hidden, seed=9)
+    a_t = T(alpha)
+    lb, grad = api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], a_t,
+                              batch.lo, batch.hi, out["infeasible"], batch.splits, want_grad=True,
+                              ws=prop.ws)
+    sync()
+    fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
+    al = [alpha[:, :, o:o + n].astype(np.float64) for o, n in
+          zip(w.net.hidden_offsets, w.net.hidden_sizes)]
+    l_list = opipe.split_layers(op.layers, ref["l"])
+    u_list = opipe.split_layers(op.layers, ref["u"])
+    olb, ograds, _, _ = opipe.bound_and_grad(op.layers, w.C, w.t, l_list, u_list, al, ref["lo"],
+                                            ref["hi"], ref["G"], ref["h"], ref["active"])
+    assert_close(H(lb)[fe], olb[fe], 1e-5, "alpha-step bound")
+    og = np.concatenate(ograds, axis=2)[fe]
+    gg = H(grad)[fe]
+    scale = np.abs(og).max(axis=2, keepdims=True) + 1e-30
+    bad = np.abs(gg - og) > 1e-5 * scale + 1e-5 * np.abs(og)
+    assert bad.mean() < 1e-3, f"{bad.sum()} gradient entries differ"
+    assert (og != 0).sum() > 100
+
+
+def test_alpha_opt_matches_oracle_and_improves():
+    w = wl.tiny_mlp(48)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 3, bias="uniform")
+    op = OracleProp(w)
+    sp = wl.draw_splits(48, w.split_counts[:48], np.arange(w.net.n_hidden))
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(), opipe.Config(), op)
+    best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=6, lr=0.1)
+    sync()
+    fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
+    l_list = opipe.split_layers(op.layers, ref["l"][fe])
+    u_list = opipe.split_layers(op.layers, ref["u"][fe])
+    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
+                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=6, lr=0.1)
+    g = H(best)[fe]
+    assert np.all(g >= H(out["lb"])[fe] - 1e-6 * np.maximum(np.abs(g), 1))
+    assert (g > H(out["lb"])[fe] + 1e-4).any()
+    assert_close(g, obest, 1e-4, "alpha-opt best bound")
+
+
+# ---------------------------------------------- full size, bench configuration
+
+def test_full_size_mnist_sampled_rows():
+    w = wl.mnist_mlp(B=16384)
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    sync()
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(w.B, 48, replace=False))
+    ref = op.run(subset_splits(sp, idx))
+    glb = H(out["lb"])[idx]
+    assert_close(glb, ref["lb"], 1e-5, "lb (sampled rows)")
+    assert_close(H(batch.lo)[idx], ref["lo"], 1e-5, "lo (sampled rows)")
+    # +inf rows are exactly the infeasible subdomains
+    ginf = H(out["infeasible"]).astype(bool)
+    assert np.array_equal(np.isinf(H(out["lb"])).any(-1), ginf)
+    assert np.isfinite(H(out["lb"])[~ginf]).all()
+
+
+# --------------------------------------------------------------- edge cases
+
+def test_edge_cases_empty_and_degenerate_inputs():
+    w = wl.tiny_mlp(4)
+    prop = gpipe.Property.from_workload(w)
+    op = OracleProp(w)
+    # B = 0 is a no-op everywhere
+    z = torch.empty(0, 5, device="cuda")
+    cons0 = api.Constraints.splits(np.zeros((0, 1), np.int32), np.zeros((0, 1), np.int8))
+    api.clip_domains(prop.root, z, z.clone(), cons0)
+    # unused slots (count 0, index -1) are ignored; kmax = 0 gives the plain bound
+    neuron = np.array([[-1, -1], [3, -1], [0, 1], [5, 7]], np.int32)
+    sign = np.array([[1, 1], [-1, 1], [1, -1], [1, 1]], np.int8)
+    count = np.array([0, 1, 2, 2], np.int32)
+    sp = wl.Splits(neuron, sign, count)
+    batch = gpipe.make_batch(prop, neuron, sign, count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    ref = op.run(wl.Splits(np.where(neuron < 0, 0, neuron), sign, count))
+    sync()
+    compare_pass(out, batch, ref, op)
+    # the subdomain without splits gets the root bound
+    batch0 = gpipe.make_batch(prop, neuron[:1], sign[:1], count[:1])
+    out0 = gpipe.plain_pass(prop, batch0, gpipe.PassConfig(clip="none", complete_final=False))
+    sync()
+    assert_close(H(out0["lb"]), ref["lb"][:1], 1e-5, "no-split bound")
+
+
+def test_invalid_arguments_are_rejected_before_launch():
+    w = wl.tiny_mlp(4)
+    prop = gpipe.Property.from_workload(w)
+    from paper_2512_11087_amd import _native as N
+    with pytest.raises(N.CvError) as e:
+        api.Root(prop.net, w.lo0, w.hi0, alpha0=1.5)
+    assert e.value.status == -1
+    lo, hi = prop.boxes(2)
+    l = torch.zeros(2, prop.net.n_hidden, device="cuda")
+    lb = torch.empty(2, 5, device="cuda")
+    import ctypes as C
+    st = N.lib().cv_bound_propagate(prop.net.handle, 2, 5, api._p(prop.C), api._p(prop.t),
+                                    api._p(l), api._p(l), None, C.c_float(0.5), api._p(lo),
+                                    api._p(hi), None, prop.root.handle, None, 1, api._p(lb),
+                                    None, None, None, C.c_size_t(0), api._stream())
+    assert st == -4   # workspace too small
+    st = N.lib().cv_clip_domains(prop.root.handle, 2, 5, None, api._p(lo), api._p(hi), None, 7,
+                                 api._stream())
+    assert st == -1

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds and
+loads, exports every function include/clipverify.h declares, and rejects
+invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2512_11087_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "clipverify.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cv_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(N.LIB_PATH):
+        from paper_2512_11087_amd import build
+        build.build()
+    return N.lib()
+
+
+def test_header_and_binding_list_the_same_functions():
+    assert header_functions() == sorted(N.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(lib):
+    assert lib.cv_status_string(0) == b"ok"
+    assert lib.cv_status_string(-4) == b"workspace too small"
+    assert lib.cv_version() >= 10000
+    assert lib.cv_last_hip_error() == 0
+
+
+def test_invalid_arguments_are_rejected_on_the_host(lib):
+    out = C.c_void_p()
+    assert lib.cv_net_create(None, 2, C.byref(out)) == -1
+    d = (N.LayerDesc * 1)()
+    assert lib.cv_net_create(d, 1, C.byref(out)) == -3          # needs a hidden layer
+    d2 = (N.LayerDesc * 2)()
+    d2[0].kind = N.CV_CONV2D
+    assert lib.cv_net_create(d2, 2, C.byref(out)) == -3         # conv: not in this build
+    d2[0].kind = 7
+    assert lib.cv_net_create(d2, 2, C.byref(out)) == -1
+    assert lib.cv_clip_domains(None, -1, 4, None, None, None, None, 0, None) == -2
+    assert lib.cv_clip_domains(None, 0, 4, None, None, None, None, 0, None) == 0   # B == 0
+    assert lib.cv_clip_domains(None, 3, 4, None, None, None, None, 0, None) == -1
+    assert lib.cv_concretize(None, 2, 2, 0, None, 0, None, None, None, None, 1, None, None,
+                             None, None, None) == -2
+    assert lib.cv_root_create(None, None, None, C.c_float(0.5), None, C.byref(out)) == -1
+    n = C.c_size_t()
+    assert lib.cv_bound_propagate_workspace(None, 1, 1, C.byref(n)) == -1
+    assert lib.cv_net_destroy(None) == 0 and lib.cv_root_destroy(None) == 0

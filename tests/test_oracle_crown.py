@@ -113,9 +113,9 @@ def test_pipeline_monotone_per_step():
     fe = ~out["infeasible"]
     assert np.all(out["lo"][fe] >= lo[fe]) and np.all(out["hi"][fe] <= hi[fe])
     _, _, _, _, l0, u0 = root.stacked()
-    assert np.all(out["l_a3"][fe] >= l0 - 1e-12) and np.all(out["u_a3"][fe] <= u0 + 1e-12)
-    assert np.all(out["l"][fe] >= out["l_a3"][fe] - 1e-12)
-    assert np.all(out["u"][fe] <= out["u_a3"][fe] + 1e-12)
+    assert np.all(out["l_reconc"][fe] >= l0 - 1e-12) and np.all(out["u_reconc"][fe] <= u0 + 1e-12)
+    assert np.all(out["l"][fe] >= out["l_reconc"][fe] - 1e-12)
+    assert np.all(out["u"][fe] <= out["u_reconc"][fe] + 1e-12)
     assert np.all(out["lb"][fe] >= out["lb_unclipped"][fe] - 1e-12)
     assert np.all(np.isinf(out["lb"][~fe]))
     # tiny config has both infeasible and improved subdomains
