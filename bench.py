@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the batched clip-and-verify hot path on one MI355X.
+
+Workload: ReLU MLP 784-256x6-10 (He-normal, zero biases), input box =
+centre U[0,1]^784 +- 0.02 clipped to [0,1], 16384 subdomains with 4 random
+activation splits each (over root-unstable neurons), 9 margin objectives.
+Synthetic, seeded inputs (the paper's benchmarks are not available).
+
+One step = one full pass of the hot path over the batch:
+  relaxed clipping of every box by its split halfspaces,
+  re-concretization of the cached planes (intermediate bounds),
+  CROWN backward pass + concretization + complete clipping (plain bound),
+  then 20 slope-optimisation iterations (bound, adjoint, Adam) with complete
+  clipping re-applied in each.
+``value`` is subdomains/s of that step; the plain pass alone is reported
+beside it, with the mean bound gain of the slope optimisation.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line on stdout (progress goes to stderr).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "subdomains/s bounded+clipped (784-256x6 MLP); alpha-opt vs plain at equal bound"
+PEAK = {"f64_mfma_tflops": 78.6, "hbm_gbs": 8000.0, "f64_valu_tflops": 78.6}
+GEMM_KERNELS = ("gemm_relax", "gemm_final", "gemm_adjoint", "gemm_planes", "top")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2512_11087_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(w, sp, sample, alpha_steps):
+    """The FP64 oracle timed on the first `sample` subdomains of the same
+    workload: the same step (plain pass + slope optimisation)."""
+    import numpy as np
+    from oracle import crown, pipeline as opipe
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = None
+    cores = len(os.sched_getaffinity(0))
+    layers = crown.dense_layers(w.net)
+    root = crown.root_pass(layers, w.lo0, w.hi0, w.alpha0)   # set-up, not timed (as on the GPU)
+    idx = np.arange(sample)
+    lo = np.broadcast_to(w.lo0, (sample, w.net.n_in)).astype(np.float64)
+    hi = np.broadcast_to(w.hi0, (sample, w.net.n_in)).astype(np.float64)
+    t0 = time.perf_counter()
+    out = opipe.run(layers, root, w.C, w.t, lo, hi, sp.neuron[idx], sp.sign[idx], sp.count[idx])
+    fe = ~out["infeasible"]
+    l_list = opipe.split_layers(layers, out["l"][fe])
+    u_list = opipe.split_layers(layers, out["u"][fe])
+    opipe.alpha_opt(layers, w.C, w.t, l_list, u_list, out["lo"][fe], out["hi"][fe], out["G"][fe],
+                    out["h"][fe], out["active"][fe], steps=alpha_steps, lr=0.1)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "subdomains/s", "cores": int(blas or cores),
+            "kind": "oracle",
+            "sample": f"first {sample} of the {w.B} subdomains, same step (plain pass + "
+                      f"{alpha_steps} slope iterations), {dt:.1f} s on {cores} host cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--alpha-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernels-json", default=None, help="write the per-kernel timing table here")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU; the batch shards over subdomains across "
+              "GPUs but no multi-GPU path is built, so --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2512_11087_amd import _native, pipeline as gpipe, workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    B, T = args.batch, args.alpha_steps
+    w = wl.mnist_mlp(B)
+    log(f"workload {w.name}: B={B}, k=4, M={w.C.shape[0]}, alpha steps={T}")
+    t0 = time.perf_counter()
+    prop = gpipe.Property.from_workload(w)
+    l0, u0 = (x.cpu().numpy() for x in prop.root.bounds())
+    cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
+    sp = wl.draw_splits(B, w.split_counts, cand)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    lo_init, hi_init = batch.lo.clone(), batch.hi.clone()
+    torch.cuda.synchronize()
+    log(f"set-up (root pass, {prop.root.n_unstable} unstable of {w.net.n_hidden}) "
+        f"{time.perf_counter() - t0:.2f} s")
+
+    state, pstate = {}, {}
+
+    def plain_step():
+        batch.lo.copy_(lo_init)
+        batch.hi.copy_(hi_init)
+        return gpipe.plain_pass(prop, batch, gpipe.PassConfig(), pstate)
+
+    def full_step():
+        out = plain_step()
+        best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=T,
+                                  lr=0.1, state=state)
+        return out, best
+
+    for i in range(args.warmup):
+        full_step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    # timed region: K full steps, kernel events recorded on the launch stream
+    _native.profile_reset()
+    _native.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out, best = full_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _native.profile_enable(False)
+    kern = _native.profile_collect()
+    ms_step = 1e3 * wall / args.steps
+    value = B / (wall / args.steps)
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step -> {value:.0f} subdomains/s")
+
+    # plain pass alone (same batch), and the bound gain of the slope optimisation
+    reps = 5
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        o = plain_step()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t1) / reps
+    lb_plain = o["lb"].cpu().numpy()
+    lb_alpha = best.cpu().numpy()
+    inf = o["infeasible"].cpu().numpy().astype(bool)
+    gain = float(np.mean(lb_alpha[~inf] - lb_plain[~inf])) if (~inf).any() else 0.0
+    log(f"plain pass {1e3 * plain_s:.2f} ms -> {B / plain_s:.0f} subdomains/s; "
+        f"mean lb gain of alpha-opt {gain:.4g}")
+
+    # roofline of the dominant kernel (largest share of the timed region)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    avg_ms = d["ms"] / d["launches"]
+    if d["flops"] > 0:
+        ach = d["flops"] / d["launches"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["f64_mfma_tflops"],
+                "unit": "TFLOP/s", "frac": round(ach / PEAK["f64_mfma_tflops"], 4)}
+    else:
+        ach = d["bytes"] / d["launches"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
+                "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = round(avg_ms, 4)
+    roof["traffic"] = traffic_for(dom)
+    if args.kernels_json:
+        with open(args.kernels_json, "w") as f:
+            json.dump({"steps": args.steps, "wall_s": wall, "kernels": kern}, f, indent=1)
+    log("kernel table (timed region):")
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"]):
+        log(f"  {k:14s} launches {v['launches']:5d}  total {v['ms']:9.2f} ms  "
+            f"avg {v['ms'] / v['launches']:8.4f} ms  share {v['ms'] / (1e3 * wall):6.1%}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_sample} subdomains ...")
+        cpu = cpu_baseline(w, sp, args.cpu_sample, T)
+        log(f"cpu baseline {cpu['value']:.2f} subdomains/s ({cpu['sample']})")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "subdomains/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {B} subdomains x 4 splits, 9 margin rows, "
+                               f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
+                   "global_batch": B, "alpha_steps": T, "io_dtype": "f32"},
+        "plain": {"value": round(B / plain_s, 1), "unit": "subdomains/s",
+                  "ms_per_pass": round(1e3 * plain_s, 3)},
+        "alpha_vs_plain": {"throughput_ratio": round(value / (B / plain_s), 5),
+                           "mean_lb_gain": gain},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

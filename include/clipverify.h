@@ -233,6 +233,22 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
                         hipStream_t stream);
 cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes);
 
+/* ------------------------------------------------------ kernel timing */
+
+/* Instrumentation for benchmarks.  While enabled, every kernel the library
+ * enqueues is bracketed by two HIP events recorded on the stream it is
+ * launched on, together with that launch's algorithmic work (floating-point
+ * operations and bytes, counted from the shapes).  Process-global and not
+ * thread-safe.  cv_profile_collect (after the streams are synchronised)
+ * aggregates the records by kernel name and returns the number of names;
+ * cv_profile_entry(i, ...) reads aggregate i (host outputs, any may be
+ * NULL); cv_profile_reset drops the records. */
+cv_status cv_profile_enable(int on);
+cv_status cv_profile_reset(void);
+cv_status cv_profile_collect(int* entries);
+cv_status cv_profile_entry(int i, const char** name, int* launches, double* ms,
+                           double* flops, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ EXPORTS = [
     "cv_clip_domains", "cv_concretize_planes", "cv_concretize_planes_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
     "cv_alpha_step", "cv_alpha_step_workspace",
+    "cv_profile_enable", "cv_profile_reset", "cv_profile_collect", "cv_profile_entry",
 ]
 
 
@@ -81,6 +82,10 @@ def lib():
         "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, P, P, P, P, P, I, P, P, I, F, F, F, F,
                               P, P, P, S, P]),
         "cv_alpha_step_workspace": (I, [P, I, I, P]),
+        "cv_profile_enable": (I, [I]),
+        "cv_profile_reset": (I, []),
+        "cv_profile_collect": (I, [P]),
+        "cv_profile_entry": (I, [I, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -100,3 +105,28 @@ def call(name, *args):
     st = getattr(lib(), name)(*args)
     check(name, st)
     return st
+
+
+def profile_enable(on=True):
+    call("cv_profile_enable", int(bool(on)))
+
+
+def profile_reset():
+    call("cv_profile_reset")
+
+
+def profile_collect():
+    """{kernel name: dict(launches, ms, flops, bytes)} of the records so far
+    (call after synchronising the streams)."""
+    n = C.c_int()
+    call("cv_profile_collect", C.byref(n))
+    out = {}
+    for i in range(n.value):
+        name = C.c_char_p()
+        cnt = C.c_int()
+        ms, fl, by = C.c_double(), C.c_double(), C.c_double()
+        call("cv_profile_entry", i, C.byref(name), C.byref(cnt), C.byref(ms), C.byref(fl),
+             C.byref(by))
+        out[name.value.decode()] = dict(launches=cnt.value, ms=ms.value, flops=fl.value,
+                                        bytes=by.value)
+    return out

@@ -26,6 +26,56 @@ cv_status hip_fail(hipError_t e) {
     if (e__ != hipSuccess) return hip_fail(e__);   \
   } while (0)
 
+// ------------------------------------------------------ kernel timing
+// Optional instrumentation: while enabled, every kernel the library enqueues
+// is bracketed by two HIP events recorded on its own stream, together with
+// the algorithmic work of that launch (flops, bytes).  Process-global, for
+// single-threaded use (benchmarks and profiling runs).
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_pool;
+size_t g_pool_used = 0;
+struct ProfAgg {
+  const char* name;
+  int launches;
+  double ms, flops, bytes;
+};
+std::vector<ProfAgg> g_agg;
+
+hipEvent_t prof_event() {
+  if (g_pool_used < g_pool.size()) return g_pool[g_pool_used++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  g_pool.push_back(e);
+  ++g_pool_used;
+  return e;
+}
+
+struct Prof {
+  const char* name;
+  double flops, bytes;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Prof(const char* n, double f, double by, hipStream_t st) : name(n), flops(f), bytes(by), s(st) {
+    if (g_prof_on && (a = prof_event())) (void)hipEventRecord(a, s);
+  }
+  ~Prof() {
+    if (!g_prof_on || !a) return;
+    hipEvent_t b = prof_event();
+    if (b && hipEventRecord(b, s) == hipSuccess) g_prof.push_back({name, a, b, flops, bytes});
+  }
+};
+#define PLAUNCH(name, flops, bytes, call)          \
+  do {                                             \
+    Prof pf__(name, (double)(flops), (double)(bytes), s); \
+    CV_HIP(call);                                  \
+  } while (0)
+
 // Bump allocator over a caller workspace (256-byte aligned slices).
 struct Carve {
   char* base;
@@ -89,25 +139,25 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
   const int R = B * M;
   const int Nh = net->n_hidden;
   const int nP = net->n[T - 1];
-  CV_HIP(launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
+  PLAUNCH("top", 2.0 * M * net->n[T] * nP, 8.0 * M * nP, launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
                     w.psiT, w.c0, w.e0, w.cabs0, s));
   // ReLU of hidden layer T-1 (array index T-2)
-  CV_HIP(launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
+  PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
                           alpha_def, net->b[T - 2], root->wrel[T - 2], w.Om0, w.trace, w.rowc,
                           w.rowerr, w.rowcabs, s));
   double* cur = w.Om0;
   double* nxt = w.Om1;
   for (int i = T - 1; i >= 2; --i) {
     const int K = net->n[i], N = net->n[i - 1];
-    CV_HIP(launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
+    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
                              alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
-    CV_HIP(launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
+    PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
   }
   const int n0 = net->n[0];
-  CV_HIP(launch_gemm_final(R, net->n[1], n0, cur, net->W[0], M, lo, hi, root->X0, w.Ax, A_out,
+  PLAUNCH("gemm_final", 2.0 * R * net->n[1] * n0, 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + 4.0 * net->n[1] * n0, launch_gemm_final(R, net->n[1], n0, cur, net->W[0], M, lo, hi, root->X0, w.Ax, A_out,
                            w.part, s));
-  CV_HIP(launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
+  PLAUNCH("finalize", 0, 8.0 * R * (2 * gemm_ntiles(n0) + 3), launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
                          root->gamma_big, infeasible, lb, c_out, s));
   return CV_OK;
 }
@@ -451,7 +501,7 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
   CvCons c;
   cv_status st = resolve_cons(root, cons, &c);
   if (st) return st;
-  CV_HIP(launch_clip(B, n, c, lo, hi, infeasible, mode, s));
+  PLAUNCH("clip", 0, 16.0 * B * n + 4.0 * B * c.kmax * n, launch_clip(B, n, c, lo, hi, infeasible, mode, s));
   return CV_OK;
 }
 
@@ -478,15 +528,15 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
   cv_status st = resolve_cons(root, splits, &sp);
   if (st) return st;
   const int Nh = root->N, U = root->U;
-  CV_HIP(launch_fill_stable(B, Nh, Nh - U, root->sidx, root->l0, root->u0, l, u, s));
-  CV_HIP(launch_gemm_planes(B, root->n0, U, lo, hi, root->P, root->cP, root->eP, root->uidx,
+  PLAUNCH("fill_stable", 0, 8.0 * B * (Nh - U), launch_fill_stable(B, Nh, Nh - U, root->sidx, root->l0, root->u0, l, u, s));
+  PLAUNCH("gemm_planes", 2.0 * B * (2.0 * root->n0) * (2.0 * U), 8.0 * B * root->n0 + 8.0 * B * U + 16.0 * root->n0 * U, launch_gemm_planes(B, root->n0, U, lo, hi, root->P, root->cP, root->eP, root->uidx,
                             root->l0, root->u0, Nh, l, u, s));
-  if (splits && splits->kmax > 0) CV_HIP(launch_split_fix(B, Nh, sp, l, u, infeasible, s));
+  if (splits && splits->kmax > 0) PLAUNCH("split_fix", 0, 8.0 * B * splits->kmax, launch_split_fix(B, Nh, sp, l, u, infeasible, s));
   if (complete && splits && splits->kmax > 0 && U > 0) {
     float* Ltmp = Carve(ws).take<float>((size_t)B * U * 2);
-    CV_HIP(launch_ca_neurons(B, U, root->n0, root->uidx, root->A_lo, root->c_lo, root->A_hi,
+    PLAUNCH("ca_neurons", 0, 8.0 * B * U * root->n0, launch_ca_neurons(B, U, root->n0, root->uidx, root->A_lo, root->c_lo, root->A_hi,
                              root->c_hi, sp, passes, lo, hi, l, u, Nh, infeasible, Ltmp, s));
-    CV_HIP(launch_merge_neurons(B, U, root->uidx, Nh, Ltmp, l, u, infeasible, s));
+    PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, root->uidx, Nh, Ltmp, l, u, infeasible, s));
   }
   return CV_OK;
 }
@@ -505,7 +555,7 @@ cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A
   CvCons cc;
   cv_status st = resolve_cons(root, cons, &cc);
   if (st) return st;
-  CV_HIP(launch_ca_generic(B, P, n, A, A_shared, c, lo, hi, cons ? &cc : nullptr, passes, lb, ub,
+  PLAUNCH("ca_generic", 0, 4.0 * B * P * n + 8.0 * B * n, launch_ca_generic(B, P, n, A, A_shared, c, lo, hi, cons ? &cc : nullptr, passes, lb, ub,
                            beta, infeasible, s));
   return CV_OK;
 }
@@ -549,7 +599,7 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
                     w, lb, A_out, c_out, s);
   if (st) return st;
   if (cons && cons->kmax > 0)
-    CV_HIP(launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
+    PLAUNCH("ca_rows", 0, 8.0 * B * M * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
                           infeasible, lb, nullptr, 0, s));
   return CV_OK;
 }
@@ -590,7 +640,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   // complete clipping (or plain concretization) leaves the minimising corner
   // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane
   CvCons none{};
-  CV_HIP(launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes < 1 ? 1 : passes,
+  PLAUNCH("ca_rows", 0, 16.0 * R * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes < 1 ? 1 : passes,
                         w.Ax, w.rowc, w.rowerr, lo, hi, infeasible, lb, nullptr, 1, s));
   const double dlr = lr;
   double* cur = w.Ax;
@@ -598,7 +648,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   for (int k = 1; k <= net->L - 1; ++k) {
     const int K = net->n[k - 1], N = net->n[k];
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
-    CV_HIP(launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
+    PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + N) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
                                net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
                                s));
@@ -607,4 +657,52 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   return CV_OK;
 }
 
+cv_status cv_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return CV_OK;
+}
+
+cv_status cv_profile_reset(void) {
+  g_prof.clear();
+  g_agg.clear();
+  g_pool_used = 0;
+  return CV_OK;
+}
+
+cv_status cv_profile_collect(int* entries) {
+  if (!entries) return CV_E_INVALID;
+  g_agg.clear();
+  for (const ProfRec& r : g_prof) {
+    float ms = 0.0f;
+    CV_HIP(hipEventSynchronize(r.b));
+    CV_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    ProfAgg* a = nullptr;
+    for (ProfAgg& x : g_agg)
+      if (strcmp(x.name, r.name) == 0) a = &x;
+    if (!a) {
+      g_agg.push_back({r.name, 0, 0.0, 0.0, 0.0});
+      a = &g_agg.back();
+    }
+    a->launches += 1;
+    a->ms += ms;
+    a->flops += r.flops;
+    a->bytes += r.bytes;
+  }
+  *entries = (int)g_agg.size();
+  return CV_OK;
+}
+
+cv_status cv_profile_entry(int i, const char** name, int* launches, double* ms, double* flops,
+                           double* bytes) {
+  if (i < 0 || i >= (int)g_agg.size()) return CV_E_INVALID;
+  const ProfAgg& a = g_agg[i];
+  if (name) *name = a.name;
+  if (launches) *launches = a.launches;
+  if (ms) *ms = a.ms;
+  if (flops) *flops = a.flops;
+  if (bytes) *bytes = a.bytes;
+  return CV_OK;
+}
+
 }  // extern "C"
+
