@@ -102,10 +102,12 @@ cv_status dev_alloc(T** p, size_t count) {
 struct Bwd {
   double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
   float* trace;
+  float2* tab;  // relaxation line of every (subdomain, hidden neuron)
 };
 
 size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, bool trace,
                   void* ws, Bwd* w) {
+  const long long B = R / M;
   Carve cv(ws);
   int nmax = 1, ntmax = 1;
   for (int i = 1; i < T; ++i) nmax = std::max(nmax, net->n[i]);
@@ -123,6 +125,7 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, b
   x.e0 = cv.take<double>(M);
   x.cabs0 = cv.take<double>(M);
   x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
+  x.tab = cv.take<float2>((size_t)B * net->n_hidden);
   if (w) *w = x;
   return cv.off + 256;
 }
@@ -141,15 +144,16 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
   const int nP = net->n[T - 1];
   PLAUNCH("top", 2.0 * M * net->n[T] * nP, 8.0 * M * nP, launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
                     w.psiT, w.c0, w.e0, w.cabs0, s));
+  PLAUNCH("relax_table", 0, 16.0 * B * Nh, launch_relax_table(B, Nh, l, u, w.tab, s));
   // ReLU of hidden layer T-1 (array index T-2)
-  PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
+  PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, w.tab, alpha,
                           alpha_def, net->b[T - 2], root->wrel[T - 2], w.Om0, w.trace, w.rowc,
                           w.rowerr, w.rowcabs, s));
   double* cur = w.Om0;
   double* nxt = w.Om1;
   for (int i = T - 1; i >= 2; --i) {
     const int K = net->n[i], N = net->n[i - 1];
-    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
+    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], w.tab, alpha,
                              alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
     PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
@@ -649,7 +653,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
     const int K = net->n[k - 1], N = net->n[k];
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
     PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + N) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
-                               net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
+                               net->off[k - 1], w.tab, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
                                s));
     cur = out;

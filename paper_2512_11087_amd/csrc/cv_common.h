@@ -34,32 +34,59 @@ __host__ __device__ __forceinline__ double cv_gamma(int K) {
 #define CV_ERR_SLACK (1.0 + 1.0e-12)
 
 // ------------------------------------------------------ wave reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, CV_WAVE);
+// Butterfly steps inside each 16-lane row use DPP lane permutes (xor 1, xor 2,
+// half-row mirror, row mirror: each step combines two disjoint partial sums),
+// then the four row results are read with readlane into scalar registers, so
+// the result is wave-uniform.  float64 values move as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+#define CV_DPP_XOR1 0xB1
+#define CV_DPP_XOR2 0x4E
+#define CV_DPP_HALF_MIRROR 0x141
+#define CV_DPP_MIRROR 0x140
+
+// Sum over the 16 lanes of each row (every lane of the row gets it).
+__device__ __forceinline__ double group16_sum(double v) {
+  v += dpp_f64<CV_DPP_XOR1>(v);
+  v += dpp_f64<CV_DPP_XOR2>(v);
+  v += dpp_f64<CV_DPP_HALF_MIRROR>(v);
+  v += dpp_f64<CV_DPP_MIRROR>(v);
   return v;
+}
+__device__ __forceinline__ double group16_max(double v) {
+  v = fmax(v, dpp_f64<CV_DPP_XOR1>(v));
+  v = fmax(v, dpp_f64<CV_DPP_XOR2>(v));
+  v = fmax(v, dpp_f64<CV_DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp_f64<CV_DPP_MIRROR>(v));
+  return v;
+}
+__device__ __forceinline__ double group16_min(double v) {
+  v = fmin(v, dpp_f64<CV_DPP_XOR1>(v));
+  v = fmin(v, dpp_f64<CV_DPP_XOR2>(v));
+  v = fmin(v, dpp_f64<CV_DPP_HALF_MIRROR>(v));
+  v = fmin(v, dpp_f64<CV_DPP_MIRROR>(v));
+  return v;
+}
+// Whole-wave reductions; all lanes must be active.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = group16_sum(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, CV_WAVE));
-  return v;
+  v = group16_max(v);
+  return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, CV_WAVE));
-  return v;
-}
-__device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, CV_WAVE);
-  return v;
-}
-// Sum over the 16 lanes that share (lane / 16): the lanes of one row group
-// of an MFMA 16x16 output block.
-__device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, CV_WAVE);
-  return v;
+  v = group16_min(v);
+  return fmin(fmin(lane_f64(v, 0), lane_f64(v, 16)), fmin(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
 // ---------------------------------------------------- ReLU relaxation
@@ -91,6 +118,31 @@ __device__ __forceinline__ Relax relu_relax(double psi, float lf, float uf, doub
   const double t = fmax(t1, t2);
   r.s = s;
   r.t = t + (u - l) * (4.0 * CV_U64);
+  return r;
+}
+
+// The same relaxation split into a per-neuron part, computed once per
+// (subdomain, neuron) and stored as float32: (slope, intercept) of the line
+// used when alpha does not apply -- (1, 0) active, (0, 0) inactive, the
+// upper line of an unstable neuron (intercept > 0, which marks it unstable)
+// -- and the per-row choice by the sign of psi.  For the upper line the
+// float32 slope s is taken as given and the intercept is computed from it
+// (t >= -s l and t >= u - s u, as in relu_relax) and rounded up, so the
+// stored line is itself a valid upper line.
+__device__ __forceinline__ float2 relax_line(float lf, float uf) {
+  const double l = (double)lf, u = (double)uf;
+  if (l >= 0.0) return make_float2(1.0f, 0.0f);
+  if (u <= 0.0) return make_float2(0.0f, 0.0f);
+  const float s32 = (float)(u / (u - l));
+  const double s = (double)s32;
+  const double t = fmax(-s * l, u - s * u) + (u - l) * (4.0 * CV_U64);
+  return make_float2(s32, ru32(t));
+}
+__device__ __forceinline__ Relax relax_apply(double psi, float2 line, double alpha) {
+  Relax r;
+  r.lower = line.y > 0.0f && psi >= 0.0;
+  r.s = r.lower ? alpha : (double)line.x;
+  r.t = r.lower ? 0.0 : (double)line.y;
   return r;
 }
 

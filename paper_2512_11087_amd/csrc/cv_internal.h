@@ -67,11 +67,13 @@ hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, con
                       double* cabs0, hipStream_t s);
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
-                            const float* l, const float* u, const float* alpha, double alpha_def,
+                            const float2* tab, const float* alpha, double alpha_def,
                             const float* bprev, const double* wrel, double* Om, float* trace,
                             double* rowc, double* rowerr, double* rowcabs, hipStream_t s);
+hipError_t launch_relax_table(int B, int Nh, const float* l, const float* u, float2* tab,
+                              hipStream_t s);
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
-                             int off, const float* l, const float* u, const float* alpha,
+                             int off, const float2* tab, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s);
 hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
@@ -84,8 +86,8 @@ hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const d
                            double* rowerr, const double* rowcabs, double gamma_big,
                            const uint8_t* infeasible, float* lb, float* c_out, hipStream_t s);
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
-                               const float* b, int M, int Nh, int off, const float* l,
-                               const float* u, float* alpha, double alpha_def,
+                               const float* b, int M, int Nh, int off, const float2* tab,
+                               float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
                                double eps, int step, double* Psibar_out, hipStream_t s);

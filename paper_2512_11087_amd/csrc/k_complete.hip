@@ -58,9 +58,17 @@ __device__ __forceinline__ void cons_row(const CvCons& c, int b, int k, int n, c
   }
 }
 
+// Weighted quantile: the smallest candidate q* with W(> q*) <= S, where
+// W(> p) sums the weights of candidates above p.  The search keeps an open
+// interval (lo, hi) of float64 bit patterns with W(> lo) > S >= W(>= hi) and
+// probes a split point inside it: on even rounds where the known weights put
+// the crossing (interpolation, clamped to [1/16, 15/16] of the interval), on
+// odd rounds the midpoint, so the interval at least halves every two rounds.
+// A probe takes the largest candidate p at or below the split point; W(> p)
+// decides the side and, only when W(> p) <= S, W(>= p) > S identifies p = q*.
 template <int EPL>
-__device__ double ca_select(const double (&q)[EPL], const double (&g)[EPL], const float (&xl)[EPL],
-                            const float (&xh)[EPL], uint32_t cand, double S) {
+__device__ double ca_select(const double (&q)[EPL], const float (&wf)[EPL], uint32_t cand, double S,
+                            double wpos) {
   double qmax = -INFINITY, qmin = INFINITY;
 #pragma unroll
   for (int e = 0; e < EPL; ++e)
@@ -70,96 +78,114 @@ __device__ double ca_select(const double (&q)[EPL], const double (&g)[EPL], cons
     }
   qmax = wave_max(qmax);
   qmin = wave_min(qmin);
-  auto above = [&](double p, double& wg, double& wge) {
-    wg = 0.0;
-    wge = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPL; ++e)
-      if ((cand >> e) & 1u) {
-        const double w = fabs(g[e]) * ((double)xh[e] - (double)xl[e]);
-        if (q[e] > p) wg += w;
-        if (q[e] >= p) wge += w;
-      }
-    wg = wave_sum(wg);
-    wge = wave_sum(wge);
-  };
-  double wg, wge;
-  above(qmin, wg, wge);
-  if (wg <= S) return qmin;
-  above(qmax, wg, wge);
-  if (wge > S) return qmax;
-  double lo_v = qmin, hi_v = qmax;  // W(> lo_v) > S,  W(>= hi_v) <= S
-  for (int it = 0; it < 80; ++it) {
-    const unsigned long long blo = (unsigned long long)__double_as_longlong(lo_v);
-    const unsigned long long bhi = (unsigned long long)__double_as_longlong(hi_v);
-    if (bhi - blo <= 1ull) break;
-    const double mv = __longlong_as_double((long long)(blo + (bhi - blo) / 2ull));
+  unsigned long long blo = (unsigned long long)__double_as_longlong(qmin) - 1ull;
+  unsigned long long bhi = (unsigned long long)__double_as_longlong(qmax) + 1ull;
+  double wlo = wpos, whi = 0.0;  // W(> lo), W(>= hi)
+#pragma unroll 1
+  for (int it = 0; it < 160; ++it) {
+    const unsigned long long span = bhi - blo;
+    if (span <= 1ull) break;
+    unsigned long long off = span / 2ull;
+    if ((it & 1) == 0) {
+      double f = (wlo - S) / (wlo - whi);
+      f = fmin(fmax(f, 0.0625), 0.9375);
+      off = (unsigned long long)((double)span * f);
+    }
+    off = off < 1ull ? 1ull : (off >= span ? span - 1ull : off);
+    const double lo_v = __longlong_as_double((long long)blo);
+    const double mv = __longlong_as_double((long long)(blo + off));
     double p = -INFINITY;
 #pragma unroll
     for (int e = 0; e < EPL; ++e)
       if (((cand >> e) & 1u) && q[e] > lo_v && q[e] <= mv) p = fmax(p, q[e]);
     p = wave_max(p);
-    if (p == -INFINITY) {
-      lo_v = mv;
+    if (p == -INFINITY) {  // no candidate in (lo, mv]: W(> mv) = W(> lo)
+      blo += off;
       continue;
     }
-    above(p, wg, wge);
-    if (wg <= S && wge > S) return p;
-    if (wg > S) lo_v = mv;
-    else hi_v = p;
+    double wg = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if (((cand >> e) & 1u) && q[e] > p) wg += (double)wf[e];
+    wg = wave_sum(wg);
+    if (wg > S) {  // q* > p, and nothing lies in (p, mv]
+      blo += off;
+      wlo = wg;
+      continue;
+    }
+    double wge = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      if (((cand >> e) & 1u) && q[e] >= p) wge += (double)wf[e];
+    wge = wave_sum(wge);
+    if (wge > S) return p;
+    bhi = (unsigned long long)__double_as_longlong(p);
+    whi = wge;
   }
-  return hi_v;
+  return __longlong_as_double((long long)bhi);
 }
 
 // One problem on one wave.  a: objective coefficients (lane-strided), c its
 // intercept; on return a holds a + beta^T G.  Returns the rigorous float64
 // lower bound (before the final float32 rounding) or +inf when empty.
+// The rounding-error scale sum_j (|a_j| + sum_k beta_k |g_kj|) max(|lo_j|,|hi_j|)
+// is accumulated per constraint (beta_k times that constraint's own
+// sum_j |g_kj| max(|lo_j|,|hi_j|)), so no per-coordinate scale is kept.
+// xstar (optional) receives the minimising corner of the final dual; it may
+// alias the objective row in memory, which is read for the kink test first.
 template <int EPL>
 __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_in,
                           const float* lo_b, const float* hi_b, const CvCons* cons, int b,
                           int passes, bool& empty, float* beta_out, double* xstar,
                           double* beta) {
   float xl[EPL], xh[EPL];
-  double sc[EPL];
+  double Ea = 0.0;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int j = lane + 64 * e;
     const bool in = j < n;
     xl[e] = in ? lo_b[j] : 0.0f;
     xh[e] = in ? hi_b[j] : 0.0f;
-    sc[e] = fabs(a[e]);
+    Ea += fabs(a[e]) * fabs_max(xl[e], xh[e]);
   }
-  double cabs = fabs(c);
+  Ea = wave_sum(Ea);
+  double cabs = fabs(c), Eb = 0.0;
   const int cnt = cons ? cons_count(*cons, b) : 0;
   // beta: this wave's slice of LDS (all lanes hold and write equal values)
   for (int k = 0; k < cnt; ++k) beta[k] = 0.0;
   empty = false;
+#pragma unroll 1
   for (int pass = 0; pass < passes && !empty; ++pass) {
+#pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
       const float* row;
       float scale;
       double h;
       cons_row(*cons, b, k, n, row, scale, h);
       if (!row) continue;
-      double g[EPL];
+      float g[EPL];  // constraint coefficients are float32 values
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const int j = lane + 64 * e;
-        g[e] = (j < n) ? (double)(scale * row[j]) : 0.0;
-      }
-      if (beta[k] != 0.0) {  // later passes: drop this constraint's own multiplier
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) a[e] -= beta[k] * g[e];
-        c -= beta[k] * h;
+        g[e] = (j < n) ? scale * row[j] : 0.0f;
       }
       double m = 0.0, em = 0.0;
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        m += fmin(g[e] * (double)xl[e], g[e] * (double)xh[e]);
-        em += fabs(g[e]) * fabs_max(xl[e], xh[e]);
+        const double gg = (double)g[e];
+        m += fmin(gg * (double)xl[e], gg * (double)xh[e]);
+        em += fabs(gg) * fabs_max(xl[e], xh[e]);
       }
       m = wave_sum(m) + h;
       em = wave_sum(em);
+      const double bold = beta[k];
+      if (bold != 0.0) {  // later passes: drop this constraint's own multiplier
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) a[e] -= bold * (double)g[e];
+        c -= bold * h;
+        Eb += bold * em;
+        cabs += bold * fabs(h);
+      }
       if (m - cv_gamma(n + 1) * (em + fabs(h)) * CV_ERR_SLACK > 0.0) {
         empty = true;
         break;
@@ -168,49 +194,68 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
       // zero: near-ties go to the smaller multiplier (the dual is exactly flat
       // on [0, q] after relaxed clipping by the same constraint)
       const double S = -m + 3.814697265625e-06 * em;
+      // breakpoints q_j = -a_j/g_j and their weights (the weights only steer
+      // the choice of beta, so float32 suffices: any beta >= 0 is valid)
       double q[EPL];
+      float wf[EPL];
       uint32_t cand = 0;
       double wpos = 0.0;
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         q[e] = 0.0;
-        if (g[e] != 0.0) {
-          q[e] = -a[e] / g[e];
-          const double w = fabs(g[e]) * ((double)xh[e] - (double)xl[e]);
-          if (q[e] > 0.0 && w > 0.0) {
+        wf[e] = 0.0f;
+        if (g[e] != 0.0f) {
+          const double gg = (double)g[e];
+          q[e] = -a[e] / gg;
+          wf[e] = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+          if (q[e] > 0.0 && wf[e] > 0.0f) {
             cand |= 1u << e;
-            wpos += w;
+            wpos += (double)wf[e];
           }
         }
       }
       wpos = wave_sum(wpos);
       double bk = 0.0;
-      if (wpos > S) bk = ca_select<EPL>(q, g, xl, xh, cand, S);
+      if (wpos > S) bk = ca_select<EPL>(q, wf, cand, S, wpos);
       beta[k] = bk;
       if (bk != 0.0) {
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          a[e] += bk * g[e];
-          sc[e] += bk * fabs(g[e]);
-        }
+        for (int e = 0; e < EPL; ++e) a[e] += bk * (double)g[e];
         c += bk * h;
+        Eb += bk * em;
         cabs += bk * fabs(h);
       }
     }
   }
   if (empty) return INFINITY;
-  double d = 0.0, E = 0.0;
+  double d = 0.0;
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
-    E += sc[e] * fabs_max(xl[e], xh[e]);
-  }
+  for (int e = 0; e < EPL; ++e) d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
   d = wave_sum(d) + c;
-  E = wave_sum(E);
-  const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (E + cabs) + e_in) * CV_ERR_SLACK;
+  const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (Ea + Eb + cabs) + e_in) * CV_ERR_SLACK;
   if (beta_out && lane == 0)
     for (int k = 0; k < cons->kmax; ++k) beta_out[k] = k < cnt ? (float)beta[k] : 0.0f;
   if (xstar) {
+    // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|)
+    double sc[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int j = lane + 64 * e;
+      sc[e] = j < n ? fabs(xstar[j]) : 0.0;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      if (beta[k] == 0.0) continue;
+      const float* row;
+      float scale;
+      double h;
+      cons_row(*cons, b, k, n, row, scale, h);
+      if (!row) continue;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int j = lane + 64 * e;
+        if (j < n) sc[e] += beta[k] * fabs((double)row[j]);
+      }
+    }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int j = lane + 64 * e;
@@ -226,7 +271,7 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
 
 // Final planes: rows r = (b, m) of the backward pass output.
 template <int EPL>
-__global__ __launch_bounds__(256) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
+__global__ __launch_bounds__(256, 2) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
                                                  double* Ax, const double* __restrict__ rowc,
                                                  const double* __restrict__ rowerr,
                                                  const float* __restrict__ lo,
@@ -263,10 +308,8 @@ __global__ __launch_bounds__(256) void k_ca_rows(int R, int M, int n, CvCons con
   }
 }
 
-// Generic: row p of subdomain b, float32 plane; also the plain minimum and
-// (optionally) the maximum over the box.
 template <int EPL>
-__global__ __launch_bounds__(256) void k_ca_generic(int B, int P, int n, const float* __restrict__ A,
+__global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, const float* __restrict__ A,
                                                     int A_shared, const float* __restrict__ cv,
                                                     const float* __restrict__ lo,
                                                     const float* __restrict__ hi, CvCons cons,
@@ -317,7 +360,7 @@ __global__ __launch_bounds__(256) void k_ca_generic(int B, int P, int n, const f
 // Intermediate neurons: lower plane (side 0) and negated upper plane (side 1) of every
 // root-unstable neuron still unstable in subdomain b.
 template <int EPL>
-__global__ __launch_bounds__(256) void k_ca_neurons(int B, int U, int n, const int32_t* __restrict__ uidx,
+__global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, const int32_t* __restrict__ uidx,
                                                     const float* __restrict__ A_lo,
                                                     const float* __restrict__ c_lo,
                                                     const float* __restrict__ A_hi,

@@ -35,13 +35,23 @@ constexpr int WN = GBN / NWAVE;  // columns per wave
 constexpr int MI = GBM / 16;
 constexpr int NI = WN / 16;
 constexpr int SA_LD = GBM + 2;   // float64 elements per staged k-row of A
-constexpr int SB_LD = GBN + 4;   // float32 elements per staged k-row of B
+constexpr int SB_LD = GBN + 16;  // float32 elements per staged k-row of B (rows 64 B apart in banks)
 constexpr int NSUM_MAX = 3;
 
+// A loaders return 4 consecutive k of one row (zeros outside [0,R) x [0,K)).
 struct LoadF64 {
   const double* p;
   int ld;
-  __device__ __forceinline__ double operator()(int r, int k) const { return p[(size_t)r * ld + k]; }
+  __device__ __forceinline__ void load4(int r, int k, int R, int K, double (&v)[4]) const {
+    if (r < R && k + 3 < K && (ld & 1) == 0) {
+      const double2* q = reinterpret_cast<const double2*>(p + (size_t)r * ld + k);
+      const double2 x = q[0], y = q[1];
+      v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+      return;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (r < R && k + t < K) ? p[(size_t)r * ld + k + t] : 0.0;
+  }
 };
 
 // Row r of [lo | hi] (the per-subdomain box, 2 n0 columns).
@@ -49,17 +59,49 @@ struct LoadBox {
   const float* lo;
   const float* hi;
   int n0;
-  __device__ __forceinline__ double operator()(int r, int k) const {
-    return k < n0 ? (double)lo[(size_t)r * n0 + k] : (double)hi[(size_t)r * n0 + (k - n0)];
+  __device__ __forceinline__ void load4(int r, int k, int R, int K, double (&v)[4]) const {
+    if (r < R && (n0 & 3) == 0 && k + 3 < K) {
+      const float* src = k < n0 ? lo + (size_t)r * n0 + k : hi + (size_t)r * n0 + (k - n0);
+      const float4 x = *reinterpret_cast<const float4*>(src);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      return;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int kk = k + t;
+      v[t] = (r < R && kk < K)
+                 ? (kk < n0 ? (double)lo[(size_t)r * n0 + kk] : (double)hi[(size_t)r * n0 + (kk - n0)])
+                 : 0.0;
+    }
   }
 };
 
+// 16 consecutive columns of one row of B (zeros outside).
+__device__ __forceinline__ void load_b16(const float* __restrict__ Bm, int ldb, int gk, int gc, int K,
+                                         int N, float (&v)[16]) {
+  const float* row = Bm + (size_t)gk * ldb + gc;
+  if (gk < K && gc + 15 < N && (ldb & 3) == 0) {
+    const float4* q = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 x = q[t];
+      v[4 * t] = x.x; v[4 * t + 1] = x.y; v[4 * t + 2] = x.z; v[4 * t + 3] = x.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t) v[t] = (gk < K && gc + t < N) ? row[t] : 0.0f;
+}
+
+// Software pipeline: while the MFMAs consume K-chunk c from one LDS buffer,
+// the global loads of chunk c+1 are in flight into registers; they are
+// written to the other buffer afterwards, one barrier per chunk.
 template <class LoadA, class Epi>
-__global__ __launch_bounds__(256) void k_gemm(int R, int K, int N, LoadA la,
-                                              const float* __restrict__ Bm, int ldb, Epi epi,
-                                              double* __restrict__ part, int ntiles) {
-  __shared__ double sA[GBK * SA_LD];
-  __shared__ float sB[GBK * SB_LD];
+__global__ __launch_bounds__(256, 2) void k_gemm(int R, int K, int N, LoadA la,
+                                                 const float* __restrict__ Bm, int ldb, Epi epi,
+                                                 double* __restrict__ part, int ntiles) {
+  __shared__ double sA[2][GBK * SA_LD];
+  __shared__ float sB[2][GBK * SB_LD];
   __shared__ double sRed[NWAVE * GBM * NSUM_MAX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GBM;
@@ -69,63 +111,100 @@ __global__ __launch_bounds__(256) void k_gemm(int R, int K, int N, LoadA la,
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  // column blocks of this wave that intersect [0, N) (wave-uniform)
+  int nblk = (N - (n0 + wave * WN) + 15) / 16;
+  nblk = nblk < 0 ? 0 : (nblk > NI ? NI : nblk);
 
   const int ar = tid >> 2, akq = (tid & 3) * 4;   // A staging: row, first k
   const int bk = tid >> 4, bc0 = (tid & 15) * 16; // B staging: k, first column
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    {
-      const int gr = m0 + ar;
+  double pa[4];
+  float pb[16];
+  auto fetch = [&](int k0) {
+    la.load4(m0 + ar, k0 + akq, R, K, pa);
+    load_b16(Bm, ldb, k0 + bk, n0 + bc0, K, N, pb);
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + akq + q;
-        sA[(akq + q) * SA_LD + ar] = (gr < R && gk < K) ? la(gr, gk) : 0.0;
-      }
-    }
-    {
-      const int gk = k0 + bk;
-      const float* brow = Bm + (size_t)gk * ldb;
+    for (int q = 0; q < 4; ++q) sA[buf][(akq + q) * SA_LD + ar] = pa[q];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int gc = n0 + bc0 + q;
-        sB[bk * SB_LD + bc0 + q] = (gk < K && gc < N) ? brow[gc] : 0.0f;
-      }
-    }
-    __syncthreads();
+    for (int q = 0; q < 16; q += 4)
+      *reinterpret_cast<float4*>(&sB[buf][bk * SB_LD + bc0 + q]) =
+          make_float4(pb[q], pb[q + 1], pb[q + 2], pb[q + 3]);
+  };
+  const int nch = (K + GBK - 1) / GBK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) fetch((c + 1) * GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       double af[MI], bf[NI];
       const int kr = kk + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < MI; ++i) af[i] = sA[kr * SA_LD + i * 16 + (lane & 15)];
+      for (int i = 0; i < MI; ++i) af[i] = sA[buf][kr * SA_LD + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < NI; ++j) bf[j] = (double)sB[kr * SB_LD + wave * WN + j * 16 + (lane & 15)];
+      for (int j = 0; j < NI; ++j) bf[j] = (double)sB[buf][kr * SB_LD + wave * WN + j * 16 + (lane & 15)];
+      if (nblk == NI) {  // full tile: straight-line MFMA issue
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < NI; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          if (j < nblk) {
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
     }
+    if (c + 1 < nch) stash(buf ^ 1);
     __syncthreads();
   }
 
+  // Epilogue, in groups of VGROUP accumulator rows: all global loads of a
+  // group are issued first (Epi::load), then the group is computed and
+  // stored (Epi::apply), so load latency is paid once per group rather than
+  // once per element (the stores could otherwise alias later loads).
   constexpr int NS = Epi::NSUM;
+  constexpr int VG = Epi::VGROUP;
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int lr = i * 16 + (lane >> 4) + 4 * v;
-      const int r = m0 + lr;
-      double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+    for (int v0 = 0; v0 < 4; v0 += VG) {
+      typename Epi::Row rw[VG];
+      typename Epi::Pre pre[VG][NI];
 #pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const int c = n0 + wave * WN + j * 16 + (lane & 15);
-        if (r < R && c < N) epi.apply(r, c, acc[i][j][v], sums);
+      for (int dv = 0; dv < VG; ++dv) {
+        const int r = m0 + i * 16 + (lane >> 4) + 4 * (v0 + dv);
+        rw[dv] = epi.row(r < R ? r : R - 1);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          const int c = n0 + wave * WN + j * 16 + (lane & 15);
+          if (r < R && j < nblk && c < N) pre[dv][j] = epi.load(rw[dv], r, c);
+        }
       }
-      if constexpr (NS > 0) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          const double t = group16_sum(sums[s]);
-          if ((lane & 15) == 0) sRed[(wave * GBM + lr) * NS + s] = t;
+      for (int dv = 0; dv < VG; ++dv) {
+        const int lr = i * 16 + (lane >> 4) + 4 * (v0 + dv);
+        const int r = m0 + lr;
+        double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          const int c = n0 + wave * WN + j * 16 + (lane & 15);
+          if (r < R && j < nblk && c < N) epi.apply(rw[dv], pre[dv][j], r, c, acc[i][j][v0 + dv], sums);
+        }
+        if constexpr (NS > 0) {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const double t = group16_sum(sums[s]);
+            if ((lane & 15) == 0) sRed[(wave * GBM + lr) * NS + s] = t;
+          }
         }
       }
     }
@@ -153,9 +232,9 @@ __global__ __launch_bounds__(256) void k_gemm(int R, int K, int N, LoadA la,
 // sum |psi| * wrel (error weight).
 struct EpiRelax {
   static constexpr int NSUM = 3;
+  static constexpr int VGROUP = 4;
   int M, Nh, off;
-  const float* l;
-  const float* u;
+  const float2* tab;
   const float* alpha;
   double alpha_def;
   const float* bprev;
@@ -163,12 +242,26 @@ struct EpiRelax {
   double* Om;
   int ldo;
   float* trace;
-  __device__ __forceinline__ void apply(int r, int j, double psi, double* s) const {
-    const int b = r / M;
-    const size_t bi = (size_t)b * Nh + off + j;
-    const size_t ri = (size_t)r * Nh + off + j;
-    const double al = alpha ? (double)alpha[ri] : alpha_def;
-    const Relax rl = relu_relax(psi, l[bi], u[bi], al);
+  struct Row {
+    const float2* tab;
+    size_t ri;
+  };
+  __device__ __forceinline__ Row row(int r) const {
+    const size_t b = (size_t)(r / M);
+    return Row{tab + b * Nh + off, (size_t)r * Nh + off};
+  }
+  struct Pre {
+    float2 line;
+    float al;
+  };
+  __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
+    return Pre{w.tab[j], alpha ? alpha[w.ri + j] : (float)alpha_def};
+  }
+  __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double psi,
+                                        double* s) const {
+    const size_t ri = w.ri + j;
+    const double al = alpha ? (double)p.al : alpha_def;
+    const Relax rl = relax_apply(psi, p.line, al);
     const double om = psi * rl.s;
     Om[(size_t)r * ldo + j] = om;
     if (trace) trace[ri] = trace32(psi);
@@ -182,15 +275,28 @@ struct EpiRelax {
 // plane; accumulate min(a lo_j, a hi_j) (Lemma A.2) and |a| X0_j (error).
 struct EpiFinal {
   static constexpr int NSUM = 2;
+  static constexpr int VGROUP = 4;
   int M, n0;
   const float* lo;
   const float* hi;
   const double* X0;
   double* Ax;
   float* A_out;
-  __device__ __forceinline__ void apply(int r, int j, double a, double* s) const {
-    const int b = r / M;
-    const double xl = (double)lo[(size_t)b * n0 + j], xh = (double)hi[(size_t)b * n0 + j];
+  struct Row {
+    const float* lo;
+    const float* hi;
+  };
+  __device__ __forceinline__ Row row(int r) const {
+    const size_t b = (size_t)(r / M);
+    return Row{lo + b * n0, hi + b * n0};
+  }
+  struct Pre {
+    float xl, xh;
+  };
+  __device__ __forceinline__ Pre load(const Row& w, int, int j) const { return Pre{w.lo[j], w.hi[j]}; }
+  __device__ __forceinline__ void apply(const Row&, const Pre& p, int r, int j, double a,
+                                        double* s) const {
+    const double xl = (double)p.xl, xh = (double)p.xh;
     s[0] += fmin(a * xl, a * xh);
     s[1] += fabs(a) * X0[j];
     if (Ax) Ax[(size_t)r * n0 + j] = a;
@@ -201,6 +307,7 @@ struct EpiFinal {
 // Re-concretized bound of cached plane column `col` over box r.
 struct EpiPlanes {
   static constexpr int NSUM = 0;
+  static constexpr int VGROUP = 4;
   int U, Nh;
   const float* cP;
   const double* eP;
@@ -209,7 +316,12 @@ struct EpiPlanes {
   const float* u0;
   float* l;
   float* u;
-  __device__ __forceinline__ void apply(int b, int col, double v, double*) const {
+  struct Row {};
+  __device__ __forceinline__ Row row(int) const { return Row{}; }
+  struct Pre {};
+  __device__ __forceinline__ Pre load(const Row&, int, int) const { return Pre{}; }
+  __device__ __forceinline__ void apply(const Row&, const Pre&, int b, int col, double v,
+                                        double*) const {
     if (col < U) {
       const int j = uidx[col];
       const double x = v + (double)cP[col] - eP[col];
@@ -228,10 +340,10 @@ struct EpiPlanes {
 // projected Adam ascent step on alpha.
 struct EpiAdj {
   static constexpr int NSUM = 0;
+  static constexpr int VGROUP = 2;
   int M, Nh, off;
   const float* bias;
-  const float* l;
-  const float* u;
+  const float2* tab;
   float* alpha;
   double alpha_def;
   const float* trace;
@@ -242,21 +354,40 @@ struct EpiAdj {
   double lr, b1, b2, eps, bc1, bc2;
   double* out;
   int ldo;
-  __device__ __forceinline__ void apply(int r, int j, double acc, double*) const {
-    const int b = r / M;
+  struct Row {
+    const float2* tab;
+    size_t ri;
+    bool dead;
+  };
+  __device__ __forceinline__ Row row(int r) const {
+    const size_t b = (size_t)(r / M);
+    return Row{tab + b * Nh + off, (size_t)r * Nh + off,
+               infeasible != nullptr && infeasible[b] != 0};
+  }
+  struct Pre {
+    float2 line;
+    float psi, al, m, v;
+  };
+  __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
+    const size_t ri = w.ri + j;
+    const bool adam = lr > 0.0 && alpha;
+    return Pre{w.tab[j], trace[ri], alpha ? alpha[ri] : (float)alpha_def, adam ? am[ri] : 0.0f,
+               adam ? av[ri] : 0.0f};
+  }
+  __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double acc,
+                                        double*) const {
     const double om = acc + (double)bias[j];
-    const size_t ri = (size_t)r * Nh + off + j;
-    const size_t bi = (size_t)b * Nh + off + j;
-    const double al = alpha ? (double)alpha[ri] : alpha_def;
-    const double psi = (double)trace[ri];
-    const Relax rl = relu_relax(psi, l[bi], u[bi], al);
-    const bool dead = infeasible && infeasible[b];
+    const size_t ri = w.ri + j;
+    const double al = alpha ? (double)p.al : alpha_def;
+    const double psi = (double)p.psi;
+    const Relax rl = relax_apply(psi, p.line, al);
+    const bool dead = w.dead;
     const double g = (rl.lower && !dead) ? om * psi : 0.0;
     if (out) out[(size_t)r * ldo + j] = om * rl.s + rl.t;
     if (grad) grad[ri] = (float)g;
     if (lr > 0.0 && alpha) {
-      const double m = b1 * (double)am[ri] + (1.0 - b1) * g;
-      const double v = b2 * (double)av[ri] + (1.0 - b2) * g * g;
+      const double m = b1 * (double)p.m + (1.0 - b1) * g;
+      const double v = b2 * (double)p.v + (1.0 - b2) * g * g;
       const double mh = m / bc1, vh = v / bc2;
       double a = al + lr * mh / (sqrt(vh) + eps);
       a = fmin(fmax(a, 0.0), 1.0);
@@ -282,10 +413,10 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
 int gemm_ntiles(int N) { return (N + GBN - 1) / GBN; }
 
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
-                             int off, const float* l, const float* u, const float* alpha,
+                             int off, const float2* tab, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s) {
-  EpiRelax e{M, Nh, off, l, u, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
+  EpiRelax e{M, Nh, off, tab, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
@@ -305,13 +436,13 @@ hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
-                               const float* b, int M, int Nh, int off, const float* l,
-                               const float* u, float* alpha, double alpha_def,
+                               const float* b, int M, int Nh, int off, const float2* tab,
+                               float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
                                double eps, int step, double* Psibar_out, hipStream_t s) {
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
-  EpiAdj e{M, Nh, off, b, l, u, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
+  EpiAdj e{M, Nh, off, b, tab, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N};
   return run_gemm(R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

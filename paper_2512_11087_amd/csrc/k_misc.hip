@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float*
 __global__ __launch_bounds__(256) void k_relax_top(
     int R, int M, int nP, int Nh, int off, const double* __restrict__ psiT,
     const double* __restrict__ c0, const double* __restrict__ e0, const double* __restrict__ cabs0,
-    const float* __restrict__ l, const float* __restrict__ u, const float* __restrict__ alpha,
+    const float2* __restrict__ tab, const float* __restrict__ alpha,
     double alpha_def, const float* __restrict__ bprev, const double* __restrict__ wrel,
     double* Om, float* trace, double* rowc, double* rowerr, double* rowcabs) {
   const int lane = threadIdx.x & 63;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_relax_top(
     const size_t bi = (size_t)b * Nh + off + j;
     const size_t ri = (size_t)r * Nh + off + j;
     const double al = alpha ? (double)alpha[ri] : alpha_def;
-    const Relax rl = relu_relax(psi, l[bi], u[bi], al);
+    const Relax rl = relax_apply(psi, tab[bi], al);
     const double om = psi * rl.s;
     Om[(size_t)r * nP + j] = om;
     if (trace) trace[ri] = trace32(psi);
@@ -71,6 +71,14 @@ __global__ __launch_bounds__(256) void k_relax_top(
     rowerr[r] = e0[m] + s3;
     rowcabs[r] = cabs0[m] + fabs(s1) + fabs(s2);
   }
+}
+
+// Relaxation lines of every (subdomain, hidden neuron), see relax_line.
+__global__ void k_relax_table(size_t total, const float* __restrict__ l,
+                              const float* __restrict__ u, float2* tab) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  tab[i] = relax_line(l[i], u[i]);
 }
 
 __global__ void k_rowacc(int R, int ntiles, const double* __restrict__ part, double* rowc,
@@ -253,13 +261,22 @@ hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, con
 
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
-                            const float* l, const float* u, const float* alpha, double alpha_def,
+                            const float2* tab, const float* alpha, double alpha_def,
                             const float* bprev, const double* wrel, double* Om, float* trace,
                             double* rowc, double* rowerr, double* rowcabs, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_relax_top, dim3((R + 3) / 4), dim3(256), 0, s, R, M, nP, Nh, off, psiT, c0,
-                     e0, cabs0, l, u, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
+                     e0, cabs0, tab, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
                      rowcabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_relax_table(int B, int Nh, const float* l, const float* u, float2* tab,
+                              hipStream_t s) {
+  const size_t tot = (size_t)B * Nh;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relax_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, l,
+                     u, tab);
   return hipGetLastError();
 }
 
