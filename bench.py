@@ -39,9 +39,13 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the device-code sources: counter figures taken for another
+    version of the kernels are not reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2512_11087_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f == "api.hip":          # host orchestration only, no kernel code
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -103,6 +107,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-json", default=None, help="write the per-kernel timing table here")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB and exit "
+                         "(calibrates the HBM byte counters of a profiler)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -116,6 +123,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 5 copies of {n} bytes")
+        return
     B, T = args.batch, args.alpha_steps
     w = wl.mnist_mlp(B)
     log(f"workload {w.name}: B={B}, k=4, M={w.C.shape[0]}, alpha steps={T}")

@@ -652,7 +652,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   for (int k = 1; k <= net->L - 1; ++k) {
     const int K = net->n[k - 1], N = net->n[k];
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
-    PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + N) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
+    PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
                                net->off[k - 1], w.tab, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
                                s));
