@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--alpha-steps", type=int, default=20)
-    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernels-json", default=None, help="write the per-kernel timing table here")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
