@@ -80,6 +80,24 @@ __device__ __forceinline__ double wave_sum(double v) {
   v = group16_sum(v);
   return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
+// Three independent sums in one pass (their permute chains interleave).
+__device__ __forceinline__ void wave_sum3(double& a, double& b, double& c) {
+  a += dpp_f64<CV_DPP_XOR1>(a);
+  b += dpp_f64<CV_DPP_XOR1>(b);
+  c += dpp_f64<CV_DPP_XOR1>(c);
+  a += dpp_f64<CV_DPP_XOR2>(a);
+  b += dpp_f64<CV_DPP_XOR2>(b);
+  c += dpp_f64<CV_DPP_XOR2>(c);
+  a += dpp_f64<CV_DPP_HALF_MIRROR>(a);
+  b += dpp_f64<CV_DPP_HALF_MIRROR>(b);
+  c += dpp_f64<CV_DPP_HALF_MIRROR>(c);
+  a += dpp_f64<CV_DPP_MIRROR>(a);
+  b += dpp_f64<CV_DPP_MIRROR>(b);
+  c += dpp_f64<CV_DPP_MIRROR>(c);
+  a = (lane_f64(a, 0) + lane_f64(a, 16)) + (lane_f64(a, 32) + lane_f64(a, 48));
+  b = (lane_f64(b, 0) + lane_f64(b, 16)) + (lane_f64(b, 32) + lane_f64(b, 48));
+  c = (lane_f64(c, 0) + lane_f64(c, 16)) + (lane_f64(c, 32) + lane_f64(c, 48));
+}
 __device__ __forceinline__ double wave_max(double v) {
   v = group16_max(v);
   return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
@@ -153,6 +171,46 @@ __device__ __forceinline__ float trace32(double psi) {
   if (psi < 0.0 && !(f < 0.0f)) f = -1.17549435e-38f;
   return f;
 }
+
+// p[j] for j < n, else 0, without a branch: the index is clamped into
+// [0, n) (callers guarantee n >= 1), so the load is always in bounds and is
+// issued together with its neighbours; a select then zeroes the tail.  (A
+// guarded load `j < n ? p[j] : 0` becomes one branch per load, which
+// serialises the loads' latencies.)
+__device__ __forceinline__ float ld_or0(const float* p, int j, int n) {
+  const float v = p[j < n ? j : n - 1];
+  return j < n ? v : 0.0f;
+}
+__device__ __forceinline__ double ld_or0(const double* p, int j, int n) {
+  const double v = p[j < n ? j : n - 1];
+  return j < n ? v : 0.0;
+}
+
+// Buffer view of `bytes` bytes at a wave-uniform address p.  Raw buffer
+// loads past the end return 0 without touching memory (the hardware range
+// check of an unstrided buffer resource), so lane-strided rows of any
+// length load without branches and keep immediate offsets.  Word 3 of the
+// descriptor is the gfx9-family default (32-bit data format).
+typedef __amdgpu_buffer_rsrc_t cv_buf;
+__device__ __forceinline__ cv_buf cv_buffer(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// Loads at a byte offset (the range check covers the vector offset and the
+// instruction's immediate offset, so constants stay in the immediate field).
+__device__ __forceinline__ float buf_f32(cv_buf r, int byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ double buf_f64(cv_buf r, int byte_off) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  return __hiloint2double((int)v.y, (int)v.x);
+}
+// Keeps the compiler from hoisting values derived from v out of a loop:
+// hoisted conversions and per-element offsets would stay live in registers
+// for the whole loop (and offsets hoisted that way no longer fold into the
+// immediate offset field of the loads).
+__device__ __forceinline__ void cv_opaque(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void cv_opaque(int& v) { asm volatile("" : "+v"(v)); }
 
 __device__ __forceinline__ double fabs_max(float a, float b) {
   return fmax(fabs((double)a), fabs((double)b));

@@ -72,9 +72,8 @@ __global__ __launch_bounds__(CT) void k_clip(int B, int n, CvCons cons, float* l
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int i = tid + q * CT;
-    const bool in = i < n;
-    olo[q] = in ? lo[(size_t)b * n + i] : 0.0f;
-    ohi[q] = in ? hi[(size_t)b * n + i] : 0.0f;
+    olo[q] = ld_or0(lo + (size_t)b * n, i, n);
+    ohi[q] = ld_or0(hi + (size_t)b * n, i, n);
     nlo[q] = olo[q];
     nhi[q] = ohi[q];
   }
@@ -91,7 +90,7 @@ __global__ __launch_bounds__(CT) void k_clip(int B, int n, CvCons cons, float* l
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int i = tid + q * CT;
-      g[q] = (i < n) ? scale * row[i] : 0.0f;
+      g[q] = scale * ld_or0(row, i, n);
       const double x0 = mode ? (double)nlo[q] : (double)olo[q];
       const double x1 = mode ? (double)nhi[q] : (double)ohi[q];
       const double gg = (double)g[q];

@@ -125,6 +125,14 @@ __device__ double ca_select(const double (&q)[EPL], const float (&wf)[EPL], uint
   return __longlong_as_double((long long)bhi);
 }
 
+// Wave-uniform copy of lane l's pointer.
+__device__ __forceinline__ const float* lane_ptr(const float* p, int l) {
+  const uint64_t u = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+  return (const float*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 // One problem on one wave.  a: objective coefficients (lane-strided), c its
 // intercept; on return a holds a + beta^T G.  Returns the rigorous float64
 // lower bound (before the final float32 rounding) or +inf when empty.
@@ -133,6 +141,8 @@ __device__ double ca_select(const double (&q)[EPL], const float (&wf)[EPL], uint
 // sum_j |g_kj| max(|lo_j|,|hi_j|)), so no per-coordinate scale is kept.
 // xstar (optional) receives the minimising corner of the final dual; it may
 // alias the objective row in memory, which is read for the kink test first.
+// Lane k fetches constraint k's row pointer, sign and offset up front, so a
+// constraint costs one dependent load (its row) instead of a chain.
 template <int EPL>
 __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_in,
                           const float* lo_b, const float* hi_b, const CvCons* cons, int b,
@@ -140,17 +150,21 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
                           double* beta) {
   float xl[EPL], xh[EPL];
   double Ea = 0.0;
+  const cv_buf blo = cv_buffer(lo_b, 4u * n), bhi = cv_buffer(hi_b, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int j = lane + 64 * e;
-    const bool in = j < n;
-    xl[e] = in ? lo_b[j] : 0.0f;
-    xh[e] = in ? hi_b[j] : 0.0f;
+    xl[e] = buf_f32(blo, 4 * j);
+    xh[e] = buf_f32(bhi, 4 * j);
     Ea += fabs(a[e]) * fabs_max(xl[e], xh[e]);
   }
-  Ea = wave_sum(Ea);
   double cabs = fabs(c), Eb = 0.0;
   const int cnt = cons ? cons_count(*cons, b) : 0;
+  const float* my_row = nullptr;
+  float my_scale = 0.0f;
+  double my_h = 0.0;
+  if (lane < cnt) cons_row(*cons, b, lane, n, my_row, my_scale, my_h);
+  Ea = wave_sum(Ea);
   // beta: this wave's slice of LDS (all lanes hold and write equal values)
   for (int k = 0; k < cnt; ++k) beta[k] = 0.0;
   empty = false;
@@ -158,30 +172,47 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   for (int pass = 0; pass < passes && !empty; ++pass) {
 #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
-      const float* row;
-      float scale;
-      double h;
-      cons_row(*cons, b, k, n, row, scale, h);
+      const float* row = lane_ptr(my_row, k);
       if (!row) continue;
+      const float scale = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_scale), k));
+      const double h = lane_f64(my_h, k);
+      const cv_buf brow = cv_buffer(row, 4u * n);
+      int vb = 4 * lane;
+      cv_opaque(vb);
       float g[EPL];  // constraint coefficients are float32 values
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        const int j = lane + 64 * e;
-        g[e] = (j < n) ? scale * row[j] : 0.0f;
+        g[e] = scale * buf_f32(brow, vb + 256 * e);
+        cv_opaque(xl[e]);
+        cv_opaque(xh[e]);
       }
-      double m = 0.0, em = 0.0;
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const double gg = (double)g[e];
-        m += fmin(gg * (double)xl[e], gg * (double)xh[e]);
-        em += fabs(gg) * fabs_max(xl[e], xh[e]);
-      }
-      m = wave_sum(m) + h;
-      em = wave_sum(em);
       const double bold = beta[k];
       if (bold != 0.0) {  // later passes: drop this constraint's own multiplier
 #pragma unroll
         for (int e = 0; e < EPL; ++e) a[e] -= bold * (double)g[e];
+      }
+      // m, its error scale, and the weight of the coordinates whose
+      // breakpoint q_j = -a_j/g_j is positive (a_j and g_j of opposite
+      // signs), without dividing; breakpoints are formed only when that
+      // weight exceeds -m, i.e. when beta* > 0 is possible.  The weights only
+      // steer the choice of beta, so float32 suffices (any beta >= 0 is valid).
+      // (products of float32 values are exact in float64, so
+      // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly)
+      double m = 0.0, em = 0.0, wsg = 0.0;
+      float wf[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const double gg = (double)g[e];
+        const float xs = g[e] >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
+        m += gg * (double)xs;
+        em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+        wf[e] = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+        const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
+        if (opp && wf[e] > 0.0f) wsg += (double)wf[e];
+      }
+      wave_sum3(m, em, wsg);
+      m += h;
+      if (bold != 0.0) {
         c -= bold * h;
         Eb += bold * em;
         cabs += bold * fabs(h);
@@ -194,33 +225,37 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
       // zero: near-ties go to the smaller multiplier (the dual is exactly flat
       // on [0, q] after relaxed clipping by the same constraint)
       const double S = -m + 3.814697265625e-06 * em;
-      // breakpoints q_j = -a_j/g_j and their weights (the weights only steer
-      // the choice of beta, so float32 suffices: any beta >= 0 is valid)
-      double q[EPL];
-      float wf[EPL];
-      uint32_t cand = 0;
-      double wpos = 0.0;
+      double bk = 0.0;
+      if (wsg > S) {
+        // breakpoints and the exact candidate set (a division may underflow
+        // to q = 0, which is not a candidate)
+        double q[EPL];
+        uint32_t cand = 0;
+        double wpos = 0.0;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        q[e] = 0.0;
-        wf[e] = 0.0f;
-        if (g[e] != 0.0f) {
-          const double gg = (double)g[e];
-          q[e] = -a[e] / gg;
-          wf[e] = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
-          if (q[e] > 0.0 && wf[e] > 0.0f) {
-            cand |= 1u << e;
-            wpos += (double)wf[e];
+        for (int e = 0; e < EPL; ++e) {
+          q[e] = 0.0;
+          if (g[e] != 0.0f) {
+            q[e] = -a[e] / (double)g[e];
+            if (q[e] > 0.0 && wf[e] > 0.0f) {
+              cand |= 1u << e;
+              wpos += (double)wf[e];
+            }
           }
         }
+        wpos = wave_sum(wpos);
+        if (wpos > S) bk = ca_select<EPL>(q, wf, cand, S, wpos);
       }
-      wpos = wave_sum(wpos);
-      double bk = 0.0;
-      if (wpos > S) bk = ca_select<EPL>(q, wf, cand, S, wpos);
       beta[k] = bk;
       if (bk != 0.0) {
+        // the row is re-read (cache hit) rather than kept live over the search
+        int vb2 = 4 * lane;
+        cv_opaque(vb2);
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) a[e] += bk * (double)g[e];
+        for (int e = 0; e < EPL; ++e) {
+          const float gr = scale * buf_f32(brow, vb2 + 256 * e);
+          a[e] += bk * (double)gr;
+        }
         c += bk * h;
         Eb += bk * em;
         cabs += bk * fabs(h);
@@ -233,27 +268,26 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   for (int e = 0; e < EPL; ++e) d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
   d = wave_sum(d) + c;
   const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (Ea + Eb + cabs) + e_in) * CV_ERR_SLACK;
-  if (beta_out && lane == 0)
-    for (int k = 0; k < cons->kmax; ++k) beta_out[k] = k < cnt ? (float)beta[k] : 0.0f;
+  if (beta_out && lane < cons->kmax) beta_out[lane] = lane < cnt ? (float)beta[lane] : 0.0f;
   if (xstar) {
     // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|)
     double sc[EPL];
+    const cv_buf bx = cv_buffer(xstar, 8u * n);
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int j = lane + 64 * e;
-      sc[e] = j < n ? fabs(xstar[j]) : 0.0;
+      sc[e] = fabs(buf_f64(bx, 8 * j));
     }
     for (int k = 0; k < cnt; ++k) {
       if (beta[k] == 0.0) continue;
-      const float* row;
-      float scale;
-      double h;
-      cons_row(*cons, b, k, n, row, scale, h);
+      const float* row = lane_ptr(my_row, k);
       if (!row) continue;
+      const cv_buf brow = cv_buffer(row, 4u * n);
+      int vb = 4 * lane;
+      cv_opaque(vb);
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        const int j = lane + 64 * e;
-        if (j < n) sc[e] += beta[k] * fabs((double)row[j]);
+        sc[e] += beta[k] * fabs((double)buf_f32(brow, vb + 256 * e));
       }
     }
 #pragma unroll
@@ -279,10 +313,11 @@ __global__ __launch_bounds__(256, 2) void k_ca_rows(int R, int M, int n, CvCons 
                                                  float* lb, float* beta_out, int write_xstar) {
   __shared__ double sbeta[4 * CA_KMAX];
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= R) return;
   const int b = r / M;
   double* arow = Ax + (size_t)r * n;
+  const cv_buf ba = cv_buffer(arow, 8u * n);
   if (infeasible && infeasible[b]) {
     if (lane == 0) lb[r] = INFINITY;
     return;
@@ -291,7 +326,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_rows(int R, int M, int n, CvCons 
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int j = lane + 64 * e;
-    a[e] = j < n ? arow[j] : 0.0;
+    a[e] = buf_f64(ba, 8 * j);
   }
   bool empty;
   const double L = ca_core<EPL>(lane, n, a, rowc[r], rowerr[r], lo + (size_t)b * n, hi + (size_t)b * n,
@@ -317,7 +352,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
                                                     float* beta_out, uint8_t* infeasible) {
   __shared__ double sbeta[4 * CA_KMAX];
   const int lane = threadIdx.x & 63;
-  const long long pid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (pid >= (long long)B * P) return;
   const int b = (int)(pid / P), p = (int)(pid % P);
   const size_t arow = A_shared ? (size_t)p : (size_t)pid;
@@ -327,16 +362,15 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
   const float* hb_ = hi + (size_t)b * n;
   double a[EPL];
   double dmin = 0.0, dmax = 0.0, ea = 0.0;
+  const cv_buf bap = cv_buffer(ap, 4u * n), blb = cv_buffer(lb_, 4u * n), bhb = cv_buffer(hb_, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int j = lane + 64 * e;
-    a[e] = j < n ? (double)ap[j] : 0.0;
-    if (j < n) {
-      const double x0 = (double)lb_[j], x1 = (double)hb_[j];
-      dmin += fmin(a[e] * x0, a[e] * x1);
-      dmax += fmax(a[e] * x0, a[e] * x1);
-      ea += fabs(a[e]) * fmax(fabs(x0), fabs(x1));
-    }
+    a[e] = (double)buf_f32(bap, 4 * j);
+    const double x0 = (double)buf_f32(blb, 4 * j), x1 = (double)buf_f32(bhb, 4 * j);
+    dmin += fmin(a[e] * x0, a[e] * x1);
+    dmax += fmax(a[e] * x0, a[e] * x1);
+    ea += fabs(a[e]) * fmax(fabs(x0), fabs(x1));
   }
   dmin = wave_sum(dmin);
   dmax = wave_sum(dmax);
@@ -373,7 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
                                                     float* Ltmp) {
   __shared__ double sbeta[4 * CA_KMAX];
   const int lane = threadIdx.x & 63;
-  const long long pid = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (pid >= (long long)B * U * 2) return;
   const int side = (int)(pid & 1);
   const long long bc = pid >> 1;
@@ -387,10 +421,12 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   const float* ap = (side ? A_hi : A_lo) + (size_t)j * n;
   const double c = side ? -(double)c_hi[j] : (double)c_lo[j];
   double a[EPL];
+  const cv_buf bap = cv_buffer(ap, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const int jj = lane + 64 * e;
-    a[e] = jj < n ? (side ? -(double)ap[jj] : (double)ap[jj]) : 0.0;
+    const double v = (double)buf_f32(bap, 4 * jj);
+    a[e] = side ? -v : v;
   }
   bool empty;
   const double L = ca_core<EPL>(lane, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n, &cons, b,
