@@ -29,28 +29,49 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int GBM = 64, GBN = 256, GBK = 16;
+constexpr int GBK = 16;
 constexpr int NWAVE = 4;
-constexpr int WN = GBN / NWAVE;  // columns per wave
-constexpr int MI = GBM / 16;
-constexpr int NI = WN / 16;
-constexpr int SA_LD = GBM + 2;   // float64 elements per staged k-row of A
-constexpr int SB_LD = GBN + 16;  // float32 elements per staged k-row of B (rows 64 B apart in banks)
 constexpr int NSUM_MAX = 3;
+
+// Output tile of one workgroup: BM rows x BN columns (4 waves side by side).
+template <int BM_, int BN_>
+struct Tile {
+  static constexpr int BM = BM_, BN = BN_;
+  static constexpr int WN = BN / NWAVE;   // columns per wave
+  static constexpr int MI = BM / 16;
+  static constexpr int NI = WN / 16;
+  static constexpr int SA_LD = BM + 2;    // float64 elements per staged k-row of A
+  static constexpr int SB_LD = BN + 16;   // float32 elements per staged k-row of B (rows 64 B apart in banks)
+  static constexpr int APT = BM * GBK / 256;  // A elements staged per thread
+  static constexpr int BPT = BN * GBK / 256;  // B elements staged per thread
+  static_assert(APT == 2 || APT == 4 || APT == 8, "A staging");
+  static_assert(BPT % 4 == 0 && BPT <= 16, "B staging");
+};
+// 64 x 128: 4 x 2 MFMA blocks per wave keep the accumulators at 64 registers,
+// so the fused epilogues fit beside them without spilling, and twice the
+// workgroups of a 64 x 256 tile (one more pass over A, which is cheap) even
+// out the last round of workgroups.  Measured at 147456 x 256 x 256: main
+// loop 76 % of the float64 MFMA peak vs 67 % with 64 x 256.
+typedef Tile<64, 128> TileDefault;
 
 // A loaders return 4 consecutive k of one row (zeros outside [0,R) x [0,K)).
 struct LoadF64 {
   const double* p;
   int ld;
-  __device__ __forceinline__ void load4(int r, int k, int R, int K, double (&v)[4]) const {
-    if (r < R && k + 3 < K && (ld & 1) == 0) {
+  template <int NV>
+  __device__ __forceinline__ void load(int r, int k, int R, int K, double (&v)[NV]) const {
+    if (r < R && k + NV - 1 < K && (ld & 1) == 0) {
       const double2* q = reinterpret_cast<const double2*>(p + (size_t)r * ld + k);
-      const double2 x = q[0], y = q[1];
-      v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+#pragma unroll
+      for (int t = 0; t < NV / 2; ++t) {
+        const double2 x = q[t];
+        v[2 * t] = x.x;
+        v[2 * t + 1] = x.y;
+      }
       return;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (r < R && k + t < K) ? p[(size_t)r * ld + k + t] : 0.0;
+    for (int t = 0; t < NV; ++t) v[t] = (r < R && k + t < K) ? p[(size_t)r * ld + k + t] : 0.0;
   }
 };
 
@@ -59,15 +80,21 @@ struct LoadBox {
   const float* lo;
   const float* hi;
   int n0;
-  __device__ __forceinline__ void load4(int r, int k, int R, int K, double (&v)[4]) const {
-    if (r < R && (n0 & 3) == 0 && k + 3 < K) {
+  template <int NV>
+  __device__ __forceinline__ void load(int r, int k, int R, int K, double (&v)[NV]) const {
+    static_assert(NV % 2 == 0, "pairs");
+    if (r < R && (n0 % NV) == 0 && k + NV - 1 < K) {
       const float* src = k < n0 ? lo + (size_t)r * n0 + k : hi + (size_t)r * n0 + (k - n0);
-      const float4 x = *reinterpret_cast<const float4*>(src);
-      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+#pragma unroll
+      for (int t = 0; t < NV / 2; ++t) {
+        const float2 x = reinterpret_cast<const float2*>(src)[t];
+        v[2 * t] = x.x;
+        v[2 * t + 1] = x.y;
+      }
       return;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NV; ++t) {
       const int kk = k + t;
       v[t] = (r < R && kk < K)
                  ? (kk < n0 ? (double)lo[(size_t)r * n0 + kk] : (double)hi[(size_t)r * n0 + (kk - n0)])
@@ -76,30 +103,33 @@ struct LoadBox {
   }
 };
 
-// 16 consecutive columns of one row of B (zeros outside).
-__device__ __forceinline__ void load_b16(const float* __restrict__ Bm, int ldb, int gk, int gc, int K,
-                                         int N, float (&v)[16]) {
+// NV consecutive columns of one row of B (zeros outside).
+template <int NV>
+__device__ __forceinline__ void load_bn(const float* __restrict__ Bm, int ldb, int gk, int gc, int K,
+                                        int N, float (&v)[NV]) {
   const float* row = Bm + (size_t)gk * ldb + gc;
-  if (gk < K && gc + 15 < N && (ldb & 3) == 0) {
+  if (gk < K && gc + NV - 1 < N && (ldb & 3) == 0) {
     const float4* q = reinterpret_cast<const float4*>(row);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NV / 4; ++t) {
       const float4 x = q[t];
       v[4 * t] = x.x; v[4 * t + 1] = x.y; v[4 * t + 2] = x.z; v[4 * t + 3] = x.w;
     }
     return;
   }
 #pragma unroll
-  for (int t = 0; t < 16; ++t) v[t] = (gk < K && gc + t < N) ? row[t] : 0.0f;
+  for (int t = 0; t < NV; ++t) v[t] = (gk < K && gc + t < N) ? row[t] : 0.0f;
 }
 
 // Software pipeline: while the MFMAs consume K-chunk c from one LDS buffer,
 // the global loads of chunk c+1 are in flight into registers; they are
 // written to the other buffer afterwards, one barrier per chunk.
-template <class LoadA, class Epi>
-__global__ __launch_bounds__(256, 2) void k_gemm(int R, int K, int N, LoadA la,
-                                                 const float* __restrict__ Bm, int ldb, Epi epi,
-                                                 double* __restrict__ part, int ntiles) {
+template <class T, int OCC, class LoadA, class Epi>
+__global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la,
+                                                   const float* __restrict__ Bm, int ldb, Epi epi,
+                                                   double* __restrict__ part, int ntiles) {
+  constexpr int GBM = T::BM, GBN = T::BN, WN = T::WN, MI = T::MI, NI = T::NI;
+  constexpr int SA_LD = T::SA_LD, SB_LD = T::SB_LD, APT = T::APT, BPT = T::BPT;
   __shared__ double sA[2][GBK * SA_LD];
   __shared__ float sB[2][GBK * SB_LD];
   __shared__ double sRed[NWAVE * GBM * NSUM_MAX];
@@ -115,19 +145,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int R, int K, int N, LoadA la,
   int nblk = (N - (n0 + wave * WN) + 15) / 16;
   nblk = nblk < 0 ? 0 : (nblk > NI ? NI : nblk);
 
-  const int ar = tid >> 2, akq = (tid & 3) * 4;   // A staging: row, first k
-  const int bk = tid >> 4, bc0 = (tid & 15) * 16; // B staging: k, first column
-  double pa[4];
-  float pb[16];
+  constexpr int AQ = GBK / APT;                        // threads per staged row of A
+  const int ar = tid / AQ, akq = (tid % AQ) * APT;     // A staging: row, first k
+  const int bk = tid >> 4, bc0 = (tid & 15) * BPT;     // B staging: k, first column
+  double pa[APT];
+  float pb[BPT];
   auto fetch = [&](int k0) {
-    la.load4(m0 + ar, k0 + akq, R, K, pa);
-    load_b16(Bm, ldb, k0 + bk, n0 + bc0, K, N, pb);
+    la.template load<APT>(m0 + ar, k0 + akq, R, K, pa);
+    load_bn<BPT>(Bm, ldb, k0 + bk, n0 + bc0, K, N, pb);
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sA[buf][(akq + q) * SA_LD + ar] = pa[q];
+    for (int q = 0; q < APT; ++q) sA[buf][(akq + q) * SA_LD + ar] = pa[q];
 #pragma unroll
-    for (int q = 0; q < 16; q += 4)
+    for (int q = 0; q < BPT; q += 4)
       *reinterpret_cast<float4*>(&sB[buf][bk * SB_LD + bc0 + q]) =
           make_float4(pb[q], pb[q + 1], pb[q + 2], pb[q + 3]);
   };
@@ -398,19 +429,20 @@ struct EpiAdj {
   }
 };
 
-template <class LoadA, class Epi>
+template <class T = TileDefault, int OCC = 2, class LoadA, class Epi>
 hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi epi,
                     double* part, hipStream_t s) {
   if (R <= 0 || N <= 0) return hipSuccess;
-  const int nt = (N + GBN - 1) / GBN;
-  dim3 grid((R + GBM - 1) / GBM, nt);
-  hipLaunchKernelGGL((k_gemm<LoadA, Epi>), grid, dim3(256), 0, s, R, K, N, la, Bm, ldb, epi, part, nt);
+  const int nt = (N + T::BN - 1) / T::BN;
+  dim3 grid((R + T::BM - 1) / T::BM, nt);
+  hipLaunchKernelGGL((k_gemm<T, OCC, LoadA, Epi>), grid, dim3(256), 0, s, R, K, N, la, Bm, ldb, epi,
+                     part, nt);
   return hipGetLastError();
 }
 
 }  // namespace
 
-int gemm_ntiles(int N) { return (N + GBN - 1) / GBN; }
+int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
 
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
                              int off, const float2* tab, const float* alpha,
