@@ -11,13 +11,14 @@
 //   * adjoint of the backward pass for the slope gradient, with the Adam
 //     step on alpha fused in.
 //
-// Tiling: a 256-thread workgroup (4 waves) computes a 64 x 256 output tile;
-// wave w owns columns [64 w, 64 w + 64) of the tile and all 64 rows, i.e.
-// 4 x 4 MFMA blocks of 16 x 16 (64 float64 accumulators per lane).  The K
+// Tiling: a 256-thread workgroup (4 waves) computes a BM x BN output tile
+// (Tile<BM, BN>); wave w owns columns [w BN/4, (w+1) BN/4) of the tile and
+// all BM rows, i.e. (BM/16) x (BN/64) MFMA blocks of 16 x 16.  The K
 // dimension is staged through LDS in chunks of 16 (A as float64, B as
-// float32 converted when the fragment is formed).  B (the weights or the
-// plane matrix) is shared by all subdomains and stays L2/MALL resident; A
-// (per-row coefficients) is streamed from HBM once per 256 output columns.
+// float32 converted when the fragment is formed), double-buffered.  B (the
+// weights or the plane matrix) is shared by all subdomains and stays
+// L2/MALL resident; A (per-row coefficients) is streamed from HBM once per
+// BN output columns.
 //
 // MFMA operand layout (16x16x4, float64; measured on gfx950): lane L supplies
 // A[L%16][L/16] and B[L/16][L%16]; accumulator element v of lane L is
@@ -47,12 +48,18 @@ struct Tile {
   static_assert(APT == 2 || APT == 4 || APT == 8, "A staging");
   static_assert(BPT % 4 == 0 && BPT <= 16, "B staging");
 };
-// 64 x 128: 4 x 2 MFMA blocks per wave keep the accumulators at 64 registers,
-// so the fused epilogues fit beside them without spilling, and twice the
-// workgroups of a 64 x 256 tile (one more pass over A, which is cheap) even
-// out the last round of workgroups.  Measured at 147456 x 256 x 256: main
-// loop 76 % of the float64 MFMA peak vs 67 % with 64 x 256.
-typedef Tile<64, 128> TileDefault;
+// Tile shapes, measured at the 784-256x6 shapes (147456 rows x 256 columns):
+// narrow tiles keep the accumulators small (32 x 128: 2 x 2 MFMA blocks per
+// wave, 16 doubles per lane), so the fused epilogues fit without
+// spilling and several workgroups share a CU; their epilogues then overlap
+// the other workgroups' MFMA work.  Backward, final and adjoint GEMMs:
+// 32 x 128 (main loop 73-81 % of the float64 MFMA peak, vs 67-72 % with
+// 64 x 256).  The plane re-concretization (K = 2 n0, N = 2 U, few rows)
+// prefers 64 x 128.  Both have 128 columns, which fixes the number of
+// column tiles that the row-sum partials are laid out for.
+typedef Tile<32, 128> TileDefault;
+typedef Tile<64, 128> TilePlanes;
+static_assert(TileDefault::BN == TilePlanes::BN, "row-sum partials assume one column tiling");
 
 // A loaders return 4 consecutive k of one row (zeros outside [0,R) x [0,K)).
 struct LoadF64 {
@@ -464,7 +471,7 @@ hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float
                               const int32_t* uidx, const float* l0, const float* u0, int Nh,
                               float* l, float* u, hipStream_t s) {
   EpiPlanes e{U, Nh, cP, eP, uidx, l0, u0, l, u};
-  return run_gemm(B, 2 * n0, 2 * U, LoadBox{lo, hi, n0}, P, 2 * U, e, nullptr, s);
+  return run_gemm<TilePlanes>(B, 2 * n0, 2 * U, LoadBox{lo, hi, n0}, P, 2 * U, e, nullptr, s);
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
