@@ -6,7 +6,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "../../include/clipverify.h"
+#include "clipverify.h"
 #include "cv_common.h"
 #include "cv_internal.h"
 

@@ -66,16 +66,18 @@ __device__ __forceinline__ void cons_row(const CvCons& c, int b, int k, int n, c
 // odd rounds the midpoint, so the interval at least halves every two rounds.
 // A probe takes the largest candidate p at or below the split point; W(> p)
 // decides the side and, only when W(> p) <= S, W(>= p) > S identifies p = q*.
+// The breakpoints and weights sit in this wave's LDS slice (element e of lane
+// L at e*64 + L; non-candidates hold -inf), which keeps them out of the
+// registers of the common path that needs no search.
 template <int EPL>
-__device__ double ca_select(const double (&q)[EPL], const float (&wf)[EPL], uint32_t cand, double S,
-                            double wpos) {
+__device__ double ca_select(const double* sq, const float* sw, int lane, double S, double wpos) {
   double qmax = -INFINITY, qmin = INFINITY;
 #pragma unroll
-  for (int e = 0; e < EPL; ++e)
-    if ((cand >> e) & 1u) {
-      qmax = fmax(qmax, q[e]);
-      qmin = fmin(qmin, q[e]);
-    }
+  for (int e = 0; e < EPL; ++e) {
+    const double q = sq[e * 64 + lane];
+    qmax = fmax(qmax, q);
+    if (q > 0.0) qmin = fmin(qmin, q);
+  }
   qmax = wave_max(qmax);
   qmin = wave_min(qmin);
   unsigned long long blo = (unsigned long long)__double_as_longlong(qmin) - 1ull;
@@ -96,27 +98,29 @@ __device__ double ca_select(const double (&q)[EPL], const float (&wf)[EPL], uint
     const double mv = __longlong_as_double((long long)(blo + off));
     double p = -INFINITY;
 #pragma unroll
-    for (int e = 0; e < EPL; ++e)
-      if (((cand >> e) & 1u) && q[e] > lo_v && q[e] <= mv) p = fmax(p, q[e]);
+    for (int e = 0; e < EPL; ++e) {
+      const double q = sq[e * 64 + lane];
+      if (q > lo_v && q <= mv) p = fmax(p, q);
+    }
     p = wave_max(p);
     if (p == -INFINITY) {  // no candidate in (lo, mv]: W(> mv) = W(> lo)
       blo += off;
       continue;
     }
-    double wg = 0.0;
+    double wg = 0.0, wge = 0.0;
 #pragma unroll
-    for (int e = 0; e < EPL; ++e)
-      if (((cand >> e) & 1u) && q[e] > p) wg += (double)wf[e];
+    for (int e = 0; e < EPL; ++e) {
+      const double q = sq[e * 64 + lane];
+      const double w = (double)sw[e * 64 + lane];
+      if (q > p) wg += w;
+      if (q >= p) wge += w;
+    }
     wg = wave_sum(wg);
     if (wg > S) {  // q* > p, and nothing lies in (p, mv]
       blo += off;
       wlo = wg;
       continue;
     }
-    double wge = 0.0;
-#pragma unroll
-    for (int e = 0; e < EPL; ++e)
-      if (((cand >> e) & 1u) && q[e] >= p) wge += (double)wf[e];
     wge = wave_sum(wge);
     if (wge > S) return p;
     bhi = (unsigned long long)__double_as_longlong(p);
@@ -147,7 +151,7 @@ template <int EPL>
 __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_in,
                           const float* lo_b, const float* hi_b, const CvCons* cons, int b,
                           int passes, bool& empty, float* beta_out, double* xstar,
-                          double* beta) {
+                          double* beta, double* sq, float* sw) {
   float xl[EPL], xh[EPL];
   double Ea = 0.0;
   const cv_buf blo = cv_buffer(lo_b, 4u * n), bhi = cv_buffer(hi_b, 4u * n);
@@ -199,16 +203,15 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
       // (products of float32 values are exact in float64, so
       // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly)
       double m = 0.0, em = 0.0, wsg = 0.0;
-      float wf[EPL];
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const double gg = (double)g[e];
         const float xs = g[e] >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
         m += gg * (double)xs;
         em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
-        wf[e] = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+        const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
         const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
-        if (opp && wf[e] > 0.0f) wsg += (double)wf[e];
+        if (opp && wf > 0.0f) wsg += (double)wf;
       }
       wave_sum3(m, em, wsg);
       m += h;
@@ -228,23 +231,26 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
       double bk = 0.0;
       if (wsg > S) {
         // breakpoints and the exact candidate set (a division may underflow
-        // to q = 0, which is not a candidate)
-        double q[EPL];
-        uint32_t cand = 0;
+        // to q = 0, which is not a candidate), staged in LDS for the search
         double wpos = 0.0;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          q[e] = 0.0;
+          double qe = -INFINITY;
+          float we = 0.0f;
           if (g[e] != 0.0f) {
-            q[e] = -a[e] / (double)g[e];
-            if (q[e] > 0.0 && wf[e] > 0.0f) {
-              cand |= 1u << e;
-              wpos += (double)wf[e];
+            const double q = -a[e] / (double)g[e];
+            const float w = (float)(fabs((double)g[e]) * ((double)xh[e] - (double)xl[e]));
+            if (q > 0.0 && w > 0.0f) {
+              qe = q;
+              we = w;
+              wpos += (double)w;
             }
           }
+          sq[e * 64 + lane] = qe;
+          sw[e * 64 + lane] = we;
         }
         wpos = wave_sum(wpos);
-        if (wpos > S) bk = ca_select<EPL>(q, wf, cand, S, wpos);
+        if (wpos > S) bk = ca_select<EPL>(sq, sw, lane, S, wpos);
       }
       beta[k] = bk;
       if (bk != 0.0) {
@@ -270,13 +276,15 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (Ea + Eb + cabs) + e_in) * CV_ERR_SLACK;
   if (beta_out && lane < cons->kmax) beta_out[lane] = lane < cnt ? (float)beta[lane] : 0.0f;
   if (xstar) {
-    // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|)
-    double sc[EPL];
+    // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|); the scale
+    // only sets a threshold far from both sides of the test, so float32
+    // holds it (a kink leaves |a'_j| at rounding level, ~2^-50 of the scale)
+    float sc[EPL];
     const cv_buf bx = cv_buffer(xstar, 8u * n);
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int j = lane + 64 * e;
-      sc[e] = fabs(buf_f64(bx, 8 * j));
+      sc[e] = (float)fabs(buf_f64(bx, 8 * j));
     }
     for (int k = 0; k < cnt; ++k) {
       if (beta[k] == 0.0) continue;
@@ -287,14 +295,14 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
       cv_opaque(vb);
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        sc[e] += beta[k] * fabs((double)buf_f32(brow, vb + 256 * e));
+        sc[e] += (float)beta[k] * fabsf(buf_f32(brow, vb + 256 * e));
       }
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int j = lane + 64 * e;
       if (j < n) {
-        const bool kink = fabs(a[e]) <= 9.094947017729282e-13 * sc[e];  // 2^-40
+        const bool kink = fabs(a[e]) <= 9.094947017729282e-13 * (double)sc[e];  // 2^-40
         xstar[j] = kink ? 0.5 * ((double)xl[e] + (double)xh[e])
                         : (a[e] > 0.0 ? (double)xl[e] : (double)xh[e]);
       }
@@ -305,13 +313,15 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
 
 // Final planes: rows r = (b, m) of the backward pass output.
 template <int EPL>
-__global__ __launch_bounds__(256, 2) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
+__global__ __launch_bounds__(256, 3) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
                                                  double* Ax, const double* __restrict__ rowc,
                                                  const double* __restrict__ rowerr,
                                                  const float* __restrict__ lo,
                                                  const float* __restrict__ hi, uint8_t* infeasible,
                                                  float* lb, float* beta_out, int write_xstar) {
   __shared__ double sbeta[4 * CA_KMAX];
+  __shared__ double sq[4 * 64 * EPL];
+  __shared__ float sw[4 * 64 * EPL];
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (r >= R) return;
@@ -332,7 +342,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_rows(int R, int M, int n, CvCons 
   const double L = ca_core<EPL>(lane, n, a, rowc[r], rowerr[r], lo + (size_t)b * n, hi + (size_t)b * n,
                                 &cons, b, passes, empty,
                                 beta_out ? beta_out + (size_t)r * cons.kmax : nullptr,
-                                write_xstar ? arow : nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX);
+                                write_xstar ? arow : nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX,
+                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
   if (lane == 0) {
     if (empty) {
       lb[r] = INFINITY;
@@ -351,6 +362,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
                                                     int has_cons, int passes, float* lb, float* ub,
                                                     float* beta_out, uint8_t* infeasible) {
   __shared__ double sbeta[4 * CA_KMAX];
+  __shared__ double sq[4 * 64 * EPL];
+  __shared__ float sw[4 * 64 * EPL];
   const int lane = threadIdx.x & 63;
   const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (pid >= (long long)B * P) return;
@@ -381,7 +394,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
   if (has_cons) {
     const double L = ca_core<EPL>(lane, n, a, c, 0.0, lb_, hb_, &cons, b, passes, empty,
                                   beta_out ? beta_out + (size_t)pid * cons.kmax : nullptr, nullptr,
-                                  sbeta + (threadIdx.x >> 6) * CA_KMAX);
+                                  sbeta + (threadIdx.x >> 6) * CA_KMAX,
+                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
     if (!empty) out = fmaxf(out, rd32(L));
   }
   if (lane == 0) {
@@ -406,6 +420,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
                                                     const uint8_t* __restrict__ infeasible,
                                                     float* Ltmp) {
   __shared__ double sbeta[4 * CA_KMAX];
+  __shared__ double sq[4 * 64 * EPL];
+  __shared__ float sw[4 * 64 * EPL];
   const int lane = threadIdx.x & 63;
   const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (pid >= (long long)B * U * 2) return;
@@ -430,7 +446,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   }
   bool empty;
   const double L = ca_core<EPL>(lane, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n, &cons, b,
-                                passes, empty, nullptr, nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX);
+                                passes, empty, nullptr, nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX,
+                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
   if (lane == 0) Ltmp[pid] = empty ? INFINITY : rd32(L);
 }
 
