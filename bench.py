@@ -102,7 +102,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--workload", default="mlp784-256x6-10",
+                    choices=["mlp784-256x6-10", "mlp784-1024x4-10"],
+                    help="784-256x6-10 (16384 x 4 splits, the metric's workload) or "
+                         "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024)")
+    ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--alpha-steps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,9 +136,15 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 5 copies of {n} bytes")
         return
-    B, T = args.batch, args.alpha_steps
-    w = wl.mnist_mlp(B)
-    log(f"workload {w.name}: B={B}, k=4, M={w.C.shape[0]}, alpha steps={T}")
+    T = args.alpha_steps
+    if args.workload == "mlp784-256x6-10":
+        B = args.batch or 16384
+        w = wl.mnist_mlp(B)
+    else:
+        B = args.batch or 8192
+        w = wl.alpha_mlp(B)
+    ksplit = int(w.split_counts[0])
+    log(f"workload {w.name}: B={B}, k={ksplit}, M={w.C.shape[0]}, alpha steps={T}")
     t0 = time.perf_counter()
     prop = gpipe.Property.from_workload(w)
     l0, u0 = (x.cpu().numpy() for x in prop.root.bounds())
@@ -228,7 +238,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {B} subdomains x 4 splits, 9 margin rows, "
+        "config": {"workload": f"{w.name}: {B} subdomains x {ksplit} splits, 9 margin rows, "
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
                    "global_batch": B, "alpha_steps": T, "io_dtype": "f32"},
         "plain": {"value": round(B / plain_s, 1), "unit": "subdomains/s",

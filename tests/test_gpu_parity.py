@@ -345,3 +345,43 @@ def test_invalid_arguments_are_rejected_before_launch():
     st = N.lib().cv_clip_domains(prop.root.handle, 2, 5, None, api._p(lo), api._p(hi), None, 7,
                                  api._stream())
     assert st == -1
+
+
+def _alpha_opt_sampled(w, n_sample, steps, seed, rel_plain=1e-5, rel_alpha=1e-4):
+    """The bench schedule (plain pass + `steps` slope iterations, lr 0.1) on the
+    whole batch; the oracle repeats it on sampled subdomains (the iterations
+    of one subdomain do not depend on the others)."""
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=steps,
+                              lr=0.1)
+    sync()
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w.B, n_sample, replace=False))
+    ref = op.run(subset_splits(sp, idx))
+    assert_close(H(out["lb"])[idx], ref["lb"], rel_plain, "plain lb (sampled)")
+    fe = ~ref["infeasible"]
+    assert np.array_equal(H(out["infeasible"])[idx].astype(bool), ref["infeasible"])
+    l_list = opipe.split_layers(op.layers, ref["l"][fe])
+    u_list = opipe.split_layers(op.layers, ref["u"][fe])
+    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
+                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=steps, lr=0.1)
+    g = H(best)[idx][fe]
+    assert_close(g, obest, rel_alpha, "alpha-opt best bound (sampled)")
+    assert np.all(g >= H(out["lb"])[idx][fe] - 1e-6 * np.maximum(np.abs(g), 1))
+    return g, H(out["lb"])[idx][fe]
+
+
+def test_full_size_mnist_alpha_opt_sampled():
+    # 784-256x6-10, 16384 subdomains x 4 splits, 20 slope iterations (bench step)
+    g, plain = _alpha_opt_sampled(wl.mnist_mlp(B=16384), 6, 20, seed=11)
+    assert (g > plain + 1.0).any()
+
+
+def test_full_size_alpha_mlp_sampled():
+    # 784-1024x4-10, 8192 subdomains x 6 splits, alpha0 0.5, 20 Adam steps lr 0.1
+    g, plain = _alpha_opt_sampled(wl.alpha_mlp(B=8192), 4, 20, seed=12)
+    assert (g > plain + 1.0).any()
