@@ -65,6 +65,7 @@ class Config:
     complete_final: bool = True      # step (7)
     ca_passes: int = 1
     alpha: float = 0.5
+    order: bool = False              # constraint importance order (heuristics appendix)
 
 
 def split_constraints(root, neuron, sign, count):
@@ -81,6 +82,35 @@ def split_constraints(root, neuron, sign, count):
     G = np.where(active[..., None], G, 0.0)
     h = np.where(active, h, 0.0)
     return G, h, active
+
+
+def constraint_order(G, h, active, lo, hi):
+    """Constraint importance order of the heuristics appendix: the distance
+    d = |g.xc + h| / ||g||_2 of each constraint's hyperplane from the centre xc
+    of the box, ascending (closest first); ties keep the list order.  Inactive
+    slots and rows with g = 0 (no hyperplane) go last.  Returns order [B, k]:
+    position -> constraint index.
+
+    Readings taken: the centre is that of the box the constraints are applied
+    to at that step (the original box for sequential relaxed clipping, the
+    clipped box for complete clipping).  The paper also drops redundant
+    constraints (satisfied on the whole box) and flags empty ones; neither
+    changes a result here (a redundant constraint clips nothing and gets a
+    zero multiplier, an empty one is detected where it is applied), so the
+    order is all this step produces."""
+    xc = 0.5 * (f64(lo) + f64(hi))
+    num = np.abs(np.einsum("bkn,bn->bk", G, xc) + h)
+    nrm = np.sqrt(np.einsum("bkn,bkn->bk", G, G))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d = np.where(nrm > 0.0, num / np.where(nrm > 0.0, nrm, 1.0), np.inf)
+    d = np.where(active, d, np.inf)
+    return np.argsort(d, axis=1, kind="stable")
+
+
+def apply_order(order, G, h, active):
+    """Constraint list permuted to ``order`` (position -> constraint index)."""
+    return (np.take_along_axis(G, order[..., None], axis=1), np.take_along_axis(h, order, axis=1),
+            np.take_along_axis(active, order, axis=1))
 
 
 def reconcretize(root, lo, hi):
@@ -163,9 +193,17 @@ def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=Non
     if cfg.relaxed == "parallel":
         lo2, hi2, inf_clip = rx.clip_parallel(G, h, lo, hi, act)
     elif cfg.relaxed == "sequential":
-        lo2, hi2, inf_clip = rx.clip_sequential(G, h, lo, hi, act)
+        Gs, hs, acts = G, h, act
+        if cfg.order:
+            Gs, hs, acts = apply_order(constraint_order(G, h, act, lo, hi), G, h, act)
+        lo2, hi2, inf_clip = rx.clip_sequential(Gs, hs, lo, hi, acts)
     else:
         lo2, hi2, inf_clip = lo.copy(), hi.copy(), np.zeros(lo.shape[0], bool)
+    if cfg.order:
+        # complete clipping (and the slope steps after it) take the
+        # constraints closest to the clipped box's centre first
+        out["order"] = constraint_order(G, h, act, lo2, hi2)
+        G, h, act = apply_order(out["order"], G, h, act)
     out.update(G=G, h=h, active=act, lo=lo2, hi=hi2, infeasible_clip=inf_clip)
     # bounds are computed on the clipped box; an empty box keeps its values
     if cfg.reconcretize:

@@ -117,3 +117,31 @@ def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0
                                lr * decay ** (s - 1), ws=prop.ws)
         torch.maximum(best, lb, out=best)
     return best, alpha
+
+
+class AlphaBound(torch.autograd.Function):
+    """lb(alpha) [B, M] as a differentiable function of the slopes alpha
+    [B, M, n_hidden]: the forward pass runs the bound (backward pass,
+    concretization, complete clipping) and the hand-written adjoint kernel in
+    one call; backward scales the stored per-row gradient by the incoming
+    gradient (lb[b, m] depends only on alpha[b, m, :]).  The complete-
+    clipping multipliers are held at their optimum (Danskin)."""
+
+    @staticmethod
+    def forward(ctx, alpha, prop, batch, l, u, infeasible, complete, passes):
+        cons = batch.splits if complete else None
+        lb, grad = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha.detach(),
+                                  batch.lo, batch.hi, infeasible, cons, passes, want_grad=True,
+                                  ws=prop.ws)
+        ctx.save_for_backward(grad)
+        return lb
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g.unsqueeze(-1) * grad, None, None, None, None, None, None, None
+
+
+def bound(prop, batch, l, u, alpha, infeasible, complete=True, passes=1):
+    """Differentiable bound: ``bound(...).sum().backward()`` fills alpha.grad."""
+    return AlphaBound.apply(alpha, prop, batch, l, u, infeasible, complete, passes)

@@ -385,3 +385,39 @@ def test_full_size_alpha_mlp_sampled():
     # 784-1024x4-10, 8192 subdomains x 6 splits, alpha0 0.5, 20 Adam steps lr 0.1
     g, plain = _alpha_opt_sampled(wl.alpha_mlp(B=8192), 4, 20, seed=12)
     assert (g > plain + 1.0).any()
+
+
+def test_autograd_bound_matches_adjoint_and_fused_adam():
+    w = wl.tiny_mlp(64)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 2, bias="uniform")
+    op = OracleProp(w)
+    sp = wl.draw_splits(64, w.split_counts[:64], np.arange(w.net.n_hidden))
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(), opipe.Config(), op)
+    alpha = T(wl.random_alpha(64, 5, w.net.n_hidden, seed=9)).requires_grad_(True)
+    lb = gpipe.bound(prop, batch, out["l"], out["u"], alpha, out["infeasible"])
+    wts = T(np.random.default_rng(3).uniform(0.5, 2.0, (64, 5)))
+    fe = T(1.0 - H(out["infeasible"]).astype(np.float32))[:, None]
+    (torch.where(fe > 0, lb, torch.zeros_like(lb)) * wts).sum().backward()
+    _, g = api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], alpha.detach(),
+                          batch.lo, batch.hi, out["infeasible"], batch.splits, want_grad=True,
+                          ws=prop.ws)
+    sync()
+    m = H(fe).astype(bool)[:, 0]
+    assert np.allclose(H(alpha.grad)[m], (H(wts)[:, :, None] * H(g))[m], rtol=1e-6, atol=0)
+    assert np.count_nonzero(H(alpha.grad)) > 100
+    # torch's Adam (ascent, clamp to [0, 1]) through the autograd bound follows
+    # the Adam step fused into the adjoint kernel
+    a1 = alpha.detach().clone().requires_grad_(True)
+    a2 = alpha.detach().clone()
+    mm, vv = torch.zeros_like(a2), torch.zeros_like(a2)
+    opt = torch.optim.Adam([a1], lr=0.1, betas=(0.9, 0.999), eps=1e-8, maximize=True)
+    for s in range(1, 4):
+        opt.zero_grad()
+        gpipe.bound(prop, batch, out["l"], out["u"], a1, out["infeasible"]).sum().backward()
+        opt.step()
+        with torch.no_grad():
+            a1.clamp_(0.0, 1.0)
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], a2, batch.lo,
+                       batch.hi, out["infeasible"], batch.splits, 1, mm, vv, s, 0.1, ws=prop.ws)
+    sync()
+    assert np.abs(H(a1) - H(a2))[m].max() < 1e-4

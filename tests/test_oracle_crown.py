@@ -75,7 +75,9 @@ def tiny_setup(B=64, seed=0, bias="zero"):
 
 @pytest.mark.parametrize("cfg", [pipeline.Config(),
                                  pipeline.Config(relaxed="sequential", complete_intermediate=True),
-                                 pipeline.Config(split_fix=False, complete_final=False)])
+                                 pipeline.Config(split_fix=False, complete_final=False),
+                                 pipeline.Config(relaxed="sequential", complete_intermediate=True,
+                                                 order=True)])
 def test_pipeline_sound_with_true_split_pattern(cfg):
     w, layers, root = tiny_setup(bias="uniform")
     rng = np.random.default_rng(wl.SEED_SAMPLES)
