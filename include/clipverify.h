@@ -120,7 +120,13 @@ cv_status cv_root_unstable_count(cv_root root, int* count);
  * (branch z <= 0) gives A_lo[j].x + c_lo[j] <= 0, sign +1 (branch z >= 0)
  * gives -A_hi[j].x - c_hi[j] <= 0.
  * Dense form (neuron == NULL): slot k of subdomain b is G[b,k,:].x + h[b,k] <= 0.
- * Slots k < count[b] are used (count == NULL: all kmax).  All device. */
+ * Slots k < count[b] are used (count == NULL: all kmax).  All device.
+ * order (optional): [B, kmax] permutation, position -> slot, whose first
+ * count[b] entries are the used slots; sequential relaxed clipping and
+ * complete clipping take the constraints in that order (NULL: slot order).
+ * Entries outside [0, kmax) are ignored slots; a non-permutation gives
+ * unspecified bounds but no out-of-range access.  cv_constraint_order
+ * computes the importance order of the heuristics appendix. */
 typedef struct {
   int kmax;
   const int32_t* count;  /* [B] or NULL */
@@ -128,7 +134,20 @@ typedef struct {
   const int8_t* sign;    /* [B, kmax] +1 / -1 */
   const float* G;        /* [B, kmax, n] */
   const float* h;        /* [B, kmax] */
+  const int32_t* order;  /* [B, kmax] or NULL */
 } cv_constraints;
+
+/* Constraint importance order (heuristics appendix): for each subdomain,
+ * the used slots sorted by the Euclidean distance |g.xc + h| / ||g||_2 of
+ * their hyperplane from the centre xc = (lo + hi)/2 of its box, closest
+ * first; ties keep slot order, slots with g = 0 go last, unused slots keep
+ * their place.  cons->order is not read.  Computed in float64.
+ * lo, hi: device [B, n]; order: device output [B, kmax] (see cv_constraints).
+ * Errors: CV_E_UNSUPPORTED if kmax > 64; CV_E_SHAPE if the split form's
+ * root has another input size. */
+cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* cons,
+                              const float* lo, const float* hi, int32_t* order,
+                              hipStream_t stream);
 
 enum { CV_CLIP_PARALLEL = 0, CV_CLIP_SEQUENTIAL = 1 };
 

@@ -21,7 +21,8 @@ EXPORTS = [
     "cv_net_create", "cv_net_destroy", "cv_net_info",
     "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
     "cv_root_unstable_count",
-    "cv_clip_domains", "cv_concretize_planes", "cv_concretize_planes_workspace",
+    "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
+    "cv_concretize_planes_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
     "cv_alpha_step", "cv_alpha_step_workspace",
     "cv_profile_enable", "cv_profile_reset", "cv_profile_collect", "cv_profile_entry",
@@ -38,7 +39,8 @@ class LayerDesc(C.Structure):
 
 class Constraints(C.Structure):
     _fields_ = [("kmax", C.c_int), ("count", C.c_void_p), ("neuron", C.c_void_p),
-                ("sign", C.c_void_p), ("G", C.c_void_p), ("h", C.c_void_p)]
+                ("sign", C.c_void_p), ("G", C.c_void_p), ("h", C.c_void_p),
+                ("order", C.c_void_p)]
 
 
 class CvError(RuntimeError):
@@ -74,6 +76,7 @@ def lib():
         "cv_root_planes": (I, [P, P, P, P, P, P]),
         "cv_root_unstable_count": (I, [P, P]),
         "cv_clip_domains": (I, [P, I, I, P, P, P, P, I, P]),
+        "cv_constraint_order": (I, [P, I, I, P, P, P, P, P]),
         "cv_concretize_planes": (I, [P, I, P, P, P, I, I, P, P, P, P, S, P]),
         "cv_concretize_planes_workspace": (I, [P, I, I, P]),
         "cv_concretize": (I, [P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),

@@ -114,10 +114,17 @@ class Constraints:
     """Per-subdomain constraints: ``splits(neuron, sign, count)`` (activation
     splits resolved with a Root's planes) or ``dense(G, h, count)``."""
 
-    def __init__(self, kmax, count=None, neuron=None, sign=None, G=None, h=None):
+    def __init__(self, kmax, count=None, neuron=None, sign=None, G=None, h=None, order=None):
         self.kmax = int(kmax)
         self.count, self.neuron, self.sign, self.G, self.h = count, neuron, sign, G, h
-        self.struct = N.Constraints(self.kmax, _p(count), _p(neuron), _p(sign), _p(G), _p(h))
+        self.order = order
+        self.struct = N.Constraints(self.kmax, _p(count), _p(neuron), _p(sign), _p(G), _p(h),
+                                    _p(order))
+
+    def with_order(self, order):
+        """The same constraints taken in ``order`` ([B, kmax] int32, position
+        -> slot; None: slot order)."""
+        return Constraints(self.kmax, self.count, self.neuron, self.sign, self.G, self.h, order)
 
     @classmethod
     def splits(cls, neuron, sign, count=None):
@@ -140,6 +147,17 @@ class Constraints:
 
 def _cref(cons):
     return None if cons is None else cons.ref()
+
+
+def constraint_order(root, lo, hi, cons, out=None):
+    """Constraint importance order of each subdomain over boxes lo/hi [B, n]
+    (cv_constraint_order): returns int32 [B, kmax], position -> slot."""
+    B, n = lo.shape
+    order = out if out is not None else torch.empty(B, cons.kmax, dtype=torch.int32,
+                                                    device="cuda")
+    N.call("cv_constraint_order", root.handle if root is not None else None, B, n, _cref(cons),
+           _p(lo), _p(hi), _p(order), _stream())
+    return order
 
 
 class Workspace:

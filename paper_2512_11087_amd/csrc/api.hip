@@ -188,6 +188,7 @@ cv_status resolve_cons(const cv_root_s* root, const cv_constraints* c, CvCons* o
     out->G = c->G;
     out->h = c->h;
   }
+  out->order = c->order;
   return CV_OK;
 }
 
@@ -506,6 +507,22 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
   cv_status st = resolve_cons(root, cons, &c);
   if (st) return st;
   PLAUNCH("clip", 0, 16.0 * B * n + 4.0 * B * c.kmax * n, launch_clip(B, n, c, lo, hi, infeasible, mode, s));
+  return CV_OK;
+}
+
+cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* cons,
+                              const float* lo, const float* hi, int32_t* order, hipStream_t s) {
+  if (B < 0 || n <= 0) return CV_E_SHAPE;
+  if (!cons) return CV_E_INVALID;
+  if (B == 0 || cons->kmax == 0) return CV_OK;
+  if (!lo || !hi || !order) return CV_E_INVALID;
+  if (cons->kmax > 64) return CV_E_UNSUPPORTED;
+  if (cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
+  CvCons c;
+  cv_status st = resolve_cons(root, cons, &c);
+  if (st) return st;
+  c.order = nullptr;
+  PLAUNCH("cons_order", 0, 8.0 * B * n + 4.0 * B * c.kmax * n, launch_cons_order(B, n, c, lo, hi, order, s));
   return CV_OK;
 }
 

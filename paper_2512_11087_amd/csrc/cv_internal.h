@@ -50,6 +50,7 @@ struct CvCons {  // device view of cv_constraints (resolved)
   const float* h;
   const float* A_lo; const float* A_hi; const float* c_lo; const float* c_hi;  // split form
   int nplanes;  // rows of the plane table; split slots with other indices are ignored
+  const int32_t* order;  // [B, kmax] position -> slot, or null (list order)
 };
 
 // Number of used slots of subdomain b, clamped to [0, kmax].
@@ -58,6 +59,51 @@ __device__ __forceinline__ int cons_count(const CvCons& c, int b) {
   return k < 0 ? 0 : (k > c.kmax ? c.kmax : k);
 }
 
+// Slot processed at position `pos` of subdomain b (the constraint order, if
+// any; an index outside [0, kmax) yields -1, an ignored slot).
+__device__ __forceinline__ int cons_slot(const CvCons& c, int b, int pos) {
+  if (!c.order) return pos;
+  const int k = c.order[(size_t)b * c.kmax + pos];
+  return (k >= 0 && k < c.kmax) ? k : -1;
+}
+
+// Row, sign and offset of slot k of subdomain b as  scale * row . x + h <= 0
+// (row == null: the slot is ignored).  Split form: branch z <= 0 gives
+// A_lo x + c_lo <= 0, branch z >= 0 gives -A_hi x - c_hi <= 0 (eqs. 9-10).
+__device__ __forceinline__ void cons_row_slot(const CvCons& c, int b, int k, int n,
+                                              const float*& row, float& scale, double& h) {
+  row = nullptr;
+  scale = 0.0f;
+  h = 0.0;
+  if (k < 0) return;
+  const size_t s = (size_t)b * c.kmax + k;
+  if (c.neuron) {
+    const int j = c.neuron[s];
+    if (j < 0 || j >= c.nplanes) return;  // not a hidden neuron: slot ignored
+    if (c.sign[s] < 0) {
+      row = c.A_lo + (size_t)j * n;
+      scale = 1.0f;
+      h = (double)c.c_lo[j];
+    } else {
+      row = c.A_hi + (size_t)j * n;
+      scale = -1.0f;
+      h = -(double)c.c_hi[j];
+    }
+  } else {
+    row = c.G + s * n;
+    scale = 1.0f;
+    h = (double)c.h[s];
+  }
+}
+
+// The constraint at position pos (in the constraint order).
+__device__ __forceinline__ void cons_row(const CvCons& c, int b, int pos, int n, const float*& row,
+                                         float& scale, double& h) {
+  cons_row_slot(c, b, cons_slot(c, b, pos), n, row, scale, h);
+}
+
+hipError_t launch_cons_order(int B, int n, const CvCons& cons, const float* lo, const float* hi,
+                             int32_t* order, hipStream_t s);
 hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, uint8_t* infeasible,
                        int mode, hipStream_t s);
 

@@ -22,33 +22,6 @@ namespace {
 constexpr int CT = 256;
 constexpr int EPT = 16;  // coordinates per thread: n <= 4096
 
-__device__ __forceinline__ void load_cons_row(const CvCons& c, int b, int k, int n,
-                                              const float*& row, float& scale, double& h) {
-  const size_t s = (size_t)b * c.kmax + k;
-  if (c.neuron) {
-    const int j = c.neuron[s];
-    if (j < 0 || j >= c.nplanes) {  // not a hidden neuron: slot ignored
-      row = nullptr;
-      scale = 0.0f;
-      h = 0.0;
-      return;
-    }
-    if (c.sign[s] < 0) {  // branch z <= 0: A_lo x + c_lo <= 0
-      row = c.A_lo + (size_t)j * n;
-      scale = 1.0f;
-      h = (double)c.c_lo[j];
-    } else {              // branch z >= 0: -A_hi x - c_hi <= 0
-      row = c.A_hi + (size_t)j * n;
-      scale = -1.0f;
-      h = -(double)c.c_hi[j];
-    }
-  } else {
-    row = c.G + s * n;
-    scale = 1.0f;
-    h = (double)c.h[s];
-  }
-}
-
 __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
   a = wave_sum(a);
   b = wave_sum(b);
@@ -83,7 +56,7 @@ __global__ __launch_bounds__(CT) void k_clip(int B, int n, CvCons cons, float* l
     const float* row;
     float scale;
     double h;
-    load_cons_row(cons, b, k, n, row, scale, h);
+    cons_row(cons, b, k, n, row, scale, h);
     if (!row) continue;
     float g[EPT];
     double m = 0.0, e = 0.0;
@@ -134,7 +107,62 @@ __global__ __launch_bounds__(CT) void k_clip(int B, int n, CvCons cons, float* l
   if (tid == 0) infeasible[b] = (empty || bad) ? 1 : 0;
 }
 
+// Constraint importance order (heuristics appendix): position -> slot for
+// each subdomain, the used slots sorted by the distance |g.xc + h| / ||g||_2
+// of their hyperplane from the centre xc of the box, closest first; ties keep
+// the list order, slots without a hyperplane (g = 0, ignored) go last, unused
+// slots keep their place.  One wave per subdomain, lane k ranks slot k
+// (kmax <= 64); the sums are float64 (products of float32 values are exact).
+__global__ __launch_bounds__(256) void k_cons_order(int B, int n, CvCons cons,
+                                                    const float* __restrict__ lo,
+                                                    const float* __restrict__ hi, int32_t* order) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (b >= B) return;
+  const int kmax = cons.kmax;
+  const int cnt = cons_count(cons, b);
+  const float* lb = lo + (size_t)b * n;
+  const float* hb = hi + (size_t)b * n;
+  double mine = INFINITY;
+  for (int k = 0; k < cnt; ++k) {
+    const float* row;
+    float scale;
+    double h;
+    cons_row_slot(cons, b, k, n, row, scale, h);
+    double sv = 0.0, nn = 0.0;
+    if (row) {
+      for (int j = lane; j < n; j += 64) {
+        const double g = (double)(scale * row[j]);
+        sv += g * (0.5 * ((double)lb[j] + (double)hb[j]));
+        nn += g * g;
+      }
+    }
+    sv = wave_sum(sv);
+    nn = wave_sum(nn);
+    double d = (row && nn > 0.0) ? fabs(sv + h) / sqrt(nn) : INFINITY;
+    if (!(d == d)) d = INFINITY;
+    if (lane == k) mine = d;
+  }
+  int r = 0;
+  for (int j = 0; j < cnt; ++j) {
+    const double dj = lane_f64(mine, j);
+    r += (dj < mine || (dj == mine && j < lane)) ? 1 : 0;
+  }
+  if (lane < cnt)
+    order[(size_t)b * kmax + r] = lane;
+  else if (lane < kmax)
+    order[(size_t)b * kmax + lane] = lane;
+}
+
 }  // namespace
+
+hipError_t launch_cons_order(int B, int n, const CvCons& cons, const float* lo, const float* hi,
+                             int32_t* order, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (cons.kmax > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cons_order, dim3((B + 3) / 4), dim3(256), 0, s, B, n, cons, lo, hi, order);
+  return hipGetLastError();
+}
 
 hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, uint8_t* infeasible,
                        int mode, hipStream_t s) {

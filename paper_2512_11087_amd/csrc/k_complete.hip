@@ -31,33 +31,6 @@ namespace {
 
 constexpr int CA_KMAX = 64;
 
-__device__ __forceinline__ void cons_row(const CvCons& c, int b, int k, int n, const float*& row,
-                                         float& scale, double& h) {
-  const size_t s = (size_t)b * c.kmax + k;
-  if (c.neuron) {
-    const int j = c.neuron[s];
-    if (j < 0 || j >= c.nplanes) {  // not a hidden neuron: slot ignored
-      row = nullptr;
-      scale = 0.0f;
-      h = 0.0;
-      return;
-    }
-    if (c.sign[s] < 0) {
-      row = c.A_lo + (size_t)j * n;
-      scale = 1.0f;
-      h = (double)c.c_lo[j];
-    } else {
-      row = c.A_hi + (size_t)j * n;
-      scale = -1.0f;
-      h = -(double)c.c_hi[j];
-    }
-  } else {
-    row = c.G + s * n;
-    scale = 1.0f;
-    h = (double)c.h[s];
-  }
-}
-
 // Weighted quantile: the smallest candidate q* with W(> q*) <= S, where
 // W(> p) sums the weights of candidates above p.  The search keeps an open
 // interval (lo, hi) of float64 bit patterns with W(> lo) > S >= W(>= hi) and
@@ -274,7 +247,10 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   for (int e = 0; e < EPL; ++e) d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
   d = wave_sum(d) + c;
   const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (Ea + Eb + cabs) + e_in) * CV_ERR_SLACK;
-  if (beta_out && lane < cons->kmax) beta_out[lane] = lane < cnt ? (float)beta[lane] : 0.0f;
+  if (beta_out && lane < cons->kmax) {  // by slot: position o holds slot cons_slot(o)
+    const int slot = cons_slot(*cons, b, lane);
+    if (slot >= 0) beta_out[slot] = lane < cnt ? (float)beta[lane] : 0.0f;
+  }
   if (xstar) {
     // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|); the scale
     // only sets a threshold far from both sides of the test, so float32

@@ -25,6 +25,7 @@ class PassConfig:
     complete_final: bool = True
     passes: int = 1
     alpha: float = 0.5
+    order: bool = False             # constraint importance order (heuristics appendix)
 
 
 class Property:
@@ -54,6 +55,11 @@ class Batch:
     lo: torch.Tensor
     hi: torch.Tensor
     splits: api.Constraints
+    ordered: api.Constraints = None   # splits in importance order over the clipped box
+
+    def cons(self):
+        """The constraints as complete clipping takes them."""
+        return self.ordered if self.ordered is not None else self.splits
 
 
 def make_batch(prop, neuron, sign, count, lo=None, hi=None):
@@ -68,8 +74,14 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None):
     Returns dict(infeasible, l, u, lb)."""
     B = batch.lo.shape[0]
     out = out if out is not None else {}
+    clip_cons = batch.splits
+    if cfg.order and cfg.clip == "sequential":
+        # sequential clipping takes the constraints closest to the box centre first
+        clip_cons = batch.splits.with_order(
+            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order0")))
+        out["order0"] = clip_cons.order
     if cfg.clip != "none":
-        inf = api.clip_domains(prop.root, batch.lo, batch.hi, batch.splits, cfg.clip,
+        inf = api.clip_domains(prop.root, batch.lo, batch.hi, clip_cons, cfg.clip,
                                infeasible=out.get("infeasible"))
     else:
         inf = out.get("infeasible")
@@ -77,10 +89,16 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None):
             inf = torch.zeros(B, dtype=torch.uint8, device="cuda")
         else:
             inf.zero_()
-    l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, batch.splits,
+    batch.ordered = None
+    if cfg.order:
+        # complete clipping: the order over the clipped box
+        batch.ordered = batch.splits.with_order(
+            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order1")))
+        out["order1"] = batch.ordered.order
+    l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, batch.cons(),
                                       cfg.complete_intermediate, cfg.passes, inf,
                                       out.get("l"), out.get("u"), prop.ws2)
-    cons = batch.splits if cfg.complete_final else None
+    cons = batch.cons() if cfg.complete_final else None
     lb = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
                              None, cfg.alpha, inf, cons, cfg.passes, ws=prop.ws)
     out.update(infeasible=inf, l=l, u=u, lb=lb)
@@ -110,7 +128,7 @@ def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0
         best = torch.empty(B, M, device="cuda")
         state["best"] = best
     best.fill_(-float("inf"))
-    cons = batch.splits if complete else None
+    cons = batch.cons() if complete else None
     for s in range(1, steps + 1):
         lb, _ = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha, batch.lo,
                                batch.hi, infeasible, cons, passes, state["m"], state["v"], s,
@@ -129,7 +147,7 @@ class AlphaBound(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, alpha, prop, batch, l, u, infeasible, complete, passes):
-        cons = batch.splits if complete else None
+        cons = batch.cons() if complete else None
         lb, grad = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha.detach(),
                                   batch.lo, batch.hi, infeasible, cons, passes, want_grad=True,
                                   ws=prop.ws)

@@ -421,3 +421,39 @@ def test_autograd_bound_matches_adjoint_and_fused_adam():
                        batch.hi, out["infeasible"], batch.splits, 1, mm, vv, s, 0.1, ws=prop.ws)
     sync()
     assert np.abs(H(a1) - H(a2))[m].max() < 1e-4
+
+
+# ---------------------------------------------------- constraint importance order
+
+def test_constraint_order_matches_oracle():
+    B, n, k = 300, 37, 8
+    lo, hi, G, h, count = wl.random_boxes_and_constraints(B, n, k, seed=31)
+    cons = api.Constraints.dense(G, h, count)
+    order = H(api.constraint_order(None, T(lo), T(hi), cons))
+    sync()
+    act = np.arange(k)[None] < count[:, None]
+    ref = opipe.constraint_order(G.astype(np.float64), h.astype(np.float64), act, lo, hi)
+    assert np.array_equal(order, ref)
+
+
+@pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(1024), lambda: wl.mnist_mlp(B=517)],
+                         ids=["mlp5-50x6-5", "mlp784-256x6-10"])
+def test_pass_with_constraint_order_matches_oracle(make):
+    w = make()
+    op = OracleProp(w)
+    cand = np.arange(w.net.n_hidden) if w.net.n_in == 5 else op.unstable()
+    sp = wl.draw_splits(w.B, w.split_counts, cand)
+    cfg_g = gpipe.PassConfig(clip="sequential", complete_intermediate=w.net.n_in == 5, order=True)
+    cfg_o = opipe.Config(relaxed="sequential", complete_intermediate=w.net.n_in == 5, order=True)
+    prop, batch, out, ref, _ = run_both(w, sp, cfg_g, cfg_o, op)
+    assert np.array_equal(H(out["order1"])[~ref["infeasible"]], ref["order"][~ref["infeasible"]])
+    compare_pass(out, batch, ref, op)
+    # the slope steps follow the same order
+    best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=3, lr=0.1)
+    sync()
+    fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
+    l_list = opipe.split_layers(op.layers, ref["l"][fe])
+    u_list = opipe.split_layers(op.layers, ref["u"][fe])
+    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
+                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=3, lr=0.1)
+    assert_close(H(best)[fe], obest, 1e-4, "alpha-opt with order")
