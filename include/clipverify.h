@@ -31,6 +31,8 @@
  *   +inf lower bounds (case 1 of the proof of Thm 3.1).
  * - Handles are immutable after creation: concurrent calls on different
  *   streams may share them; calls sharing one workspace must not overlap.
+ * - Limits of this build: input dimension n <= 4096 and, for complete
+ *   clipping and the constraint order, kmax <= 64 (CV_E_UNSUPPORTED beyond).
  */
 #ifndef CLIPVERIFY_H
 #define CLIPVERIFY_H
@@ -77,8 +79,13 @@ typedef struct {
 
 typedef struct cv_net_s* cv_net;
 
-/* Copies the weights to the current device.  n_layers >= 1.
- * Conv layers return CV_E_UNSUPPORTED in this build. */
+/* Copies the weights to the current device.  n_layers >= 2 (one hidden ReLU
+ * layer at least).  A conv layer is stored as the dense matrix of its linear
+ * map (in_features = in_c*in_h*in_w, out_features = out_c*out_h*out_w,
+ * out_h = (in_h + 2 pad - kernel)/stride + 1, likewise out_w), so every
+ * later step treats it like a linear layer; layers whose dense matrix
+ * exceeds 2^28 entries return CV_E_UNSUPPORTED, inconsistent sizes
+ * CV_E_SHAPE. */
 cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out);
 cv_status cv_net_destroy(cv_net net);
 /* Host outputs: input dim, output dim, total hidden neurons, layer count. */
@@ -95,8 +102,10 @@ typedef struct cv_root_s* cv_root;
  * lower plane is CROWN with objective +e_j on the cut network and the
  * upper plane the negation of CROWN with objective -e_j (Lemma A.3 and the
  * plane recursion of appendix A.3), with the fixed slope alpha0 in [0,1]
- * for unstable neurons.  Planes are stored float32 with intercepts moved
- * outward so that they remain valid planes.
+ * for unstable neurons.  Plane coefficients are stored float32 and the
+ * intercepts float64, corrected at the root box centre and moved outward by
+ * the rounding of the coefficients over the box radius, so the stored planes
+ * are valid on the whole root box.
  * lo0, hi0: device [n_in].  Synchronises `stream` before returning. */
 cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
                          hipStream_t stream, cv_root* out);
@@ -105,7 +114,8 @@ cv_status cv_root_destroy(cv_root root);
  * order = layer by layer). */
 cv_status cv_root_bounds(cv_root root, float* l0, float* u0, hipStream_t stream);
 /* Device outputs: A_lo, A_hi [n_hidden, n_in], c_lo, c_hi [n_hidden]:
- * z_j >= A_lo[j].x + c_lo[j] and z_j <= A_hi[j].x + c_hi[j] on the root box. */
+ * z_j >= A_lo[j].x + c_lo[j] and z_j <= A_hi[j].x + c_hi[j] on the root box
+ * (intercepts rounded outward to float32). */
 cv_status cv_root_planes(cv_root root, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
                          hipStream_t stream);
 /* Host output: number of root-unstable neurons (l0 < 0 < u0). */
@@ -157,7 +167,8 @@ enum { CV_CLIP_PARALLEL = 0, CV_CLIP_SEQUENTIAL = 1 };
  * G_ki > 0) or hi_i - m/G_ki (lower bound, G_ki < 0): the closed form of
  * Thm 3.2.  CV_CLIP_PARALLEL applies every constraint to the original box
  * and keeps the tightest value (Alg. 2); CV_CLIP_SEQUENTIAL applies them in
- * slot order to the box left by the previous one (Alg. 3).
+ * the constraint order (cons->order, else slot order) to the box left by the
+ * previous one (Alg. 3).
  * root: required for the split form, else may be NULL.
  * lo, hi: device [B, n] in/out.  infeasible: device [B] uint8 out, 1 when
  * some constraint is certainly empty over the box or lo > hi afterwards.

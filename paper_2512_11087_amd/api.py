@@ -35,37 +35,49 @@ def _f32(t, dev=None):
 
 
 class Net:
-    """A ReLU network (linear layers; ReLU after every layer but the last).
-    ``layers``: list of (W [out, in], b [out]) float32 arrays."""
+    """A ReLU network (ReLU after every layer but the last).  ``layers``: list
+    of (W [out, in], b [out]) float32 arrays (linear layers), or of objects
+    with ``kind`` ("linear" | "conv"), ``W``, ``b`` and, for conv, ``stride``,
+    ``pad``, ``in_shape`` and ``out_shape`` ((C, H, W); W [oc, ic, k, k])."""
 
     def __init__(self, layers):
-        self._keep = []
+        keep = []
         descs = (N.LayerDesc * len(layers))()
-        for i, (W, b) in enumerate(layers):
+        sizes = []
+        for i, ly in enumerate(layers):
+            if isinstance(ly, tuple):
+                kind, W, b = "linear", ly[0], ly[1]
+            else:
+                kind, W, b = ly.kind, ly.W, ly.b
             W = np.ascontiguousarray(W, dtype=np.float32)
             b = np.ascontiguousarray(b, dtype=np.float32)
-            self._keep += [W, b]
-            descs[i].kind = N.CV_LINEAR
-            descs[i].in_features = W.shape[1]
-            descs[i].out_features = W.shape[0]
-            descs[i].W = W.ctypes.data
-            descs[i].b = b.ctypes.data
+            keep += [W, b]
+            d = descs[i]
+            if kind == "linear":
+                d.kind = N.CV_LINEAR
+                d.in_features, d.out_features = W.shape[1], W.shape[0]
+            else:
+                d.kind = N.CV_CONV2D
+                (d.in_c, d.in_h, d.in_w), (d.out_c, d.out_h, d.out_w) = ly.in_shape, ly.out_shape
+                d.kernel, d.stride, d.pad = W.shape[2], ly.stride, ly.pad
+                d.in_features = int(np.prod(ly.in_shape))
+                d.out_features = int(np.prod(ly.out_shape))
+            d.W = W.ctypes.data
+            d.b = b.ctypes.data
+            sizes.append(d.out_features)
         h = C.c_void_p()
         N.call("cv_net_create", descs, len(layers), C.byref(h))
         self.handle = h
-        self._keep = []
+        del keep
         a, o, nh, nl = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         N.call("cv_net_info", h, C.byref(a), C.byref(o), C.byref(nh), C.byref(nl))
         self.n_in, self.n_out, self.n_hidden, self.n_layers = a.value, o.value, nh.value, nl.value
-        self.hidden_sizes = [np.asarray(W).shape[0] for W, _ in layers[:-1]]
+        self.hidden_sizes = sizes[:-1]
 
     @classmethod
     def from_network(cls, net):
-        """From an object with ``.layers`` of (kind, W, b) (linear only)."""
-        for ly in net.layers:
-            if ly.kind != "linear":
-                raise NotImplementedError("conv layers are not supported by this build")
-        return cls([(ly.W, ly.b) for ly in net.layers])
+        """From an object with ``.layers`` (see the class docstring)."""
+        return cls(list(net.layers))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -102,7 +102,6 @@ cv_status dev_alloc(T** p, size_t count) {
 struct Bwd {
   double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
   float* trace;
-  float2* tab;  // relaxation line of every (subdomain, hidden neuron)
 };
 
 size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, bool trace,
@@ -125,7 +124,6 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, b
   x.e0 = cv.take<double>(M);
   x.cabs0 = cv.take<double>(M);
   x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
-  x.tab = cv.take<float2>((size_t)B * net->n_hidden);
   if (w) *w = x;
   return cv.off + 256;
 }
@@ -144,16 +142,15 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
   const int nP = net->n[T - 1];
   PLAUNCH("top", 2.0 * M * net->n[T] * nP, 8.0 * M * nP, launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
                     w.psiT, w.c0, w.e0, w.cabs0, s));
-  PLAUNCH("relax_table", 0, 16.0 * B * Nh, launch_relax_table(B, Nh, l, u, w.tab, s));
   // ReLU of hidden layer T-1 (array index T-2)
-  PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, w.tab, alpha,
+  PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
                           alpha_def, net->b[T - 2], root->wrel[T - 2], w.Om0, w.trace, w.rowc,
                           w.rowerr, w.rowcabs, s));
   double* cur = w.Om0;
   double* nxt = w.Om1;
   for (int i = T - 1; i >= 2; --i) {
     const int K = net->n[i], N = net->n[i - 1];
-    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], w.tab, alpha,
+    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
                              alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
     PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
@@ -222,9 +219,23 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
   if (n_layers > CV_MAX_LAYERS) return CV_E_UNSUPPORTED;
   for (int i = 0; i < n_layers; ++i) {
     const cv_layer_desc& d = layers[i];
-    if (d.kind == CV_CONV2D) return CV_E_UNSUPPORTED;
-    if (d.kind != CV_LINEAR) return CV_E_INVALID;
-    if (d.in_features <= 0 || d.out_features <= 0 || !d.W || !d.b) return CV_E_INVALID;
+    if (d.kind != CV_LINEAR && d.kind != CV_CONV2D) return CV_E_INVALID;
+    if (!d.W || !d.b) return CV_E_INVALID;
+    if (d.kind == CV_CONV2D) {
+      if (d.in_c <= 0 || d.in_h <= 0 || d.in_w <= 0 || d.out_c <= 0 || d.kernel <= 0 ||
+          d.stride <= 0 || d.pad < 0)
+        return CV_E_INVALID;
+      const long long oh = (d.in_h + 2LL * d.pad - d.kernel) / d.stride + 1;
+      const long long ow = (d.in_w + 2LL * d.pad - d.kernel) / d.stride + 1;
+      if (d.in_h + 2LL * d.pad < d.kernel || d.in_w + 2LL * d.pad < d.kernel) return CV_E_SHAPE;
+      if (oh != d.out_h || ow != d.out_w) return CV_E_SHAPE;
+      if ((long long)d.in_c * d.in_h * d.in_w != d.in_features ||
+          (long long)d.out_c * d.out_h * d.out_w != d.out_features)
+        return CV_E_SHAPE;
+    }
+    if (d.in_features <= 0 || d.out_features <= 0) return CV_E_INVALID;
+    // conv layers are stored as their dense matrices (below): cap the size
+    if ((long long)d.in_features * d.out_features > (1LL << 28)) return CV_E_UNSUPPORTED;
     if (i > 0 && d.in_features != layers[i - 1].out_features) return CV_E_SHAPE;
   }
   cv_net_s* net = new cv_net_s();
@@ -236,7 +247,35 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
     const int no = d.out_features, ni = d.in_features;
     net->n[i + 1] = no;
     net->W[i] = net->Wt[i] = net->b[i] = nullptr;
-    std::vector<float> W(d.W, d.W + (size_t)no * ni), Wt((size_t)no * ni), bb(d.b, d.b + no);
+    std::vector<float> W, Wt((size_t)no * ni), bb;
+    if (d.kind == CV_LINEAR) {
+      W.assign(d.W, d.W + (size_t)no * ni);
+      bb.assign(d.b, d.b + no);
+    } else {
+      // The convolution as the dense matrix of the same linear map: output
+      // (co, oy, ox) takes input (ci, oy*stride - pad + ky, ox*stride - pad + kx)
+      // with weight W[co, ci, ky, kx] (cross-correlation, zero padding, maps
+      // flattened channel-major); the bias repeats over output positions.
+      W.assign((size_t)no * ni, 0.0f);
+      bb.resize(no);
+      const int K = d.kernel, ic = d.in_c, ih = d.in_h, iw = d.in_w, oh = d.out_h, ow = d.out_w;
+      for (int co = 0; co < d.out_c; ++co)
+        for (int oy = 0; oy < oh; ++oy)
+          for (int ox = 0; ox < ow; ++ox) {
+            const size_t r = ((size_t)co * oh + oy) * ow + ox;
+            bb[r] = d.b[co];
+            for (int ci = 0; ci < ic; ++ci)
+              for (int ky = 0; ky < K; ++ky) {
+                const int iy = oy * d.stride - d.pad + ky;
+                if (iy < 0 || iy >= ih) continue;
+                for (int kx = 0; kx < K; ++kx) {
+                  const int ix = ox * d.stride - d.pad + kx;
+                  if (ix < 0 || ix >= iw) continue;
+                  W[r * ni + ((size_t)ci * ih + iy) * iw + ix] = d.W[(((size_t)co * ic + ci) * K + ky) * K + kx];
+                }
+              }
+          }
+    }
     for (int r = 0; r < no; ++r)
       for (int c = 0; c < ni; ++c) Wt[(size_t)c * no + r] = W[(size_t)r * ni + c];
     if (dev_alloc(&net->W[i], W.size()) || dev_alloc(&net->Wt[i], Wt.size()) ||
@@ -285,8 +324,11 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
 
 cv_status cv_root_destroy(cv_root r) {
   if (!r) return CV_OK;
-  float* fs[] = {r->A_lo, r->A_hi, r->c_lo, r->c_hi, r->l0, r->u0, r->lo0, r->hi0, r->P, r->cP};
+  float* fs[] = {r->A_lo, r->A_hi, r->l0, r->u0, r->lo0, r->hi0, r->P};
   for (float* p : fs)
+    if (p) (void)hipFree(p);
+  double* ds[] = {r->c_lo, r->c_hi, r->cP, r->xc0, r->rad0};
+  for (double* p : ds)
     if (p) (void)hipFree(p);
   if (r->X0) (void)hipFree(r->X0);
   if (r->eP) (void)hipFree(r->eP);
@@ -321,7 +363,8 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
       (st = dev_alloc(&r->c_lo, N)) || (st = dev_alloc(&r->c_hi, N)) ||
       (st = dev_alloc(&r->l0, N)) || (st = dev_alloc(&r->u0, N)) ||
       (st = dev_alloc(&r->lo0, n0)) || (st = dev_alloc(&r->hi0, n0)) ||
-      (st = dev_alloc(&r->X0, n0)))
+      (st = dev_alloc(&r->X0, n0)) || (st = dev_alloc(&r->xc0, n0)) ||
+      (st = dev_alloc(&r->rad0, n0)))
     return fail(st);
   // root box and |x| bound
   std::vector<float> hlo(n0), hhi(n0);
@@ -331,11 +374,17 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
     return fail(hip_fail(hipGetLastError()));
   for (int j = 0; j < n0; ++j)
     if (!(hlo[j] <= hhi[j])) return fail(CV_E_INVALID);
-  std::vector<double> hX0(n0);
-  for (int j = 0; j < n0; ++j) hX0[j] = std::max(fabs((double)hlo[j]), fabs((double)hhi[j]));
+  std::vector<double> hX0(n0), hxc(n0), hrad(n0);
+  for (int j = 0; j < n0; ++j) {
+    hX0[j] = std::max(fabs((double)hlo[j]), fabs((double)hhi[j]));
+    hxc[j] = 0.5 * ((double)hlo[j] + (double)hhi[j]);   // exact
+    hrad[j] = 0.5 * ((double)hhi[j] - (double)hlo[j]);  // exact
+  }
   if (hipMemcpy(r->lo0, hlo.data(), n0 * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(r->hi0, hhi.data(), n0 * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(r->X0, hX0.data(), n0 * 8, hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(r->X0, hX0.data(), n0 * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(r->xc0, hxc.data(), n0 * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(r->rad0, hrad.data(), n0 * 8, hipMemcpyHostToDevice) != hipSuccess)
     return fail(hip_fail(hipGetLastError()));
   int kmax_dot = 2 * n0 + 2;
   for (int i = 0; i <= L; ++i) kmax_dot = std::max(kmax_dot, net->n[i] + 2);
@@ -384,10 +433,11 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
   // hidden layer 1: planes are W1, b1 exactly
   const int n1 = net->n[1];
   if ((st = make_vgemm(1))) return fail(st);
+  std::vector<double> hb1(net->hb[0].begin(), net->hb[0].end());
   if (hipMemcpyAsync(r->A_lo, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
       hipMemcpyAsync(r->A_hi, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
-      hipMemcpyAsync(r->c_lo, net->b[0], n1 * 4, hipMemcpyDeviceToDevice, s) ||
-      hipMemcpyAsync(r->c_hi, net->b[0], n1 * 4, hipMemcpyDeviceToDevice, s))
+      hipMemcpy(r->c_lo, hb1.data(), n1 * 8, hipMemcpyHostToDevice) ||
+      hipMemcpy(r->c_hi, hb1.data(), n1 * 8, hipMemcpyHostToDevice))
     return fail(hip_fail(hipGetLastError()));
   if (launch_concretize_rows(n1, n0, r->A_lo, r->c_lo, r->lo0, r->hi0, 0, r->l0, s) ||
       launch_concretize_rows(n1, n0, r->A_hi, r->c_hi, r->lo0, r->hi0, 1, r->u0, s) ||
@@ -433,8 +483,9 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
                         r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
       if (st) { cleanup(); return fail(st); }
       float* Adst = (side ? r->A_hi : r->A_lo) + (size_t)off * n0;
-      float* cdst = (side ? r->c_hi : r->c_lo) + off;
-      if (launch_root_store_planes(ni, n0, w.Ax, w.rowc, w.rowerr, r->X0, side, Adst, cdst, s)) {
+      double* cdst = (side ? r->c_hi : r->c_lo) + off;
+      if (launch_root_store_planes(ni, n0, w.Ax, w.rowc, w.rowerr, r->xc0, r->rad0, side, Adst,
+                                   cdst, s)) {
         cleanup();
         return fail(hip_fail(hipGetLastError()));
       }
@@ -481,11 +532,11 @@ cv_status cv_root_bounds(cv_root r, float* l0, float* u0, hipStream_t s) {
 cv_status cv_root_planes(cv_root r, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
                          hipStream_t s) {
   if (!r || !A_lo || !c_lo || !A_hi || !c_hi) return CV_E_INVALID;
-  const size_t na = (size_t)r->N * r->n0 * 4, nc = (size_t)r->N * 4;
+  const size_t na = (size_t)r->N * r->n0 * 4;
   CV_HIP(hipMemcpyAsync(A_lo, r->A_lo, na, hipMemcpyDeviceToDevice, s));
   CV_HIP(hipMemcpyAsync(A_hi, r->A_hi, na, hipMemcpyDeviceToDevice, s));
-  CV_HIP(hipMemcpyAsync(c_lo, r->c_lo, nc, hipMemcpyDeviceToDevice, s));
-  CV_HIP(hipMemcpyAsync(c_hi, r->c_hi, nc, hipMemcpyDeviceToDevice, s));
+  CV_HIP(launch_round_intercepts(r->N, r->c_lo, 0, c_lo, s));
+  CV_HIP(launch_round_intercepts(r->N, r->c_hi, 1, c_hi, s));
   return CV_OK;
 }
 
@@ -544,7 +595,7 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
   size_t need = 0;
   cv_concretize_planes_workspace(root, B, complete, &need);
   if (complete && ws_bytes < need) return CV_E_WORKSPACE;
-  if (complete && root->n0 > 1024) return CV_E_UNSUPPORTED;
+  if (complete && root->n0 > 4096) return CV_E_UNSUPPORTED;
   CvCons sp;
   cv_status st = resolve_cons(root, splits, &sp);
   if (st) return st;
@@ -569,7 +620,7 @@ cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A
   if (B < 0 || P < 0 || n <= 0) return CV_E_SHAPE;
   if ((long long)B * P == 0) return CV_OK;
   if (!A || !c || !lo || !hi || !lb) return CV_E_INVALID;
-  if (n > 1024) return CV_E_UNSUPPORTED;
+  if (n > 4096) return CV_E_UNSUPPORTED;
   if (cons && passes < 1) return CV_E_INVALID;
   if (cons && cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
   if (beta && !cons) return CV_E_INVALID;
@@ -588,7 +639,7 @@ static cv_status check_prop(cv_net net, cv_root root, int B, int M, const float*
   if (root->net != net) return CV_E_INVALID;
   if (B == 0) return CV_OK;
   if (!C || !t || !l || !u || !lo || !hi || !lb) return CV_E_INVALID;
-  if (net->n[0] > 1024) return CV_E_UNSUPPORTED;
+  if (net->n[0] > 4096) return CV_E_UNSUPPORTED;
   return CV_OK;
 }
 
@@ -670,7 +721,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
     const int K = net->n[k - 1], N = net->n[k];
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
     PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
-                               net->off[k - 1], w.tab, alpha, 0.0, w.trace, infeasible, grad,
+                               net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
                                s));
     cur = out;

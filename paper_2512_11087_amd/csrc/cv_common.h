@@ -139,28 +139,27 @@ __device__ __forceinline__ Relax relu_relax(double psi, float lf, float uf, doub
   return r;
 }
 
-// The same relaxation split into a per-neuron part, computed once per
-// (subdomain, neuron) and stored as float32: (slope, intercept) of the line
-// used when alpha does not apply -- (1, 0) active, (0, 0) inactive, the
-// upper line of an unstable neuron (intercept > 0, which marks it unstable)
-// -- and the per-row choice by the sign of psi.  For the upper line the
-// float32 slope s is taken as given and the intercept is computed from it
-// (t >= -s l and t >= u - s u, as in relu_relax) and rounded up, so the
-// stored line is itself a valid upper line.
-__device__ __forceinline__ float2 relax_line(float lf, float uf) {
+// The same relaxation split into a per-neuron part -- (slope, intercept) of
+// the line used when alpha does not apply: (1, 0) active, (0, 0) inactive,
+// the upper line of an unstable neuron (intercept > 0, which marks it
+// unstable) -- and the per-row choice by the sign of psi.  Evaluated in
+// float64 where it is used (a stored float32 slope and intercept would
+// loosen every unstable neuron's line by ~2^-24 of its height, which adds up
+// over thousands of neurons; recomputing costs one division per element).
+typedef double2 cv_line;
+__device__ __forceinline__ cv_line relax_line(float lf, float uf) {
   const double l = (double)lf, u = (double)uf;
-  if (l >= 0.0) return make_float2(1.0f, 0.0f);
-  if (u <= 0.0) return make_float2(0.0f, 0.0f);
-  const float s32 = (float)(u / (u - l));
-  const double s = (double)s32;
+  if (l >= 0.0) return make_double2(1.0, 0.0);
+  if (u <= 0.0) return make_double2(0.0, 0.0);
+  const double s = u / (u - l);
   const double t = fmax(-s * l, u - s * u) + (u - l) * (4.0 * CV_U64);
-  return make_float2(s32, ru32(t));
+  return make_double2(s, t);
 }
-__device__ __forceinline__ Relax relax_apply(double psi, float2 line, double alpha) {
+__device__ __forceinline__ Relax relax_apply(double psi, cv_line line, double alpha) {
   Relax r;
-  r.lower = line.y > 0.0f && psi >= 0.0;
-  r.s = r.lower ? alpha : (double)line.x;
-  r.t = r.lower ? 0.0 : (double)line.y;
+  r.lower = line.y > 0.0 && psi >= 0.0;
+  r.s = r.lower ? alpha : line.x;
+  r.t = r.lower ? 0.0 : line.y;
   return r;
 }
 

@@ -23,7 +23,10 @@ struct cv_root_s {
   cv_net_s* net = nullptr;
   int n0 = 0, N = 0, U = 0;
   float alpha0 = 0.5f;
-  float *A_lo = nullptr, *A_hi = nullptr, *c_lo = nullptr, *c_hi = nullptr;  // [N, n0], [N]
+  float *A_lo = nullptr, *A_hi = nullptr;    // [N, n0] float32 plane coefficients
+  double *c_lo = nullptr, *c_hi = nullptr;   // [N] intercepts (float64, see k_root_store)
+  double* xc0 = nullptr;                     // [n0] centre of the root box
+  double* rad0 = nullptr;                    // [n0] half-width of the root box
   float *l0 = nullptr, *u0 = nullptr;                                        // [N]
   float *lo0 = nullptr, *hi0 = nullptr;                                      // [n0]
   double* X0 = nullptr;                       // [n0] max(|lo0|, |hi0|)
@@ -34,7 +37,7 @@ struct cv_root_s {
   int32_t* uidx = nullptr;                    // [U] global index of each root-unstable neuron
   int32_t* sidx = nullptr;                    // [N - U] root-stable neurons
   float* P = nullptr;                         // [2 n0, 2U]
-  float* cP = nullptr;                        // [2U] intercepts (lower | upper)
+  double* cP = nullptr;                       // [2U] intercepts (lower | upper)
   double* eP = nullptr;                       // [2U] rigorous error bound per column
 };
 
@@ -48,7 +51,7 @@ struct CvCons {  // device view of cv_constraints (resolved)
   const int8_t* sign;
   const float* G;
   const float* h;
-  const float* A_lo; const float* A_hi; const float* c_lo; const float* c_hi;  // split form
+  const float* A_lo; const float* A_hi; const double* c_lo; const double* c_hi;  // split form
   int nplanes;  // rows of the plane table; split slots with other indices are ignored
   const int32_t* order;  // [B, kmax] position -> slot, or null (list order)
 };
@@ -83,11 +86,11 @@ __device__ __forceinline__ void cons_row_slot(const CvCons& c, int b, int k, int
     if (c.sign[s] < 0) {
       row = c.A_lo + (size_t)j * n;
       scale = 1.0f;
-      h = (double)c.c_lo[j];
+      h = c.c_lo[j];
     } else {
       row = c.A_hi + (size_t)j * n;
       scale = -1.0f;
-      h = -(double)c.c_hi[j];
+      h = -c.c_hi[j];
     }
   } else {
     row = c.G + s * n;
@@ -113,13 +116,12 @@ hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, con
                       double* cabs0, hipStream_t s);
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
-                            const float2* tab, const float* alpha, double alpha_def,
-                            const float* bprev, const double* wrel, double* Om, float* trace,
-                            double* rowc, double* rowerr, double* rowcabs, hipStream_t s);
-hipError_t launch_relax_table(int B, int Nh, const float* l, const float* u, float2* tab,
-                              hipStream_t s);
+                            const float* lz, const float* uz, const float* alpha,
+                            double alpha_def, const float* bprev, const double* wrel, double* Om,
+                            float* trace, double* rowc, double* rowerr, double* rowcabs,
+                            hipStream_t s);
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
-                             int off, const float2* tab, const float* alpha,
+                             int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s);
 hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
@@ -132,7 +134,8 @@ hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const d
                            double* rowerr, const double* rowcabs, double gamma_big,
                            const uint8_t* infeasible, float* lb, float* c_out, hipStream_t s);
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
-                               const float* b, int M, int Nh, int off, const float2* tab,
+                               const float* b, int M, int Nh, int off, const float* lz,
+                               const float* uz,
                                float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
@@ -142,7 +145,7 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
 hipError_t launch_fill_stable(int B, int Nh, int nS, const int32_t* sidx, const float* l0,
                               const float* u0, float* l, float* u, hipStream_t s);
 hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float* hi,
-                              const float* P, const float* cP, const double* eP,
+                              const float* P, const double* cP, const double* eP,
                               const int32_t* uidx, const float* l0, const float* u0, int Nh,
                               float* l, float* u, hipStream_t s);
 hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float* u,
@@ -158,7 +161,7 @@ hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, 
                              float* lb, float* ub, float* beta_out, uint8_t* infeasible,
                              hipStream_t s);
 hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
-                             const float* c_lo, const float* A_hi, const float* c_hi,
+                             const double* c_lo, const float* A_hi, const double* c_hi,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
                              float* Ltmp, hipStream_t s);
@@ -167,11 +170,12 @@ hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const
 
 // root set-up helpers
 hipError_t launch_root_store_planes(int rows, int n0, const double* Ax, const double* rowc,
-                                    const double* rowerr, const double* X0, int negate,
-                                    float* A_dst, float* c_dst, hipStream_t s);
-hipError_t launch_concretize_rows(int rows, int n0, const float* A, const float* c,
+                                    const double* rowerr, const double* xc0, const double* rad0,
+                                    int negate, float* A_dst, double* c_dst, hipStream_t s);
+hipError_t launch_concretize_rows(int rows, int n0, const float* A, const double* c,
                                   const float* lo, const float* hi, int upper, float* out,
                                   hipStream_t s);
 hipError_t launch_build_P(int n0, int U, const int32_t* uidx, const float* A_lo, const float* A_hi,
-                          const float* c_lo, const float* c_hi, const double* X0, float* P,
-                          float* cP, double* eP, hipStream_t s);
+                          const double* c_lo, const double* c_hi, const double* X0, float* P,
+                          double* cP, double* eP, hipStream_t s);
+hipError_t launch_round_intercepts(int N, const double* c, int upper, float* out, hipStream_t s);

@@ -12,9 +12,9 @@
 // within a small tolerance of zero count as zero, so near-ties between
 // maximisers go to the smallest one.
 //
-// GPU mapping: one wave64 per problem; lane L owns coordinates L, L+64, ...
-// (EPL per lane) and keeps a', its absolute scale and the breakpoints in
-// registers.  The weighted quantile is found without sorting by bisection
+// GPU mapping: one team per problem -- a wave64 for n <= 1024, a 256-thread
+// workgroup for n <= 4096 -- whose member t owns coordinates t, t + T, ...
+// (EPL per member, T the team size) and keeps a' and the box in registers.  The weighted quantile is found without sorting by bisection
 // over the float64 bit patterns of the breakpoints (positive doubles order
 // like their bit patterns): each round picks the largest breakpoint at or
 // below the midpoint and tests it with two wave-wide sums; a hit ends the
@@ -31,6 +31,95 @@ namespace {
 
 constexpr int CA_KMAX = 64;
 
+// A team of threads that holds one problem.  Wave: the 64 lanes of a wave,
+// four problems per 256-thread workgroup, reductions by DPP and readlane,
+// constraint metadata broadcast by readlane.  Block: the 256 threads of a
+// workgroup, one problem each, reductions through LDS.  Every member calls
+// every team operation (control flow is uniform within a team).
+struct WaveTeam {
+  static constexpr int SIZE = 64;
+  static constexpr int PER_BLOCK = 4;
+  int t;
+  __device__ static int index_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+  __device__ double sum(double v) const { return wave_sum(v); }
+  __device__ void sum3(double& a, double& b, double& c) const { wave_sum3(a, b, c); }
+  __device__ double max(double v) const { return wave_max(v); }
+  __device__ double min(double v) const { return wave_min(v); }
+  // member k < cnt holds constraint k's row pointer, scale and offset
+  __device__ void publish(const float*, float, double, int) const {}
+  __device__ void meta(const float* my_row, float my_scale, double my_h, int k, const float*& row,
+                       float& scale, double& h) const {
+    const uint64_t u = (uint64_t)(uintptr_t)my_row;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), k);
+    row = (const float*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    scale = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_scale), k));
+    h = lane_f64(my_h, k);
+  }
+};
+
+struct BlockTeam {
+  static constexpr int SIZE = 256;
+  static constexpr int PER_BLOCK = 1;
+  int t;
+  double* red;          // LDS [12]
+  const float** mrow;   // LDS [CA_KMAX]
+  float* mscale;        // LDS [CA_KMAX]
+  double* mh;           // LDS [CA_KMAX]
+  __device__ static int index_in_block() { return 0; }
+  __device__ double sum(double v) const {
+    v = wave_sum(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+  }
+  __device__ void sum3(double& a, double& b, double& c) const {
+    wave_sum3(a, b, c);
+    if ((t & 63) == 0) {
+      red[t >> 6] = a;
+      red[4 + (t >> 6)] = b;
+      red[8 + (t >> 6)] = c;
+    }
+    __syncthreads();
+    a = (red[0] + red[1]) + (red[2] + red[3]);
+    b = (red[4] + red[5]) + (red[6] + red[7]);
+    c = (red[8] + red[9]) + (red[10] + red[11]);
+    __syncthreads();
+  }
+  __device__ double max(double v) const {
+    v = wave_max(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+  }
+  __device__ double min(double v) const {
+    v = wave_min(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    __syncthreads();
+    return r;
+  }
+  __device__ void publish(const float* my_row, float my_scale, double my_h, int cnt) const {
+    if (t < cnt) {
+      mrow[t] = my_row;
+      mscale[t] = my_scale;
+      mh[t] = my_h;
+    }
+    __syncthreads();
+  }
+  __device__ void meta(const float*, float, double, int k, const float*& row, float& scale,
+                       double& h) const {
+    row = mrow[k];
+    scale = mscale[k];
+    h = mh[k];
+  }
+};
+
 // Weighted quantile: the smallest candidate q* with W(> q*) <= S, where
 // W(> p) sums the weights of candidates above p.  The search keeps an open
 // interval (lo, hi) of float64 bit patterns with W(> lo) > S >= W(>= hi) and
@@ -39,20 +128,22 @@ constexpr int CA_KMAX = 64;
 // odd rounds the midpoint, so the interval at least halves every two rounds.
 // A probe takes the largest candidate p at or below the split point; W(> p)
 // decides the side and, only when W(> p) <= S, W(>= p) > S identifies p = q*.
-// The breakpoints and weights sit in this wave's LDS slice (element e of lane
-// L at e*64 + L; non-candidates hold -inf), which keeps them out of the
+// The breakpoints and weights sit in the team's LDS slice (element e of
+// member t at e*T + t; non-candidates hold -inf), which keeps them out of the
 // registers of the common path that needs no search.
-template <int EPL>
-__device__ double ca_select(const double* sq, const float* sw, int lane, double S, double wpos) {
+template <class Team, int EPL>
+__device__ double ca_select(const Team& tm, const double* sq, const float* sw, double S,
+                            double wpos) {
+  constexpr int T = Team::SIZE;
   double qmax = -INFINITY, qmin = INFINITY;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const double q = sq[e * 64 + lane];
+    const double q = sq[e * T + tm.t];
     qmax = fmax(qmax, q);
     if (q > 0.0) qmin = fmin(qmin, q);
   }
-  qmax = wave_max(qmax);
-  qmin = wave_min(qmin);
+  qmax = tm.max(qmax);
+  qmin = tm.min(qmin);
   unsigned long long blo = (unsigned long long)__double_as_longlong(qmin) - 1ull;
   unsigned long long bhi = (unsigned long long)__double_as_longlong(qmax) + 1ull;
   double wlo = wpos, whi = 0.0;  // W(> lo), W(>= hi)
@@ -72,10 +163,10 @@ __device__ double ca_select(const double* sq, const float* sw, int lane, double 
     double p = -INFINITY;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      const double q = sq[e * 64 + lane];
+      const double q = sq[e * T + tm.t];
       if (q > lo_v && q <= mv) p = fmax(p, q);
     }
-    p = wave_max(p);
+    p = tm.max(p);
     if (p == -INFINITY) {  // no candidate in (lo, mv]: W(> mv) = W(> lo)
       blo += off;
       continue;
@@ -83,18 +174,18 @@ __device__ double ca_select(const double* sq, const float* sw, int lane, double 
     double wg = 0.0, wge = 0.0;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      const double q = sq[e * 64 + lane];
-      const double w = (double)sw[e * 64 + lane];
+      const double q = sq[e * T + tm.t];
+      const double w = (double)sw[e * T + tm.t];
       if (q > p) wg += w;
       if (q >= p) wge += w;
     }
-    wg = wave_sum(wg);
+    wg = tm.sum(wg);
     if (wg > S) {  // q* > p, and nothing lies in (p, mv]
       blo += off;
       wlo = wg;
       continue;
     }
-    wge = wave_sum(wge);
+    wge = tm.sum(wge);
     if (wge > S) return p;
     bhi = (unsigned long long)__double_as_longlong(p);
     whi = wge;
@@ -102,35 +193,29 @@ __device__ double ca_select(const double* sq, const float* sw, int lane, double 
   return __longlong_as_double((long long)bhi);
 }
 
-// Wave-uniform copy of lane l's pointer.
-__device__ __forceinline__ const float* lane_ptr(const float* p, int l) {
-  const uint64_t u = (uint64_t)(uintptr_t)p;
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
-  return (const float*)(uintptr_t)(((uint64_t)hi << 32) | lo);
-}
-
-// One problem on one wave.  a: objective coefficients (lane-strided), c its
-// intercept; on return a holds a + beta^T G.  Returns the rigorous float64
-// lower bound (before the final float32 rounding) or +inf when empty.
+// One problem on one team.  a: objective coefficients (member-strided), c
+// its intercept; on return a holds a + beta^T G.  Returns the rigorous
+// float64 lower bound (before the final float32 rounding) or +inf when empty.
 // The rounding-error scale sum_j (|a_j| + sum_k beta_k |g_kj|) max(|lo_j|,|hi_j|)
 // is accumulated per constraint (beta_k times that constraint's own
 // sum_j |g_kj| max(|lo_j|,|hi_j|)), so no per-coordinate scale is kept.
 // xstar (optional) receives the minimising corner of the final dual; it may
 // alias the objective row in memory, which is read for the kink test first.
-// Lane k fetches constraint k's row pointer, sign and offset up front, so a
+// Member k fetches constraint k's row pointer, sign and offset up front, so a
 // constraint costs one dependent load (its row) instead of a chain.
-template <int EPL>
-__device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_in,
+template <class Team, int EPL>
+__device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, double e_in,
                           const float* lo_b, const float* hi_b, const CvCons* cons, int b,
                           int passes, bool& empty, float* beta_out, double* xstar,
                           double* beta, double* sq, float* sw) {
+  constexpr int T = Team::SIZE;
+  const int t = tm.t;
   float xl[EPL], xh[EPL];
   double Ea = 0.0;
   const cv_buf blo = cv_buffer(lo_b, 4u * n), bhi = cv_buffer(hi_b, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const int j = lane + 64 * e;
+    const int j = t + T * e;
     xl[e] = buf_f32(blo, 4 * j);
     xh[e] = buf_f32(bhi, 4 * j);
     Ea += fabs(a[e]) * fabs_max(xl[e], xh[e]);
@@ -140,26 +225,28 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   const float* my_row = nullptr;
   float my_scale = 0.0f;
   double my_h = 0.0;
-  if (lane < cnt) cons_row(*cons, b, lane, n, my_row, my_scale, my_h);
-  Ea = wave_sum(Ea);
-  // beta: this wave's slice of LDS (all lanes hold and write equal values)
+  if (t < cnt) cons_row(*cons, b, t, n, my_row, my_scale, my_h);
+  tm.publish(my_row, my_scale, my_h, cnt);
+  Ea = tm.sum(Ea);
+  // beta: this team's slice of LDS (all members hold and write equal values)
   for (int k = 0; k < cnt; ++k) beta[k] = 0.0;
   empty = false;
 #pragma unroll 1
   for (int pass = 0; pass < passes && !empty; ++pass) {
 #pragma unroll 1
     for (int k = 0; k < cnt; ++k) {
-      const float* row = lane_ptr(my_row, k);
+      const float* row;
+      float scale;
+      double h;
+      tm.meta(my_row, my_scale, my_h, k, row, scale, h);
       if (!row) continue;
-      const float scale = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_scale), k));
-      const double h = lane_f64(my_h, k);
       const cv_buf brow = cv_buffer(row, 4u * n);
-      int vb = 4 * lane;
+      int vb = 4 * t;
       cv_opaque(vb);
       float g[EPL];  // constraint coefficients are float32 values
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        g[e] = scale * buf_f32(brow, vb + 256 * e);
+        g[e] = scale * buf_f32(brow, vb + 4 * T * e);
         cv_opaque(xl[e]);
         cv_opaque(xh[e]);
       }
@@ -186,7 +273,7 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
         const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
         if (opp && wf > 0.0f) wsg += (double)wf;
       }
-      wave_sum3(m, em, wsg);
+      tm.sum3(m, em, wsg);
       m += h;
       if (bold != 0.0) {
         c -= bold * h;
@@ -219,20 +306,20 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
               wpos += (double)w;
             }
           }
-          sq[e * 64 + lane] = qe;
-          sw[e * 64 + lane] = we;
+          sq[e * T + t] = qe;
+          sw[e * T + t] = we;
         }
-        wpos = wave_sum(wpos);
-        if (wpos > S) bk = ca_select<EPL>(sq, sw, lane, S, wpos);
+        wpos = tm.sum(wpos);
+        if (wpos > S) bk = ca_select<Team, EPL>(tm, sq, sw, S, wpos);
       }
       beta[k] = bk;
       if (bk != 0.0) {
         // the row is re-read (cache hit) rather than kept live over the search
-        int vb2 = 4 * lane;
+        int vb2 = 4 * t;
         cv_opaque(vb2);
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          const float gr = scale * buf_f32(brow, vb2 + 256 * e);
+          const float gr = scale * buf_f32(brow, vb2 + 4 * T * e);
           a[e] += bk * (double)gr;
         }
         c += bk * h;
@@ -245,11 +332,11 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   double d = 0.0;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) d += fmin(a[e] * (double)xl[e], a[e] * (double)xh[e]);
-  d = wave_sum(d) + c;
+  d = tm.sum(d) + c;
   const double err = (cv_gamma(n + 2 * passes * cnt + 8) * (Ea + Eb + cabs) + e_in) * CV_ERR_SLACK;
-  if (beta_out && lane < cons->kmax) {  // by slot: position o holds slot cons_slot(o)
-    const int slot = cons_slot(*cons, b, lane);
-    if (slot >= 0) beta_out[slot] = lane < cnt ? (float)beta[lane] : 0.0f;
+  if (beta_out && t < cons->kmax) {  // by slot: position o holds slot cons_slot(o)
+    const int slot = cons_slot(*cons, b, t);
+    if (slot >= 0) beta_out[slot] = t < cnt ? (float)beta[t] : 0.0f;
   }
   if (xstar) {
     // kink test: |a'_j| <= 2^-40 (|a_j| + sum_k beta_k |g_kj|); the scale
@@ -259,24 +346,27 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
     const cv_buf bx = cv_buffer(xstar, 8u * n);
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      const int j = lane + 64 * e;
+      const int j = t + T * e;
       sc[e] = (float)fabs(buf_f64(bx, 8 * j));
     }
     for (int k = 0; k < cnt; ++k) {
       if (beta[k] == 0.0) continue;
-      const float* row = lane_ptr(my_row, k);
+      const float* row;
+      float scale;
+      double h;
+      tm.meta(my_row, my_scale, my_h, k, row, scale, h);
       if (!row) continue;
       const cv_buf brow = cv_buffer(row, 4u * n);
-      int vb = 4 * lane;
+      int vb = 4 * t;
       cv_opaque(vb);
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        sc[e] += (float)beta[k] * fabsf(buf_f32(brow, vb + 256 * e));
+        sc[e] += (float)beta[k] * fabsf(buf_f32(brow, vb + 4 * T * e));
       }
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      const int j = lane + 64 * e;
+      const int j = t + T * e;
       if (j < n) {
         const bool kink = fabs(a[e]) <= 9.094947017729282e-13 * (double)sc[e];  // 2^-40
         xstar[j] = kink ? 0.5 * ((double)xl[e] + (double)xh[e])
@@ -287,40 +377,71 @@ __device__ double ca_core(int lane, int n, double (&a)[EPL], double c, double e_
   return d - err;
 }
 
+// LDS of a workgroup: beta, the search slices and the team scratch, with
+// the team of member threadIdx.x.
+template <class Team, int EPL>
+struct CaShared {
+  double beta[Team::PER_BLOCK * CA_KMAX];
+  double q[Team::PER_BLOCK * Team::SIZE * EPL];
+  float w[Team::PER_BLOCK * Team::SIZE * EPL];
+  double red[12];
+  const float* mrow[CA_KMAX];
+  float mscale[CA_KMAX];
+  double mh[CA_KMAX];
+};
+template <class Team, int EPL>
+__device__ __forceinline__ Team team_of(CaShared<Team, EPL>& sh) {
+  if constexpr (Team::PER_BLOCK == 1)
+    return Team{(int)threadIdx.x, sh.red, sh.mrow, sh.mscale, sh.mh};
+  else
+    return Team{(int)(threadIdx.x & 63)};
+}
+template <class Team, int EPL>
+__device__ __forceinline__ double* beta_slice(CaShared<Team, EPL>& sh) {
+  return sh.beta + Team::index_in_block() * CA_KMAX;
+}
+template <class Team, int EPL>
+__device__ __forceinline__ double* q_slice(CaShared<Team, EPL>& sh) {
+  return sh.q + Team::index_in_block() * Team::SIZE * EPL;
+}
+template <class Team, int EPL>
+__device__ __forceinline__ float* w_slice(CaShared<Team, EPL>& sh) {
+  return sh.w + Team::index_in_block() * Team::SIZE * EPL;
+}
+
 // Final planes: rows r = (b, m) of the backward pass output.
-template <int EPL>
+template <class Team, int EPL>
 __global__ __launch_bounds__(256, 3) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
                                                  double* Ax, const double* __restrict__ rowc,
                                                  const double* __restrict__ rowerr,
                                                  const float* __restrict__ lo,
                                                  const float* __restrict__ hi, uint8_t* infeasible,
                                                  float* lb, float* beta_out, int write_xstar) {
-  __shared__ double sbeta[4 * CA_KMAX];
-  __shared__ double sq[4 * 64 * EPL];
-  __shared__ float sw[4 * 64 * EPL];
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ CaShared<Team, EPL> sh;
+  const Team tm = team_of(sh);
+  constexpr int T = Team::SIZE;
+  const int r = blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
   if (r >= R) return;
   const int b = r / M;
   double* arow = Ax + (size_t)r * n;
   const cv_buf ba = cv_buffer(arow, 8u * n);
   if (infeasible && infeasible[b]) {
-    if (lane == 0) lb[r] = INFINITY;
+    if (tm.t == 0) lb[r] = INFINITY;
     return;
   }
   double a[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const int j = lane + 64 * e;
+    const int j = tm.t + T * e;
     a[e] = buf_f64(ba, 8 * j);
   }
   bool empty;
-  const double L = ca_core<EPL>(lane, n, a, rowc[r], rowerr[r], lo + (size_t)b * n, hi + (size_t)b * n,
-                                &cons, b, passes, empty,
-                                beta_out ? beta_out + (size_t)r * cons.kmax : nullptr,
-                                write_xstar ? arow : nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX,
-                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
-  if (lane == 0) {
+  const double L = ca_core<Team, EPL>(tm, n, a, rowc[r], rowerr[r], lo + (size_t)b * n,
+                                      hi + (size_t)b * n, &cons, b, passes, empty,
+                                      beta_out ? beta_out + (size_t)r * cons.kmax : nullptr,
+                                      write_xstar ? arow : nullptr, beta_slice(sh), q_slice(sh),
+                                      w_slice(sh));
+  if (tm.t == 0) {
     if (empty) {
       lb[r] = INFINITY;
       if (infeasible) infeasible[b] = 1;
@@ -330,18 +451,17 @@ __global__ __launch_bounds__(256, 3) void k_ca_rows(int R, int M, int n, CvCons 
   }
 }
 
-template <int EPL>
+template <class Team, int EPL>
 __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, const float* __restrict__ A,
                                                     int A_shared, const float* __restrict__ cv,
                                                     const float* __restrict__ lo,
                                                     const float* __restrict__ hi, CvCons cons,
                                                     int has_cons, int passes, float* lb, float* ub,
                                                     float* beta_out, uint8_t* infeasible) {
-  __shared__ double sbeta[4 * CA_KMAX];
-  __shared__ double sq[4 * 64 * EPL];
-  __shared__ float sw[4 * 64 * EPL];
-  const int lane = threadIdx.x & 63;
-  const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ CaShared<Team, EPL> sh;
+  const Team tm = team_of(sh);
+  constexpr int T = Team::SIZE;
+  const long long pid = (long long)blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
   if (pid >= (long long)B * P) return;
   const int b = (int)(pid / P), p = (int)(pid % P);
   const size_t arow = A_shared ? (size_t)p : (size_t)pid;
@@ -354,27 +474,24 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
   const cv_buf bap = cv_buffer(ap, 4u * n), blb = cv_buffer(lb_, 4u * n), bhb = cv_buffer(hb_, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const int j = lane + 64 * e;
+    const int j = tm.t + T * e;
     a[e] = (double)buf_f32(bap, 4 * j);
     const double x0 = (double)buf_f32(blb, 4 * j), x1 = (double)buf_f32(bhb, 4 * j);
     dmin += fmin(a[e] * x0, a[e] * x1);
     dmax += fmax(a[e] * x0, a[e] * x1);
     ea += fabs(a[e]) * fmax(fabs(x0), fabs(x1));
   }
-  dmin = wave_sum(dmin);
-  dmax = wave_sum(dmax);
-  ea = wave_sum(ea);
+  tm.sum3(dmin, dmax, ea);
   const double e0 = cv_gamma(n + 1) * (ea + fabs(c)) * CV_ERR_SLACK;
   float out = rd32(dmin + c - e0);
   bool empty = false;
   if (has_cons) {
-    const double L = ca_core<EPL>(lane, n, a, c, 0.0, lb_, hb_, &cons, b, passes, empty,
-                                  beta_out ? beta_out + (size_t)pid * cons.kmax : nullptr, nullptr,
-                                  sbeta + (threadIdx.x >> 6) * CA_KMAX,
-                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
+    const double L = ca_core<Team, EPL>(tm, n, a, c, 0.0, lb_, hb_, &cons, b, passes, empty,
+                                        beta_out ? beta_out + (size_t)pid * cons.kmax : nullptr,
+                                        nullptr, beta_slice(sh), q_slice(sh), w_slice(sh));
     if (!empty) out = fmaxf(out, rd32(L));
   }
-  if (lane == 0) {
+  if (tm.t == 0) {
     lb[pid] = empty ? INFINITY : out;
     if (ub) ub[pid] = ru32(dmax + c + e0);
     if (empty && infeasible) infeasible[b] = 1;
@@ -383,23 +500,22 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
 
 // Intermediate neurons: lower plane (side 0) and negated upper plane (side 1) of every
 // root-unstable neuron still unstable in subdomain b.
-template <int EPL>
+template <class Team, int EPL>
 __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, const int32_t* __restrict__ uidx,
                                                     const float* __restrict__ A_lo,
-                                                    const float* __restrict__ c_lo,
+                                                    const double* __restrict__ c_lo,
                                                     const float* __restrict__ A_hi,
-                                                    const float* __restrict__ c_hi, CvCons cons,
+                                                    const double* __restrict__ c_hi, CvCons cons,
                                                     int passes, const float* __restrict__ lo,
                                                     const float* __restrict__ hi,
                                                     const float* __restrict__ l,
                                                     const float* __restrict__ u, int Nh,
                                                     const uint8_t* __restrict__ infeasible,
                                                     float* Ltmp) {
-  __shared__ double sbeta[4 * CA_KMAX];
-  __shared__ double sq[4 * 64 * EPL];
-  __shared__ float sw[4 * 64 * EPL];
-  const int lane = threadIdx.x & 63;
-  const long long pid = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ CaShared<Team, EPL> sh;
+  const Team tm = team_of(sh);
+  constexpr int T = Team::SIZE;
+  const long long pid = (long long)blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
   if (pid >= (long long)B * U * 2) return;
   const int side = (int)(pid & 1);
   const long long bc = pid >> 1;
@@ -407,24 +523,24 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   const int j = uidx[q];
   const float lj = l[(size_t)b * Nh + j], uj = u[(size_t)b * Nh + j];
   if ((infeasible && infeasible[b]) || !(lj < 0.0f && uj > 0.0f)) {
-    if (lane == 0) Ltmp[pid] = -INFINITY;
+    if (tm.t == 0) Ltmp[pid] = -INFINITY;
     return;
   }
   const float* ap = (side ? A_hi : A_lo) + (size_t)j * n;
-  const double c = side ? -(double)c_hi[j] : (double)c_lo[j];
+  const double c = side ? -c_hi[j] : c_lo[j];
   double a[EPL];
   const cv_buf bap = cv_buffer(ap, 4u * n);
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const int jj = lane + 64 * e;
+    const int jj = tm.t + T * e;
     const double v = (double)buf_f32(bap, 4 * jj);
     a[e] = side ? -v : v;
   }
   bool empty;
-  const double L = ca_core<EPL>(lane, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n, &cons, b,
-                                passes, empty, nullptr, nullptr, sbeta + (threadIdx.x >> 6) * CA_KMAX,
-                                sq + (threadIdx.x >> 6) * 64 * EPL, sw + (threadIdx.x >> 6) * 64 * EPL);
-  if (lane == 0) Ltmp[pid] = empty ? INFINITY : rd32(L);
+  const double L = ca_core<Team, EPL>(tm, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n,
+                                      &cons, b, passes, empty, nullptr, nullptr, beta_slice(sh),
+                                      q_slice(sh), w_slice(sh));
+  if (tm.t == 0) Ltmp[pid] = empty ? INFINITY : rd32(L);
 }
 
 int epl_for(int n) {
@@ -438,16 +554,33 @@ int epl_for(int n) {
   return -1;
 }
 
-#define CV_DISPATCH_EPL(n, CALL)          \
-  switch (epl_for(n)) {                   \
-    case 1: { constexpr int E = 1; CALL; } break;   \
-    case 2: { constexpr int E = 2; CALL; } break;   \
-    case 4: { constexpr int E = 4; CALL; } break;   \
-    case 8: { constexpr int E = 8; CALL; } break;   \
-    case 13: { constexpr int E = 13; CALL; } break; \
-    case 16: { constexpr int E = 16; CALL; } break; \
-    default: return hipErrorInvalidValue;           \
+// Team and elements per member for an input dimension n (<= 4096): a wave
+// up to 1024 coordinates, a workgroup beyond.
+#define CV_DISPATCH_CA(n, CALL)                                            \
+  if ((n) <= 1024) {                                                       \
+    typedef WaveTeam TM;                                                   \
+    switch (epl_for(n)) {                                                  \
+      case 1: { constexpr int E = 1; CALL; } break;                        \
+      case 2: { constexpr int E = 2; CALL; } break;                        \
+      case 4: { constexpr int E = 4; CALL; } break;                        \
+      case 8: { constexpr int E = 8; CALL; } break;                        \
+      case 13: { constexpr int E = 13; CALL; } break;                      \
+      case 16: { constexpr int E = 16; CALL; } break;                      \
+      default: return hipErrorInvalidValue;                                \
+    }                                                                      \
+  } else if ((n) <= 2048) {                                                \
+    typedef BlockTeam TM; constexpr int E = 8; CALL;                       \
+  } else if ((n) <= 3072) {                                                \
+    typedef BlockTeam TM; constexpr int E = 12; CALL;                      \
+  } else if ((n) <= 4096) {                                                \
+    typedef BlockTeam TM; constexpr int E = 16; CALL;                      \
+  } else {                                                                 \
+    return hipErrorInvalidValue;                                           \
   }
+
+inline unsigned ca_blocks(long long problems, int per_block) {
+  return (unsigned)((problems + per_block - 1) / per_block);
+}
 
 }  // namespace
 
@@ -457,10 +590,9 @@ hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, d
                           int write_xstar, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
-  dim3 grid((R + 3) / 4);
-  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_rows<E>), grid, dim3(256), 0, s, R, M, n, cons, passes,
-                                        Ax, rowc, rowerr, lo, hi, infeasible, lb, beta_out,
-                                        write_xstar));
+  CV_DISPATCH_CA(n, hipLaunchKernelGGL((k_ca_rows<TM, E>), dim3(ca_blocks(R, TM::PER_BLOCK)),
+                                       dim3(256), 0, s, R, M, n, cons, passes, Ax, rowc, rowerr,
+                                       lo, hi, infeasible, lb, beta_out, write_xstar));
   return hipGetLastError();
 }
 
@@ -475,24 +607,22 @@ hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, 
     cc = *cons;
     if (cc.kmax > CA_KMAX) return hipErrorInvalidValue;
   }
-  dim3 grid((unsigned)((tot + 3) / 4));
-  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_generic<E>), grid, dim3(256), 0, s, B, P, n, A,
-                                        A_shared, c, lo, hi, cc, cons ? 1 : 0, passes, lb, ub,
-                                        beta_out, infeasible));
+  CV_DISPATCH_CA(n, hipLaunchKernelGGL((k_ca_generic<TM, E>), dim3(ca_blocks(tot, TM::PER_BLOCK)),
+                                       dim3(256), 0, s, B, P, n, A, A_shared, c, lo, hi, cc,
+                                       cons ? 1 : 0, passes, lb, ub, beta_out, infeasible));
   return hipGetLastError();
 }
 
 hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
-                             const float* c_lo, const float* A_hi, const float* c_hi,
+                             const double* c_lo, const float* A_hi, const double* c_hi,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
                              float* Ltmp, hipStream_t s) {
   const long long tot = (long long)B * U * 2;
   if (tot <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((tot + 3) / 4));
-  CV_DISPATCH_EPL(n, hipLaunchKernelGGL((k_ca_neurons<E>), grid, dim3(256), 0, s, B, U, n, uidx, A_lo,
-                                        c_lo, A_hi, c_hi, cons, passes, lo, hi, l, u, Nh,
-                                        infeasible, Ltmp));
+  CV_DISPATCH_CA(n, hipLaunchKernelGGL((k_ca_neurons<TM, E>), dim3(ca_blocks(tot, TM::PER_BLOCK)),
+                                       dim3(256), 0, s, B, U, n, uidx, A_lo, c_lo, A_hi, c_hi,
+                                       cons, passes, lo, hi, l, u, Nh, infeasible, Ltmp));
   return hipGetLastError();
 }

@@ -272,7 +272,8 @@ struct EpiRelax {
   static constexpr int NSUM = 3;
   static constexpr int VGROUP = 4;
   int M, Nh, off;
-  const float2* tab;
+  const float* lz;   // pre-activation bounds l, u of the layer below [B, Nh]
+  const float* uz;
   const float* alpha;
   double alpha_def;
   const float* bprev;
@@ -281,25 +282,25 @@ struct EpiRelax {
   int ldo;
   float* trace;
   struct Row {
-    const float2* tab;
+    const float* l;
+    const float* u;
     size_t ri;
   };
   __device__ __forceinline__ Row row(int r) const {
     const size_t b = (size_t)(r / M);
-    return Row{tab + b * Nh + off, (size_t)r * Nh + off};
+    return Row{lz + b * Nh + off, uz + b * Nh + off, (size_t)r * Nh + off};
   }
   struct Pre {
-    float2 line;
-    float al;
+    float l, u, al;
   };
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
-    return Pre{w.tab[j], alpha ? alpha[w.ri + j] : (float)alpha_def};
+    return Pre{w.l[j], w.u[j], alpha ? alpha[w.ri + j] : (float)alpha_def};
   }
   __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double psi,
                                         double* s) const {
     const size_t ri = w.ri + j;
     const double al = alpha ? (double)p.al : alpha_def;
-    const Relax rl = relax_apply(psi, p.line, al);
+    const Relax rl = relax_apply(psi, relax_line(p.l, p.u), al);
     const double om = psi * rl.s;
     Om[(size_t)r * ldo + j] = om;
     if (trace) trace[ri] = trace32(psi);
@@ -347,7 +348,7 @@ struct EpiPlanes {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 4;
   int U, Nh;
-  const float* cP;
+  const double* cP;
   const double* eP;
   const int32_t* uidx;
   const float* l0;
@@ -362,11 +363,11 @@ struct EpiPlanes {
                                         double*) const {
     if (col < U) {
       const int j = uidx[col];
-      const double x = v + (double)cP[col] - eP[col];
+      const double x = v + cP[col] - eP[col];
       l[(size_t)b * Nh + j] = fmaxf(rd32(x), l0[j]);
     } else {
       const int j = uidx[col - U];
-      const double x = v + (double)cP[col] + eP[col];
+      const double x = v + cP[col] + eP[col];
       u[(size_t)b * Nh + j] = fminf(ru32(x), u0[j]);
     }
   }
@@ -381,7 +382,8 @@ struct EpiAdj {
   static constexpr int VGROUP = 2;
   int M, Nh, off;
   const float* bias;
-  const float2* tab;
+  const float* lz;
+  const float* uz;
   float* alpha;
   double alpha_def;
   const float* trace;
@@ -393,24 +395,24 @@ struct EpiAdj {
   double* out;
   int ldo;
   struct Row {
-    const float2* tab;
+    const float* l;
+    const float* u;
     size_t ri;
     bool dead;
   };
   __device__ __forceinline__ Row row(int r) const {
     const size_t b = (size_t)(r / M);
-    return Row{tab + b * Nh + off, (size_t)r * Nh + off,
+    return Row{lz + b * Nh + off, uz + b * Nh + off, (size_t)r * Nh + off,
                infeasible != nullptr && infeasible[b] != 0};
   }
   struct Pre {
-    float2 line;
-    float psi, al, m, v;
+    float l, u, psi, al, m, v;
   };
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
     const size_t ri = w.ri + j;
     const bool adam = lr > 0.0 && alpha;
-    return Pre{w.tab[j], trace[ri], alpha ? alpha[ri] : (float)alpha_def, adam ? am[ri] : 0.0f,
-               adam ? av[ri] : 0.0f};
+    return Pre{w.l[j], w.u[j], trace[ri], alpha ? alpha[ri] : (float)alpha_def,
+               adam ? am[ri] : 0.0f, adam ? av[ri] : 0.0f};
   }
   __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double acc,
                                         double*) const {
@@ -418,7 +420,7 @@ struct EpiAdj {
     const size_t ri = w.ri + j;
     const double al = alpha ? (double)p.al : alpha_def;
     const double psi = (double)p.psi;
-    const Relax rl = relax_apply(psi, p.line, al);
+    const Relax rl = relax_apply(psi, relax_line(p.l, p.u), al);
     const bool dead = w.dead;
     const double g = (rl.lower && !dead) ? om * psi : 0.0;
     if (out) out[(size_t)r * ldo + j] = om * rl.s + rl.t;
@@ -452,10 +454,10 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
 int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
 
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
-                             int off, const float2* tab, const float* alpha,
+                             int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s) {
-  EpiRelax e{M, Nh, off, tab, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
+  EpiRelax e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
@@ -467,7 +469,7 @@ hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float*
 }
 
 hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float* hi,
-                              const float* P, const float* cP, const double* eP,
+                              const float* P, const double* cP, const double* eP,
                               const int32_t* uidx, const float* l0, const float* u0, int Nh,
                               float* l, float* u, hipStream_t s) {
   EpiPlanes e{U, Nh, cP, eP, uidx, l0, u0, l, u};
@@ -475,13 +477,14 @@ hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
-                               const float* b, int M, int Nh, int off, const float2* tab,
+                               const float* b, int M, int Nh, int off, const float* lz,
+                               const float* uz,
                                float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
                                double eps, int step, double* Psibar_out, hipStream_t s) {
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
-  EpiAdj e{M, Nh, off, b, tab, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
+  EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N};
   return run_gemm(R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

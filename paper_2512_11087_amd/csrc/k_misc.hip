@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float*
 __global__ __launch_bounds__(256) void k_relax_top(
     int R, int M, int nP, int Nh, int off, const double* __restrict__ psiT,
     const double* __restrict__ c0, const double* __restrict__ e0, const double* __restrict__ cabs0,
-    const float2* __restrict__ tab, const float* __restrict__ alpha,
+    const float* __restrict__ lz, const float* __restrict__ uz, const float* __restrict__ alpha,
     double alpha_def, const float* __restrict__ bprev, const double* __restrict__ wrel,
     double* Om, float* trace, double* rowc, double* rowerr, double* rowcabs) {
   const int lane = threadIdx.x & 63;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_relax_top(
     const size_t bi = (size_t)b * Nh + off + j;
     const size_t ri = (size_t)r * Nh + off + j;
     const double al = alpha ? (double)alpha[ri] : alpha_def;
-    const Relax rl = relax_apply(psi, tab[bi], al);
+    const Relax rl = relax_apply(psi, relax_line(lz[bi], uz[bi]), al);
     const double om = psi * rl.s;
     Om[(size_t)r * nP + j] = om;
     if (trace) trace[ri] = trace32(psi);
@@ -71,14 +71,6 @@ __global__ __launch_bounds__(256) void k_relax_top(
     rowerr[r] = e0[m] + s3;
     rowcabs[r] = cabs0[m] + fabs(s1) + fabs(s2);
   }
-}
-
-// Relaxation lines of every (subdomain, hidden neuron), see relax_line.
-__global__ void k_relax_table(size_t total, const float* __restrict__ l,
-                              const float* __restrict__ u, float2* tab) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  tab[i] = relax_line(l[i], u[i]);
 }
 
 __global__ void k_rowacc(int R, int ntiles, const double* __restrict__ part, double* rowc,
@@ -165,36 +157,50 @@ __global__ void k_merge_neurons(int B, int U, const int32_t* __restrict__ uidx, 
   if (l[bi] > u[bi]) infeasible[b] = 1;
 }
 
-// Root set-up: the float64 plane (A, c) of a row with error bound e becomes a
-// float32 plane that is still valid: A32 = nearest(A) and the intercept moves
-// outward by e + sum |A32 - A| X0 (bounded by 2^-24 sum |A32| X0).
-// negate != 0 stores (-A, -c) moved up instead (upper planes from -I).
+// Root set-up: the float64 plane (A, c) of a row, valid up to its error bound
+// e, becomes a plane with float32 coefficients A32 = nearest(A) that is still
+// valid on the root box: A x + c and A32 x + c' differ by (A - A32).x, which
+// is (A - A32).xc exactly at the box centre xc and varies by at most
+// sum |A - A32| r over the box (r its half-width), so
+//   c' = c - e + (A - A32).xc - sum |A - A32| r     (lower plane)
+// stays below the exact plane everywhere on the box (A - A32 is exact in
+// float64; the two sums get their own rounding bound).  The intercept is
+// kept in float64.  negate != 0 stores the upper plane (-A, -c) from the
+// objective -I, moved up instead.  Centring keeps the widening at
+// 2^-24 sum |A| r instead of 2^-24 sum |A| max(|lo|, |hi|), which matters for
+// narrow boxes far from the origin (images in [0, 1] with eps 2/255).
 __global__ __launch_bounds__(64) void k_root_store(int rows, int n0, const double* __restrict__ Ax,
                                                    const double* __restrict__ rowc,
                                                    const double* __restrict__ rowerr,
-                                                   const double* __restrict__ X0, int negate,
-                                                   float* A_dst, float* c_dst) {
+                                                   const double* __restrict__ xc0,
+                                                   const double* __restrict__ rad0, int negate,
+                                                   float* A_dst, double* c_dst) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
-  double sa = 0.0;
+  double corr = 0.0, wid = 0.0, scale = 0.0;
   for (int j = lane; j < n0; j += 64) {
-    const double a = Ax[(size_t)r * n0 + j];
-    const float f = negate ? (float)(-a) : (float)a;
+    const double a = negate ? -Ax[(size_t)r * n0 + j] : Ax[(size_t)r * n0 + j];
+    const float f = (float)a;
     A_dst[(size_t)r * n0 + j] = f;
-    sa += fabs((double)f) * X0[j];
+    const double d = a - (double)f;  // exact
+    corr += d * xc0[j];
+    wid += fabs(d) * rad0[j];
+    scale += fabs(d) * (fabs(xc0[j]) + rad0[j]);
   }
-  sa = wave_sum(sa);
+  corr = wave_sum(corr);
+  wid = wave_sum(wid);
+  scale = wave_sum(scale);
   if (lane == 0) {
-    const double e = (rowerr[r] + 1.2e-7 * sa) * CV_ERR_SLACK;
-    const double c = rowc[r];
-    c_dst[r] = negate ? ru32(-c + e) : rd32(c - e);
+    const double e = rowerr[r] * CV_ERR_SLACK + cv_gamma(n0 + 2) * scale;
+    const double c = negate ? -rowc[r] : rowc[r];
+    c_dst[r] = negate ? c + corr + wid + e : c + corr - wid - e;
   }
 }
 
 // min (upper = 0) or max (upper = 1) of A[r].x + c[r] over one box, rounded
 // outward after a rigorous float64 error bound.
 __global__ __launch_bounds__(64) void k_concretize_rows(int rows, int n0, const float* __restrict__ A,
-                                                        const float* __restrict__ c,
+                                                        const double* __restrict__ c,
                                                         const float* __restrict__ lo,
                                                         const float* __restrict__ hi, int upper,
                                                         float* out) {
@@ -210,10 +216,18 @@ __global__ __launch_bounds__(64) void k_concretize_rows(int rows, int n0, const 
   s = wave_sum(s);
   e = wave_sum(e);
   if (lane == 0) {
-    const double cc = (double)c[r];
+    const double cc = c[r];
     const double err = (cv_gamma(n0 + 1) * (e + fabs(cc))) * CV_ERR_SLACK;
     out[r] = upper ? ru32(s + cc + err) : rd32(s + cc - err);
   }
+}
+
+// float32 images of the intercepts, rounded outward (down for lower planes,
+// up for upper planes), for callers that read the planes.
+__global__ __launch_bounds__(256) void k_round_intercepts(int N, const double* __restrict__ c,
+                                                          int upper, float* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < N) out[i] = upper ? ru32(c[i]) : rd32(c[i]);
 }
 
 // Packed plane matrix for the re-concretization GEMM.  Column q < U is the
@@ -224,9 +238,9 @@ __global__ __launch_bounds__(64) void k_concretize_rows(int rows, int n0, const 
 __global__ __launch_bounds__(64) void k_build_P(int n0, int U, const int32_t* __restrict__ uidx,
                                                 const float* __restrict__ A_lo,
                                                 const float* __restrict__ A_hi,
-                                                const float* __restrict__ c_lo,
-                                                const float* __restrict__ c_hi,
-                                                const double* __restrict__ X0, float* P, float* cP,
+                                                const double* __restrict__ c_lo,
+                                                const double* __restrict__ c_hi,
+                                                const double* __restrict__ X0, float* P, double* cP,
                                                 double* eP) {
   const int q = blockIdx.x;  // 0 .. 2U-1
   const int lane = threadIdx.x;
@@ -244,9 +258,9 @@ __global__ __launch_bounds__(64) void k_build_P(int n0, int U, const int32_t* __
   }
   e = wave_sum(e);
   if (lane == 0) {
-    const float cc = up ? c_hi[j] : c_lo[j];
+    const double cc = up ? c_hi[j] : c_lo[j];
     cP[q] = cc;
-    eP[q] = cv_gamma(2 * n0 + 2) * (e + fabs((double)cc)) * CV_ERR_SLACK;
+    eP[q] = cv_gamma(2 * n0 + 2) * (e + fabs(cc)) * CV_ERR_SLACK;
   }
 }
 
@@ -261,22 +275,14 @@ hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, con
 
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
-                            const float2* tab, const float* alpha, double alpha_def,
-                            const float* bprev, const double* wrel, double* Om, float* trace,
-                            double* rowc, double* rowerr, double* rowcabs, hipStream_t s) {
+                            const float* lz, const float* uz, const float* alpha,
+                            double alpha_def, const float* bprev, const double* wrel, double* Om,
+                            float* trace, double* rowc, double* rowerr, double* rowcabs,
+                            hipStream_t s) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_relax_top, dim3((R + 3) / 4), dim3(256), 0, s, R, M, nP, Nh, off, psiT, c0,
-                     e0, cabs0, tab, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
+                     e0, cabs0, lz, uz, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
                      rowcabs);
-  return hipGetLastError();
-}
-
-hipError_t launch_relax_table(int B, int Nh, const float* l, const float* u, float2* tab,
-                              hipStream_t s) {
-  const size_t tot = (size_t)B * Nh;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_relax_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, l,
-                     u, tab);
   return hipGetLastError();
 }
 
@@ -325,15 +331,21 @@ hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const
 }
 
 hipError_t launch_root_store_planes(int rows, int n0, const double* Ax, const double* rowc,
-                                    const double* rowerr, const double* X0, int negate,
-                                    float* A_dst, float* c_dst, hipStream_t s) {
+                                    const double* rowerr, const double* xc0, const double* rad0,
+                                    int negate, float* A_dst, double* c_dst, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_root_store, dim3(rows), dim3(64), 0, s, rows, n0, Ax, rowc, rowerr, X0,
-                     negate, A_dst, c_dst);
+  hipLaunchKernelGGL(k_root_store, dim3(rows), dim3(64), 0, s, rows, n0, Ax, rowc, rowerr, xc0,
+                     rad0, negate, A_dst, c_dst);
   return hipGetLastError();
 }
 
-hipError_t launch_concretize_rows(int rows, int n0, const float* A, const float* c,
+hipError_t launch_round_intercepts(int N, const double* c, int upper, float* out, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_round_intercepts, dim3((N + 255) / 256), dim3(256), 0, s, N, c, upper, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_concretize_rows(int rows, int n0, const float* A, const double* c,
                                   const float* lo, const float* hi, int upper, float* out,
                                   hipStream_t s) {
   if (rows <= 0) return hipSuccess;
@@ -343,8 +355,8 @@ hipError_t launch_concretize_rows(int rows, int n0, const float* A, const float*
 }
 
 hipError_t launch_build_P(int n0, int U, const int32_t* uidx, const float* A_lo, const float* A_hi,
-                          const float* c_lo, const float* c_hi, const double* X0, float* P,
-                          float* cP, double* eP, hipStream_t s) {
+                          const double* c_lo, const double* c_hi, const double* X0, float* P,
+                          double* cP, double* eP, hipStream_t s) {
   if (U <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_P, dim3(2 * U), dim3(64), 0, s, n0, U, uidx, A_lo, A_hi, c_lo, c_hi,
                      X0, P, cP, eP);

@@ -42,7 +42,7 @@ class Property:
 
     @classmethod
     def from_workload(cls, w):
-        return cls([(ly.W, ly.b) for ly in w.net.layers], w.lo0, w.hi0, w.C, w.t, w.alpha0)
+        return cls(list(w.net.layers), w.lo0, w.hi0, w.C, w.t, w.alpha0)
 
     def boxes(self, B):
         lo = self.root.lo0.expand(B, -1).contiguous()

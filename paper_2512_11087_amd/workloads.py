@@ -311,6 +311,21 @@ def alpha_mlp(B: int = 8192, seed: int = SEED_WEIGHTS) -> Workload:
     return mnist_mlp(B, (784,) + (1024,) * 4 + (10,), 6, seed, "mlp784-1024x4-10")
 
 
+def cifar_cnn(B: int = 4096, seed: int = SEED_WEIGHTS, depth=(1, 12)) -> Workload:
+    """CNN 3x32x32 -> conv 16 (4x4, stride 2, pad 1) -> conv 32 (4x4, stride 2,
+    pad 1) -> linear 100 -> linear 10, He-normal, zero biases; one property:
+    image centre U[0,1]^3072, eps 2/255 clipped to [0, 1], 9 margin rows;
+    split depth per subdomain ~ U{depth[0]..depth[1]}."""
+    net = he_cnn((3, 32, 32), [(16, 4, 2, 1), (32, 4, 2, 1)], [100, 10], seed)
+    c = centres(3072, 1, 0.0, 1.0)[0]
+    lo, hi = box_around(c, 2.0 / 255.0, clip=(0.0, 1.0))
+    label = int(np.argmax(forward(net, c[None, :].astype(np.float32))[0]))
+    C, t = margin_spec(10, label)
+    counts = np.random.default_rng(SEED_SIZES).integers(depth[0], depth[1] + 1, size=B)
+    return Workload("cnn3x32x32-c16-c32-100-10", net, lo, hi, C, t, B, counts.astype(np.int32),
+                    extra={"label": label})
+
+
 def random_boxes_and_constraints(B: int, n: int, k: int, seed: int, width=0.5,
                                  p_zero_coef=0.1, p_flat=0.05, slack=0.5, nnz=8):
     """Random boxes [B, n] and dense constraints G [B, k, n], h [B, k] with

@@ -118,8 +118,9 @@ def test_complete_clip_single_constraint_is_exact_lp():
 
 # ---------------------------------------------------------------- root pass
 
-@pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(8), lambda: wl.mnist_mlp(8)],
-                         ids=["mlp5-50x6-5", "mlp784-256x6-10"])
+@pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(8), lambda: wl.mnist_mlp(8),
+                                  lambda: wl.cifar_cnn(8)],
+                         ids=["mlp5-50x6-5", "mlp784-256x6-10", "cnn3x32x32"])
 def test_root_pass_matches_oracle_and_is_sound(make):
     w = make()
     op = OracleProp(w)
@@ -457,3 +458,27 @@ def test_pass_with_constraint_order_matches_oracle(make):
     obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
                                   ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=3, lr=0.1)
     assert_close(H(best)[fe], obest, 1e-4, "alpha-opt with order")
+
+
+# ------------------------------------------------------- conv layers (CNN)
+
+def test_pass_cnn_matches_oracle():
+    # 3x32x32 -> conv16 4x4/2 -> conv32 4x4/2 -> 100 -> 10; 3072-dim input boxes
+    # take the workgroup-per-row complete clipping
+    w = wl.cifar_cnn(B=64)
+    op = OracleProp(w)
+    sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
+    prop, batch, out, ref, _ = run_both(w, sp, gpipe.PassConfig(clip="sequential", order=True),
+                                        opipe.Config(relaxed="sequential", order=True), op)
+    compare_pass(out, batch, ref, op)
+    fe = ~ref["infeasible"]
+    assert (ref["lb"][fe] > ref["lb_unclipped"][fe] + 1e-6).any()   # clipping acts
+    best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=2, lr=0.1)
+    sync()
+    idx = np.nonzero(fe)[0][:16]
+    l_list = opipe.split_layers(op.layers, ref["l"][idx])
+    u_list = opipe.split_layers(op.layers, ref["u"][idx])
+    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][idx],
+                                  ref["hi"][idx], ref["G"][idx], ref["h"][idx], ref["active"][idx],
+                                  steps=2, lr=0.1)
+    assert_close(H(best)[idx], obest, 1e-4, "cnn alpha-opt")

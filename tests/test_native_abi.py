@@ -2,6 +2,8 @@
 loads, exports every function include/clipverify.h declares, and rejects
 invalid arguments before touching the device."""
 import ctypes as C
+
+import numpy as np
 import os
 import re
 
@@ -50,7 +52,17 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.cv_net_create(d, 1, C.byref(out)) == -3          # needs a hidden layer
     d2 = (N.LayerDesc * 2)()
     d2[0].kind = N.CV_CONV2D
-    assert lib.cv_net_create(d2, 2, C.byref(out)) == -3         # conv: not in this build
+    assert lib.cv_net_create(d2, 2, C.byref(out)) == -1         # conv without W / geometry
+    W = np.zeros(16 * 3 * 4 * 4, np.float32)
+    b = np.zeros(16, np.float32)
+    d2[0].W, d2[0].b = W.ctypes.data, b.ctypes.data
+    d2[0].in_c, d2[0].in_h, d2[0].in_w, d2[0].kernel, d2[0].stride, d2[0].pad = 3, 32, 32, 4, 2, 1
+    d2[0].out_c, d2[0].out_h, d2[0].out_w = 16, 15, 16                  # 16 x 16 expected
+    d2[0].in_features, d2[0].out_features = 3072, 16 * 15 * 16
+    assert lib.cv_net_create(d2, 2, C.byref(out)) == -2         # output size inconsistent
+    d2[0].out_h = 16
+    d2[0].out_features = 4000                                          # not 16*16*16
+    assert lib.cv_net_create(d2, 2, C.byref(out)) == -2
     d2[0].kind = 7
     assert lib.cv_net_create(d2, 2, C.byref(out)) == -1
     assert lib.cv_clip_domains(None, -1, 4, None, None, None, None, 0, None) == -2
