@@ -66,6 +66,9 @@ class Config:
     ca_passes: int = 1
     alpha: float = 0.5
     order: bool = False              # constraint importance order (heuristics appendix)
+    topk: int = -1                   # step (4) on the top-k neurons per layer by BaBSR score
+                                     # (-1: every unstable neuron)
+    babsr_weight: object = None      # [N] weights of the score (see babsr_weights)
 
 
 def split_constraints(root, neuron, sign, count):
@@ -138,14 +141,57 @@ def fix_bounds(root, l, u, neuron, sign, count, split_fix=True):
     return l, u, np.any(l > u, axis=-1)
 
 
-def complete_intermediate(root, l, u, G, h, active, lo, hi, passes=1):
+def babsr_weights(layers, C, t, root, alpha0=0.5):
+    """Weights of the neuron-selection score (heuristics appendix): for
+    neuron k, max(0, -mean_m Psi_mk), where Psi_mk is the coefficient with
+    which the output of ReLU k enters the lower bound of objective row m
+    (CROWN at the root bounds with the root slope).  Reading taken: the
+    paper's "mean of the lower-bound A of neuron k" is this mean over the
+    objective rows, taken once per property from the root pass."""
+    l_list = [x[None] for x in root.l]
+    u_list = [x[None] for x in root.u]
+    _, _, psis = crown.backward(layers, C, t, l_list, u_list, alpha0, trace=True)
+    return np.concatenate([np.maximum(0.0, -p[0].mean(axis=0)) for p in psis])
+
+
+def babsr_scores(l, u, weight):
+    """score_k = max(0, -l_k) max(0, u_k) / (u_k - l_k) * weight_k for unstable
+    neurons (l_k < 0 < u_k), 0 otherwise.  l, u: [B, N]; weight: [N]."""
+    unst = (l < 0.0) & (u > 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        icpt = np.where(unst, np.maximum(0.0, -l) * np.maximum(0.0, u) / np.where(unst, u - l, 1.0), 0.0)
+    return icpt * weight[None, :]
+
+
+def topk_select(l, u, weight, layer_sizes, k):
+    """For every subdomain and hidden layer, the k unstable neurons with the
+    largest score (ties: lower index first); mask [B, N]."""
+    sc = babsr_scores(l, u, weight)
+    unst = (l < 0.0) & (u > 0.0)
+    sel = np.zeros(l.shape, bool)
+    off = 0
+    for n in layer_sizes:
+        for b in range(l.shape[0]):
+            idx = np.nonzero(unst[b, off:off + n])[0]
+            # sort by score descending, index ascending
+            order = idx[np.lexsort((idx, -sc[b, off + idx]))]
+            sel[b, off + order[:k]] = True
+        off += n
+    return sel
+
+
+def complete_intermediate(root, l, u, G, h, active, lo, hi, passes=1, select=None):
     """Step (4): complete clipping of every unstable neuron's cached lower plane
-    (tightens l) and negated upper plane (tightens u).  Returns (l, u, empty)."""
+    (tightens l) and negated upper plane (tightens u); with ``select`` [B, N]
+    only the selected neurons.  Returns (l, u, empty)."""
     A_lo, c_lo, A_hi, c_hi, _, _ = root.stacked()
     l, u = l.copy(), u.copy()
     empty = np.zeros(l.shape[0], bool)
     for b in range(l.shape[0]):
-        js = np.nonzero((l[b] < 0.0) & (u[b] > 0.0))[0]
+        mask = (l[b] < 0.0) & (u[b] > 0.0)
+        if select is not None:
+            mask &= select[b]
+        js = np.nonzero(mask)[0]
         if js.size == 0 or not active[b].any():
             continue
         R = js.size
@@ -216,7 +262,12 @@ def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=Non
     out.update(l_reconc=l.copy(), u_reconc=u.copy(), empty_reconc=emp_r)
     emp_n = np.zeros_like(emp_r)
     if cfg.complete_intermediate:
-        l, u, emp_n = complete_intermediate(root, l, u, G, h, act, lo2, hi2, cfg.ca_passes)
+        sel = None
+        if cfg.topk >= 0:
+            sel = topk_select(l, u, f64(cfg.babsr_weight), [W.shape[0] for W, _ in layers[:-1]],
+                              cfg.topk)
+            out["select"] = sel
+        l, u, emp_n = complete_intermediate(root, l, u, G, h, act, lo2, hi2, cfg.ca_passes, sel)
     out.update(l=l, u=u, empty_neurons=emp_n)
     a = cfg.alpha if alpha is None else alpha
     A, c = crown.backward(layers, C, t, split_layers(layers, l), split_layers(layers, u), a)
