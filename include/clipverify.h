@@ -186,15 +186,31 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
  * to their branch (l_j = max(l_j, 0) for +1, u_j = min(u_j, 0) for -1).
  * splits: split form or NULL.  l, u: device [B, n_hidden] out.
  * infeasible: device [B] in/out (OR-ed with "some neuron has l > u").
- * With complete != 0 the bounds of every neuron still unstable are then
- * tightened by complete clipping (Alg. 1, `passes` passes) of its lower and
- * negated upper plane against the subdomain's split halfspaces. */
+ * With complete != 0 the bounds of the neurons still unstable are then
+ * tightened by complete clipping (Alg. 1, `passes` passes) of their lower and
+ * negated upper planes against the subdomain's split halfspaces: all of them
+ * when topk < 0, else per hidden layer the topk neurons with the largest
+ * BaBSR intercept score max(0,-l) max(0,u) / (u-l) * weight[j] (heuristics
+ * appendix; ties to the lower index; weight from cv_babsr_weights or the
+ * caller, device [n_hidden]).  select (optional) device [B, n_hidden]
+ * receives the selection mask (1 = clipped). */
 cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
                                const cv_constraints* splits, int complete, int passes,
-                               float* l, float* u, uint8_t* infeasible,
+                               int topk, const float* weight,
+                               float* l, float* u, uint8_t* infeasible, uint8_t* select,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 /* Workspace bytes of cv_concretize_planes (0 unless complete != 0). */
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes);
+
+/* Weights of the neuron-selection score (heuristics appendix): weight[j] =
+ * max(0, -mean over the M objective rows of Psi_mj), the coefficient with
+ * which the ReLU output of hidden neuron j enters the CROWN lower bound of
+ * row m, from one backward pass over the root box with the root bounds and
+ * slope (once per property).  C, t: device [M, n_out], [M]; weight: device
+ * [n_hidden] out.  ws: cv_babsr_weights_workspace(...) bytes. */
+cv_status cv_babsr_weights(cv_net net, cv_root root, int M, const float* C, const float* t,
+                           float* weight, void* ws, size_t ws_bytes, hipStream_t stream);
+cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes);
 
 /* Concretization of linear functions over boxes (Lemma A.2), optionally
  * with complete clipping.  Row p of subdomain b is A[b,p,:].x + c[b,p]

@@ -22,7 +22,7 @@ EXPORTS = [
     "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
     "cv_root_unstable_count",
     "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
-    "cv_concretize_planes_workspace",
+    "cv_concretize_planes_workspace", "cv_babsr_weights", "cv_babsr_weights_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
     "cv_alpha_step", "cv_alpha_step_workspace",
     "cv_profile_enable", "cv_profile_reset", "cv_profile_collect", "cv_profile_entry",
@@ -77,7 +77,9 @@ def lib():
         "cv_root_unstable_count": (I, [P, P]),
         "cv_clip_domains": (I, [P, I, I, P, P, P, P, I, P]),
         "cv_constraint_order": (I, [P, I, I, P, P, P, P, P]),
-        "cv_concretize_planes": (I, [P, I, P, P, P, I, I, P, P, P, P, S, P]),
+        "cv_concretize_planes": (I, [P, I, P, P, P, I, I, I, P, P, P, P, P, P, S, P]),
+        "cv_babsr_weights": (I, [P, P, I, P, P, P, P, S, P]),
+        "cv_babsr_weights_workspace": (I, [P, I, P]),
         "cv_concretize_planes_workspace": (I, [P, I, I, P]),
         "cv_concretize": (I, [P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),
         "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, I, P, P, P, P, S, P]),

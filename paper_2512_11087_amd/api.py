@@ -197,9 +197,11 @@ def clip_domains(root, lo, hi, cons, mode="parallel", infeasible=None):
 
 
 def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infeasible=None,
-                      l=None, u=None, ws=None):
+                      l=None, u=None, ws=None, topk=-1, weight=None, select=None):
     """Bounds [B, n_hidden] of every hidden neuron over each box from the
-    cached planes; returns (l, u, infeasible)."""
+    cached planes, then (complete) complete clipping of the unstable ones --
+    all, or the top-k per layer by BaBSR score with ``weight``; returns
+    (l, u, infeasible).  ``select`` (uint8 [B, n_hidden]) receives the mask."""
     B = lo.shape[0]
     nh = root.net.n_hidden
     l = torch.empty(B, nh, device="cuda") if l is None else l
@@ -212,9 +214,21 @@ def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infea
     if need.value:
         buf = (ws or Workspace()).get(need.value)
     N.call("cv_concretize_planes", root.handle, B, _p(lo), _p(hi), _cref(splits),
-           int(bool(complete)), int(passes), _p(l), _p(u), _p(infeasible), _p(buf),
-           need.value, _stream())
+           int(bool(complete)), int(passes), int(topk), _p(weight), _p(l), _p(u), _p(infeasible),
+           _p(select), _p(buf), need.value, _stream())
     return l, u, infeasible
+
+
+def babsr_weights(net, root, C_, t, ws=None):
+    """Weights [n_hidden] of the neuron-selection score (cv_babsr_weights)."""
+    M = C_.shape[0]
+    need = C.c_size_t()
+    N.call("cv_babsr_weights_workspace", net.handle, M, C.byref(need))
+    buf = (ws or Workspace()).get(need.value)
+    w = torch.empty(net.n_hidden, device="cuda")
+    N.call("cv_babsr_weights", net.handle, root.handle, M, _p(C_), _p(t), _p(w), _p(buf),
+           need.value, _stream())
+    return w
 
 
 def concretize(A, c, lo, hi, cons=None, passes=1, root=None, shared=False, want_ub=False,

@@ -579,19 +579,20 @@ cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* 
 
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes) {
   if (!root || !bytes || B < 0) return CV_E_INVALID;
-  *bytes = complete ? (size_t)B * root->U * 2 * sizeof(float) + 256 : 0;
+  *bytes = complete ? (size_t)B * root->U * 2 * sizeof(float) + (size_t)B * root->N + 512 : 0;
   return CV_OK;
 }
 
 cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
-                               const cv_constraints* splits, int complete, int passes, float* l,
-                               float* u, uint8_t* infeasible, void* ws, size_t ws_bytes,
-                               hipStream_t s) {
+                               const cv_constraints* splits, int complete, int passes, int topk,
+                               const float* weight, float* l, float* u, uint8_t* infeasible,
+                               uint8_t* select, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!root || B < 0) return CV_E_INVALID;
   if (B == 0) return CV_OK;
   if (!lo || !hi || !l || !u || !infeasible) return CV_E_INVALID;
   if (splits && splits->kmax > 0 && (!splits->neuron || !splits->sign)) return CV_E_INVALID;
   if (complete && passes < 1) return CV_E_INVALID;
+  if (complete && topk >= 0 && !weight) return CV_E_INVALID;
   size_t need = 0;
   cv_concretize_planes_workspace(root, B, complete, &need);
   if (complete && ws_bytes < need) return CV_E_WORKSPACE;
@@ -605,11 +606,45 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
                             root->l0, root->u0, Nh, l, u, s));
   if (splits && splits->kmax > 0) PLAUNCH("split_fix", 0, 8.0 * B * splits->kmax, launch_split_fix(B, Nh, sp, l, u, infeasible, s));
   if (complete && splits && splits->kmax > 0 && U > 0) {
-    float* Ltmp = Carve(ws).take<float>((size_t)B * U * 2);
+    Carve cv(ws);
+    float* Ltmp = cv.take<float>((size_t)B * U * 2);
+    uint8_t* sel = nullptr;
+    if (topk >= 0) {
+      // top-k unstable neurons per layer by the BaBSR intercept score
+      sel = select ? select : cv.take<uint8_t>((size_t)B * Nh);
+      const cv_net_s* net = root->net;
+      const int nl = net->L - 1;
+      PLAUNCH("select_topk", 0, 8.0 * B * Nh + 1.0 * B * Nh, launch_select_topk(B, Nh, nl, net->off, net->n + 1, l, u, weight, topk, sel, s));
+    }
     PLAUNCH("ca_neurons", 0, 8.0 * B * U * root->n0, launch_ca_neurons(B, U, root->n0, root->uidx, root->A_lo, root->c_lo, root->A_hi,
-                             root->c_hi, sp, passes, lo, hi, l, u, Nh, infeasible, Ltmp, s));
+                             root->c_hi, sp, passes, lo, hi, l, u, Nh, infeasible, sel, Ltmp, s));
     PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, root->uidx, Nh, Ltmp, l, u, infeasible, s));
   }
+  return CV_OK;
+}
+
+cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes) {
+  if (!net || !bytes || M <= 0) return CV_E_INVALID;
+  *bytes = bwd_layout(net, net->L, M, M, false, true, nullptr, nullptr) + (size_t)M * 4 + 256;
+  return CV_OK;
+}
+
+cv_status cv_babsr_weights(cv_net net, cv_root root, int M, const float* C, const float* t,
+                           float* weight, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!net || !root || M <= 0 || !C || !t || !weight) return CV_E_INVALID;
+  if (root->net != net) return CV_E_INVALID;
+  size_t need = 0;
+  cv_babsr_weights_workspace(net, M, &need);
+  if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
+  Bwd w;
+  const size_t used = bwd_layout(net, net->L, M, M, false, true, ws, &w);
+  float* lbtmp = Carve((char*)ws + used).take<float>(M);
+  // one backward pass over the root box with the root bounds and slope
+  cv_status st = backward_run(net, root, net->L, 1, M, C, t, root->l0, root->u0, nullptr,
+                              root->alpha0, root->lo0, root->hi0, nullptr, w, lbtmp, nullptr,
+                              nullptr, s);
+  if (st) return st;
+  PLAUNCH("babsr_weight", 0, 4.0 * M * net->n_hidden, launch_babsr_weight(M, net->n_hidden, w.trace, weight, s));
   return CV_OK;
 }
 

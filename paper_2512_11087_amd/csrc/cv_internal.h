@@ -164,7 +164,11 @@ hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const flo
                              const double* c_lo, const float* A_hi, const double* c_hi,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
-                             float* Ltmp, hipStream_t s);
+                             const uint8_t* select, float* Ltmp, hipStream_t s);
+hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s);
+hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
+                              const float* l, const float* u, const float* weight, int k,
+                              uint8_t* select, hipStream_t s);
 hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const float* Ltmp,
                                 float* l, float* u, uint8_t* infeasible, hipStream_t s);
 

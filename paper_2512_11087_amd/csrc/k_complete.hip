@@ -511,6 +511,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
                                                     const float* __restrict__ l,
                                                     const float* __restrict__ u, int Nh,
                                                     const uint8_t* __restrict__ infeasible,
+                                                    const uint8_t* __restrict__ select,
                                                     float* Ltmp) {
   __shared__ CaShared<Team, EPL> sh;
   const Team tm = team_of(sh);
@@ -522,7 +523,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   const int b = (int)(bc / U), q = (int)(bc % U);
   const int j = uidx[q];
   const float lj = l[(size_t)b * Nh + j], uj = u[(size_t)b * Nh + j];
-  if ((infeasible && infeasible[b]) || !(lj < 0.0f && uj > 0.0f)) {
+  if ((infeasible && infeasible[b]) || !(lj < 0.0f && uj > 0.0f) ||
+      (select && !select[(size_t)b * Nh + j])) {
     if (tm.t == 0) Ltmp[pid] = -INFINITY;
     return;
   }
@@ -617,12 +619,12 @@ hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const flo
                              const double* c_lo, const float* A_hi, const double* c_hi,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
-                             float* Ltmp, hipStream_t s) {
+                             const uint8_t* select, float* Ltmp, hipStream_t s) {
   const long long tot = (long long)B * U * 2;
   if (tot <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
   CV_DISPATCH_CA(n, hipLaunchKernelGGL((k_ca_neurons<TM, E>), dim3(ca_blocks(tot, TM::PER_BLOCK)),
                                        dim3(256), 0, s, B, U, n, uidx, A_lo, c_lo, A_hi, c_hi,
-                                       cons, passes, lo, hi, l, u, Nh, infeasible, Ltmp));
+                                       cons, passes, lo, hi, l, u, Nh, infeasible, select, Ltmp));
   return hipGetLastError();
 }

@@ -264,6 +264,54 @@ __global__ __launch_bounds__(64) void k_build_P(int n0, int U, const int32_t* __
   }
 }
 
+// Weights of the neuron-selection score: max(0, -mean over the objective rows
+// of the backward coefficient Psi of each hidden neuron), from the trace of a
+// backward pass over one box (rows m = 0..M-1).
+__global__ __launch_bounds__(256) void k_babsr_weight(int M, int Nh, const float* __restrict__ trace,
+                                                      float* weight) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= Nh) return;
+  double s = 0.0;
+  for (int m = 0; m < M; ++m) s += (double)trace[(size_t)m * Nh + k];
+  weight[k] = (float)fmax(0.0, -(s / (double)M));
+}
+
+// Top-k unstable neurons of one hidden layer of one subdomain by the BaBSR
+// intercept score  max(0,-l) max(0,u) / (u - l) * weight  (float64), ties to
+// the lower index.  One workgroup per (subdomain, layer); the layer's scores
+// sit in LDS and every neuron counts the ones ranked above it.
+struct LayerTable {
+  int count;
+  int off[CV_MAX_LAYERS];
+  int size[CV_MAX_LAYERS];
+};
+constexpr int TOPK_NMAX = 4096;
+__global__ __launch_bounds__(256) void k_select_topk(int Nh, LayerTable lt, const float* __restrict__ l,
+                                                     const float* __restrict__ u,
+                                                     const float* __restrict__ weight, int k,
+                                                     uint8_t* select) {
+  __shared__ double ssc[TOPK_NMAX];
+  const int b = blockIdx.x, layer = blockIdx.y;
+  const int off = lt.off[layer], n = lt.size[layer];
+  const float* lb = l + (size_t)b * Nh + off;
+  const float* ub = u + (size_t)b * Nh + off;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double lj = (double)lb[j], uj = (double)ub[j];
+    ssc[j] = (lj < 0.0 && uj > 0.0) ? (-lj) * uj / (uj - lj) * (double)weight[off + j] : -1.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double sj = ssc[j];
+    int rank = 0;
+    if (sj >= 0.0)
+      for (int i = 0; i < n && rank < k; ++i) {
+        const double si = ssc[i];
+        rank += (si > sj || (si == sj && i < j)) ? 1 : 0;
+      }
+    select[(size_t)b * Nh + off + j] = (sj >= 0.0 && rank < k) ? 1 : 0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
@@ -360,5 +408,27 @@ hipError_t launch_build_P(int n0, int U, const int32_t* uidx, const float* A_lo,
   if (U <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_P, dim3(2 * U), dim3(64), 0, s, n0, U, uidx, A_lo, A_hi, c_lo, c_hi,
                      X0, P, cP, eP);
+  return hipGetLastError();
+}
+
+hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s) {
+  if (Nh <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_babsr_weight, dim3((Nh + 255) / 256), dim3(256), 0, s, M, Nh, trace, weight);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
+                              const float* l, const float* u, const float* weight, int k,
+                              uint8_t* select, hipStream_t s) {
+  if (B <= 0 || nlayers <= 0) return hipSuccess;
+  LayerTable lt{};
+  lt.count = nlayers;
+  for (int i = 0; i < nlayers; ++i) {
+    if (size[i] > TOPK_NMAX) return hipErrorInvalidValue;
+    lt.off[i] = off[i];
+    lt.size[i] = size[i];
+  }
+  hipLaunchKernelGGL(k_select_topk, dim3(B, nlayers), dim3(256), 0, s, Nh, lt, l, u, weight, k,
+                     select);
   return hipGetLastError();
 }

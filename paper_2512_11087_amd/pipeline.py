@@ -26,6 +26,7 @@ class PassConfig:
     passes: int = 1
     alpha: float = 0.5
     order: bool = False             # constraint importance order (heuristics appendix)
+    topk: int = -1                  # complete_intermediate on the top-k per layer (-1: all)
 
 
 class Property:
@@ -39,6 +40,13 @@ class Property:
         self.M = self.C.shape[0]
         self.ws = api.Workspace()
         self.ws2 = api.Workspace()
+        self._babsr = None
+
+    def babsr_weight(self):
+        """Per-neuron weights of the selection score, computed once."""
+        if self._babsr is None:
+            self._babsr = api.babsr_weights(self.net, self.root, self.C, self.t, self.ws)
+        return self._babsr
 
     @classmethod
     def from_workload(cls, w):
@@ -95,9 +103,16 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None):
         batch.ordered = batch.splits.with_order(
             api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order1")))
         out["order1"] = batch.ordered.order
+    weight, select = None, None
+    if cfg.complete_intermediate and cfg.topk >= 0:
+        weight = prop.babsr_weight()
+        select = out.get("select")
+        if select is None:
+            select = torch.empty(B, prop.net.n_hidden, dtype=torch.uint8, device="cuda")
+        out["select"] = select
     l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, batch.cons(),
                                       cfg.complete_intermediate, cfg.passes, inf,
-                                      out.get("l"), out.get("u"), prop.ws2)
+                                      out.get("l"), out.get("u"), prop.ws2, cfg.topk, weight, select)
     cons = batch.cons() if cfg.complete_final else None
     lb = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
                              None, cfg.alpha, inf, cons, cfg.passes, ws=prop.ws)

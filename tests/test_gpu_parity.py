@@ -482,3 +482,33 @@ def test_pass_cnn_matches_oracle():
                                   ref["hi"][idx], ref["G"][idx], ref["h"][idx], ref["active"][idx],
                                   steps=2, lr=0.1)
     assert_close(H(best)[idx], obest, 1e-4, "cnn alpha-opt")
+
+
+# ------------------------------------- top-k intermediate neurons (BaBSR score)
+
+@pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(256), lambda: wl.mnist_mlp(B=64)],
+                         ids=["mlp5-50x6-5", "mlp784-256x6-10"])
+def test_topk_complete_clipping_matches_oracle(make):
+    w = make()
+    op = OracleProp(w)
+    tiny = w.net.n_in == 5
+    cand = np.arange(w.net.n_hidden) if tiny else op.unstable()
+    sp = wl.draw_splits(w.B, w.split_counts, cand)
+    k = 5 if tiny else 20
+    prop = gpipe.Property.from_workload(w)
+    gw = H(prop.babsr_weight())
+    ow = opipe.babsr_weights(op.layers, w.C, w.t, op.root)
+    assert_close(gw, ow, 1e-5, "babsr weights")
+    assert (ow > 0).sum() > 10
+    cfg_g = gpipe.PassConfig(complete_intermediate=True, topk=k)
+    cfg_o = opipe.Config(complete_intermediate=True, topk=k, babsr_weight=ow)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, cfg_g)
+    sync()
+    ref = op.run(sp, cfg=cfg_o)
+    fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
+    gsel = H(out["select"]).astype(bool)[fe]
+    osel = ref["select"][fe]
+    assert (gsel != osel).sum() <= max(2, osel.sum() // 1000), "selection differs"
+    assert osel.sum(-1).max() <= k * (len(w.net.layers) - 1) and osel.any()
+    compare_pass(out, batch, ref, op)
