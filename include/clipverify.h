@@ -184,7 +184,8 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
  * for every root-unstable neuron j, intersected with the root bounds;
  * root-stable neurons keep their root bounds.  Split neurons are then fixed
  * to their branch (l_j = max(l_j, 0) for +1, u_j = min(u_j, 0) for -1).
- * splits: split form or NULL.  l, u: device [B, n_hidden] out.
+ * splits: split form, dense form (complete clipping only; no split fix) or
+ * NULL.  l, u: device [B, n_hidden] out.
  * infeasible: device [B] in/out (OR-ed with "some neuron has l > u").
  * With complete != 0 the bounds of the neurons still unstable are then
  * tightened by complete clipping (Alg. 1, `passes` passes) of their lower and
@@ -278,6 +279,45 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
                         float* lb, float* grad, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes);
+
+/* CROWN bounds of every hidden neuron over each subdomain's own box (the
+ * bounding of a fresh input box, as opposed to re-concretizing the root
+ * planes): for hidden layers 2..L-1 in order, a backward pass with the
+ * objectives +I and -I on that layer's pre-activations through the layers
+ * below (Lemma A.3 with the root slope, the subdomain's bounds of the
+ * earlier layers), concretized over the box and intersected with the
+ * bounds passed in.  l, u: device [B, n_hidden] in/out, valid bounds on
+ * entry (e.g. from cv_concretize_planes, which gives layer 1 exactly); lo,
+ * hi: device [B, n_in] inside the root box.  infeasible: [B] or NULL. */
+cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* lo, const float* hi,
+                                 float* l, float* u, const uint8_t* infeasible, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes);
+
+/* ---------------------------------------------------- branch and bound */
+
+/* ReLU branching (Alg. 5): each parent subdomain b (splits, box lo/hi
+ * [B, n_in], bounds l/u [B, n_hidden]) is split on the unstable neuron
+ * (l < 0 < u) not split yet with the largest BaBSR intercept score
+ * max(0,-l) max(0,u) / (u-l) * weight[j] (ties to the lower index) into
+ * child 2b (branch z <= 0) and child 2b+1 (branch z >= 0): the parent's
+ * splits plus the new one, and the parent's box.  chosen[b] = -1 when no
+ * unstable neuron is left or the parent already uses all kmax_out slots
+ * (the children then equal the parent).
+ * Outputs (device): chosen [B]; neuron2, sign2 [2B, kmax_out]; count2 [2B];
+ * lo2, hi2 [2B, n_in].  kmax_out >= splits->kmax (else CV_E_SHAPE). */
+cv_status cv_branch_relu(cv_root root, int B, const float* l, const float* u, const float* weight,
+                         const cv_constraints* splits, const float* lo, const float* hi,
+                         int kmax_out, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
+                         int32_t* count2, float* lo2, float* hi2, hipStream_t stream);
+
+/* Input branching (Alg. 4): each box b is halved along the dimension with
+ * the largest (hi_d - lo_d) * sum_m |A[b,m,d]| (A: the parent's final planes
+ * [B, M, n]; ties to the lower index) at the float32 midpoint: child 2b is
+ * the lower half, child 2b+1 the upper half (they share the cut).
+ * Outputs (device): dim [B]; lo2, hi2 [2B, n]. */
+cv_status cv_branch_input(int B, int M, int n, const float* lo, const float* hi, const float* A,
+                          int32_t* dim, float* lo2, float* hi2, hipStream_t stream);
 
 /* ------------------------------------------------------ kernel timing */
 

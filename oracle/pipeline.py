@@ -66,6 +66,7 @@ class Config:
     ca_passes: int = 1
     alpha: float = 0.5
     order: bool = False              # constraint importance order (heuristics appendix)
+    intermediate: str = "reconcretize"   # step (3): "reconcretize" | "crown" (fresh box)
     topk: int = -1                   # step (4) on the top-k neurons per layer by BaBSR score
                                      # (-1: every unstable neuron)
     babsr_weight: object = None      # [N] weights of the score (see babsr_weights)
@@ -208,6 +209,28 @@ def complete_intermediate(root, l, u, G, h, active, lo, hi, passes=1, select=Non
     return l, u, empty | np.any(l > u, axis=-1)
 
 
+def crown_intermediate(layers, root, lo, hi, l, u, alpha0=0.5):
+    """Bounds of a fresh box (input BaB): for hidden layers 2..L-1 in order,
+    CROWN with objectives +I and -I on the layer's pre-activations over the
+    cut network, using the box's own bounds of the earlier layers,
+    concretized over each box and intersected with the bounds given (l, u
+    [B, N]: valid bounds, e.g. the re-concretized cached planes)."""
+    l, u = l.copy(), u.copy()
+    off = layers[0][0].shape[0]
+    for i in range(2, len(layers)):
+        n_i = layers[i - 1][0].shape[0]
+        sub = layers[:i]
+        ll = split_layers(layers, l)[:i - 1]
+        uu = split_layers(layers, u)[:i - 1]
+        I = np.eye(n_i)
+        A1, c1 = crown.backward(sub, I, np.zeros(n_i), ll, uu, alpha0)
+        A2, c2 = crown.backward(sub, -I, np.zeros(n_i), ll, uu, alpha0)
+        l[:, off:off + n_i] = np.maximum(l[:, off:off + n_i], concretize_min(A1, c1, lo, hi))
+        u[:, off:off + n_i] = np.minimum(u[:, off:off + n_i], -concretize_min(A2, c2, lo, hi))
+        off += n_i
+    return l, u
+
+
 def split_layers(net_layers, flat):
     """Cut [B, N] concatenated hidden quantities into per-layer arrays."""
     out, off = [], 0
@@ -229,13 +252,20 @@ def final_clip(A, c, G, h, active, lo, hi, passes=1):
     return L.reshape(B, M), beta.reshape(B, M, k), inf.reshape(B, M).any(-1)
 
 
-def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=None):
+def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=None, dense=None):
     """Steps (1)-(7) for a batch of subdomains; returns a dict of every
     intermediate result.  ``layers``: dense (W, b) list; lo/hi: [B, n0];
-    alpha: None (use cfg.alpha) or per-layer [B, M, n_i] arrays."""
+    alpha: None (use cfg.alpha) or per-layer [B, M, n_i] arrays.  ``dense``:
+    (G [B,k,n0], h [B,k], active [B,k]) constraints used instead of splits
+    (e.g. a parent's final plane in input BaB; no split fix then)."""
     lo, hi = f64(lo), f64(hi)
     out = {}
-    G, h, act = split_constraints(root, neuron, sign, count)
+    if dense is not None:
+        G, h, act = (f64(dense[0]), f64(dense[1]), np.asarray(dense[2], bool))
+        B = lo.shape[0]
+        neuron, sign, count = np.zeros((B, 0), int), np.zeros((B, 0), int), np.zeros(B, int)
+    else:
+        G, h, act = split_constraints(root, neuron, sign, count)
     if cfg.relaxed == "parallel":
         lo2, hi2, inf_clip = rx.clip_parallel(G, h, lo, hi, act)
     elif cfg.relaxed == "sequential":
@@ -259,6 +289,9 @@ def run(layers, root, C, t, lo, hi, neuron, sign, count, cfg=Config(), alpha=Non
         l = np.broadcast_to(l0, (lo.shape[0], l0.size)).copy()
         u = np.broadcast_to(u0, (lo.shape[0], u0.size)).copy()
     l, u, emp_r = fix_bounds(root, l, u, neuron, sign, count, cfg.split_fix)
+    if cfg.intermediate == "crown":
+        l, u = crown_intermediate(layers, root, lo2, hi2, l, u)
+        emp_r = emp_r | np.any(l > u, axis=-1)
     out.update(l_reconc=l.copy(), u_reconc=u.copy(), empty_reconc=emp_r)
     emp_n = np.zeros_like(emp_r)
     if cfg.complete_intermediate:

@@ -24,6 +24,8 @@ EXPORTS = [
     "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
     "cv_concretize_planes_workspace", "cv_babsr_weights", "cv_babsr_weights_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
+    "cv_branch_relu", "cv_branch_input", "cv_intermediate_bounds",
+    "cv_intermediate_bounds_workspace",
     "cv_alpha_step", "cv_alpha_step_workspace",
     "cv_profile_enable", "cv_profile_reset", "cv_profile_collect", "cv_profile_entry",
 ]
@@ -80,6 +82,10 @@ def lib():
         "cv_concretize_planes": (I, [P, I, P, P, P, I, I, I, P, P, P, P, P, P, S, P]),
         "cv_babsr_weights": (I, [P, P, I, P, P, P, P, S, P]),
         "cv_babsr_weights_workspace": (I, [P, I, P]),
+        "cv_branch_relu": (I, [P, I, P, P, P, P, P, P, I, P, P, P, P, P, P, P]),
+        "cv_branch_input": (I, [I, I, I, P, P, P, P, P, P, P]),
+        "cv_intermediate_bounds": (I, [P, P, I, P, P, P, P, P, P, S, P]),
+        "cv_intermediate_bounds_workspace": (I, [P, I, P]),
         "cv_concretize_planes_workspace": (I, [P, I, I, P]),
         "cv_concretize": (I, [P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),
         "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, I, P, P, P, P, S, P]),

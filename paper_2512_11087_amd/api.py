@@ -172,6 +172,47 @@ def constraint_order(root, lo, hi, cons, out=None):
     return order
 
 
+def intermediate_bounds(net, root, lo, hi, l, u, infeasible=None, ws=None):
+    """CROWN bounds of layers 2.. over each box, intersected with l, u in
+    place (cv_intermediate_bounds)."""
+    B = lo.shape[0]
+    need = C.c_size_t()
+    N.call("cv_intermediate_bounds_workspace", net.handle, B, C.byref(need))
+    buf = (ws or Workspace()).get(need.value)
+    N.call("cv_intermediate_bounds", net.handle, root.handle, B, _p(lo), _p(hi), _p(l), _p(u),
+           _p(infeasible), _p(buf), need.value, _stream())
+    return l, u
+
+
+def branch_relu(root, l, u, weight, splits, lo, hi, kmax_out):
+    """ReLU branching (cv_branch_relu): returns (chosen [B], child splits
+    (Constraints, 2B rows), lo2, hi2 [2B, n_in])."""
+    B, n0 = lo.shape
+    dev = "cuda"
+    chosen = torch.empty(B, dtype=torch.int32, device=dev)
+    neuron2 = torch.empty(2 * B, kmax_out, dtype=torch.int32, device=dev)
+    sign2 = torch.empty(2 * B, kmax_out, dtype=torch.int8, device=dev)
+    count2 = torch.empty(2 * B, dtype=torch.int32, device=dev)
+    lo2 = torch.empty(2 * B, n0, device=dev)
+    hi2 = torch.empty(2 * B, n0, device=dev)
+    N.call("cv_branch_relu", root.handle, B, _p(l), _p(u), _p(weight), _cref(splits), _p(lo),
+           _p(hi), int(kmax_out), _p(chosen), _p(neuron2), _p(sign2), _p(count2), _p(lo2),
+           _p(hi2), _stream())
+    return chosen, Constraints(kmax_out, count2, neuron2, sign2), lo2, hi2
+
+
+def branch_input(lo, hi, A):
+    """Input branching (cv_branch_input): A [B, M, n]; returns (dim [B],
+    lo2, hi2 [2B, n])."""
+    B, n = lo.shape
+    M = A.shape[1]
+    dim = torch.empty(B, dtype=torch.int32, device="cuda")
+    lo2 = torch.empty(2 * B, n, device="cuda")
+    hi2 = torch.empty(2 * B, n, device="cuda")
+    N.call("cv_branch_input", B, M, n, _p(lo), _p(hi), _p(A), _p(dim), _p(lo2), _p(hi2), _stream())
+    return dim, lo2, hi2
+
+
 class Workspace:
     """Grow-only device scratch buffer handed to the library."""
 

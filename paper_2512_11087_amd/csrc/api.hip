@@ -590,7 +590,9 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
   if (!root || B < 0) return CV_E_INVALID;
   if (B == 0) return CV_OK;
   if (!lo || !hi || !l || !u || !infeasible) return CV_E_INVALID;
-  if (splits && splits->kmax > 0 && (!splits->neuron || !splits->sign)) return CV_E_INVALID;
+  if (splits && splits->kmax > 0 && splits->neuron && !splits->sign) return CV_E_INVALID;
+  if (splits && splits->kmax > 0 && !splits->neuron && (!splits->G || !splits->h))
+    return CV_E_INVALID;
   if (complete && passes < 1) return CV_E_INVALID;
   if (complete && topk >= 0 && !weight) return CV_E_INVALID;
   size_t need = 0;
@@ -604,7 +606,7 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
   PLAUNCH("fill_stable", 0, 8.0 * B * (Nh - U), launch_fill_stable(B, Nh, Nh - U, root->sidx, root->l0, root->u0, l, u, s));
   PLAUNCH("gemm_planes", 2.0 * B * (2.0 * root->n0) * (2.0 * U), 8.0 * B * root->n0 + 8.0 * B * U + 16.0 * root->n0 * U, launch_gemm_planes(B, root->n0, U, lo, hi, root->P, root->cP, root->eP, root->uidx,
                             root->l0, root->u0, Nh, l, u, s));
-  if (splits && splits->kmax > 0) PLAUNCH("split_fix", 0, 8.0 * B * splits->kmax, launch_split_fix(B, Nh, sp, l, u, infeasible, s));
+  if (splits && splits->kmax > 0 && splits->neuron) PLAUNCH("split_fix", 0, 8.0 * B * splits->kmax, launch_split_fix(B, Nh, sp, l, u, infeasible, s));
   if (complete && splits && splits->kmax > 0 && U > 0) {
     Carve cv(ws);
     float* Ltmp = cv.take<float>((size_t)B * U * 2);
@@ -645,6 +647,76 @@ cv_status cv_babsr_weights(cv_net net, cv_root root, int M, const float* C, cons
                               nullptr, s);
   if (st) return st;
   PLAUNCH("babsr_weight", 0, 4.0 * M * net->n_hidden, launch_babsr_weight(M, net->n_hidden, w.trace, weight, s));
+  return CV_OK;
+}
+
+cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes) {
+  if (!net || !bytes || B < 0) return CV_E_INVALID;
+  size_t best = 0;
+  int nmax = 1;
+  for (int i = 2; i <= net->L - 1; ++i) {
+    const int ni = net->n[i];
+    nmax = std::max(nmax, ni);
+    best = std::max(best, bwd_layout(net, i, (long long)B * ni, ni, false, false, nullptr, nullptr));
+  }
+  *bytes = best + (size_t)nmax * nmax * 4 + (size_t)nmax * 4 + 2 * (size_t)B * nmax * 4 + 1024;
+  return CV_OK;
+}
+
+cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* lo, const float* hi,
+                                 float* l, float* u, const uint8_t* infeasible, void* ws,
+                                 size_t ws_bytes, hipStream_t s) {
+  if (!net || !root || B < 0) return CV_E_INVALID;
+  if (root->net != net) return CV_E_INVALID;
+  if (B == 0) return CV_OK;
+  if (!lo || !hi || !l || !u) return CV_E_INVALID;
+  size_t need = 0;
+  cv_intermediate_bounds_workspace(net, B, &need);
+  if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
+  const int Nh = net->n_hidden;
+  for (int i = 2; i <= net->L - 1; ++i) {
+    const int ni = net->n[i];
+    Bwd w;
+    const size_t used = bwd_layout(net, i, (long long)B * ni, ni, false, false, ws, &w);
+    Carve cv((char*)ws + used);
+    float* C = cv.take<float>((size_t)ni * ni);
+    float* t = cv.take<float>(ni);
+    float* lbl = cv.take<float>((size_t)B * ni);
+    float* lbn = cv.take<float>((size_t)B * ni);
+    for (int side = 0; side < 2; ++side) {
+      CV_HIP(launch_fill_eye(ni, side ? -1.0f : 1.0f, C, t, s));
+      cv_status st = backward_run(net, root, i, B, ni, C, t, l, u, nullptr, root->alpha0, lo, hi,
+                                  infeasible, w, side ? lbn : lbl, nullptr, nullptr, s);
+      if (st) return st;
+    }
+    PLAUNCH("merge_layer", 0, 16.0 * B * ni, launch_merge_layer(B, ni, Nh, net->off[i - 1], lbl, lbn, l, u, s));
+  }
+  return CV_OK;
+}
+
+cv_status cv_branch_relu(cv_root root, int B, const float* l, const float* u, const float* weight,
+                         const cv_constraints* splits, const float* lo, const float* hi,
+                         int kmax_out, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
+                         int32_t* count2, float* lo2, float* hi2, hipStream_t s) {
+  if (!root || B < 0) return CV_E_INVALID;
+  if (B == 0) return CV_OK;
+  if (!l || !u || !weight || !splits || !lo || !hi || !chosen || !neuron2 || !sign2 || !count2 ||
+      !lo2 || !hi2)
+    return CV_E_INVALID;
+  if (splits->kmax > 0 && (!splits->neuron || !splits->sign)) return CV_E_INVALID;
+  if (kmax_out < splits->kmax || kmax_out < 1) return CV_E_SHAPE;
+  PLAUNCH("branch_relu", 0, 8.0 * B * root->N + 16.0 * B * root->n0, launch_branch_relu(B, root->N, l, u, weight, splits->kmax, splits->neuron, splits->sign,
+                             splits->count, root->n0, lo, hi, kmax_out, chosen, neuron2, sign2,
+                             count2, lo2, hi2, s));
+  return CV_OK;
+}
+
+cv_status cv_branch_input(int B, int M, int n, const float* lo, const float* hi, const float* A,
+                          int32_t* dim, float* lo2, float* hi2, hipStream_t s) {
+  if (B < 0 || M <= 0 || n <= 0) return CV_E_SHAPE;
+  if (B == 0) return CV_OK;
+  if (!lo || !hi || !A || !dim || !lo2 || !hi2) return CV_E_INVALID;
+  PLAUNCH("branch_input", 0, 4.0 * B * M * n + 24.0 * B * n, launch_branch_input(B, M, n, lo, hi, A, dim, lo2, hi2, s));
   return CV_OK;
 }
 

@@ -165,6 +165,17 @@ hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const flo
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
                              const uint8_t* select, float* Ltmp, hipStream_t s);
+hipError_t launch_branch_relu(int B, int Nh, const float* l, const float* u, const float* weight,
+                              int kin, const int32_t* neuron, const int8_t* sign,
+                              const int32_t* count, int n0, const float* lo, const float* hi,
+                              int kout, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
+                              int32_t* count2, float* lo2, float* hi2, hipStream_t s);
+hipError_t launch_branch_input(int B, int M, int n0, const float* lo, const float* hi,
+                               const float* A, int32_t* dim, float* lo2, float* hi2,
+                               hipStream_t s);
+hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s);
+hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, const float* lbn,
+                              float* l, float* u, hipStream_t s);
 hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s);
 hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
                               const float* l, const float* u, const float* weight, int k,

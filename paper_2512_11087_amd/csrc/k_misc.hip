@@ -312,6 +312,27 @@ __global__ __launch_bounds__(256) void k_select_topk(int Nh, LayerTable lt, cons
   }
 }
 
+// Objective +-I (n x n) for the intermediate bounds of one layer.
+__global__ void k_fill_eye(int n, float v, float* C, float* t) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < (size_t)n * n) C[i] = (i / n == i % n) ? v : 0.0f;
+  if (i < (size_t)n) t[i] = 0.0f;
+}
+
+// l[b, off + m] = max(l, lbl[b, m]) and u[b, off + m] = min(u, -lbn[b, m]):
+// the CROWN bounds of one layer over each box (objective +I: lower bound,
+// objective -I: minus the upper bound), intersected with the bounds at hand.
+__global__ void k_merge_layer(int B, int n, int Nh, int off, const float* __restrict__ lbl,
+                              const float* __restrict__ lbn, float* l, float* u) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)B * n) return;
+  const size_t b = i / n, m = i % n;
+  float* pl = l + b * Nh + off + m;
+  float* pu = u + b * Nh + off + m;
+  *pl = fmaxf(*pl, lbl[i]);
+  *pu = fminf(*pu, -lbn[i]);
+}
+
 }  // namespace
 
 hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
@@ -430,5 +451,20 @@ hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const 
   }
   hipLaunchKernelGGL(k_select_topk, dim3(B, nlayers), dim3(256), 0, s, Nh, lt, l, u, weight, k,
                      select);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s) {
+  const size_t tot = (size_t)n * n;
+  hipLaunchKernelGGL(k_fill_eye, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, v, C, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, const float* lbn,
+                              float* l, float* u, hipStream_t s) {
+  const size_t tot = (size_t)B * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_layer, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, n, Nh,
+                     off, lbl, lbn, l, u);
   return hipGetLastError();
 }

@@ -77,18 +77,19 @@ def make_batch(prop, neuron, sign, count, lo=None, hi=None):
     return Batch(lo, hi, api.Constraints.splits(neuron, sign, count))
 
 
-def plain_pass(prop, batch, cfg=PassConfig(), out=None):
+def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
     """One pass of the hot path over a batch; boxes are clipped in place.
-    Returns dict(infeasible, l, u, lb)."""
+    Returns dict(infeasible, l, u, lb) and, with ``planes``, the final CROWN
+    plane of every row (A [B, M, n_in], c [B, M]; valid lower planes)."""
     B = batch.lo.shape[0]
     out = out if out is not None else {}
     clip_cons = batch.splits
-    if cfg.order and cfg.clip == "sequential":
+    if cfg.order and cfg.clip == "sequential" and batch.splits is not None:
         # sequential clipping takes the constraints closest to the box centre first
         clip_cons = batch.splits.with_order(
             api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order0")))
         out["order0"] = clip_cons.order
-    if cfg.clip != "none":
+    if cfg.clip != "none" and batch.splits is not None:
         inf = api.clip_domains(prop.root, batch.lo, batch.hi, clip_cons, cfg.clip,
                                infeasible=out.get("infeasible"))
     else:
@@ -98,7 +99,7 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None):
         else:
             inf.zero_()
     batch.ordered = None
-    if cfg.order:
+    if cfg.order and batch.splits is not None:
         # complete clipping: the order over the clipped box
         batch.ordered = batch.splits.with_order(
             api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order1")))
@@ -114,8 +115,13 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None):
                                       cfg.complete_intermediate, cfg.passes, inf,
                                       out.get("l"), out.get("u"), prop.ws2, cfg.topk, weight, select)
     cons = batch.cons() if cfg.complete_final else None
-    lb = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
-                             None, cfg.alpha, inf, cons, cfg.passes, ws=prop.ws)
+    res = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
+                              None, cfg.alpha, inf, cons, cfg.passes, want_plane=planes, ws=prop.ws)
+    if planes:
+        lb, A, c = res
+        out.update(A=A, c=c)
+    else:
+        lb = res
     out.update(infeasible=inf, l=l, u=u, lb=lb)
     return out
 

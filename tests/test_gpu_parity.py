@@ -512,3 +512,80 @@ def test_topk_complete_clipping_matches_oracle(make):
     assert (gsel != osel).sum() <= max(2, osel.sum() // 1000), "selection differs"
     assert osel.sum(-1).max() <= k * (len(w.net.layers) - 1) and osel.any()
     compare_pass(out, batch, ref, op)
+
+
+# ---------------------------------------------------------- branch and bound
+
+def test_branching_kernels_match_oracle():
+    from oracle import bab as obab
+    rng = np.random.default_rng(21)
+    B, Nh, n0, k = 200, 300, 17, 6
+    l = rng.normal(size=(B, Nh)).astype(np.float32)
+    u = (l + rng.uniform(0, 2, (B, Nh))).astype(np.float32)
+    u[:3] = np.abs(u[:3]) + 1.0
+    l[:3] = np.abs(l[:3]) + 0.1          # rows with nothing unstable
+    weight = rng.uniform(0, 1, Nh).astype(np.float32)
+    weight[::7] = 0.0
+    neuron = rng.integers(0, Nh, (B, k)).astype(np.int32)
+    sign = rng.choice([-1, 1], (B, k)).astype(np.int8)
+    count = rng.integers(0, k, B).astype(np.int32)
+    lo = rng.uniform(-1, 0, (B, n0)).astype(np.float32)
+    hi = (lo + rng.uniform(0, 1, (B, n0))).astype(np.float32)
+    # cv_branch_relu reads n_hidden / n_in from the root: a net of matching sizes
+    net = wl.he_mlp([n0, Nh, 3], 0)
+    p2 = gpipe.Property(list(net.layers), lo[0], hi[0], np.eye(3, dtype=np.float32),
+                        np.zeros(3, np.float32))
+    cons = api.Constraints.splits(neuron, sign, count)
+    chosen, ccons, lo2, hi2 = api.branch_relu(p2.root, T(l), T(u), T(weight), cons, T(lo), T(hi), k + 1)
+    sync()
+    ref = obab.branch_relu(l, u, weight, neuron, sign, count)
+    assert np.array_equal(H(chosen), ref)
+    n2, s2, c2, olo2, ohi2 = obab.children_relu(neuron, sign, count, lo, hi, ref)
+    assert np.array_equal(H(ccons.count), c2)
+    for r in range(2 * B):
+        assert np.array_equal(H(ccons.neuron)[r, :c2[r]], n2[r, :c2[r]])
+        assert np.array_equal(H(ccons.sign)[r, :c2[r]], s2[r, :c2[r]])
+    assert np.array_equal(H(lo2), olo2) and np.array_equal(H(hi2), ohi2)
+    A = rng.normal(size=(B, 2, n0)).astype(np.float32)
+    dim, ilo2, ihi2 = api.branch_input(T(lo), T(hi), T(A))
+    sync()
+    rd = obab.branch_input(lo, hi, A)
+    assert np.array_equal(H(dim), rd)
+    rlo2, rhi2 = obab.children_input(lo, hi, rd)
+    assert np.array_equal(H(ilo2), rlo2) and np.array_equal(H(ihi2), rhi2)
+
+
+def _tiny_property(row, frac):
+    """One output row of the tiny net, y_row >= thr, with thr = L + frac (m - L)
+    where L is the root CROWN bound and m the minimum over 2e5 samples:
+    0 < frac < 1 gives a true property the root bound cannot verify, frac > 1
+    a false one (the sampled minimum violates it)."""
+    w = wl.tiny_mlp(8)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 1, bias="uniform")
+    x = np.random.default_rng(wl.SEED_SAMPLES).uniform(w.lo0, w.hi0, size=(200000, 5))
+    m = wl.forward(w.net, x)[:, row].min()
+    C = np.zeros((1, 5), np.float32)
+    C[0, row] = 1.0
+    prop = gpipe.Property(list(w.net.layers), w.lo0, w.hi0, C, np.zeros(1, np.float32))
+    L = float(H(gpipe.plain_pass(prop, gpipe.Batch(*prop.boxes(1), None))["lb"])[0, 0])
+    thr = L + frac * (m - L)
+    prop = gpipe.Property(list(w.net.layers), w.lo0, w.hi0, C, np.array([-thr], np.float32))
+    return w, prop, thr
+
+
+@pytest.mark.parametrize("loop", ["activation", "input"])
+def test_bab_verifies_a_true_property_and_never_a_false_one(loop):
+    from paper_2512_11087_amd import bab
+    run = bab.activation_bab if loop == "activation" else bab.input_bab
+    w, prop, thr = _tiny_property(0, 0.5)
+    base = gpipe.plain_pass(prop, gpipe.Batch(*prop.boxes(1), None))
+    sync()
+    assert float(H(base["lb"]).min()) <= 0.0, "root bound already verifies: not a BaB test"
+    res = run(prop, batch=8192, max_iters=300)
+    assert res.verified, res
+    assert res.iterations >= 1 and res.visited > 1
+    x = np.random.default_rng(99).uniform(w.lo0, w.hi0, size=(100000, 5))
+    assert wl.forward(w.net, x)[:, 0].min() >= thr     # the verified claim holds at samples
+    w, prop, thr = _tiny_property(0, 1.02)
+    res = run(prop, batch=512, max_iters=15)
+    assert not res.verified

@@ -187,3 +187,32 @@ def test_alpha_opt_never_worse_than_plain():
     assert np.allclose(hist[0], out["lb"][fe])          # first iterate = plain bound
     assert np.all(best >= out["lb"][fe] - 1e-12)
     assert (best > out["lb"][fe] + 1e-6).any()
+
+
+def test_crown_intermediate_bounds_of_fresh_boxes():
+    # the root box reproduces the root pass; sub-boxes get sound bounds that
+    # are at least as tight as the re-concretized cached planes, and tighter
+    # somewhere
+    w, layers, root = tiny_setup(bias="uniform")
+    _, _, _, _, l0, u0 = root.stacked()
+    lo0 = w.lo0.astype(float)[None]
+    hi0 = w.hi0.astype(float)[None]
+    l, u = pipeline.reconcretize(root, lo0, hi0)
+    l, u, _ = pipeline.fix_bounds(root, l, u, np.zeros((1, 0), int), np.zeros((1, 0), int),
+                                  np.zeros(1, int), False)
+    lc, uc = pipeline.crown_intermediate(layers, root, lo0, hi0, l, u)
+    assert np.allclose(lc[0], l0, atol=1e-12) and np.allclose(uc[0], u0, atol=1e-12)
+    rng = np.random.default_rng(7)
+    B = 32
+    a = rng.uniform(w.lo0, w.hi0, size=(B, 5))
+    b = rng.uniform(w.lo0, w.hi0, size=(B, 5))
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    l, u = pipeline.reconcretize(root, lo, hi)
+    l, u, _ = pipeline.fix_bounds(root, l, u, np.zeros((B, 0), int), np.zeros((B, 0), int),
+                                  np.zeros(B, int), False)
+    lc, uc = pipeline.crown_intermediate(layers, root, lo, hi, l, u)
+    assert np.all(lc >= l) and np.all(uc <= u) and (lc > l + 1e-9).any()
+    for bb in range(B):
+        x = rng.uniform(lo[bb], hi[bb], size=(3000, 5))
+        z = wl.pre_activations(w.net, x)
+        assert np.all(z >= lc[bb] - 1e-9) and np.all(z <= uc[bb] + 1e-9)
