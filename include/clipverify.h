@@ -288,9 +288,11 @@ cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes);
  * earlier layers), concretized over the box and intersected with the
  * bounds passed in.  l, u: device [B, n_hidden] in/out, valid bounds on
  * entry (e.g. from cv_concretize_planes, which gives layer 1 exactly); lo,
- * hi: device [B, n_in] inside the root box.  infeasible: [B] or NULL. */
+ * hi: device [B, n_in] inside the root box.  infeasible: [B] in/out or
+ * NULL: flagged boxes are skipped; a box whose bounds cross (l > u) is
+ * flagged. */
 cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* lo, const float* hi,
-                                 float* l, float* u, const uint8_t* infeasible, void* ws,
+                                 float* l, float* u, uint8_t* infeasible, void* ws,
                                  size_t ws_bytes, hipStream_t stream);
 cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes);
 

@@ -14,10 +14,13 @@ Input BaB (Alg. 4, with the paper's reordering): a subdomain is an input
 box with the final CROWN plane A x + c of its parent.  Each round splits
 the picked boxes in two (cv_branch_input), clips both children by their
 parent's plane (the region where the objective can be negative lies in
-A x + c <= 0) and bounds them with that plane as the constraint of complete
-clipping; each child keeps its own plane for its children.  One objective
-row per run (for several rows the violating region is a union, which one
-row's plane cannot clip).
+A x + c <= 0), bounds their hidden neurons afresh (cached planes
+re-concretized, then CROWN over the box, cv_intermediate_bounds: the box
+shrinks, so re-concretized root planes alone would not converge) and bounds
+the objective with that plane as the constraint of complete clipping; each
+child keeps its own plane for its children.  One objective row per run
+(for several rows the violating region is a union, which one row's plane
+cannot clip).
 
 The pool lives in device memory; picking, filtering and appending are
 tensor slicing.  Every bound, clip and branch is a library call.
@@ -27,7 +30,7 @@ from dataclasses import dataclass, field
 import torch
 
 from . import api
-from .pipeline import Batch, PassConfig, plain_pass
+from .pipeline import Batch, PassConfig, input_pass, plain_pass
 
 
 @dataclass
@@ -45,11 +48,7 @@ def _verified(out):
     return inf | (out["lb"] > 0).all(dim=-1)
 
 
-def _cat(a, b):
-    return b if a is None else torch.cat([a, b], 0)
-
-
-def activation_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20, kmax=32,
+def activation_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20, kmax=64,
                    cfg=PassConfig(complete_intermediate=True, topk=20)):
     """Activation BaB of one property over its root box.  Returns BabResult."""
     root = prop.root
@@ -93,13 +92,12 @@ def activation_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20, kmax=32
     return BabResult(remaining == 0 and stuck == 0, it, visited, remaining, stuck, hist)
 
 
-def input_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20,
-              cfg=PassConfig(complete_intermediate=True, topk=20)):
+def input_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20, cfg=PassConfig()):
     """Input BaB of a one-row property (prop.M == 1).  Returns BabResult."""
     if prop.M != 1:
         raise ValueError("input_bab bounds one objective row (see the module docstring)")
     lo, hi = prop.boxes(1)
-    out = plain_pass(prop, Batch(lo.clone(), hi.clone(), None), cfg, planes=True)
+    out = input_pass(prop, Batch(lo.clone(), hi.clone(), None), cfg)
     if bool(_verified(out).all()):
         return BabResult(True, 0, 1, 0)
     pool = dict(lo=lo, hi=hi, A=out["A"][:, 0, :], c=out["c"][:, 0])
@@ -115,7 +113,7 @@ def input_bab(prop, batch=1024, max_iters=100, max_domains=1 << 20,
         G = par["A"].repeat_interleave(2, 0)[:, None, :].contiguous()
         h = par["c"].repeat_interleave(2, 0)[:, None].contiguous()
         ccons = api.Constraints.dense(G, h)
-        out = plain_pass(prop, Batch(lo2, hi2, ccons), cfg, planes=True)
+        out = input_pass(prop, Batch(lo2, hi2, ccons), cfg)
         visited += 2 * take
         keep = ~_verified(out)
         kids = dict(lo=lo2[keep], hi=hi2[keep], A=out["A"][keep][:, 0, :], c=out["c"][keep][:, 0])

@@ -664,7 +664,7 @@ cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes) {
 }
 
 cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* lo, const float* hi,
-                                 float* l, float* u, const uint8_t* infeasible, void* ws,
+                                 float* l, float* u, uint8_t* infeasible, void* ws,
                                  size_t ws_bytes, hipStream_t s) {
   if (!net || !root || B < 0) return CV_E_INVALID;
   if (root->net != net) return CV_E_INVALID;
@@ -689,7 +689,7 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
                                   infeasible, w, side ? lbn : lbl, nullptr, nullptr, s);
       if (st) return st;
     }
-    PLAUNCH("merge_layer", 0, 16.0 * B * ni, launch_merge_layer(B, ni, Nh, net->off[i - 1], lbl, lbn, l, u, s));
+    PLAUNCH("merge_layer", 0, 16.0 * B * ni, launch_merge_layer(B, ni, Nh, net->off[i - 1], lbl, lbn, l, u, infeasible, s));
   }
   return CV_OK;
 }

@@ -175,7 +175,7 @@ hipError_t launch_branch_input(int B, int M, int n0, const float* lo, const floa
                                hipStream_t s);
 hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s);
 hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, const float* lbn,
-                              float* l, float* u, hipStream_t s);
+                              float* l, float* u, uint8_t* infeasible, hipStream_t s);
 hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s);
 hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
                               const float* l, const float* u, const float* weight, int k,

@@ -323,14 +323,17 @@ __global__ void k_fill_eye(int n, float v, float* C, float* t) {
 // the CROWN bounds of one layer over each box (objective +I: lower bound,
 // objective -I: minus the upper bound), intersected with the bounds at hand.
 __global__ void k_merge_layer(int B, int n, int Nh, int off, const float* __restrict__ lbl,
-                              const float* __restrict__ lbn, float* l, float* u) {
+                              const float* __restrict__ lbn, float* l, float* u,
+                              uint8_t* infeasible) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)B * n) return;
   const size_t b = i / n, m = i % n;
   float* pl = l + b * Nh + off + m;
   float* pu = u + b * Nh + off + m;
-  *pl = fmaxf(*pl, lbl[i]);
-  *pu = fminf(*pu, -lbn[i]);
+  const float nl = fmaxf(*pl, lbl[i]), nu = fminf(*pu, -lbn[i]);
+  *pl = nl;
+  *pu = nu;
+  if (nl > nu && infeasible) infeasible[b] = 1;  // both bounds valid: the box is empty
 }
 
 }  // namespace
@@ -461,10 +464,10 @@ hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s) {
 }
 
 hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, const float* lbn,
-                              float* l, float* u, hipStream_t s) {
+                              float* l, float* u, uint8_t* infeasible, hipStream_t s) {
   const size_t tot = (size_t)B * n;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_layer, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, n, Nh,
-                     off, lbl, lbn, l, u);
+                     off, lbl, lbn, l, u, infeasible);
   return hipGetLastError();
 }

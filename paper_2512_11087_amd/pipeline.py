@@ -158,6 +158,30 @@ def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0
     return best, alpha
 
 
+def input_pass(prop, batch, cfg=PassConfig(), out=None):
+    """Bounding of fresh input boxes (input BaB): relaxed clipping by the
+    boxes' constraints (batch.splits, e.g. the parent's final plane in dense
+    form), intermediate bounds from the cached planes tightened by CROWN over
+    each box, the CROWN bound and complete clipping of the final plane
+    against the constraints.  Returns dict(infeasible, l, u, lb, A, c)."""
+    B = batch.lo.shape[0]
+    out = out if out is not None else {}
+    if cfg.clip != "none" and batch.splits is not None:
+        inf = api.clip_domains(prop.root, batch.lo, batch.hi, batch.splits, cfg.clip,
+                               infeasible=out.get("infeasible"))
+    else:
+        inf = torch.zeros(B, dtype=torch.uint8, device="cuda")
+    l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, None, False, 1, inf,
+                                      out.get("l"), out.get("u"), prop.ws2)
+    api.intermediate_bounds(prop.net, prop.root, batch.lo, batch.hi, l, u, inf, prop.ws2)
+    cons = batch.splits if cfg.complete_final else None
+    lb, A, c = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
+                                   None, cfg.alpha, inf, cons, cfg.passes, want_plane=True,
+                                   ws=prop.ws)
+    out.update(infeasible=inf, l=l, u=u, lb=lb, A=A, c=c)
+    return out
+
+
 class AlphaBound(torch.autograd.Function):
     """lb(alpha) [B, M] as a differentiable function of the slopes alpha
     [B, M, n_hidden]: the forward pass runs the bound (backward pass,

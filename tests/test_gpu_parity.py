@@ -577,7 +577,7 @@ def _tiny_property(row, frac):
 def test_bab_verifies_a_true_property_and_never_a_false_one(loop):
     from paper_2512_11087_amd import bab
     run = bab.activation_bab if loop == "activation" else bab.input_bab
-    w, prop, thr = _tiny_property(0, 0.5)
+    w, prop, thr = _tiny_property(0, 0.3)
     base = gpipe.plain_pass(prop, gpipe.Batch(*prop.boxes(1), None))
     sync()
     assert float(H(base["lb"]).min()) <= 0.0, "root bound already verifies: not a BaB test"
@@ -589,3 +589,29 @@ def test_bab_verifies_a_true_property_and_never_a_false_one(loop):
     w, prop, thr = _tiny_property(0, 1.02)
     res = run(prop, batch=512, max_iters=15)
     assert not res.verified
+
+
+def test_input_pass_matches_oracle():
+    # fresh sub-boxes of the tiny net's root box with one dense plane constraint
+    # each: relaxed clipping, CROWN intermediate bounds over the box, final bound
+    # with complete clipping against the plane
+    w = wl.tiny_mlp(8)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 1, bias="uniform")
+    op = OracleProp(w)
+    rng = np.random.default_rng(17)
+    B = 96
+    a = rng.uniform(w.lo0, w.hi0, size=(B, 5))
+    b = rng.uniform(w.lo0, w.hi0, size=(B, 5))
+    lo, hi = np.minimum(a, b).astype(np.float32), np.maximum(a, b).astype(np.float32)
+    G = rng.normal(size=(B, 1, 5)).astype(np.float32)
+    xs = rng.uniform(lo, hi)
+    h = (-(G[:, 0] * xs).sum(-1, keepdims=True) + rng.normal(0, 0.05, (B, 1))).astype(np.float32)
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.Batch(T(lo), T(hi), api.Constraints.dense(G, h))
+    out = gpipe.input_pass(prop, batch)
+    sync()
+    ref = opipe.run(op.layers, op.root, w.C, w.t, lo, hi, None, None, None,
+                    opipe.Config(intermediate="crown"), dense=(G, h, np.ones((B, 1), bool)))
+    compare_pass(out, batch, ref, op)
+    assert ref["infeasible"].any() and (ref["lb"][~ref["infeasible"]] >
+                                        ref["lb_unclipped"][~ref["infeasible"]] + 1e-6).any()
