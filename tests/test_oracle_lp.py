@@ -200,3 +200,26 @@ def test_coordinate_ascent_is_a_valid_and_useful_dual_bound():
         assert L2[0] >= L[0] - 1e-9                          # ascent
         assert L2[0] <= Lp + 1e-9
         assert np.all(beta >= 0.0)
+
+
+def test_coordinate_ascent_is_exact_for_disjoint_constraints():
+    # constraints on disjoint coordinate sets: the dual separates into one
+    # concave function per multiplier, so one pass of exact 1-D maximisations
+    # reaches the dual optimum, which equals the LP optimum (strong duality)
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        n, k = 9, 3
+        lo = rng.uniform(-1, 0, n)
+        hi = rng.uniform(0, 1, n)
+        a = rng.normal(size=n)
+        perm = rng.permutation(n)
+        G = np.zeros((k, n))
+        for q, part in enumerate(np.array_split(perm, k)):
+            G[q, part] = rng.normal(size=part.size)
+        xs = rng.uniform(lo, hi)
+        h = -(G @ xs) - rng.uniform(0.0, 0.2, k)
+        act = np.ones((1, k), bool)
+        L, _, emp = complete.coord_ascent(a[None], np.zeros(1), G[None], h[None], lo[None], hi[None], act)
+        assert not emp[0]
+        lp = exact.lp_simplex(a, 0.0, G, h, lo, hi)
+        assert L[0] == pytest.approx(float(lp), abs=1e-9)
