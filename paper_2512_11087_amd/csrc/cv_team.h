@@ -1,0 +1,150 @@
+// Teams of threads that hold one problem over an input of dimension n
+// (a wave64 for n <= 1024, a 256-thread workgroup for n <= 4096), and the
+// dispatch of (team, elements per member) from n.  Shared by the kernels that
+// keep one subdomain's box in registers (relaxed and complete clipping).
+#pragma once
+#include "cv_common.h"
+
+namespace {
+
+constexpr int CV_TEAM_KMAX = 64;  // constraint slots whose metadata a team broadcasts
+
+// A team of threads that holds one problem.  Wave: the 64 lanes of a wave,
+// four problems per 256-thread workgroup, reductions by DPP and readlane,
+// constraint metadata broadcast by readlane.  Block: the 256 threads of a
+// workgroup, one problem each, reductions through LDS.  Every member calls
+// every team operation (control flow is uniform within a team).
+struct WaveTeam {
+  static constexpr int SIZE = 64;
+  static constexpr int PER_BLOCK = 4;
+  int t;
+  __device__ static int index_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+  __device__ double sum(double v) const { return wave_sum(v); }
+  __device__ void sum3(double& a, double& b, double& c) const { wave_sum3(a, b, c); }
+  __device__ double max(double v) const { return wave_max(v); }
+  __device__ double min(double v) const { return wave_min(v); }
+  // member k < cnt holds constraint k's row pointer, scale and offset
+  __device__ void publish(const float*, float, double, int) const {}
+  __device__ void meta(const float* my_row, float my_scale, double my_h, int k, const float*& row,
+                       float& scale, double& h) const {
+    const uint64_t u = (uint64_t)(uintptr_t)my_row;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), k);
+    row = (const float*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    scale = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_scale), k));
+    h = lane_f64(my_h, k);
+  }
+};
+
+struct BlockTeam {
+  static constexpr int SIZE = 256;
+  static constexpr int PER_BLOCK = 1;
+  int t;
+  double* red;          // LDS [12]
+  const float** mrow;   // LDS [CV_TEAM_KMAX]
+  float* mscale;        // LDS [CV_TEAM_KMAX]
+  double* mh;           // LDS [CV_TEAM_KMAX]
+  __device__ static int index_in_block() { return 0; }
+  __device__ double sum(double v) const {
+    v = wave_sum(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+  }
+  __device__ void sum3(double& a, double& b, double& c) const {
+    wave_sum3(a, b, c);
+    if ((t & 63) == 0) {
+      red[t >> 6] = a;
+      red[4 + (t >> 6)] = b;
+      red[8 + (t >> 6)] = c;
+    }
+    __syncthreads();
+    a = (red[0] + red[1]) + (red[2] + red[3]);
+    b = (red[4] + red[5]) + (red[6] + red[7]);
+    c = (red[8] + red[9]) + (red[10] + red[11]);
+    __syncthreads();
+  }
+  __device__ double max(double v) const {
+    v = wave_max(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+  }
+  __device__ double min(double v) const {
+    v = wave_min(v);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    __syncthreads();
+    return r;
+  }
+  __device__ void publish(const float* my_row, float my_scale, double my_h, int cnt) const {
+    if (t < cnt) {
+      mrow[t] = my_row;
+      mscale[t] = my_scale;
+      mh[t] = my_h;
+    }
+    __syncthreads();
+  }
+  __device__ void meta(const float*, float, double, int k, const float*& row, float& scale,
+                       double& h) const {
+    row = mrow[k];
+    scale = mscale[k];
+    h = mh[k];
+  }
+};
+
+// The team of member threadIdx.x, with its LDS scratch (used by BlockTeam).
+template <class Team>
+__device__ __forceinline__ Team make_team(double* red, const float** mrow, float* mscale,
+                                          double* mh) {
+  if constexpr (Team::PER_BLOCK == 1)
+    return Team{(int)threadIdx.x, red, mrow, mscale, mh};
+  else
+    return Team{(int)(threadIdx.x & 63)};
+}
+
+int epl_for(int n) {
+  const int e = (n + 63) / 64;
+  if (e <= 1) return 1;
+  if (e <= 2) return 2;
+  if (e <= 4) return 4;
+  if (e <= 8) return 8;
+  if (e <= 13) return 13;
+  if (e <= 16) return 16;
+  return -1;
+}
+
+// Team TM and elements per member E for an input dimension n (<= 4096): a
+// wave up to 1024 coordinates, a workgroup beyond.
+#define CV_DISPATCH_TEAM(n, CALL)                                          \
+  if ((n) <= 1024) {                                                       \
+    typedef WaveTeam TM;                                                   \
+    switch (epl_for(n)) {                                                  \
+      case 1: { constexpr int E = 1; CALL; } break;                        \
+      case 2: { constexpr int E = 2; CALL; } break;                        \
+      case 4: { constexpr int E = 4; CALL; } break;                        \
+      case 8: { constexpr int E = 8; CALL; } break;                        \
+      case 13: { constexpr int E = 13; CALL; } break;                      \
+      case 16: { constexpr int E = 16; CALL; } break;                      \
+      default: return hipErrorInvalidValue;                                \
+    }                                                                      \
+  } else if ((n) <= 2048) {                                                \
+    typedef BlockTeam TM; constexpr int E = 8; CALL;                       \
+  } else if ((n) <= 3072) {                                                \
+    typedef BlockTeam TM; constexpr int E = 12; CALL;                      \
+  } else if ((n) <= 4096) {                                                \
+    typedef BlockTeam TM; constexpr int E = 16; CALL;                      \
+  } else {                                                                 \
+    return hipErrorInvalidValue;                                           \
+  }
+
+inline unsigned team_blocks(long long problems, int per_block) {
+  return (unsigned)((problems + per_block - 1) / per_block);
+}
+
+}  // namespace

@@ -1,8 +1,9 @@
 // Relaxed clipping of subdomain boxes by linear constraints G x + h <= 0
 // (Thm 3.2; parallel form Alg. 2, sequential form Alg. 3).
 //
-// One 256-thread workgroup per subdomain; thread t owns coordinates
-// t, t + 256, ... of the box (kept in registers), so the per-constraint
+// One team per subdomain -- a wave64 for n <= 1024 (four subdomains per
+// workgroup), a 256-thread workgroup up to 4096; member t owns coordinates
+// t, t + T, ... of the box (kept in registers), so the per-constraint
 // reduction m = min over the box of g.x + h is the only cross-thread step.
 // Constraint rows are read either from the cached root planes (split form,
 // eqs. 9-10) or from a dense G.
@@ -16,95 +17,103 @@
 // float32 box always contains the exact clipped box.
 #include "cv_common.h"
 #include "cv_internal.h"
+#include "cv_team.h"
 
 namespace {
 
-constexpr int CT = 256;
-constexpr int EPT = 16;  // coordinates per thread: n <= 4096
-
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) {
-    sh[w * 2] = a;
-    sh[w * 2 + 1] = b;
-  }
-  __syncthreads();
-  a = sh[0] + sh[2] + sh[4] + sh[6];
-  b = sh[1] + sh[3] + sh[5] + sh[7];
-}
-
-__global__ __launch_bounds__(CT) void k_clip(int B, int n, CvCons cons, float* lo, float* hi,
-                                             uint8_t* infeasible, int mode) {
-  __shared__ double sh[8];
-  const int b = blockIdx.x;
-  const int tid = threadIdx.x;
-  float olo[EPT], ohi[EPT], nlo[EPT], nhi[EPT];
+// One team per subdomain (a wave for n <= 1024, a workgroup up to 4096);
+// member t owns coordinates t, t + T, ... of the box in registers, loaded
+// with range-checked buffer loads (no branch per element).
+template <class Team, int EPL>
+__global__ __launch_bounds__(256) void k_clip(int B, int n, CvCons cons, float* lo, float* hi,
+                                              uint8_t* infeasible, int mode) {
+  __shared__ double red[12];
+  __shared__ const float* mrow[CV_TEAM_KMAX];
+  __shared__ float mscale[CV_TEAM_KMAX];
+  __shared__ double mh[CV_TEAM_KMAX];
+  const Team tm = make_team<Team>(red, mrow, mscale, mh);
+  constexpr int T = Team::SIZE;
+  const int t = tm.t;
+  const int b = blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
+  if (b >= B) return;
+  float* lob = lo + (size_t)b * n;
+  float* hib = hi + (size_t)b * n;
+  const cv_buf blo = cv_buffer(lob, 4u * n), bhi = cv_buffer(hib, 4u * n);
+  float olo[EPL], ohi[EPL], nlo[EPL], nhi[EPL];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + q * CT;
-    olo[q] = ld_or0(lo + (size_t)b * n, i, n);
-    ohi[q] = ld_or0(hi + (size_t)b * n, i, n);
-    nlo[q] = olo[q];
-    nhi[q] = ohi[q];
+  for (int e = 0; e < EPL; ++e) {
+    const int j = t + T * e;
+    olo[e] = buf_f32(blo, 4 * j);
+    ohi[e] = buf_f32(bhi, 4 * j);
+    nlo[e] = olo[e];
+    nhi[e] = ohi[e];
   }
   const int cnt = cons_count(cons, b);
+  // member k fetches constraint k's row pointer, sign and offset up front
+  // (up to CV_TEAM_KMAX constraints; beyond, each is fetched in the loop)
+  const float* my_row = nullptr;
+  float my_scale = 0.0f;
+  double my_h = 0.0;
+  if (t < cnt && t < CV_TEAM_KMAX) cons_row(cons, b, t, n, my_row, my_scale, my_h);
+  tm.publish(my_row, my_scale, my_h, cnt < CV_TEAM_KMAX ? cnt : CV_TEAM_KMAX);
   bool empty = false;
+#pragma unroll 1
   for (int k = 0; k < cnt; ++k) {
     const float* row;
     float scale;
     double h;
-    cons_row(cons, b, k, n, row, scale, h);
+    if (k < CV_TEAM_KMAX)
+      tm.meta(my_row, my_scale, my_h, k, row, scale, h);
+    else
+      cons_row(cons, b, k, n, row, scale, h);
     if (!row) continue;
-    float g[EPT];
-    double m = 0.0, e = 0.0;
+    const cv_buf brow = cv_buffer(row, 4u * n);
+    float g[EPL];
+    double m = 0.0, err = 0.0, zero = 0.0;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int i = tid + q * CT;
-      g[q] = scale * ld_or0(row, i, n);
-      const double x0 = mode ? (double)nlo[q] : (double)olo[q];
-      const double x1 = mode ? (double)nhi[q] : (double)ohi[q];
-      const double gg = (double)g[q];
+    for (int e = 0; e < EPL; ++e) {
+      g[e] = scale * buf_f32(brow, 4 * (t + T * e));
+      const double x0 = mode ? (double)nlo[e] : (double)olo[e];
+      const double x1 = mode ? (double)nhi[e] : (double)ohi[e];
+      const double gg = (double)g[e];
       m += fmin(gg * x0, gg * x1);
-      e += fabs(gg) * fmax(fabs(x0), fabs(x1));
+      err += fabs(gg) * fmax(fabs(x0), fabs(x1));
     }
-    block_sum2(m, e, sh);
+    tm.sum3(m, err, zero);
     m += h;
-    const double mlo = m - cv_gamma(n + 1) * (e + fabs(h)) * CV_ERR_SLACK;
+    const double mlo = m - cv_gamma(n + 1) * (err + fabs(h)) * CV_ERR_SLACK;
     if (mlo > 0.0) {
       empty = true;
       break;
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const double gg = (double)g[q];
+    for (int e = 0; e < EPL; ++e) {
+      const double gg = (double)g[e];
       if (gg > 0.0) {
-        const double base = mode ? (double)nlo[q] : (double)olo[q];
+        const double base = mode ? (double)nlo[e] : (double)olo[e];
         const double d = mlo / gg;
         const double v = base - d + (fabs(base) + fabs(d)) * (4.0 * CV_U64);
-        nhi[q] = fminf(nhi[q], ru32(v));
+        nhi[e] = fminf(nhi[e], ru32(v));
       } else if (gg < 0.0) {
-        const double base = mode ? (double)nhi[q] : (double)ohi[q];
+        const double base = mode ? (double)nhi[e] : (double)ohi[e];
         const double d = mlo / gg;
         const double v = base - d - (fabs(base) + fabs(d)) * (4.0 * CV_U64);
-        nlo[q] = fmaxf(nlo[q], rd32(v));
+        nlo[e] = fmaxf(nlo[e], rd32(v));
       }
     }
   }
-  int bad = 0;
+  double bad = 0.0;
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int i = tid + q * CT;
-    if (i < n) {
-      lo[(size_t)b * n + i] = nlo[q];
-      hi[(size_t)b * n + i] = nhi[q];
-      bad |= (nlo[q] > nhi[q]) ? 1 : 0;
+  for (int e = 0; e < EPL; ++e) {
+    const int j = t + T * e;
+    if (j < n) {
+      lob[j] = nlo[e];
+      hib[j] = nhi[e];
+      if (nlo[e] > nhi[e]) bad = 1.0;
     }
   }
-  bad = __syncthreads_or(bad);
-  if (tid == 0) infeasible[b] = (empty || bad) ? 1 : 0;
+  bad = tm.max(bad);
+  if (t == 0) infeasible[b] = (empty || bad > 0.0) ? 1 : 0;
 }
 
 // Constraint importance order (heuristics appendix): position -> slot for
@@ -167,7 +176,7 @@ hipError_t launch_cons_order(int B, int n, const CvCons& cons, const float* lo, 
 hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, uint8_t* infeasible,
                        int mode, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  if (n > CT * EPT) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_clip, dim3(B), dim3(CT), 0, s, B, n, cons, lo, hi, infeasible, mode);
+  CV_DISPATCH_TEAM(n, hipLaunchKernelGGL((k_clip<TM, E>), dim3(team_blocks(B, TM::PER_BLOCK)),
+                                         dim3(256), 0, s, B, n, cons, lo, hi, infeasible, mode));
   return hipGetLastError();
 }
