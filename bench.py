@@ -110,6 +110,10 @@ def main():
     ap.add_argument("--alpha-steps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the slope iterations as one captured HIP graph (their kernels "
+                         "are then not timed one by one, so the roofline entry covers the "
+                         "plain pass only)")
     ap.add_argument("--kernels-json", default=None, help="write the per-kernel timing table here")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB and exit "
@@ -163,8 +167,18 @@ def main():
         batch.hi.copy_(hi_init)
         return gpipe.plain_pass(prop, batch, gpipe.PassConfig(), pstate)
 
+    graph = None
+    if args.graph:
+        # the plain pass writes its bounds into the same buffers every step,
+        # so one capture of the slope iterations serves every step
+        out0 = plain_step()
+        graph = gpipe.AlphaOptGraph(prop, batch, out0["l"], out0["u"], out0["infeasible"],
+                                    steps=T, lr=0.1)
+
     def full_step():
         out = plain_step()
+        if graph is not None:
+            return out, graph.run()
         best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=T,
                                   lr=0.1, state=state)
         return out, best
@@ -240,7 +254,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {B} subdomains x {ksplit} splits, 9 margin rows, "
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
-                   "global_batch": B, "alpha_steps": T, "io_dtype": "f32"},
+                   "global_batch": B, "alpha_steps": T, "io_dtype": "f32",
+                   "launch": "hip graph (slope iterations)" if args.graph else "eager"},
         "plain": {"value": round(B / plain_s, 1), "unit": "subdomains/s",
                   "ms_per_pass": round(1e3 * plain_s, 3)},
         "alpha_vs_plain": {"throughput_ratio": round(value / (B / plain_s), 5),

@@ -306,6 +306,25 @@ def bound_propagate(net, root, C_, t, l, u, lo, hi, alpha=None, alpha_default=0.
     return (lb, A, c) if want_plane else lb
 
 
+def alpha_step_into(net, root, C_, t, l, u, alpha, lo, hi, infeasible, cons, passes, adam_m,
+                    adam_v, step, lr, lb, ws, beta1=0.9, beta2=0.999, eps=1e-8):
+    """alpha_step writing the bound into a given buffer lb [B, M] and using a
+    workspace that is already large enough (no allocation: usable under
+    stream capture)."""
+    B = lo.shape[0]
+    M = C_.shape[0]
+    need = C.c_size_t()
+    N.call("cv_alpha_step_workspace", net.handle, B, M, C.byref(need))
+    buf = ws.buf
+    if buf is None or buf.numel() < need.value:
+        raise RuntimeError("workspace too small for alpha_step_into; size it before capture")
+    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
+           _p(hi), _p(infeasible), root.handle, _cref(cons), int(passes), _p(adam_m),
+           _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
+           None, _p(buf), need.value, _stream())
+    return lb
+
+
 def alpha_step(net, root, C_, t, l, u, alpha, lo, hi, infeasible=None, cons=None, passes=1,
                adam_m=None, adam_v=None, step=1, lr=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
                want_grad=False, ws=None):

@@ -208,3 +208,45 @@ class AlphaBound(torch.autograd.Function):
 def bound(prop, batch, l, u, alpha, infeasible, complete=True, passes=1):
     """Differentiable bound: ``bound(...).sum().backward()`` fills alpha.grad."""
     return AlphaBound.apply(alpha, prop, batch, l, u, infeasible, complete, passes)
+
+
+class AlphaOptGraph:
+    """Slope optimisation (`steps` x alpha_step, fixed batch and bounds)
+    captured once into a HIP graph and replayed: the step index and learning
+    rate of every iteration are baked into its launches, the buffers are
+    allocated before capture (the calls themselves only launch kernels).
+    ``run()`` resets alpha and the Adam moments inside the graph and returns
+    the best bound [B, M] over the iterations (a buffer the graph writes)."""
+
+    def __init__(self, prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0=0.5,
+                 complete=True, passes=1):
+        B, M, nh = batch.lo.shape[0], prop.M, prop.net.n_hidden
+        self.alpha = torch.full((B, M, nh), alpha0, device="cuda")
+        self.m = torch.zeros_like(self.alpha)
+        self.v = torch.zeros_like(self.alpha)
+        self.best = torch.full((B, M), -float("inf"), device="cuda")
+        self.lbs = [torch.empty(B, M, device="cuda") for _ in range(steps)]
+        cons = batch.cons() if complete else None
+        # size the workspace outside the capture
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, self.alpha, batch.lo, batch.hi,
+                       infeasible, cons, passes, self.m, self.v, 1, 0.0, ws=prop.ws)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(self.graph, stream=side):
+                self.alpha.fill_(alpha0)
+                self.m.fill_(0.0)
+                self.v.fill_(0.0)
+                self.best.fill_(-float("inf"))
+                for s in range(1, steps + 1):
+                    api.alpha_step_into(prop.net, prop.root, prop.C, prop.t, l, u, self.alpha,
+                                        batch.lo, batch.hi, infeasible, cons, passes, self.m,
+                                        self.v, s, lr * decay ** (s - 1), self.lbs[s - 1], prop.ws)
+                    torch.maximum(self.best, self.lbs[s - 1], out=self.best)
+        torch.cuda.current_stream().wait_stream(side)
+
+    def run(self):
+        self.graph.replay()
+        return self.best

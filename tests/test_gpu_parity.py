@@ -615,3 +615,28 @@ def test_input_pass_matches_oracle():
     compare_pass(out, batch, ref, op)
     assert ref["infeasible"].any() and (ref["lb"][~ref["infeasible"]] >
                                         ref["lb_unclipped"][~ref["infeasible"]] + 1e-6).any()
+
+
+def test_alpha_opt_graph_replays_match_eager():
+    # the captured slope optimisation, replayed several times with eager work
+    # in between, gives the eager result bit for bit every time
+    w = wl.tiny_mlp(128)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 3, bias="uniform")
+    sp = wl.draw_splits(128, w.split_counts[:128], np.arange(w.net.n_hidden))
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    eager, alpha_e = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=6,
+                                     lr=0.1)
+    eager = H(eager).copy()
+    alpha_e = H(alpha_e).copy()
+    g = gpipe.AlphaOptGraph(prop, batch, out["l"], out["u"], out["infeasible"], steps=6, lr=0.1)
+    for rep in range(3):
+        best = H(g.run()).copy()
+        sync()
+        assert np.array_equal(best, eager), f"replay {rep}"
+        assert np.array_equal(H(g.alpha), alpha_e), f"replay {rep} alpha"
+        # unrelated eager work between replays
+        gpipe.plain_pass(prop, gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count),
+                         gpipe.PassConfig())
+        sync()
