@@ -103,9 +103,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mlp784-256x6-10",
-                    choices=["mlp784-256x6-10", "mlp784-1024x4-10"],
-                    help="784-256x6-10 (16384 x 4 splits, the metric's workload) or "
-                         "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024)")
+                    choices=["mlp784-256x6-10", "mlp784-1024x4-10", "cnn3x32x32"],
+                    help="784-256x6-10 (16384 x 4 splits, the metric's workload), "
+                         "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024) or "
+                         "cnn3x32x32 (conv16-conv32-100-10 on 3x32x32 inputs, one property, "
+                         "4096 subdomains, split depth 1..12)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--alpha-steps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=256)
@@ -144,10 +146,13 @@ def main():
     if args.workload == "mlp784-256x6-10":
         B = args.batch or 16384
         w = wl.mnist_mlp(B)
-    else:
+    elif args.workload == "mlp784-1024x4-10":
         B = args.batch or 8192
         w = wl.alpha_mlp(B)
-    ksplit = int(w.split_counts[0])
+    else:
+        B = args.batch or 4096
+        w = wl.cifar_cnn(B)
+    ksplit = int(w.split_counts.max())
     log(f"workload {w.name}: B={B}, k={ksplit}, M={w.C.shape[0]}, alpha steps={T}")
     t0 = time.perf_counter()
     prop = gpipe.Property.from_workload(w)
@@ -252,7 +257,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {B} subdomains x {ksplit} splits, 9 margin rows, "
+        "config": {"workload": f"{w.name}: {B} subdomains x {'<=' if w.split_counts.min() < ksplit else ''}{ksplit} splits, 9 margin rows, "
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
                    "global_batch": B, "alpha_steps": T, "io_dtype": "f32",
                    "launch": "hip graph (slope iterations)" if args.graph else "eager"},

@@ -80,12 +80,13 @@ typedef struct {
 typedef struct cv_net_s* cv_net;
 
 /* Copies the weights to the current device.  n_layers >= 2 (one hidden ReLU
- * layer at least).  A conv layer is stored as the dense matrix of its linear
- * map (in_features = in_c*in_h*in_w, out_features = out_c*out_h*out_w,
- * out_h = (in_h + 2 pad - kernel)/stride + 1, likewise out_w), so every
- * later step treats it like a linear layer; layers whose dense matrix
- * exceeds 2^28 entries return CV_E_UNSUPPORTED, inconsistent sizes
- * CV_E_SHAPE. */
+ * layer at least).  A conv layer (in_features = in_c*in_h*in_w, out_features
+ * = out_c*out_h*out_w, out_h = (in_h + 2 pad - kernel)/stride + 1, likewise
+ * out_w, activations flattened channel-major) is kept twice: as the dense
+ * matrix of its linear map (root planes, objective layer) and as its kernel,
+ * with which the backward passes and the adjoint run direct (transposed)
+ * convolutions.  Layers whose dense matrix exceeds 2^28 entries return
+ * CV_E_UNSUPPORTED, inconsistent sizes CV_E_SHAPE. */
 cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out);
 cv_status cv_net_destroy(cv_net net);
 /* Host outputs: input dim, output dim, total hidden neurons, layer count. */

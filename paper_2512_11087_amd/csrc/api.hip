@@ -98,6 +98,26 @@ cv_status dev_alloc(T** p, size_t count) {
   return CV_OK;
 }
 
+// Layer i (1-based) computed as a direct convolution, or null for a GEMM.
+const ConvDesc* conv_of(const cv_net_s* net, int i) {
+  return net->is_conv[i - 1] ? &net->conv[i - 1] : nullptr;
+}
+
+// Algorithmic float64 flops of one pass of R rows through layer i: the
+// multiply-adds of the convolution (every tap, borders included) or of the
+// dense product.
+double layer_flops(const cv_net_s* net, int i, long long R) {
+  if (const ConvDesc* c = conv_of(net, i))
+    return 2.0 * R * c->co * c->ho * c->wo * c->ci * c->k * c->k;
+  return 2.0 * R * net->n[i] * net->n[i - 1];
+}
+
+// Weight bytes one pass reads from memory (float32).
+double layer_wbytes(const cv_net_s* net, int i) {
+  if (const ConvDesc* c = conv_of(net, i)) return 4.0 * c->co * c->ci * c->k * c->k;
+  return 4.0 * net->n[i] * net->n[i - 1];
+}
+
 // Workspace of one backward pass (rows R = B*M, objective rows M).
 struct Bwd {
   double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
@@ -150,13 +170,14 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
   double* nxt = w.Om1;
   for (int i = T - 1; i >= 2; --i) {
     const int K = net->n[i], N = net->n[i - 1];
-    PLAUNCH("gemm_relax", 2.0 * R * K * N, 8.0 * R * (K + N) + 4.0 * K * N, launch_gemm_relax(R, K, N, cur, net->W[i - 1], M, Nh, net->off[i - 2], l, u, alpha,
+    const ConvDesc* cd = conv_of(net, i);
+    PLAUNCH(cd ? "conv_relax" : "gemm_relax", layer_flops(net, i, R), 8.0 * R * (K + N) + layer_wbytes(net, i), launch_gemm_relax(R, K, N, cur, net->W[i - 1], cd, M, Nh, net->off[i - 2], l, u, alpha,
                              alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
     PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
   }
   const int n0 = net->n[0];
-  PLAUNCH("gemm_final", 2.0 * R * net->n[1] * n0, 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + 4.0 * net->n[1] * n0, launch_gemm_final(R, net->n[1], n0, cur, net->W[0], M, lo, hi, root->X0, w.Ax, A_out,
+  PLAUNCH(conv_of(net, 1) ? "conv_final" : "gemm_final", layer_flops(net, 1, R), 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + layer_wbytes(net, 1), launch_gemm_final(R, net->n[1], n0, cur, net->W[0], conv_of(net, 1), M, lo, hi, root->X0, w.Ax, A_out,
                            w.part, s));
   PLAUNCH("finalize", 0, 8.0 * R * (2 * gemm_ntiles(n0) + 3), launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
                          root->gamma_big, infeasible, lb, c_out, s));
@@ -247,6 +268,8 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
     const int no = d.out_features, ni = d.in_features;
     net->n[i + 1] = no;
     net->W[i] = net->Wt[i] = net->b[i] = nullptr;
+    net->is_conv[i] = false;
+    net->conv[i] = ConvDesc{};
     std::vector<float> W, Wt((size_t)no * ni), bb;
     if (d.kind == CV_LINEAR) {
       W.assign(d.W, d.W + (size_t)no * ni);
@@ -289,6 +312,35 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
       cv_net_destroy(net);
       return hip_fail(hipGetLastError());
     }
+    if (d.kind == CV_CONV2D) {
+      // Kernels of the direct convolutions: Wb [co][k][k][ci padded to cbt]
+      // (transposed, blocks of input channels) and Wf [ci][k][k][co padded
+      // to cbf] (forward, blocks of output channels); padding is zero.
+      ConvDesc& c = net->conv[i];
+      c = ConvDesc{d.in_c, d.in_h, d.in_w, d.out_c, d.out_h, d.out_w, d.kernel, d.stride, d.pad,
+                   d.in_c <= 4 ? 4 : 16, d.out_c <= 4 ? 4 : 16, nullptr, nullptr};
+      net->is_conv[i] = true;
+      const int K = c.k;
+      const int pt = (c.ci + c.cbt - 1) / c.cbt * c.cbt, pf = (c.co + c.cbf - 1) / c.cbf * c.cbf;
+      std::vector<float> Wb((size_t)c.co * K * K * pt, 0.0f), Wf((size_t)c.ci * K * K * pf, 0.0f);
+      for (int co = 0; co < c.co; ++co)
+        for (int ci = 0; ci < c.ci; ++ci)
+          for (int ky = 0; ky < K; ++ky)
+            for (int kx = 0; kx < K; ++kx) {
+              const float v = d.W[(((size_t)co * c.ci + ci) * K + ky) * K + kx];
+              Wb[(((size_t)co * K + ky) * K + kx) * pt + ci] = v;
+              Wf[(((size_t)ci * K + ky) * K + kx) * pf + co] = v;
+            }
+      if (dev_alloc(&c.Wb, Wb.size()) || dev_alloc(&c.Wf, Wf.size())) {
+        cv_net_destroy(net);
+        return CV_E_NOMEM;
+      }
+      if (hipMemcpy(c.Wb, Wb.data(), Wb.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c.Wf, Wf.data(), Wf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        cv_net_destroy(net);
+        return hip_fail(hipGetLastError());
+      }
+    }
     net->hW.push_back(W);
     net->hb.push_back(bb);
     if (i < n_layers - 1) {
@@ -308,6 +360,10 @@ cv_status cv_net_destroy(cv_net net) {
     if (net->W[i]) (void)hipFree(net->W[i]);
     if (net->Wt[i]) (void)hipFree(net->Wt[i]);
     if (net->b[i]) (void)hipFree(net->b[i]);
+    if (net->is_conv[i]) {
+      if (net->conv[i].Wb) (void)hipFree(net->conv[i].Wb);
+      if (net->conv[i].Wf) (void)hipFree(net->conv[i].Wf);
+    }
   }
   delete net;
   return CV_OK;
@@ -827,7 +883,8 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   for (int k = 1; k <= net->L - 1; ++k) {
     const int K = net->n[k - 1], N = net->n[k];
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
-    PLAUNCH("gemm_adjoint", 2.0 * R * K * N, 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N, launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], net->b[k - 1], M, net->n_hidden,
+    const ConvDesc* cd = conv_of(net, k);
+    PLAUNCH(cd ? "conv_adjoint" : "gemm_adjoint", layer_flops(net, k, R), 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N + layer_wbytes(net, k), launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], cd, net->b[k - 1], M, net->n_hidden,
                                net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
                                s));

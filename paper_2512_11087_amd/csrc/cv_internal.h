@@ -7,16 +7,27 @@
 
 #define CV_MAX_LAYERS 32
 
+// A convolution layer (cross-correlation, zero padding; activations
+// flattened channel-major): input (ci, hi, wi) -> output (co, ho, wo).
+struct ConvDesc {
+  int ci, hi, wi, co, ho, wo, k, s, p;
+  int cbt, cbf;      // channel block of the transposed (over ci) and forward (over co) kernels
+  float* Wb;         // device [co][k][k][ci padded to cbt]: transposed convolution
+  float* Wf;         // device [ci][k][k][co padded to cbf]: forward convolution
+};
+
 struct cv_net_s {
   int L = 0;                  // number of affine layers
   int n[CV_MAX_LAYERS + 1];   // n[0] input dim, n[i] output dim of layer i (1-based)
   float* W[CV_MAX_LAYERS];    // device, layer i at index i-1: [n_i, n_{i-1}]
   float* Wt[CV_MAX_LAYERS];   // device transposes [n_{i-1}, n_i]
-  float* b[CV_MAX_LAYERS];    // device [n_i]
+  float* b[CV_MAX_LAYERS];    // device [n_i] (conv: the bias repeated over positions)
+  ConvDesc conv[CV_MAX_LAYERS];  // conv layers: kernels of the direct convolutions
+  bool is_conv[CV_MAX_LAYERS];
   int off[CV_MAX_LAYERS];     // global offset of hidden layer i (index i-1)
   int n_hidden = 0;
   int nmax_hidden = 0;
-  std::vector<std::vector<float>> hW, hb;  // host copies (root set-up)
+  std::vector<std::vector<float>> hW, hb;  // host copies (root set-up; conv: the dense matrix)
 };
 
 struct cv_root_s {
@@ -120,13 +131,15 @@ hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double*
                             double alpha_def, const float* bprev, const double* wrel, double* Om,
                             float* trace, double* rowc, double* rowerr, double* rowcabs,
                             hipStream_t s);
-hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
+hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W,
+                             const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s);
 hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
                          double* rowcabs, hipStream_t s);
-hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W, int M,
+hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
+                             const ConvDesc* conv, int M,
                              const float* lo, const float* hi, const double* X0, double* Ax,
                              float* A_out, double* part, hipStream_t s);
 int gemm_ntiles(int N);
@@ -134,6 +147,7 @@ hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const d
                            double* rowerr, const double* rowcabs, double gamma_big,
                            const uint8_t* infeasible, float* lb, float* c_out, hipStream_t s);
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
+                               const ConvDesc* conv,
                                const float* b, int M, int Nh, int off, const float* lz,
                                const float* uz,
                                float* alpha, double alpha_def,

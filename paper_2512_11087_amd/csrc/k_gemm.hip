@@ -438,6 +438,203 @@ struct EpiAdj {
   }
 };
 
+// ------------------------------------------------------------ convolutions
+// The backward pass through a conv layer is a transposed convolution of each
+// row of Omega (and the adjoint a forward convolution), computed directly
+// rather than as a product with the layer's dense matrix: float64 FMAs on the
+// vector units (whose float64 rate equals the matrix cores' on gfx950), one
+// workgroup per row, the same fused epilogues as the GEMMs.  A wave takes a
+// task = (channel block, chunk of 64 output positions); the block's weights
+// are wave-uniform (scalar loads), each input value read feeds CB FMAs.
+// Transposed convolution: the lanes of a task share one stride-parity class
+// of output positions (iy = cy + s a, ix = cx + s b), so for every tap the
+// divisibility (iy + p - ky) % s is uniform and only the ~k^2/s^2 valid taps
+// are visited; borders are masked per lane.
+
+// Row sums of a workgroup into the partials of column tile 0 (the other
+// tiles of the row get zeros), the layout the GEMM epilogues write.
+template <int NS>
+__device__ __forceinline__ void conv_row_sums(double (&sums)[NSUM_MAX], double* sred, double* part,
+                                              int r, int ntiles) {
+  if constexpr (NS > 0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const double t = wave_sum(sums[q]);
+      if (lane == 0) sred[wave * NSUM_MAX + q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+      const int q = threadIdx.x;
+      part[((size_t)r * ntiles) * NS + q] =
+          (sred[q] + sred[NSUM_MAX + q]) + (sred[2 * NSUM_MAX + q] + sred[3 * NSUM_MAX + q]);
+    }
+    for (int i = threadIdx.x; i < (ntiles - 1) * NS; i += 256)
+      part[((size_t)r * ntiles + 1) * NS + i] = 0.0;
+  }
+}
+
+template <class Epi, int CB>
+__global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double* __restrict__ in,
+                                               Epi epi, double* __restrict__ part, int ntiles) {
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double* row = in + (size_t)r * cd.co * cd.ho * cd.wo;
+  const size_t cin = (size_t)cd.ho * cd.wo;
+  const int cpad = (cd.ci + CB - 1) / CB * CB;
+  const int nblk = cpad / CB;
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+  // tasks: (block, parity class, chunk of 64 positions of that class)
+  int ntask = 0;
+  for (int cy = 0; cy < cd.s; ++cy)
+    for (int cx = 0; cx < cd.s; ++cx) {
+      const int ny = (cd.hi - cy + cd.s - 1) / cd.s, nx = (cd.wi - cx + cd.s - 1) / cd.s;
+      ntask += (ny * nx + 63) / 64;
+    }
+  ntask *= nblk;
+  for (int task = wave; task < ntask; task += 4) {
+    // decode (uniform): block, class, chunk
+    int rem = task;
+    const int per_blk = ntask / nblk;
+    const int blk = rem / per_blk;
+    rem -= blk * per_blk;
+    int cy = 0, cx = 0, ny = 0, nx = 0;
+    for (int c = 0; c < cd.s * cd.s; ++c) {
+      const int y = c / cd.s, x = c % cd.s;
+      const int yy = (cd.hi - y + cd.s - 1) / cd.s, xx = (cd.wi - x + cd.s - 1) / cd.s;
+      const int nch = (yy * xx + 63) / 64;
+      if (rem < nch) {
+        cy = y; cx = x; ny = yy; nx = xx;
+        break;
+      }
+      rem -= nch;
+    }
+    const int idx = rem * 64 + lane;
+    const bool live = idx < ny * nx;
+    const int iy = cy + cd.s * (live ? idx / nx : 0), ix = cx + cd.s * (live ? idx % nx : 0);
+    const int ci0 = blk * CB;
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    const int ky0 = ((cy + cd.p) % cd.s + cd.s) % cd.s, kx0 = ((cx + cd.p) % cd.s + cd.s) % cd.s;
+    for (int ky = ky0; ky < cd.k; ky += cd.s) {
+      const int oy = (iy + cd.p - ky) / cd.s;  // exact: iy + p - ky = s * oy (uniform parity)
+      const bool vy = live && iy + cd.p - ky >= 0 && oy < cd.ho;
+      for (int kx = kx0; kx < cd.k; kx += cd.s) {
+        const int ox = (ix + cd.p - kx) / cd.s;
+        const bool v = vy && ix + cd.p - kx >= 0 && ox < cd.wo;
+        const size_t base = v ? (size_t)oy * cd.wo + ox : 0;
+        const float* wk = cd.Wb + ((size_t)ky * cd.k + kx) * cpad + ci0;
+#pragma unroll 2
+        for (int co = 0; co < cd.co; ++co) {
+          const double x0 = row[co * cin + base];
+          const double x = v ? x0 : 0.0;
+          const float* wq = wk + (size_t)co * cd.k * cd.k * cpad;
+#pragma unroll
+          for (int q = 0; q < CB; ++q) acc[q] += x * (double)wq[q];
+        }
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int ci = ci0 + q;
+        if (ci < cd.ci) {
+          const int c = (ci * cd.hi + iy) * cd.wi + ix;
+          const auto pre = epi.load(w, r, c);
+          epi.apply(w, pre, r, c, acc[q], sums);
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles);
+}
+
+// Forward convolution of each row (adjoint): out (co, oy, ox) =
+// sum over ci and taps of in (ci, oy*s - p + ky, ox*s - p + kx) * W (co, ci, ky, kx).
+template <class Epi, int CB>
+__global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double* __restrict__ in,
+                                               Epi epi, double* __restrict__ part, int ntiles) {
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double* row = in + (size_t)r * cd.ci * cd.hi * cd.wi;
+  const size_t cin = (size_t)cd.hi * cd.wi;
+  const int cpad = (cd.co + CB - 1) / CB * CB;
+  const int nblk = cpad / CB;
+  const int npos = cd.ho * cd.wo, nchunk = (npos + 63) / 64;
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+  for (int task = wave; task < nblk * nchunk; task += 4) {
+    const int blk = task / nchunk, chunk = task % nchunk;
+    const int pos = chunk * 64 + lane;
+    const bool live = pos < npos;
+    const int oy = live ? pos / cd.wo : 0, ox = live ? pos % cd.wo : 0;
+    const int co0 = blk * CB;
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int ky = 0; ky < cd.k; ++ky) {
+      const int iy = oy * cd.s - cd.p + ky;
+      const bool vy = live && iy >= 0 && iy < cd.hi;
+      for (int kx = 0; kx < cd.k; ++kx) {
+        const int ix = ox * cd.s - cd.p + kx;
+        const bool v = vy && ix >= 0 && ix < cd.wi;
+        const size_t base = v ? (size_t)iy * cd.wi + ix : 0;
+        const float* wk = cd.Wf + ((size_t)ky * cd.k + kx) * cpad + co0;
+#pragma unroll 2
+        for (int ci = 0; ci < cd.ci; ++ci) {
+          const double x0 = row[ci * cin + base];
+          const double x = v ? x0 : 0.0;
+          const float* wq = wk + (size_t)ci * cd.k * cd.k * cpad;
+#pragma unroll
+          for (int q = 0; q < CB; ++q) acc[q] += x * (double)wq[q];
+        }
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int co = co0 + q;
+        if (co < cd.co) {
+          const int c = (co * cd.ho + oy) * cd.wo + ox;
+          const auto pre = epi.load(w, r, c);
+          epi.apply(w, pre, r, c, acc[q], sums);
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles);
+}
+
+template <class Epi>
+hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  if (cd.cbt == 4)
+    hipLaunchKernelGGL((k_convt<Epi, 4>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  else
+    hipLaunchKernelGGL((k_convt<Epi, 16>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  return hipGetLastError();
+}
+
+template <class Epi>
+hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  if (cd.cbf == 4)
+    hipLaunchKernelGGL((k_convf<Epi, 4>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  else
+    hipLaunchKernelGGL((k_convf<Epi, 16>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  return hipGetLastError();
+}
+
 template <class T = TileDefault, int OCC = 2, class LoadA, class Epi>
 hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi epi,
                     double* part, hipStream_t s) {
@@ -453,18 +650,22 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
 
 int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
 
-hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W, int M, int Nh,
+hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W,
+                             const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, const double* wrel,
                              double* Om_out, float* trace, double* part, hipStream_t s) {
   EpiRelax e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
+  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
-hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W, int M,
+hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
+                             const ConvDesc* conv, int M,
                              const float* lo, const float* hi, const double* X0, double* Ax,
                              float* A_out, double* part, hipStream_t s) {
   EpiFinal e{M, N, lo, hi, X0, Ax, A_out};
+  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
@@ -477,7 +678,7 @@ hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
-                               const float* b, int M, int Nh, int off, const float* lz,
+                               const ConvDesc* conv, const float* b, int M, int Nh, int off, const float* lz,
                                const float* uz,
                                float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
@@ -486,5 +687,6 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
   EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N};
+  if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s);
   return run_gemm(R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

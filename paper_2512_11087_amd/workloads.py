@@ -326,6 +326,19 @@ def cifar_cnn(B: int = 4096, seed: int = SEED_WEIGHTS, depth=(1, 12)) -> Workloa
                     extra={"label": label})
 
 
+def ragged_cnn(B: int = 64, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
+    """CNN 5x9x7 -> conv 6 (3x3, stride 1, pad 1) -> conv 17 (4x4, stride 3,
+    pad 2) -> linear 12 -> linear 4, He-normal weights, uniform biases: channel
+    counts that fill no channel block, stride 3, non-square maps; box = centre
+    U[-1,1]^315 +- 0.05, the 4 outputs as objectives."""
+    net = he_cnn((5, 9, 7), [(6, 3, 1, 1), (17, 4, 3, 2)], [12, 4], seed, bias="uniform")
+    c = centres(315, 1, -1.0, 1.0)[0]
+    lo, hi = box_around(c, 0.05)
+    C, t = identity_spec(4)
+    counts = np.random.default_rng(SEED_SIZES).integers(depth[0], depth[1] + 1, size=B)
+    return Workload("cnn5x9x7-c6-c17-12-4", net, lo, hi, C, t, B, counts.astype(np.int32))
+
+
 def random_boxes_and_constraints(B: int, n: int, k: int, seed: int, width=0.5,
                                  p_zero_coef=0.1, p_flat=0.05, slack=0.5, nnz=8):
     """Random boxes [B, n] and dense constraints G [B, k, n], h [B, k] with
