@@ -112,9 +112,9 @@ double layer_flops(const cv_net_s* net, int i, long long R) {
   return 2.0 * R * net->n[i] * net->n[i - 1];
 }
 
-// Weight bytes one pass reads from memory (float32).
+// Weight bytes one pass reads from memory (float32 matrices, float64 kernels).
 double layer_wbytes(const cv_net_s* net, int i) {
-  if (const ConvDesc* c = conv_of(net, i)) return 4.0 * c->co * c->ci * c->k * c->k;
+  if (const ConvDesc* c = conv_of(net, i)) return 8.0 * c->co * c->ci * c->k * c->k;
   return 4.0 * net->n[i] * net->n[i - 1];
 }
 
@@ -313,21 +313,21 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
       return hip_fail(hipGetLastError());
     }
     if (d.kind == CV_CONV2D) {
-      // Kernels of the direct convolutions: Wb [co][k][k][ci padded to cbt]
+      // Kernels of the direct convolutions: Wb [co][k][k][ci padded to 16]
       // (transposed, blocks of input channels) and Wf [ci][k][k][co padded
-      // to cbf] (forward, blocks of output channels); padding is zero.
+      // to 16] (forward, blocks of output channels); padding is zero.
       ConvDesc& c = net->conv[i];
       c = ConvDesc{d.in_c, d.in_h, d.in_w, d.out_c, d.out_h, d.out_w, d.kernel, d.stride, d.pad,
-                   d.in_c <= 4 ? 4 : 16, d.out_c <= 4 ? 4 : 16, nullptr, nullptr};
+                   (d.in_c + 15) / 16 * 16, (d.out_c + 15) / 16 * 16, nullptr, nullptr};
       net->is_conv[i] = true;
       const int K = c.k;
-      const int pt = (c.ci + c.cbt - 1) / c.cbt * c.cbt, pf = (c.co + c.cbf - 1) / c.cbf * c.cbf;
-      std::vector<float> Wb((size_t)c.co * K * K * pt, 0.0f), Wf((size_t)c.ci * K * K * pf, 0.0f);
+      const int pt = c.ptp, pf = c.pfp;
+      std::vector<double> Wb((size_t)c.co * K * K * pt, 0.0), Wf((size_t)c.ci * K * K * pf, 0.0);
       for (int co = 0; co < c.co; ++co)
         for (int ci = 0; ci < c.ci; ++ci)
           for (int ky = 0; ky < K; ++ky)
             for (int kx = 0; kx < K; ++kx) {
-              const float v = d.W[(((size_t)co * c.ci + ci) * K + ky) * K + kx];
+              const double v = d.W[(((size_t)co * c.ci + ci) * K + ky) * K + kx];
               Wb[(((size_t)co * K + ky) * K + kx) * pt + ci] = v;
               Wf[(((size_t)ci * K + ky) * K + kx) * pf + co] = v;
             }
@@ -335,8 +335,8 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
         cv_net_destroy(net);
         return CV_E_NOMEM;
       }
-      if (hipMemcpy(c.Wb, Wb.data(), Wb.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(c.Wf, Wf.data(), Wf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      if (hipMemcpy(c.Wb, Wb.data(), Wb.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c.Wf, Wf.data(), Wf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
         cv_net_destroy(net);
         return hip_fail(hipGetLastError());
       }

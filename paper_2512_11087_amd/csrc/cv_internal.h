@@ -11,9 +11,9 @@
 // flattened channel-major): input (ci, hi, wi) -> output (co, ho, wo).
 struct ConvDesc {
   int ci, hi, wi, co, ho, wo, k, s, p;
-  int cbt, cbf;      // channel block of the transposed (over ci) and forward (over co) kernels
-  float* Wb;         // device [co][k][k][ci padded to cbt]: transposed convolution
-  float* Wf;         // device [ci][k][k][co padded to cbf]: forward convolution
+  int ptp, pfp;      // ci and co rounded up to a multiple of 16 (weight padding)
+  double* Wb;        // device [co][k][k][ptp]: transposed convolution (blocks of ci)
+  double* Wf;        // device [ci][k][k][pfp]: forward convolution (blocks of co)
 };
 
 struct cv_net_s {

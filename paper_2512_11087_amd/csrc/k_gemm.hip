@@ -445,7 +445,9 @@ struct EpiAdj {
 // vector units (whose float64 rate equals the matrix cores' on gfx950), one
 // workgroup per row, the same fused epilogues as the GEMMs.  A wave takes a
 // task = (channel block, chunk of 64 output positions); the block's weights
-// are wave-uniform (scalar loads), each input value read feeds CB FMAs.
+// are wave-uniform (scalar loads), each input value read feeds CB FMAs.  A
+// row that fits is first staged in LDS with wide coalesced loads, so the
+// taps read LDS instead of issuing one dependent global load each.
 // Transposed convolution: the lanes of a task share one stride-parity class
 // of output positions (iy = cy + s a, ix = cx + s b), so for every tap the
 // divisibility (iy + p - ky) % s is uniform and only the ~k^2/s^2 valid taps
@@ -474,34 +476,59 @@ __device__ __forceinline__ void conv_row_sums(double (&sums)[NSUM_MAX], double* 
   }
 }
 
-template <class Epi, int CB>
+// Kernel weights are read through the constant address space: their
+// addresses are wave-uniform and nothing in these kernels writes them, so
+// they come in by scalar loads and feed the FMAs from SGPRs.
+typedef const __attribute__((address_space(4))) double* conv_wptr;
+
+// Largest input row staged in LDS (doubles): 64 KiB keeps two workgroups
+// per CU; longer rows are read from global memory directly.
+constexpr int CONV_STAGE_MAX = 8192;
+
+// Copy one row into LDS with many loads in flight per thread.
+__device__ __forceinline__ void conv_stage(double* __restrict__ dst, const double* __restrict__ src,
+                                           int n) {
+  int i = threadIdx.x;
+  for (; i + 3 * 256 < n; i += 4 * 256) {
+    const double a0 = src[i], a1 = src[i + 256], a2 = src[i + 512], a3 = src[i + 768];
+    dst[i] = a0;
+    dst[i + 256] = a1;
+    dst[i + 512] = a2;
+    dst[i + 768] = a3;
+  }
+  for (; i < n; i += 256) dst[i] = src[i];
+  __syncthreads();
+}
+
+template <class Epi, int CB, bool STAGE>
 __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
   constexpr int NS = Epi::NSUM;
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const double* row = in + (size_t)r * cd.co * cd.ho * cd.wo;
   const size_t cin = (size_t)cd.ho * cd.wo;
-  const int cpad = (cd.ci + CB - 1) / CB * CB;
-  const int nblk = cpad / CB;
+  const double* row = in + (size_t)r * cd.co * cin;
+  if constexpr (STAGE) conv_stage(srow, row, (int)(cd.co * cin));
+  const double* src = STAGE ? srow : row;
+  const int cpad = cd.ptp;
+  const int nblk = (cd.ci + CB - 1) / CB;
   const auto w = epi.row(r);
   double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
   // tasks: (block, parity class, chunk of 64 positions of that class)
-  int ntask = 0;
+  int per_blk = 0;
   for (int cy = 0; cy < cd.s; ++cy)
     for (int cx = 0; cx < cd.s; ++cx) {
       const int ny = (cd.hi - cy + cd.s - 1) / cd.s, nx = (cd.wi - cx + cd.s - 1) / cd.s;
-      ntask += (ny * nx + 63) / 64;
+      per_blk += (ny * nx + 63) / 64;
     }
-  ntask *= nblk;
+  const int ntask = per_blk * nblk;
   for (int task = wave; task < ntask; task += 4) {
     // decode (uniform): block, class, chunk
-    int rem = task;
-    const int per_blk = ntask / nblk;
-    const int blk = rem / per_blk;
-    rem -= blk * per_blk;
+    const int blk = task / per_blk;
+    int rem = task - blk * per_blk;
     int cy = 0, cx = 0, ny = 0, nx = 0;
     for (int c = 0; c < cd.s * cd.s; ++c) {
       const int y = c / cd.s, x = c % cd.s;
@@ -520,22 +547,23 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
     double acc[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) acc[q] = 0.0;
-    const int ky0 = ((cy + cd.p) % cd.s + cd.s) % cd.s, kx0 = ((cx + cd.p) % cd.s + cd.s) % cd.s;
+    const int ky0 = (cy + cd.p) % cd.s, kx0 = (cx + cd.p) % cd.s;
     for (int ky = ky0; ky < cd.k; ky += cd.s) {
-      const int oy = (iy + cd.p - ky) / cd.s;  // exact: iy + p - ky = s * oy (uniform parity)
+      const int oy = (iy + cd.p - ky) / cd.s;  // exact when >= 0: iy + p - ky = s * oy (same class)
       const bool vy = live && iy + cd.p - ky >= 0 && oy < cd.ho;
       for (int kx = kx0; kx < cd.k; kx += cd.s) {
         const int ox = (ix + cd.p - kx) / cd.s;
         const bool v = vy && ix + cd.p - kx >= 0 && ox < cd.wo;
-        const size_t base = v ? (size_t)oy * cd.wo + ox : 0;
-        const float* wk = cd.Wb + ((size_t)ky * cd.k + kx) * cpad + ci0;
+        const int base = v ? oy * cd.wo + ox : 0;
+        const conv_wptr wk = (conv_wptr)(cd.Wb + (ky * cd.k + kx) * cpad + ci0);
+        const int wstep = cd.k * cd.k * cpad;
 #pragma unroll 2
         for (int co = 0; co < cd.co; ++co) {
-          const double x0 = row[co * cin + base];
+          const double x0 = src[co * (int)cin + base];
           const double x = v ? x0 : 0.0;
-          const float* wq = wk + (size_t)co * cd.k * cd.k * cpad;
+          const conv_wptr wq = wk + co * wstep;
 #pragma unroll
-          for (int q = 0; q < CB; ++q) acc[q] += x * (double)wq[q];
+          for (int q = 0; q < CB; ++q) acc[q] += x * wq[q];
         }
       }
     }
@@ -556,18 +584,21 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
 
 // Forward convolution of each row (adjoint): out (co, oy, ox) =
 // sum over ci and taps of in (ci, oy*s - p + ky, ox*s - p + kx) * W (co, ci, ky, kx).
-template <class Epi, int CB>
+template <class Epi, int CB, bool STAGE>
 __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
   constexpr int NS = Epi::NSUM;
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const double* row = in + (size_t)r * cd.ci * cd.hi * cd.wi;
   const size_t cin = (size_t)cd.hi * cd.wi;
-  const int cpad = (cd.co + CB - 1) / CB * CB;
-  const int nblk = cpad / CB;
+  const double* row = in + (size_t)r * cd.ci * cin;
+  if constexpr (STAGE) conv_stage(srow, row, (int)(cd.ci * cin));
+  const double* src = STAGE ? srow : row;
+  const int cpad = cd.pfp;
+  const int nblk = (cd.co + CB - 1) / CB;
   const int npos = cd.ho * cd.wo, nchunk = (npos + 63) / 64;
   const auto w = epi.row(r);
   double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
@@ -586,15 +617,16 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
       for (int kx = 0; kx < cd.k; ++kx) {
         const int ix = ox * cd.s - cd.p + kx;
         const bool v = vy && ix >= 0 && ix < cd.wi;
-        const size_t base = v ? (size_t)iy * cd.wi + ix : 0;
-        const float* wk = cd.Wf + ((size_t)ky * cd.k + kx) * cpad + co0;
+        const int base = v ? iy * cd.wi + ix : 0;
+        const conv_wptr wk = (conv_wptr)(cd.Wf + (ky * cd.k + kx) * cpad + co0);
+        const int wstep = cd.k * cd.k * cpad;
 #pragma unroll 2
         for (int ci = 0; ci < cd.ci; ++ci) {
-          const double x0 = row[ci * cin + base];
+          const double x0 = src[ci * (int)cin + base];
           const double x = v ? x0 : 0.0;
-          const float* wq = wk + (size_t)ci * cd.k * cd.k * cpad;
+          const conv_wptr wq = wk + ci * wstep;
 #pragma unroll
-          for (int q = 0; q < CB; ++q) acc[q] += x * (double)wq[q];
+          for (int q = 0; q < CB; ++q) acc[q] += x * wq[q];
         }
       }
     }
@@ -613,14 +645,53 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
   conv_row_sums<NS>(sums, sred, part, r, ntiles);
 }
 
+// Channel block of a convolution: the largest of 16, 8, 4 that still gives
+// every wave of a row a task (fewer channels: the smallest block covering them).
+inline int conv_block(int ch, int tasks_per_block) {
+  int cb = 16;
+  while (cb > 4 && ((ch + cb - 1) / cb) * tasks_per_block < 4) cb >>= 1;
+  if (ch <= 4) cb = 4;
+  else if (ch <= 8 && cb > 8) cb = 8;
+  return cb;
+}
+
+template <class Epi, int CB>
+void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s) {
+  const int n = cd.co * cd.ho * cd.wo;
+  if (n <= CONV_STAGE_MAX)
+    hipLaunchKernelGGL((k_convt<Epi, CB, true>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
+                       epi, part, ntiles);
+  else
+    hipLaunchKernelGGL((k_convt<Epi, CB, false>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
+                       ntiles);
+}
+
+template <class Epi, int CB>
+void launch_convf_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s) {
+  const int n = cd.ci * cd.hi * cd.wi;
+  if (n <= CONV_STAGE_MAX)
+    hipLaunchKernelGGL((k_convf<Epi, CB, true>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
+                       epi, part, ntiles);
+  else
+    hipLaunchKernelGGL((k_convf<Epi, CB, false>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
+                       ntiles);
+}
+
 template <class Epi>
 hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  if (cd.cbt == 4)
-    hipLaunchKernelGGL((k_convt<Epi, 4>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
-  else
-    hipLaunchKernelGGL((k_convt<Epi, 16>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  int per_blk = 0;
+  for (int cy = 0; cy < cd.s; ++cy)
+    for (int cx = 0; cx < cd.s; ++cx)
+      per_blk += (((cd.hi - cy + cd.s - 1) / cd.s) * ((cd.wi - cx + cd.s - 1) / cd.s) + 63) / 64;
+  switch (conv_block(cd.ci, per_blk)) {
+    case 4: launch_convt_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s); break;
+    case 8: launch_convt_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s); break;
+    default: launch_convt_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s); break;
+  }
   return hipGetLastError();
 }
 
@@ -628,10 +699,11 @@ template <class Epi>
 hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  if (cd.cbf == 4)
-    hipLaunchKernelGGL((k_convf<Epi, 4>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
-  else
-    hipLaunchKernelGGL((k_convf<Epi, 16>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part, ntiles);
+  switch (conv_block(cd.co, (cd.ho * cd.wo + 63) / 64)) {
+    case 4: launch_convf_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s); break;
+    case 8: launch_convf_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s); break;
+    default: launch_convf_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s); break;
+  }
   return hipGetLastError();
 }
 

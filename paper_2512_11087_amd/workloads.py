@@ -339,6 +339,19 @@ def ragged_cnn(B: int = 64, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
     return Workload("cnn5x9x7-c6-c17-12-4", net, lo, hi, C, t, B, counts.astype(np.int32))
 
 
+def wide_cnn(B: int = 32, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
+    """CNN 4x24x24 -> conv 16 (3x3, stride 1, pad 1) -> conv 8 (4x4, stride 2,
+    pad 1) -> linear 10 -> linear 3, uniform biases: the first conv's output
+    (9216 values a row) is too long to stage in LDS; box = centre U[0,1]^2304
+    +- 0.01, the 3 outputs as objectives."""
+    net = he_cnn((4, 24, 24), [(16, 3, 1, 1), (8, 4, 2, 1)], [10, 3], seed, bias="uniform")
+    c = centres(2304, 1, 0.0, 1.0)[0]
+    lo, hi = box_around(c, 0.01)
+    C, t = identity_spec(3)
+    counts = np.random.default_rng(SEED_SIZES).integers(depth[0], depth[1] + 1, size=B)
+    return Workload("cnn4x24x24-c16-c8-10-3", net, lo, hi, C, t, B, counts.astype(np.int32))
+
+
 def random_boxes_and_constraints(B: int, n: int, k: int, seed: int, width=0.5,
                                  p_zero_coef=0.1, p_flat=0.05, slack=0.5, nnz=8):
     """Random boxes [B, n] and dense constraints G [B, k, n], h [B, k] with
