@@ -103,11 +103,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mlp784-256x6-10",
-                    choices=["mlp784-256x6-10", "mlp784-1024x4-10", "cnn3x32x32"],
+                    choices=["mlp784-256x6-10", "mlp784-1024x4-10", "cnn3x32x32",
+                             "cnn3x32x32-set64"],
                     help="784-256x6-10 (16384 x 4 splits, the metric's workload), "
-                         "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024) or "
+                         "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024), "
                          "cnn3x32x32 (conv16-conv32-100-10 on 3x32x32 inputs, one property, "
-                         "4096 subdomains, split depth 1..12)")
+                         "4096 subdomains, split depth 1..12) or cnn3x32x32-set64 (the same "
+                         "CNN, 64 properties of Geometric(0.002) subdomains each, 32414 in all, "
+                         "bounded together)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--alpha-steps", type=int, default=20)
     ap.add_argument("--cpu-sample", type=int, default=256)
@@ -143,26 +146,55 @@ def main():
         log(f"copy probe: 5 copies of {n} bytes")
         return
     T = args.alpha_steps
+    wset = None
     if args.workload == "mlp784-256x6-10":
         B = args.batch or 16384
         w = wl.mnist_mlp(B)
     elif args.workload == "mlp784-1024x4-10":
         B = args.batch or 8192
         w = wl.alpha_mlp(B)
-    else:
+    elif args.workload == "cnn3x32x32":
         B = args.batch or 4096
         w = wl.cifar_cnn(B)
-    ksplit = int(w.split_counts.max())
-    log(f"workload {w.name}: B={B}, k={ksplit}, M={w.C.shape[0]}, alpha steps={T}")
+    else:
+        wset = wl.cifar_cnn_set(64)
+        B = wset.B
     t0 = time.perf_counter()
-    prop = gpipe.Property.from_workload(w)
-    l0, u0 = (x.cpu().numpy() for x in prop.root.bounds())
-    cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
-    sp = wl.draw_splits(B, w.split_counts, cand)
-    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    if wset is None:
+        ksplit = int(w.split_counts.max())
+        log(f"workload {w.name}: B={B}, k={ksplit}, M={w.C.shape[0]}, alpha steps={T}")
+        prop = gpipe.Property.from_workload(w)
+        l0, u0 = (x.cpu().numpy() for x in prop.root.bounds())
+        cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
+        sp = wl.draw_splits(B, w.split_counts, cand)
+        batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+        n_unst = f"{prop.root.n_unstable}"
+        name, split_counts = w.name, w.split_counts
+    else:
+        # one root per property, bounded together; each property's splits are
+        # drawn over its own root-unstable neurons
+        ksplit = int(wset.split_counts.max())
+        log(f"workload {wset.name}: B={B} over {wset.P} properties "
+            f"(sizes {wset.counts.min()}..{wset.counts.max()}), k<={ksplit}, alpha steps={T}")
+        prop = gpipe.PropertySet(list(wset.net.layers), wset.lo0s, wset.hi0s, wset.Cs, wset.ts)
+        sps, unst = [], []
+        for p_, r in enumerate(prop.roots):
+            l0, u0 = (x.cpu().numpy() for x in r.bounds())
+            cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
+            unst.append(cand.size)
+            sps.append(wl.draw_splits(int(wset.counts[p_]), wset.member(p_).split_counts, cand,
+                                      seed=wl.SEED_SPLITS + p_, kmax=ksplit))
+        sp = wl.Splits(np.concatenate([x.neuron for x in sps]),
+                       np.concatenate([x.sign for x in sps]),
+                       np.concatenate([x.count for x in sps]))
+        lo, hi, pid = prop.boxes(wset.counts)
+        batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count, lo, hi, pid)
+        n_unst = f"{min(unst)}..{max(unst)}"
+        name, split_counts = wset.name, wset.split_counts
+        w = wset
     lo_init, hi_init = batch.lo.clone(), batch.hi.clone()
     torch.cuda.synchronize()
-    log(f"set-up (root pass, {prop.root.n_unstable} unstable of {w.net.n_hidden}) "
+    log(f"set-up (root pass, {n_unst} unstable of {w.net.n_hidden}) "
         f"{time.perf_counter() - t0:.2f} s")
 
     state, pstate = {}, {}
@@ -247,9 +279,15 @@ def main():
             f"avg {v['ms'] / v['launches']:8.4f} ms  share {v['ms'] / (1e3 * wall):6.1%}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} subdomains ...")
-        cpu = cpu_baseline(w, sp, args.cpu_sample, T)
+        if wset is None:
+            cpu = cpu_baseline(w, sp, args.cpu_sample, T)
+        else:
+            # the largest property's first subdomains
+            p_ = int(np.argmax(wset.counts))
+            cpu = cpu_baseline(wset.member(p_), sps[p_], min(args.cpu_sample, int(wset.counts[p_])), T)
+            cpu["sample"] = f"property {p_}: " + cpu["sample"]
         log(f"cpu baseline {cpu['value']:.2f} subdomains/s ({cpu['sample']})")
 
     line = {
@@ -257,7 +295,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {B} subdomains x {'<=' if w.split_counts.min() < ksplit else ''}{ksplit} splits, 9 margin rows, "
+        "config": {"workload": f"{name}: {B} subdomains x {'<=' if split_counts.min() < ksplit else ''}{ksplit} splits, 9 margin rows, "
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
                    "global_batch": B, "alpha_steps": T, "io_dtype": "f32",
                    "launch": "hip graph (slope iterations)" if args.graph else "eager"},

@@ -122,6 +122,22 @@ cv_status cv_root_planes(cv_root root, float* A_lo, float* c_lo, float* A_hi, fl
 /* Host output: number of root-unstable neurons (l0 < 0 < u0). */
 cv_status cv_root_unstable_count(cv_root root, int* count);
 
+/* A set of P properties over one network (batching: many properties, each
+ * with its own root box, root state and objective, bounded in the same
+ * launches).  roots: host array of P single roots of the same net; the set
+ * borrows their state (they must outlive it) and owns only a device table
+ * of it.  Every call that takes a root accepts a set together with
+ * pid: device [B] int32, the property of each subdomain (subdomains of one
+ * property need not be contiguous, but grouping them is faster for
+ * cv_concretize_planes; values outside [0, P) are clamped).  pid == NULL
+ * means property 0 for every subdomain.  The objective of a set is
+ * per property: C [P, M, n_out], t [P, M].  cv_root_bounds, cv_root_planes,
+ * cv_root_unstable_count and cv_intermediate_bounds take single roots only
+ * (CV_E_INVALID / CV_E_UNSUPPORTED for a set).  Destroy with cv_root_destroy. */
+cv_status cv_rootset_create(const cv_root* roots, int P, cv_root* out);
+/* Host output: number of properties (1 for a single root). */
+cv_status cv_root_count(cv_root root, int* P);
+
 /* --------------------------------------------------------- constraints */
 
 /* The linear constraints of each subdomain, in one of two forms.
@@ -156,7 +172,8 @@ typedef struct {
  * lo, hi: device [B, n]; order: device output [B, kmax] (see cv_constraints).
  * Errors: CV_E_UNSUPPORTED if kmax > 64; CV_E_SHAPE if the split form's
  * root has another input size. */
-cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* cons,
+cv_status cv_constraint_order(cv_root root, const int32_t* pid, int B, int n,
+                              const cv_constraints* cons,
                               const float* lo, const float* hi, int32_t* order,
                               hipStream_t stream);
 
@@ -174,7 +191,8 @@ enum { CV_CLIP_PARALLEL = 0, CV_CLIP_SEQUENTIAL = 1 };
  * lo, hi: device [B, n] in/out.  infeasible: device [B] uint8 out, 1 when
  * some constraint is certainly empty over the box or lo > hi afterwards.
  * B == 0 is a no-op. */
-cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons,
+cv_status cv_clip_domains(cv_root root, const int32_t* pid, int B, int n,
+                          const cv_constraints* cons,
                           float* lo, float* hi, uint8_t* infeasible, int mode,
                           hipStream_t stream);
 
@@ -194,9 +212,10 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
  * when topk < 0, else per hidden layer the topk neurons with the largest
  * BaBSR intercept score max(0,-l) max(0,u) / (u-l) * weight[j] (heuristics
  * appendix; ties to the lower index; weight from cv_babsr_weights or the
- * caller, device [n_hidden]).  select (optional) device [B, n_hidden]
+ * caller, device [P, n_hidden]).  select (optional) device [B, n_hidden]
  * receives the selection mask (1 = clipped). */
-cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
+cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const float* lo,
+                               const float* hi,
                                const cv_constraints* splits, int complete, int passes,
                                int topk, const float* weight,
                                float* l, float* u, uint8_t* infeasible, uint8_t* select,
@@ -208,8 +227,9 @@ cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size
  * max(0, -mean over the M objective rows of Psi_mj), the coefficient with
  * which the ReLU output of hidden neuron j enters the CROWN lower bound of
  * row m, from one backward pass over the root box with the root bounds and
- * slope (once per property).  C, t: device [M, n_out], [M]; weight: device
- * [n_hidden] out.  ws: cv_babsr_weights_workspace(...) bytes. */
+ * slope (once per property).  C, t: device [P, M, n_out], [P, M]; weight:
+ * device [P, n_hidden] out (P = 1 for a single root).
+ * ws: cv_babsr_weights_workspace(...) bytes. */
 cv_status cv_babsr_weights(cv_net net, cv_root root, int M, const float* C, const float* t,
                            float* weight, void* ws, size_t ws_bytes, hipStream_t stream);
 cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes);
@@ -225,7 +245,8 @@ cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes);
  * infeasible[b] = 1.  ub (optional) gets the maximum without constraints.
  * beta (optional) device [B, P, kmax] gets the multipliers.
  * lo, hi: device [B, n].  lb, ub: device [B, P].  infeasible: [B] or NULL. */
-cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A_shared,
+cv_status cv_concretize(cv_root root, const int32_t* pid, int B, int P, int n, const float* A,
+                        int A_shared,
                         const float* c, const float* lo, const float* hi,
                         const cv_constraints* cons, int passes, float* lb, float* ub,
                         float* beta, uint8_t* infeasible, hipStream_t stream);
@@ -239,7 +260,8 @@ cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A
  * adds Omega b to the intercept; each ReLU neuron uses the relaxation of
  * Lemma A.3 chosen by the sign of Psi: slope 1 (l >= 0), 0 (u <= 0), alpha
  * (unstable, Psi >= 0) or the upper line u/(u-l)(z-l) (unstable, Psi < 0).
- * C: device [M, n_out], t: device [M].  l, u: device [B, n_hidden]
+ * C: device [P, M, n_out], t: device [P, M] (P = 1 for a single root;
+ * subdomain b uses the rows of its property pid[b]).  l, u: device [B, n_hidden]
  * (per-subdomain pre-activation bounds, e.g. from cv_concretize_planes).
  * alpha: device [B, M, n_hidden] in [0,1] or NULL (alpha_default for all).
  * lo, hi: device [B, n_in], inside the root box of `root` (the root's bounds
@@ -254,11 +276,12 @@ cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A
 cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const float* t,
                              const float* l, const float* u, const float* alpha,
                              float alpha_default, const float* lo, const float* hi,
-                             uint8_t* infeasible, cv_root root,
+                             uint8_t* infeasible, cv_root root, const int32_t* pid,
                              const cv_constraints* cons, int passes,
                              float* lb, float* A_out, float* c_out,
                              void* ws, size_t ws_bytes, hipStream_t stream);
-cv_status cv_bound_propagate_workspace(cv_net net, int B, int M, size_t* bytes);
+/* P: number of properties of the root the call will use. */
+cv_status cv_bound_propagate_workspace(cv_net net, int P, int B, int M, size_t* bytes);
 
 /* One slope-optimisation step.  Computes the bound of cv_bound_propagate
  * (with complete clipping when cons != NULL) at the current alpha into lb,
@@ -274,12 +297,12 @@ cv_status cv_bound_propagate_workspace(cv_net net, int B, int M, size_t* bytes);
 cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t,
                         const float* l, const float* u, float* alpha,
                         const float* lo, const float* hi, uint8_t* infeasible,
-                        cv_root root, const cv_constraints* cons, int passes,
-                        float* adam_m, float* adam_v, int step, float lr,
+                        cv_root root, const int32_t* pid, const cv_constraints* cons,
+                        int passes, float* adam_m, float* adam_v, int step, float lr,
                         float beta1, float beta2, float eps,
                         float* lb, float* grad, void* ws, size_t ws_bytes,
                         hipStream_t stream);
-cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes);
+cv_status cv_alpha_step_workspace(cv_net net, int P, int B, int M, size_t* bytes);
 
 /* CROWN bounds of every hidden neuron over each subdomain's own box (the
  * bounding of a fresh input box, as opposed to re-concretizing the root
@@ -302,14 +325,16 @@ cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes);
 /* ReLU branching (Alg. 5): each parent subdomain b (splits, box lo/hi
  * [B, n_in], bounds l/u [B, n_hidden]) is split on the unstable neuron
  * (l < 0 < u) not split yet with the largest BaBSR intercept score
- * max(0,-l) max(0,u) / (u-l) * weight[j] (ties to the lower index) into
+ * max(0,-l) max(0,u) / (u-l) * weight[j] (ties to the lower index; weight
+ * [P, n_hidden], row pid[b] for subdomain b) into
  * child 2b (branch z <= 0) and child 2b+1 (branch z >= 0): the parent's
  * splits plus the new one, and the parent's box.  chosen[b] = -1 when no
  * unstable neuron is left or the parent already uses all kmax_out slots
  * (the children then equal the parent).
  * Outputs (device): chosen [B]; neuron2, sign2 [2B, kmax_out]; count2 [2B];
  * lo2, hi2 [2B, n_in].  kmax_out >= splits->kmax (else CV_E_SHAPE). */
-cv_status cv_branch_relu(cv_root root, int B, const float* l, const float* u, const float* weight,
+cv_status cv_branch_relu(cv_root root, const int32_t* pid, int B, const float* l, const float* u,
+                         const float* weight,
                          const cv_constraints* splits, const float* lo, const float* hi,
                          int kmax_out, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
                          int32_t* count2, float* lo2, float* hi2, hipStream_t stream);

@@ -20,7 +20,7 @@ EXPORTS = [
     "cv_status_string", "cv_last_hip_error", "cv_version",
     "cv_net_create", "cv_net_destroy", "cv_net_info",
     "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
-    "cv_root_unstable_count",
+    "cv_root_unstable_count", "cv_rootset_create", "cv_root_count",
     "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
     "cv_concretize_planes_workspace", "cv_babsr_weights", "cv_babsr_weights_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
@@ -77,22 +77,25 @@ def lib():
         "cv_root_bounds": (I, [P, P, P, P]),
         "cv_root_planes": (I, [P, P, P, P, P, P]),
         "cv_root_unstable_count": (I, [P, P]),
-        "cv_clip_domains": (I, [P, I, I, P, P, P, P, I, P]),
-        "cv_constraint_order": (I, [P, I, I, P, P, P, P, P]),
-        "cv_concretize_planes": (I, [P, I, P, P, P, I, I, I, P, P, P, P, P, P, S, P]),
+        "cv_rootset_create": (I, [P, I, P]),
+        "cv_root_count": (I, [P, P]),
+        "cv_clip_domains": (I, [P, P, I, I, P, P, P, P, I, P]),
+        "cv_constraint_order": (I, [P, P, I, I, P, P, P, P, P]),
+        "cv_concretize_planes": (I, [P, P, I, P, P, P, I, I, I, P, P, P, P, P, P, S, P]),
         "cv_babsr_weights": (I, [P, P, I, P, P, P, P, S, P]),
         "cv_babsr_weights_workspace": (I, [P, I, P]),
-        "cv_branch_relu": (I, [P, I, P, P, P, P, P, P, I, P, P, P, P, P, P, P]),
+        "cv_branch_relu": (I, [P, P, I, P, P, P, P, P, P, I, P, P, P, P, P, P, P]),
         "cv_branch_input": (I, [I, I, I, P, P, P, P, P, P, P]),
         "cv_intermediate_bounds": (I, [P, P, I, P, P, P, P, P, P, S, P]),
         "cv_intermediate_bounds_workspace": (I, [P, I, P]),
         "cv_concretize_planes_workspace": (I, [P, I, I, P]),
-        "cv_concretize": (I, [P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),
-        "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, I, P, P, P, P, S, P]),
-        "cv_bound_propagate_workspace": (I, [P, I, I, P]),
-        "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, P, P, P, P, P, I, P, P, I, F, F, F, F,
+        "cv_concretize": (I, [P, P, I, I, I, P, I, P, P, P, P, I, P, P, P, P, P]),
+        "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, P, I, P, P, P, P, S,
+                                   P]),
+        "cv_bound_propagate_workspace": (I, [P, I, I, I, P]),
+        "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, P, P, P, P, P, P, I, P, P, I, F, F, F, F,
                               P, P, P, S, P]),
-        "cv_alpha_step_workspace": (I, [P, I, I, P]),
+        "cv_alpha_step_workspace": (I, [P, I, I, I, P]),
         "cv_profile_enable": (I, [I]),
         "cv_profile_reset": (I, []),
         "cv_profile_collect": (I, [P]),

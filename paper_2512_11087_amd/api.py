@@ -89,6 +89,8 @@ class Net:
 class Root:
     """Root bounds and cached planes of a property (root box lo0, hi0)."""
 
+    P = 1
+
     def __init__(self, net, lo0, hi0, alpha0=0.5):
         self.net = net
         self.lo0, self.hi0 = _f32(lo0), _f32(hi0)
@@ -120,6 +122,43 @@ class Root:
         if h is not None and h.value and N._lib is not None:
             N._lib.cv_root_destroy(h)
             self.handle = None
+
+
+class RootSet:
+    """Several properties over one network, bounded together
+    (cv_rootset_create): calls taking a root accept a RootSet with ``pid``
+    (int32 [B], the property of each subdomain); objectives are then
+    per property, C [P, M, n_out] and t [P, M]."""
+
+    def __init__(self, roots):
+        roots = list(roots)
+        if not roots:
+            raise ValueError("RootSet needs at least one root")
+        self.roots = roots          # the set borrows their device state
+        self.net = roots[0].net
+        self.P = len(roots)
+        arr = (C.c_void_p * self.P)(*[r.handle.value for r in roots])
+        h = C.c_void_p()
+        N.call("cv_rootset_create", arr, self.P, C.byref(h))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and N._lib is not None:
+            N._lib.cv_root_destroy(h)
+            self.handle = None
+
+
+def _rh(root):
+    return root.handle if root is not None else None
+
+
+def _pid(pid):
+    if pid is None:
+        return None
+    if pid.dtype != torch.int32 or not pid.is_cuda or not pid.is_contiguous():
+        raise ValueError("pid must be a contiguous int32 CUDA tensor")
+    return _p(pid)
 
 
 class Constraints:
@@ -161,13 +200,13 @@ def _cref(cons):
     return None if cons is None else cons.ref()
 
 
-def constraint_order(root, lo, hi, cons, out=None):
+def constraint_order(root, lo, hi, cons, out=None, pid=None):
     """Constraint importance order of each subdomain over boxes lo/hi [B, n]
     (cv_constraint_order): returns int32 [B, kmax], position -> slot."""
     B, n = lo.shape
     order = out if out is not None else torch.empty(B, cons.kmax, dtype=torch.int32,
                                                     device="cuda")
-    N.call("cv_constraint_order", root.handle if root is not None else None, B, n, _cref(cons),
+    N.call("cv_constraint_order", _rh(root), _pid(pid), B, n, _cref(cons),
            _p(lo), _p(hi), _p(order), _stream())
     return order
 
@@ -184,9 +223,10 @@ def intermediate_bounds(net, root, lo, hi, l, u, infeasible=None, ws=None):
     return l, u
 
 
-def branch_relu(root, l, u, weight, splits, lo, hi, kmax_out):
+def branch_relu(root, l, u, weight, splits, lo, hi, kmax_out, pid=None):
     """ReLU branching (cv_branch_relu): returns (chosen [B], child splits
-    (Constraints, 2B rows), lo2, hi2 [2B, n_in])."""
+    (Constraints, 2B rows), lo2, hi2 [2B, n_in]); children 2b, 2b+1 belong
+    to parent b's property."""
     B, n0 = lo.shape
     dev = "cuda"
     chosen = torch.empty(B, dtype=torch.int32, device=dev)
@@ -195,7 +235,8 @@ def branch_relu(root, l, u, weight, splits, lo, hi, kmax_out):
     count2 = torch.empty(2 * B, dtype=torch.int32, device=dev)
     lo2 = torch.empty(2 * B, n0, device=dev)
     hi2 = torch.empty(2 * B, n0, device=dev)
-    N.call("cv_branch_relu", root.handle, B, _p(l), _p(u), _p(weight), _cref(splits), _p(lo),
+    N.call("cv_branch_relu", root.handle, _pid(pid), B, _p(l), _p(u), _p(weight), _cref(splits),
+           _p(lo),
            _p(hi), int(kmax_out), _p(chosen), _p(neuron2), _p(sign2), _p(count2), _p(lo2),
            _p(hi2), _stream())
     return chosen, Constraints(kmax_out, count2, neuron2, sign2), lo2, hi2
@@ -225,20 +266,20 @@ class Workspace:
         return self.buf
 
 
-def clip_domains(root, lo, hi, cons, mode="parallel", infeasible=None):
+def clip_domains(root, lo, hi, cons, mode="parallel", infeasible=None, pid=None):
     """Relaxed clipping of boxes lo/hi [B, n] in place; returns the
     infeasible flags [B] (uint8)."""
     B, n = lo.shape
     if infeasible is None:
         infeasible = torch.empty(B, dtype=torch.uint8, device="cuda")
     m = N.CV_CLIP_SEQUENTIAL if mode == "sequential" else N.CV_CLIP_PARALLEL
-    N.call("cv_clip_domains", root.handle if root is not None else None, B, n, _cref(cons),
+    N.call("cv_clip_domains", _rh(root), _pid(pid), B, n, _cref(cons),
            _p(lo), _p(hi), _p(infeasible), m, _stream())
     return infeasible
 
 
 def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infeasible=None,
-                      l=None, u=None, ws=None, topk=-1, weight=None, select=None):
+                      l=None, u=None, ws=None, topk=-1, weight=None, select=None, pid=None):
     """Bounds [B, n_hidden] of every hidden neuron over each box from the
     cached planes, then (complete) complete clipping of the unstable ones --
     all, or the top-k per layer by BaBSR score with ``weight``; returns
@@ -254,26 +295,27 @@ def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infea
     buf = None
     if need.value:
         buf = (ws or Workspace()).get(need.value)
-    N.call("cv_concretize_planes", root.handle, B, _p(lo), _p(hi), _cref(splits),
+    N.call("cv_concretize_planes", root.handle, _pid(pid), B, _p(lo), _p(hi), _cref(splits),
            int(bool(complete)), int(passes), int(topk), _p(weight), _p(l), _p(u), _p(infeasible),
            _p(select), _p(buf), need.value, _stream())
     return l, u, infeasible
 
 
 def babsr_weights(net, root, C_, t, ws=None):
-    """Weights [n_hidden] of the neuron-selection score (cv_babsr_weights)."""
-    M = C_.shape[0]
+    """Weights of the neuron-selection score (cv_babsr_weights): [n_hidden]
+    for a Root and C [M, n_out]; [P, n_hidden] for per-property C [P, M, n_out]."""
+    M = C_.shape[-2]
     need = C.c_size_t()
     N.call("cv_babsr_weights_workspace", net.handle, M, C.byref(need))
     buf = (ws or Workspace()).get(need.value)
-    w = torch.empty(net.n_hidden, device="cuda")
+    w = torch.empty(*C_.shape[:-2], net.n_hidden, device="cuda")
     N.call("cv_babsr_weights", net.handle, root.handle, M, _p(C_), _p(t), _p(w), _p(buf),
            need.value, _stream())
     return w
 
 
 def concretize(A, c, lo, hi, cons=None, passes=1, root=None, shared=False, want_ub=False,
-               want_beta=False, infeasible=None):
+               want_beta=False, infeasible=None, pid=None):
     """min (and optionally max) of A x + c over each box, with complete
     clipping against ``cons`` when given.  A: [B, P, n] or [P, n] (shared)."""
     B, n = lo.shape
@@ -281,45 +323,46 @@ def concretize(A, c, lo, hi, cons=None, passes=1, root=None, shared=False, want_
     lb = torch.empty(B, P, device="cuda")
     ub = torch.empty(B, P, device="cuda") if want_ub else None
     beta = torch.empty(B, P, max(cons.kmax, 1), device="cuda") if (want_beta and cons) else None
-    N.call("cv_concretize", root.handle if root is not None else None, B, P, n, _p(A),
+    N.call("cv_concretize", _rh(root), _pid(pid), B, P, n, _p(A),
            int(bool(shared)), _p(c), _p(lo), _p(hi), _cref(cons), int(passes), _p(lb), _p(ub),
            _p(beta), _p(infeasible), _stream())
     return lb, ub, beta
 
 
 def bound_propagate(net, root, C_, t, l, u, lo, hi, alpha=None, alpha_default=0.5,
-                    infeasible=None, cons=None, passes=1, want_plane=False, ws=None):
+                    infeasible=None, cons=None, passes=1, want_plane=False, ws=None, pid=None):
     """CROWN bound of the objective rows C y + t for every subdomain (with
     complete clipping when ``cons`` is given).  Returns lb [B, M] and, with
     ``want_plane``, the input plane (A [B, M, n_in], c [B, M])."""
     B = lo.shape[0]
-    M = C_.shape[0]
+    M = C_.shape[-2]
     lb = torch.empty(B, M, device="cuda")
     A = torch.empty(B, M, net.n_in, device="cuda") if want_plane else None
     c = torch.empty(B, M, device="cuda") if want_plane else None
     need = C.c_size_t()
-    N.call("cv_bound_propagate_workspace", net.handle, B, M, C.byref(need))
+    N.call("cv_bound_propagate_workspace", net.handle, root.P, B, M, C.byref(need))
     buf = (ws or Workspace()).get(need.value)
     N.call("cv_bound_propagate", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha),
-           float(alpha_default), _p(lo), _p(hi), _p(infeasible), root.handle, _cref(cons),
+           float(alpha_default), _p(lo), _p(hi), _p(infeasible), root.handle, _pid(pid),
+           _cref(cons),
            int(passes), _p(lb), _p(A), _p(c), _p(buf), need.value, _stream())
     return (lb, A, c) if want_plane else lb
 
 
 def alpha_step_into(net, root, C_, t, l, u, alpha, lo, hi, infeasible, cons, passes, adam_m,
-                    adam_v, step, lr, lb, ws, beta1=0.9, beta2=0.999, eps=1e-8):
+                    adam_v, step, lr, lb, ws, beta1=0.9, beta2=0.999, eps=1e-8, pid=None):
     """alpha_step writing the bound into a given buffer lb [B, M] and using a
     workspace that is already large enough (no allocation: usable under
     stream capture)."""
     B = lo.shape[0]
-    M = C_.shape[0]
+    M = C_.shape[-2]
     need = C.c_size_t()
-    N.call("cv_alpha_step_workspace", net.handle, B, M, C.byref(need))
+    N.call("cv_alpha_step_workspace", net.handle, root.P, B, M, C.byref(need))
     buf = ws.buf
     if buf is None or buf.numel() < need.value:
         raise RuntimeError("workspace too small for alpha_step_into; size it before capture")
     N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
-           _p(hi), _p(infeasible), root.handle, _cref(cons), int(passes), _p(adam_m),
+           _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons), int(passes), _p(adam_m),
            _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
            None, _p(buf), need.value, _stream())
     return lb
@@ -327,18 +370,18 @@ def alpha_step_into(net, root, C_, t, l, u, alpha, lo, hi, infeasible, cons, pas
 
 def alpha_step(net, root, C_, t, l, u, alpha, lo, hi, infeasible=None, cons=None, passes=1,
                adam_m=None, adam_v=None, step=1, lr=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
-               want_grad=False, ws=None):
+               want_grad=False, ws=None, pid=None):
     """Bound at the current alpha [B, M, n_hidden] and its gradient, then
     (lr > 0) one Adam ascent step on alpha in place.  Returns (lb, grad)."""
     B = lo.shape[0]
-    M = C_.shape[0]
+    M = C_.shape[-2]
     lb = torch.empty(B, M, device="cuda")
     grad = torch.empty_like(alpha) if want_grad else None
     need = C.c_size_t()
-    N.call("cv_alpha_step_workspace", net.handle, B, M, C.byref(need))
+    N.call("cv_alpha_step_workspace", net.handle, root.P, B, M, C.byref(need))
     buf = (ws or Workspace()).get(need.value)
     N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
-           _p(hi), _p(infeasible), root.handle, _cref(cons), int(passes), _p(adam_m),
+           _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons), int(passes), _p(adam_m),
            _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
            _p(grad), _p(buf), need.value, _stream())
     return lb, grad

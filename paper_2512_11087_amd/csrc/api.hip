@@ -124,7 +124,7 @@ struct Bwd {
   float* trace;
 };
 
-size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, bool trace,
+size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool keepAx, bool trace,
                   void* ws, Bwd* w) {
   const long long B = R / M;
   Carve cv(ws);
@@ -139,20 +139,22 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, bool keepAx, b
   x.rowc = cv.take<double>(R);
   x.rowerr = cv.take<double>(R);
   x.rowcabs = cv.take<double>(R);
-  x.psiT = cv.take<double>((size_t)M * net->n[T - 1]);
-  x.c0 = cv.take<double>(M);
-  x.e0 = cv.take<double>(M);
-  x.cabs0 = cv.take<double>(M);
+  x.psiT = cv.take<double>((size_t)P * M * net->n[T - 1]);
+  x.c0 = cv.take<double>((size_t)P * M);
+  x.e0 = cv.take<double>((size_t)P * M);
+  x.cabs0 = cv.take<double>((size_t)P * M);
   x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
   if (w) *w = x;
   return cv.off + 256;
 }
 
 // CROWN backward pass through layers T..1 of `net` for rows r = (b, m):
-// objective C (M x n_T) on z_T, then concretization over each box.  Leaves
-// the intercept and the plane's error bound in w.rowc / w.rowerr and, when
-// w.Ax is set, the input plane in w.Ax.
-cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B, int M,
+// objective C (M x n_T per property, [P, M, n_T]) on z_T, then concretization
+// over each box; the root-derived error weights are those of each subdomain's
+// property.  Leaves the intercept and the plane's error bound in w.rowc /
+// w.rowerr and, when w.Ax is set, the input plane in w.Ax.
+cv_status backward_run(const cv_net_s* net, const cv_root_s* root, CvProps props, int T, int B,
+                       int M,
                        const float* C, const float* t, const float* l, const float* u,
                        const float* alpha, double alpha_def, const float* lo, const float* hi,
                        const uint8_t* infeasible, const Bwd& w, float* lb, float* A_out,
@@ -160,11 +162,11 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
   const int R = B * M;
   const int Nh = net->n_hidden;
   const int nP = net->n[T - 1];
-  PLAUNCH("top", 2.0 * M * net->n[T] * nP, 8.0 * M * nP, launch_top(M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], root->vgemm[T - 1],
+  PLAUNCH("top", 2.0 * props.P * M * net->n[T] * nP, 8.0 * props.P * M * nP, launch_top(props.P, M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], props, T - 1,
                     w.psiT, w.c0, w.e0, w.cabs0, s));
   // ReLU of hidden layer T-1 (array index T-2)
   PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
-                          alpha_def, net->b[T - 2], root->wrel[T - 2], w.Om0, w.trace, w.rowc,
+                          alpha_def, net->b[T - 2], props, T - 2, w.Om0, w.trace, w.rowc,
                           w.rowerr, w.rowcabs, s));
   double* cur = w.Om0;
   double* nxt = w.Om1;
@@ -172,19 +174,25 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, int T, int B,
     const int K = net->n[i], N = net->n[i - 1];
     const ConvDesc* cd = conv_of(net, i);
     PLAUNCH(cd ? "conv_relax" : "gemm_relax", layer_flops(net, i, R), 8.0 * R * (K + N) + layer_wbytes(net, i), launch_gemm_relax(R, K, N, cur, net->W[i - 1], cd, M, Nh, net->off[i - 2], l, u, alpha,
-                             alpha_def, net->b[i - 2], root->wrel[i - 2], nxt, w.trace, w.part, s));
+                             alpha_def, net->b[i - 2], props, i - 2, nxt, w.trace, w.part, s));
     PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
   }
   const int n0 = net->n[0];
-  PLAUNCH(conv_of(net, 1) ? "conv_final" : "gemm_final", layer_flops(net, 1, R), 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + layer_wbytes(net, 1), launch_gemm_final(R, net->n[1], n0, cur, net->W[0], conv_of(net, 1), M, lo, hi, root->X0, w.Ax, A_out,
+  PLAUNCH(conv_of(net, 1) ? "conv_final" : "gemm_final", layer_flops(net, 1, R), 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + layer_wbytes(net, 1), launch_gemm_final(R, net->n[1], n0, cur, net->W[0], conv_of(net, 1), M, lo, hi, props, w.Ax, A_out,
                            w.part, s));
   PLAUNCH("finalize", 0, 8.0 * R * (2 * gemm_ntiles(n0) + 3), launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
                          root->gamma_big, infeasible, lb, c_out, s));
   return CV_OK;
 }
 
-cv_status resolve_cons(const cv_root_s* root, const cv_constraints* c, CvCons* out) {
+// The property table of `root` with each subdomain's property index.
+CvProps props_of(const cv_root_s* root, const int32_t* pid) {
+  return CvProps{root ? root->dtab : nullptr, pid, root ? root->P : 1};
+}
+
+cv_status resolve_cons(const cv_root_s* root, const int32_t* pid, const cv_constraints* c,
+                       CvCons* out) {
   memset(out, 0, sizeof(*out));
   if (!c) return CV_OK;
   if (c->kmax < 0) return CV_E_SHAPE;
@@ -196,10 +204,7 @@ cv_status resolve_cons(const cv_root_s* root, const cv_constraints* c, CvCons* o
     if (!c->sign) return CV_E_INVALID;
     out->neuron = c->neuron;
     out->sign = c->sign;
-    out->A_lo = root->A_lo;
-    out->A_hi = root->A_hi;
-    out->c_lo = root->c_lo;
-    out->c_hi = root->c_hi;
+    out->props = props_of(root, pid);
     out->nplanes = root->N;
   } else {
     if (!c->G || !c->h) return CV_E_INVALID;
@@ -211,6 +216,43 @@ cv_status resolve_cons(const cv_root_s* root, const cv_constraints* c, CvCons* o
 }
 
 bool finite01(float a) { return a >= 0.0f && a <= 1.0f; }
+
+RootDev root_dev(const cv_root_s* r) {
+  RootDev d{};
+  d.A_lo = r->A_lo;
+  d.A_hi = r->A_hi;
+  d.c_lo = r->c_lo;
+  d.c_hi = r->c_hi;
+  d.l0 = r->l0;
+  d.u0 = r->u0;
+  d.X0 = r->X0;
+  d.uidx = r->uidx;
+  d.sidx = r->sidx;
+  d.P = r->P_planes;
+  d.cP = r->cP;
+  d.eP = r->eP;
+  d.U = r->U;
+  for (int i = 0; i < CV_MAX_LAYERS; ++i) {
+    d.wrel[i] = r->wrel[i];
+    d.vgemm[i] = r->vgemm[i];
+  }
+  return d;
+}
+
+// (Re)writes the one-entry property table of a single root.
+cv_status root_sync_tab(cv_root_s* r) {
+  if (!r->dtab) {
+    if (hipMalloc((void**)&r->dtab, sizeof(RootDev)) != hipSuccess) {
+      r->dtab = nullptr;
+      return CV_E_NOMEM;
+    }
+  }
+  const RootDev d = root_dev(r);
+  if (hipMemcpy(r->dtab, &d, sizeof(RootDev), hipMemcpyHostToDevice) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  r->Umax = r->U;
+  return CV_OK;
+}
 
 }  // namespace
 
@@ -380,7 +422,12 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
 
 cv_status cv_root_destroy(cv_root r) {
   if (!r) return CV_OK;
-  float* fs[] = {r->A_lo, r->A_hi, r->l0, r->u0, r->lo0, r->hi0, r->P};
+  if (r->dtab) (void)hipFree(r->dtab);
+  if (!r->members.empty()) {  // a set owns only its table
+    delete r;
+    return CV_OK;
+  }
+  float* fs[] = {r->A_lo, r->A_hi, r->l0, r->u0, r->lo0, r->hi0, r->P_planes};
   for (float* p : fs)
     if (p) (void)hipFree(p);
   double* ds[] = {r->c_lo, r->c_hi, r->cP, r->xc0, r->rad0};
@@ -514,11 +561,11 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
     const int ni = net->n[i], off = net->off[i - 1];
     if ((st = make_vgemm(i))) { cleanup(); return fail(st); }
     Bwd w;
-    const size_t bytes = bwd_layout(net, i, ni, ni, true, false, nullptr, nullptr);
+    const size_t bytes = bwd_layout(net, i, ni, ni, 1, true, false, nullptr, nullptr);
     if (ws) (void)hipFree(ws);
     ws = nullptr;
     if (hipMalloc(&ws, bytes) != hipSuccess) { cleanup(); return fail(CV_E_NOMEM); }
-    bwd_layout(net, i, ni, ni, true, false, ws, &w);
+    bwd_layout(net, i, ni, ni, 1, true, false, ws, &w);
     if (Cdev) (void)hipFree(Cdev);
     if (tdev) (void)hipFree(tdev);
     if (lbtmp) (void)hipFree(lbtmp);
@@ -535,8 +582,9 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
         cleanup();
         return fail(hip_fail(hipGetLastError()));
       }
-      st = backward_run(net, r, i, 1, ni, Cdev, tdev, r->l0, r->u0, nullptr, alpha0, r->lo0,
-                        r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
+      if ((st = root_sync_tab(r))) { cleanup(); return fail(st); }
+      st = backward_run(net, r, props_of(r, nullptr), i, 1, ni, Cdev, tdev, r->l0, r->u0,
+                        nullptr, alpha0, r->lo0, r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
       if (st) { cleanup(); return fail(st); }
       float* Adst = (side ? r->A_hi : r->A_lo) + (size_t)off * n0;
       double* cdst = (side ? r->c_hi : r->c_lo) + off;
@@ -564,22 +612,66 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
   for (int j = 0; j < N; ++j) (hl0[j] < 0.0f && hu0[j] > 0.0f ? us : ss).push_back(j);
   r->U = (int)us.size();
   if ((st = dev_alloc(&r->uidx, us.size())) || (st = dev_alloc(&r->sidx, ss.size())) ||
-      (st = dev_alloc(&r->P, (size_t)2 * n0 * 2 * r->U)) || (st = dev_alloc(&r->cP, 2 * r->U)) ||
+      (st = dev_alloc(&r->P_planes, (size_t)2 * n0 * 2 * r->U)) || (st = dev_alloc(&r->cP, 2 * r->U)) ||
       (st = dev_alloc(&r->eP, 2 * r->U)))
     return fail(st);
   if ((!us.empty() && hipMemcpy(r->uidx, us.data(), us.size() * 4, hipMemcpyHostToDevice)) ||
       (!ss.empty() && hipMemcpy(r->sidx, ss.data(), ss.size() * 4, hipMemcpyHostToDevice)))
     return fail(hip_fail(hipGetLastError()));
-  if (launch_build_P(n0, r->U, r->uidx, r->A_lo, r->A_hi, r->c_lo, r->c_hi, r->X0, r->P, r->cP,
-                     r->eP, s) ||
+  if (launch_build_P(n0, r->U, r->uidx, r->A_lo, r->A_hi, r->c_lo, r->c_hi, r->X0, r->P_planes,
+                     r->cP, r->eP, s) ||
       hipStreamSynchronize(s))
     return fail(hip_fail(hipGetLastError()));
+  if ((st = root_sync_tab(r))) return fail(st);
   *out = r;
   return CV_OK;
 }
 
+cv_status cv_rootset_create(const cv_root* roots, int P, cv_root* out) {
+  if (!roots || !out || P < 1) return CV_E_INVALID;
+  *out = nullptr;
+  std::vector<RootDev> tab(P);
+  for (int p = 0; p < P; ++p) {
+    const cv_root_s* m = roots[p];
+    if (!m || !m->members.empty()) return CV_E_INVALID;  // members are single roots
+    if (m->net != roots[0]->net) return CV_E_INVALID;
+    tab[p] = root_dev(m);
+  }
+  cv_root_s* r = new cv_root_s();
+  for (int i = 0; i < CV_MAX_LAYERS; ++i) r->vgemm[i] = r->wrel[i] = nullptr;
+  const cv_root_s* r0 = roots[0];
+  r->net = r0->net;
+  r->n0 = r0->n0;
+  r->N = r0->N;
+  r->alpha0 = r0->alpha0;
+  r->gamma_big = r0->gamma_big;  // depends on the layer widths only
+  r->P = P;
+  r->U = -1;
+  for (int p = 0; p < P; ++p) {
+    r->members.push_back(roots[p]);
+    r->Umax = std::max(r->Umax, roots[p]->U);
+  }
+  if (hipMalloc((void**)&r->dtab, sizeof(RootDev) * P) != hipSuccess) {
+    r->dtab = nullptr;
+    cv_root_destroy(r);
+    return CV_E_NOMEM;
+  }
+  if (hipMemcpy(r->dtab, tab.data(), sizeof(RootDev) * P, hipMemcpyHostToDevice) != hipSuccess) {
+    cv_root_destroy(r);
+    return hip_fail(hipGetLastError());
+  }
+  *out = r;
+  return CV_OK;
+}
+
+cv_status cv_root_count(cv_root r, int* P) {
+  if (!r || !P) return CV_E_INVALID;
+  *P = r->P;
+  return CV_OK;
+}
+
 cv_status cv_root_bounds(cv_root r, float* l0, float* u0, hipStream_t s) {
-  if (!r || !l0 || !u0) return CV_E_INVALID;
+  if (!r || !l0 || !u0 || !r->members.empty()) return CV_E_INVALID;
   CV_HIP(hipMemcpyAsync(l0, r->l0, (size_t)r->N * 4, hipMemcpyDeviceToDevice, s));
   CV_HIP(hipMemcpyAsync(u0, r->u0, (size_t)r->N * 4, hipMemcpyDeviceToDevice, s));
   return CV_OK;
@@ -587,7 +679,7 @@ cv_status cv_root_bounds(cv_root r, float* l0, float* u0, hipStream_t s) {
 
 cv_status cv_root_planes(cv_root r, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
                          hipStream_t s) {
-  if (!r || !A_lo || !c_lo || !A_hi || !c_hi) return CV_E_INVALID;
+  if (!r || !A_lo || !c_lo || !A_hi || !c_hi || !r->members.empty()) return CV_E_INVALID;
   const size_t na = (size_t)r->N * r->n0 * 4;
   CV_HIP(hipMemcpyAsync(A_lo, r->A_lo, na, hipMemcpyDeviceToDevice, s));
   CV_HIP(hipMemcpyAsync(A_hi, r->A_hi, na, hipMemcpyDeviceToDevice, s));
@@ -597,13 +689,14 @@ cv_status cv_root_planes(cv_root r, float* A_lo, float* c_lo, float* A_hi, float
 }
 
 cv_status cv_root_unstable_count(cv_root r, int* count) {
-  if (!r || !count) return CV_E_INVALID;
+  if (!r || !count || !r->members.empty()) return CV_E_INVALID;
   *count = r->U;
   return CV_OK;
 }
 
-cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons, float* lo,
-                          float* hi, uint8_t* infeasible, int mode, hipStream_t s) {
+cv_status cv_clip_domains(cv_root root, const int32_t* pid, int B, int n,
+                          const cv_constraints* cons, float* lo, float* hi, uint8_t* infeasible,
+                          int mode, hipStream_t s) {
   if (B < 0 || n <= 0) return CV_E_SHAPE;
   if (mode != CV_CLIP_PARALLEL && mode != CV_CLIP_SEQUENTIAL) return CV_E_INVALID;
   if (B == 0) return CV_OK;
@@ -611,14 +704,15 @@ cv_status cv_clip_domains(cv_root root, int B, int n, const cv_constraints* cons
   if (n > 4096) return CV_E_UNSUPPORTED;
   if (cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
   CvCons c;
-  cv_status st = resolve_cons(root, cons, &c);
+  cv_status st = resolve_cons(root, pid, cons, &c);
   if (st) return st;
   PLAUNCH("clip", 0, 16.0 * B * n + 4.0 * B * c.kmax * n, launch_clip(B, n, c, lo, hi, infeasible, mode, s));
   return CV_OK;
 }
 
-cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* cons,
-                              const float* lo, const float* hi, int32_t* order, hipStream_t s) {
+cv_status cv_constraint_order(cv_root root, const int32_t* pid, int B, int n,
+                              const cv_constraints* cons, const float* lo, const float* hi,
+                              int32_t* order, hipStream_t s) {
   if (B < 0 || n <= 0) return CV_E_SHAPE;
   if (!cons) return CV_E_INVALID;
   if (B == 0 || cons->kmax == 0) return CV_OK;
@@ -626,7 +720,7 @@ cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* 
   if (cons->kmax > 64) return CV_E_UNSUPPORTED;
   if (cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
   CvCons c;
-  cv_status st = resolve_cons(root, cons, &c);
+  cv_status st = resolve_cons(root, pid, cons, &c);
   if (st) return st;
   c.order = nullptr;
   PLAUNCH("cons_order", 0, 8.0 * B * n + 4.0 * B * c.kmax * n, launch_cons_order(B, n, c, lo, hi, order, s));
@@ -635,12 +729,13 @@ cv_status cv_constraint_order(cv_root root, int B, int n, const cv_constraints* 
 
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes) {
   if (!root || !bytes || B < 0) return CV_E_INVALID;
-  *bytes = complete ? (size_t)B * root->U * 2 * sizeof(float) + (size_t)B * root->N + 512 : 0;
+  *bytes = complete ? (size_t)B * root->Umax * 2 * sizeof(float) + (size_t)B * root->N + 512 : 0;
   return CV_OK;
 }
 
-cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float* hi,
-                               const cv_constraints* splits, int complete, int passes, int topk,
+cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const float* lo,
+                               const float* hi, const cv_constraints* splits, int complete,
+                               int passes, int topk,
                                const float* weight, float* l, float* u, uint8_t* infeasible,
                                uint8_t* select, void* ws, size_t ws_bytes, hipStream_t s) {
   if (!root || B < 0) return CV_E_INVALID;
@@ -656,12 +751,15 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
   if (complete && ws_bytes < need) return CV_E_WORKSPACE;
   if (complete && root->n0 > 4096) return CV_E_UNSUPPORTED;
   CvCons sp;
-  cv_status st = resolve_cons(root, splits, &sp);
+  cv_status st = resolve_cons(root, pid, splits, &sp);
   if (st) return st;
-  const int Nh = root->N, U = root->U;
-  PLAUNCH("fill_stable", 0, 8.0 * B * (Nh - U), launch_fill_stable(B, Nh, Nh - U, root->sidx, root->l0, root->u0, l, u, s));
-  PLAUNCH("gemm_planes", 2.0 * B * (2.0 * root->n0) * (2.0 * U), 8.0 * B * root->n0 + 8.0 * B * U + 16.0 * root->n0 * U, launch_gemm_planes(B, root->n0, U, lo, hi, root->P, root->cP, root->eP, root->uidx,
-                            root->l0, root->u0, Nh, l, u, s));
+  const CvProps props = props_of(root, pid);
+  const int Nh = root->N, U = root->Umax;
+  int Umin = U;
+  for (const cv_root_s* m : root->members) Umin = std::min(Umin, m->U);
+  // algorithmic work at the widest property (exact for a single root)
+  PLAUNCH("fill_stable", 0, 8.0 * B * (Nh - U), launch_fill_stable(B, Nh, Nh - Umin, props, l, u, s));
+  PLAUNCH("gemm_planes", 2.0 * B * (2.0 * root->n0) * (2.0 * U), 8.0 * B * root->n0 + 8.0 * B * U + 16.0 * root->n0 * U, launch_gemm_planes(B, root->n0, U, lo, hi, props, Nh, l, u, s));
   if (splits && splits->kmax > 0 && splits->neuron) PLAUNCH("split_fix", 0, 8.0 * B * splits->kmax, launch_split_fix(B, Nh, sp, l, u, infeasible, s));
   if (complete && splits && splits->kmax > 0 && U > 0) {
     Carve cv(ws);
@@ -672,18 +770,17 @@ cv_status cv_concretize_planes(cv_root root, int B, const float* lo, const float
       sel = select ? select : cv.take<uint8_t>((size_t)B * Nh);
       const cv_net_s* net = root->net;
       const int nl = net->L - 1;
-      PLAUNCH("select_topk", 0, 8.0 * B * Nh + 1.0 * B * Nh, launch_select_topk(B, Nh, nl, net->off, net->n + 1, l, u, weight, topk, sel, s));
+      PLAUNCH("select_topk", 0, 8.0 * B * Nh + 1.0 * B * Nh, launch_select_topk(B, Nh, nl, net->off, net->n + 1, l, u, weight, props, topk, sel, s));
     }
-    PLAUNCH("ca_neurons", 0, 8.0 * B * U * root->n0, launch_ca_neurons(B, U, root->n0, root->uidx, root->A_lo, root->c_lo, root->A_hi,
-                             root->c_hi, sp, passes, lo, hi, l, u, Nh, infeasible, sel, Ltmp, s));
-    PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, root->uidx, Nh, Ltmp, l, u, infeasible, s));
+    PLAUNCH("ca_neurons", 0, 8.0 * B * U * root->n0, launch_ca_neurons(B, U, root->n0, props, sp, passes, lo, hi, l, u, Nh, infeasible, sel, Ltmp, s));
+    PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, props, Nh, Ltmp, l, u, infeasible, s));
   }
   return CV_OK;
 }
 
 cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes) {
   if (!net || !bytes || M <= 0) return CV_E_INVALID;
-  *bytes = bwd_layout(net, net->L, M, M, false, true, nullptr, nullptr) + (size_t)M * 4 + 256;
+  *bytes = bwd_layout(net, net->L, M, M, 1, false, true, nullptr, nullptr) + (size_t)M * 4 + 256;
   return CV_OK;
 }
 
@@ -695,14 +792,18 @@ cv_status cv_babsr_weights(cv_net net, cv_root root, int M, const float* C, cons
   cv_babsr_weights_workspace(net, M, &need);
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   Bwd w;
-  const size_t used = bwd_layout(net, net->L, M, M, false, true, ws, &w);
+  const size_t used = bwd_layout(net, net->L, M, M, 1, false, true, ws, &w);
   float* lbtmp = Carve((char*)ws + used).take<float>(M);
-  // one backward pass over the root box with the root bounds and slope
-  cv_status st = backward_run(net, root, net->L, 1, M, C, t, root->l0, root->u0, nullptr,
-                              root->alpha0, root->lo0, root->hi0, nullptr, w, lbtmp, nullptr,
-                              nullptr, s);
-  if (st) return st;
-  PLAUNCH("babsr_weight", 0, 4.0 * M * net->n_hidden, launch_babsr_weight(M, net->n_hidden, w.trace, weight, s));
+  // per property: one backward pass over its root box with its root bounds and slope
+  const int nL = net->n[net->L], Nh = net->n_hidden;
+  for (int p = 0; p < root->P; ++p) {
+    const cv_root_s* m = root->members.empty() ? root : root->members[p];
+    cv_status st = backward_run(net, m, props_of(m, nullptr), net->L, 1, M, C + (size_t)p * M * nL,
+                                t + (size_t)p * M, m->l0, m->u0, nullptr, m->alpha0, m->lo0,
+                                m->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
+    if (st) return st;
+    PLAUNCH("babsr_weight", 0, 4.0 * M * Nh, launch_babsr_weight(M, Nh, w.trace, weight + (size_t)p * Nh, s));
+  }
   return CV_OK;
 }
 
@@ -713,7 +814,7 @@ cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes) {
   for (int i = 2; i <= net->L - 1; ++i) {
     const int ni = net->n[i];
     nmax = std::max(nmax, ni);
-    best = std::max(best, bwd_layout(net, i, (long long)B * ni, ni, false, false, nullptr, nullptr));
+    best = std::max(best, bwd_layout(net, i, (long long)B * ni, ni, 1, false, false, nullptr, nullptr));
   }
   *bytes = best + (size_t)nmax * nmax * 4 + (size_t)nmax * 4 + 2 * (size_t)B * nmax * 4 + 1024;
   return CV_OK;
@@ -724,6 +825,7 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
                                  size_t ws_bytes, hipStream_t s) {
   if (!net || !root || B < 0) return CV_E_INVALID;
   if (root->net != net) return CV_E_INVALID;
+  if (!root->members.empty()) return CV_E_UNSUPPORTED;
   if (B == 0) return CV_OK;
   if (!lo || !hi || !l || !u) return CV_E_INVALID;
   size_t need = 0;
@@ -733,7 +835,7 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
   for (int i = 2; i <= net->L - 1; ++i) {
     const int ni = net->n[i];
     Bwd w;
-    const size_t used = bwd_layout(net, i, (long long)B * ni, ni, false, false, ws, &w);
+    const size_t used = bwd_layout(net, i, (long long)B * ni, ni, 1, false, false, ws, &w);
     Carve cv((char*)ws + used);
     float* C = cv.take<float>((size_t)ni * ni);
     float* t = cv.take<float>(ni);
@@ -741,8 +843,9 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
     float* lbn = cv.take<float>((size_t)B * ni);
     for (int side = 0; side < 2; ++side) {
       CV_HIP(launch_fill_eye(ni, side ? -1.0f : 1.0f, C, t, s));
-      cv_status st = backward_run(net, root, i, B, ni, C, t, l, u, nullptr, root->alpha0, lo, hi,
-                                  infeasible, w, side ? lbn : lbl, nullptr, nullptr, s);
+      cv_status st = backward_run(net, root, props_of(root, nullptr), i, B, ni, C, t, l, u,
+                                  nullptr, root->alpha0, lo, hi, infeasible, w,
+                                  side ? lbn : lbl, nullptr, nullptr, s);
       if (st) return st;
     }
     PLAUNCH("merge_layer", 0, 16.0 * B * ni, launch_merge_layer(B, ni, Nh, net->off[i - 1], lbl, lbn, l, u, infeasible, s));
@@ -750,7 +853,8 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
   return CV_OK;
 }
 
-cv_status cv_branch_relu(cv_root root, int B, const float* l, const float* u, const float* weight,
+cv_status cv_branch_relu(cv_root root, const int32_t* pid, int B, const float* l, const float* u,
+                         const float* weight,
                          const cv_constraints* splits, const float* lo, const float* hi,
                          int kmax_out, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
                          int32_t* count2, float* lo2, float* hi2, hipStream_t s) {
@@ -761,7 +865,7 @@ cv_status cv_branch_relu(cv_root root, int B, const float* l, const float* u, co
     return CV_E_INVALID;
   if (splits->kmax > 0 && (!splits->neuron || !splits->sign)) return CV_E_INVALID;
   if (kmax_out < splits->kmax || kmax_out < 1) return CV_E_SHAPE;
-  PLAUNCH("branch_relu", 0, 8.0 * B * root->N + 16.0 * B * root->n0, launch_branch_relu(B, root->N, l, u, weight, splits->kmax, splits->neuron, splits->sign,
+  PLAUNCH("branch_relu", 0, 8.0 * B * root->N + 16.0 * B * root->n0, launch_branch_relu(B, root->N, l, u, weight, props_of(root, pid), splits->kmax, splits->neuron, splits->sign,
                              splits->count, root->n0, lo, hi, kmax_out, chosen, neuron2, sign2,
                              count2, lo2, hi2, s));
   return CV_OK;
@@ -776,7 +880,8 @@ cv_status cv_branch_input(int B, int M, int n, const float* lo, const float* hi,
   return CV_OK;
 }
 
-cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A_shared,
+cv_status cv_concretize(cv_root root, const int32_t* pid, int B, int P, int n, const float* A,
+                        int A_shared,
                         const float* c, const float* lo, const float* hi,
                         const cv_constraints* cons, int passes, float* lb, float* ub, float* beta,
                         uint8_t* infeasible, hipStream_t s) {
@@ -788,7 +893,7 @@ cv_status cv_concretize(cv_root root, int B, int P, int n, const float* A, int A
   if (cons && cons->neuron && root && root->n0 != n) return CV_E_SHAPE;
   if (beta && !cons) return CV_E_INVALID;
   CvCons cc;
-  cv_status st = resolve_cons(root, cons, &cc);
+  cv_status st = resolve_cons(root, pid, cons, &cc);
   if (st) return st;
   PLAUNCH("ca_generic", 0, 4.0 * B * P * n + 8.0 * B * n, launch_ca_generic(B, P, n, A, A_shared, c, lo, hi, cons ? &cc : nullptr, passes, lb, ub,
                            beta, infeasible, s));
@@ -806,32 +911,32 @@ static cv_status check_prop(cv_net net, cv_root root, int B, int M, const float*
   return CV_OK;
 }
 
-cv_status cv_bound_propagate_workspace(cv_net net, int B, int M, size_t* bytes) {
-  if (!net || !bytes || B < 0 || M <= 0) return CV_E_INVALID;
-  *bytes = bwd_layout(net, net->L, (long long)B * M, M, true, false, nullptr, nullptr);
+cv_status cv_bound_propagate_workspace(cv_net net, int P, int B, int M, size_t* bytes) {
+  if (!net || !bytes || B < 0 || M <= 0 || P < 1) return CV_E_INVALID;
+  *bytes = bwd_layout(net, net->L, (long long)B * M, M, P, true, false, nullptr, nullptr);
   return CV_OK;
 }
 
 cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const float* t,
                              const float* l, const float* u, const float* alpha,
                              float alpha_default, const float* lo, const float* hi,
-                             uint8_t* infeasible, cv_root root, const cv_constraints* cons,
-                             int passes, float* lb, float* A_out, float* c_out, void* ws,
-                             size_t ws_bytes, hipStream_t s) {
+                             uint8_t* infeasible, cv_root root, const int32_t* pid,
+                             const cv_constraints* cons, int passes, float* lb, float* A_out,
+                             float* c_out, void* ws, size_t ws_bytes, hipStream_t s) {
   cv_status st = check_prop(net, root, B, M, C, t, l, u, lo, hi, lb);
   if (st || B == 0) return st;
   if (!alpha && !finite01(alpha_default)) return CV_E_INVALID;
   if (cons && passes < 1) return CV_E_INVALID;
   if ((A_out == nullptr) != (c_out == nullptr)) return CV_E_INVALID;
   size_t need = 0;
-  cv_bound_propagate_workspace(net, B, M, &need);
+  cv_bound_propagate_workspace(net, root->P, B, M, &need);
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
-  if ((st = resolve_cons(root, cons, &cc))) return st;
+  if ((st = resolve_cons(root, pid, cons, &cc))) return st;
   Bwd w;
-  bwd_layout(net, net->L, (long long)B * M, M, true, false, ws, &w);
-  st = backward_run(net, root, net->L, B, M, C, t, l, u, alpha, alpha_default, lo, hi, infeasible,
-                    w, lb, A_out, c_out, s);
+  bwd_layout(net, net->L, (long long)B * M, M, root->P, true, false, ws, &w);
+  st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u, alpha,
+                    alpha_default, lo, hi, infeasible, w, lb, A_out, c_out, s);
   if (st) return st;
   if (cons && cons->kmax > 0)
     PLAUNCH("ca_rows", 0, 8.0 * B * M * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
@@ -839,15 +944,16 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
   return CV_OK;
 }
 
-cv_status cv_alpha_step_workspace(cv_net net, int B, int M, size_t* bytes) {
-  if (!net || !bytes || B < 0 || M <= 0) return CV_E_INVALID;
-  *bytes = bwd_layout(net, net->L, (long long)B * M, M, true, true, nullptr, nullptr);
+cv_status cv_alpha_step_workspace(cv_net net, int P, int B, int M, size_t* bytes) {
+  if (!net || !bytes || B < 0 || M <= 0 || P < 1) return CV_E_INVALID;
+  *bytes = bwd_layout(net, net->L, (long long)B * M, M, P, true, true, nullptr, nullptr);
   return CV_OK;
 }
 
 cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t, const float* l,
                         const float* u, float* alpha, const float* lo, const float* hi,
-                        uint8_t* infeasible, cv_root root, const cv_constraints* cons, int passes,
+                        uint8_t* infeasible, cv_root root, const int32_t* pid,
+                        const cv_constraints* cons, int passes,
                         float* adam_m, float* adam_v, int step, float lr, float beta1, float beta2,
                         float eps, float* lb, float* grad, void* ws, size_t ws_bytes,
                         hipStream_t s) {
@@ -862,15 +968,15 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
       return CV_E_INVALID;
   }
   size_t need = 0;
-  cv_alpha_step_workspace(net, B, M, &need);
+  cv_alpha_step_workspace(net, root->P, B, M, &need);
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
-  if ((st = resolve_cons(root, cons, &cc))) return st;
+  if ((st = resolve_cons(root, pid, cons, &cc))) return st;
   Bwd w;
   const int R = B * M;
-  bwd_layout(net, net->L, R, M, true, true, ws, &w);
-  st = backward_run(net, root, net->L, B, M, C, t, l, u, alpha, 0.0, lo, hi, infeasible, w, lb,
-                    nullptr, nullptr, s);
+  bwd_layout(net, net->L, R, M, root->P, true, true, ws, &w);
+  st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u, alpha, 0.0, lo, hi,
+                    infeasible, w, lb, nullptr, nullptr, s);
   if (st) return st;
   // complete clipping (or plain concretization) leaves the minimising corner
   // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane

@@ -30,8 +30,52 @@ struct cv_net_s {
   std::vector<std::vector<float>> hW, hb;  // host copies (root set-up; conv: the dense matrix)
 };
 
+// Device view of one property's root state: pointers into its cv_root_s.
+struct RootDev {
+  const float* A_lo;      // [N, n0] cached planes (float32 coefficients)
+  const float* A_hi;
+  const double* c_lo;     // [N] float64 intercepts
+  const double* c_hi;
+  const float* l0;        // [N] root bounds
+  const float* u0;
+  const double* X0;       // [n0] max(|lo0|, |hi0|)
+  const int32_t* uidx;    // [U] root-unstable neurons
+  const int32_t* sidx;    // [N - U] root-stable neurons
+  const float* P;         // [2 n0, 2U] packed planes
+  const double* cP;       // [2U]
+  const double* eP;       // [2U]
+  int U;
+  const double* wrel[CV_MAX_LAYERS];   // hidden layer i at index i-1
+  const double* vgemm[CV_MAX_LAYERS];  // layer i at index i-1
+};
+
+// Property of each subdomain: subdomain b reads tab[pid[b]] (pid clamped to
+// [0, P)); pid null: every subdomain belongs to property 0.
+struct CvProps {
+  const RootDev* tab;
+  const int32_t* pid;
+  int P;
+};
+
+__device__ __forceinline__ int prop_index(const CvProps& p, int b) {
+  if (!p.pid) return 0;
+  const int q = p.pid[b];
+  return q < 0 ? 0 : (q >= p.P ? p.P - 1 : q);
+}
+
+__device__ __forceinline__ const RootDev& prop_of(const CvProps& p, int b) {
+  return p.tab[prop_index(p, b)];
+}
+
 struct cv_root_s {
   cv_net_s* net = nullptr;
+  // A set of properties (cv_rootset_create) has P > 1 members sharing one
+  // network; it borrows their state and owns only its table.  A single
+  // root is the set of itself (P = 1).
+  int P = 1;
+  std::vector<cv_root_s*> members;
+  RootDev* dtab = nullptr;                    // device [P]
+  int Umax = 0;                               // max U over the members
   int n0 = 0, N = 0, U = 0;
   float alpha0 = 0.5f;
   float *A_lo = nullptr, *A_hi = nullptr;    // [N, n0] float32 plane coefficients
@@ -47,7 +91,7 @@ struct cv_root_s {
   // re-concretization of cached planes: unstable neurons, packed plane matrix P [2 n0, 2U]
   int32_t* uidx = nullptr;                    // [U] global index of each root-unstable neuron
   int32_t* sidx = nullptr;                    // [N - U] root-stable neurons
-  float* P = nullptr;                         // [2 n0, 2U]
+  float* P_planes = nullptr;                  // [2 n0, 2U]
   double* cP = nullptr;                       // [2U] intercepts (lower | upper)
   double* eP = nullptr;                       // [2U] rigorous error bound per column
 };
@@ -62,8 +106,8 @@ struct CvCons {  // device view of cv_constraints (resolved)
   const int8_t* sign;
   const float* G;
   const float* h;
-  const float* A_lo; const float* A_hi; const double* c_lo; const double* c_hi;  // split form
-  int nplanes;  // rows of the plane table; split slots with other indices are ignored
+  CvProps props;  // split form: the planes of each subdomain's property (eqs. 9-10)
+  int nplanes;    // rows of the plane table; split slots with other indices are ignored
   const int32_t* order;  // [B, kmax] position -> slot, or null (list order)
 };
 
@@ -94,14 +138,15 @@ __device__ __forceinline__ void cons_row_slot(const CvCons& c, int b, int k, int
   if (c.neuron) {
     const int j = c.neuron[s];
     if (j < 0 || j >= c.nplanes) return;  // not a hidden neuron: slot ignored
+    const RootDev& rd = prop_of(c.props, b);
     if (c.sign[s] < 0) {
-      row = c.A_lo + (size_t)j * n;
+      row = rd.A_lo + (size_t)j * n;
       scale = 1.0f;
-      h = c.c_lo[j];
+      h = rd.c_lo[j];
     } else {
-      row = c.A_hi + (size_t)j * n;
+      row = rd.A_hi + (size_t)j * n;
       scale = -1.0f;
-      h = -c.c_hi[j];
+      h = -rd.c_hi[j];
     }
   } else {
     row = c.G + s * n;
@@ -122,25 +167,26 @@ hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, u
                        int mode, hipStream_t s);
 
 // backward pass building blocks
-hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
-                      const float* b, const double* vT, double* psiT, double* c0, double* e0,
-                      double* cabs0, hipStream_t s);
+hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float* t,
+                      const float* W, const float* b, CvProps props, int layer, double* psiT,
+                      double* c0, double* e0, double* cabs0, hipStream_t s);
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
                             const float* lz, const float* uz, const float* alpha,
-                            double alpha_def, const float* bprev, const double* wrel, double* Om,
+                            double alpha_def, const float* bprev, CvProps props, int layer,
+                            double* Om,
                             float* trace, double* rowc, double* rowerr, double* rowcabs,
                             hipStream_t s);
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
-                             double alpha_def, const float* bprev, const double* wrel,
+                             double alpha_def, const float* bprev, CvProps props, int layer,
                              double* Om_out, float* trace, double* part, hipStream_t s);
 hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
                          double* rowcabs, hipStream_t s);
 hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M,
-                             const float* lo, const float* hi, const double* X0, double* Ax,
+                             const float* lo, const float* hi, CvProps props, double* Ax,
                              float* A_out, double* part, hipStream_t s);
 int gemm_ntiles(int N);
 hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const double* rowc,
@@ -156,12 +202,10 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
                                double eps, int step, double* Psibar_out, hipStream_t s);
 
 // re-concretization of the cached planes
-hipError_t launch_fill_stable(int B, int Nh, int nS, const int32_t* sidx, const float* l0,
-                              const float* u0, float* l, float* u, hipStream_t s);
-hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float* hi,
-                              const float* P, const double* cP, const double* eP,
-                              const int32_t* uidx, const float* l0, const float* u0, int Nh,
-                              float* l, float* u, hipStream_t s);
+hipError_t launch_fill_stable(int B, int Nh, int nSmax, CvProps props, float* l, float* u,
+                              hipStream_t s);
+hipError_t launch_gemm_planes(int B, int n0, int Umax, const float* lo, const float* hi,
+                              CvProps props, int Nh, float* l, float* u, hipStream_t s);
 hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float* u,
                             uint8_t* infeasible, hipStream_t s);
 
@@ -174,13 +218,12 @@ hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, 
                              const float* lo, const float* hi, const CvCons* cons, int passes,
                              float* lb, float* ub, float* beta_out, uint8_t* infeasible,
                              hipStream_t s);
-hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
-                             const double* c_lo, const float* A_hi, const double* c_hi,
+hipError_t launch_ca_neurons(int B, int Umax, int n, CvProps props,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
                              const uint8_t* select, float* Ltmp, hipStream_t s);
 hipError_t launch_branch_relu(int B, int Nh, const float* l, const float* u, const float* weight,
-                              int kin, const int32_t* neuron, const int8_t* sign,
+                              CvProps props, int kin, const int32_t* neuron, const int8_t* sign,
                               const int32_t* count, int n0, const float* lo, const float* hi,
                               int kout, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
                               int32_t* count2, float* lo2, float* hi2, hipStream_t s);
@@ -192,9 +235,9 @@ hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, c
                               float* l, float* u, uint8_t* infeasible, hipStream_t s);
 hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s);
 hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
-                              const float* l, const float* u, const float* weight, int k,
-                              uint8_t* select, hipStream_t s);
-hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const float* Ltmp,
+                              const float* l, const float* u, const float* weight, CvProps props,
+                              int k, uint8_t* select, hipStream_t s);
+hipError_t launch_merge_neurons(int B, int Umax, CvProps props, int Nh, const float* Ltmp,
                                 float* l, float* u, uint8_t* infeasible, hipStream_t s);
 
 // root set-up helpers

@@ -36,7 +36,8 @@ __device__ __forceinline__ void wave_argmax(double& s, int& i) {
 
 __global__ __launch_bounds__(256) void k_branch_relu(int B, int Nh, const float* __restrict__ l,
                                                      const float* __restrict__ u,
-                                                     const float* __restrict__ weight, int kin,
+                                                     const float* __restrict__ wall, CvProps props,
+                                                     int kin,
                                                      const int32_t* __restrict__ neuron,
                                                      const int8_t* __restrict__ sign,
                                                      const int32_t* __restrict__ count, int n0,
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(256) void k_branch_relu(int B, int Nh, const float*
   const int lane = threadIdx.x & 63;
   const int b = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (b >= B) return;
+  const float* __restrict__ weight = wall + (size_t)prop_index(props, b) * Nh;  // [P, Nh]
   int cnt = count ? count[b] : kin;
   cnt = cnt < 0 ? 0 : (cnt > kin ? kin : cnt);
   const float* lb = l + (size_t)b * Nh;
@@ -126,12 +128,12 @@ __global__ __launch_bounds__(256) void k_branch_input(int B, int M, int n0,
 }  // namespace
 
 hipError_t launch_branch_relu(int B, int Nh, const float* l, const float* u, const float* weight,
-                              int kin, const int32_t* neuron, const int8_t* sign,
+                              CvProps props, int kin, const int32_t* neuron, const int8_t* sign,
                               const int32_t* count, int n0, const float* lo, const float* hi,
                               int kout, int32_t* chosen, int32_t* neuron2, int8_t* sign2,
                               int32_t* count2, float* lo2, float* hi2, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_branch_relu, dim3((B + 3) / 4), dim3(256), 0, s, B, Nh, l, u, weight, kin,
+  hipLaunchKernelGGL(k_branch_relu, dim3((B + 3) / 4), dim3(256), 0, s, B, Nh, l, u, weight, props, kin,
                      neuron, sign, count, n0, lo, hi, kout, chosen, neuron2, sign2, count2, lo2,
                      hi2);
   return hipGetLastError();

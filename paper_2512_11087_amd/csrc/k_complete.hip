@@ -413,12 +413,9 @@ __global__ __launch_bounds__(256, 2) void k_ca_generic(int B, int P, int n, cons
 // Intermediate neurons: lower plane (side 0) and negated upper plane (side 1) of every
 // root-unstable neuron still unstable in subdomain b.
 template <class Team, int EPL>
-__global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, const int32_t* __restrict__ uidx,
-                                                    const float* __restrict__ A_lo,
-                                                    const double* __restrict__ c_lo,
-                                                    const float* __restrict__ A_hi,
-                                                    const double* __restrict__ c_hi, CvCons cons,
-                                                    int passes, const float* __restrict__ lo,
+__global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int Umax, int n, CvProps props,
+                                                    CvCons cons, int passes,
+                                                    const float* __restrict__ lo,
                                                     const float* __restrict__ hi,
                                                     const float* __restrict__ l,
                                                     const float* __restrict__ u, int Nh,
@@ -428,20 +425,25 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   __shared__ CaShared<Team, EPL> sh;
   const Team tm = team_of(sh);
   constexpr int T = Team::SIZE;
-  const long long pid = (long long)blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
-  if (pid >= (long long)B * U * 2) return;
-  const int side = (int)(pid & 1);
-  const long long bc = pid >> 1;
-  const int b = (int)(bc / U), q = (int)(bc % U);
-  const int j = uidx[q];
+  const long long id = (long long)blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
+  if (id >= (long long)B * Umax * 2) return;
+  const int side = (int)(id & 1);
+  const long long bc = id >> 1;
+  const int b = (int)(bc / Umax), q = (int)(bc % Umax);
+  const RootDev& rd = prop_of(props, b);
+  if (q >= rd.U) {  // past this property's unstable neurons
+    if (tm.t == 0) Ltmp[id] = -INFINITY;
+    return;
+  }
+  const int j = rd.uidx[q];
   const float lj = l[(size_t)b * Nh + j], uj = u[(size_t)b * Nh + j];
   if ((infeasible && infeasible[b]) || !(lj < 0.0f && uj > 0.0f) ||
       (select && !select[(size_t)b * Nh + j])) {
-    if (tm.t == 0) Ltmp[pid] = -INFINITY;
+    if (tm.t == 0) Ltmp[id] = -INFINITY;
     return;
   }
-  const float* ap = (side ? A_hi : A_lo) + (size_t)j * n;
-  const double c = side ? -c_hi[j] : c_lo[j];
+  const float* ap = (side ? rd.A_hi : rd.A_lo) + (size_t)j * n;
+  const double c = side ? -rd.c_hi[j] : rd.c_lo[j];
   double a[EPL];
   const cv_buf bap = cv_buffer(ap, 4u * n);
 #pragma unroll
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int U, int n, cons
   const double L = ca_core<Team, EPL>(tm, n, a, c, 0.0, lo + (size_t)b * n, hi + (size_t)b * n,
                                       &cons, b, passes, empty, nullptr, nullptr, beta_slice(sh),
                                       q_slice(sh), w_slice(sh));
-  if (tm.t == 0) Ltmp[pid] = empty ? INFINITY : rd32(L);
+  if (tm.t == 0) Ltmp[id] = empty ? INFINITY : rd32(L);
 }
 
 }  // namespace
@@ -488,16 +490,15 @@ hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, 
   return hipGetLastError();
 }
 
-hipError_t launch_ca_neurons(int B, int U, int n, const int32_t* uidx, const float* A_lo,
-                             const double* c_lo, const float* A_hi, const double* c_hi,
+hipError_t launch_ca_neurons(int B, int Umax, int n, CvProps props,
                              const CvCons& cons, int passes, const float* lo, const float* hi,
                              const float* l, const float* u, int Nh, const uint8_t* infeasible,
                              const uint8_t* select, float* Ltmp, hipStream_t s) {
-  const long long tot = (long long)B * U * 2;
+  const long long tot = (long long)B * Umax * 2;
   if (tot <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
   CV_DISPATCH_TEAM(n, hipLaunchKernelGGL((k_ca_neurons<TM, E>), dim3(team_blocks(tot, TM::PER_BLOCK)),
-                                       dim3(256), 0, s, B, U, n, uidx, A_lo, c_lo, A_hi, c_hi,
-                                       cons, passes, lo, hi, l, u, Nh, infeasible, select, Ltmp));
+                                       dim3(256), 0, s, B, Umax, n, props, cons, passes, lo, hi,
+                                       l, u, Nh, infeasible, select, Ltmp));
   return hipGetLastError();
 }

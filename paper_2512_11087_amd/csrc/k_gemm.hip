@@ -131,18 +131,19 @@ __device__ __forceinline__ void load_bn(const float* __restrict__ Bm, int ldb, i
 // Software pipeline: while the MFMAs consume K-chunk c from one LDS buffer,
 // the global loads of chunk c+1 are in flight into registers; they are
 // written to the other buffer afterwards, one barrier per chunk.
-template <class T, int OCC, class LoadA, class Epi>
-__global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la,
-                                                   const float* __restrict__ Bm, int ldb, Epi epi,
-                                                   double* __restrict__ part, int ntiles) {
+// One BM x BN output tile at (m0, n0); its row-sum partials go to column
+// tile blockIdx.y.  Ends with LDS free for the next call.
+template <class T, class LoadA, class Epi>
+__device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, const LoadA& la,
+                                          const float* __restrict__ Bm, int ldb, const Epi& epi,
+                                          double* __restrict__ part, int ntiles) {
   constexpr int GBM = T::BM, GBN = T::BN, WN = T::WN, MI = T::MI, NI = T::NI;
   constexpr int SA_LD = T::SA_LD, SB_LD = T::SB_LD, APT = T::APT, BPT = T::BPT;
   __shared__ double sA[2][GBK * SA_LD];
   __shared__ float sB[2][GBK * SB_LD];
   __shared__ double sRed[NWAVE * GBM * NSUM_MAX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.x * GBM;
-  const int n0 = blockIdx.y * GBN;
+  (void)GBN;
   d4_t acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -264,6 +265,13 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la
   }
 }
 
+template <class T, int OCC, class LoadA, class Epi>
+__global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la,
+                                                   const float* __restrict__ Bm, int ldb, Epi epi,
+                                                   double* __restrict__ part, int ntiles) {
+  gemm_tile<T>(blockIdx.x * T::BM, blockIdx.y * T::BN, R, K, N, la, Bm, ldb, epi, part, ntiles);
+}
+
 // Hidden layer of the backward pass: psi = (Omega W)[r, j] is the coefficient
 // of post-activation j of the layer below; relax it, store the next Omega and
 // accumulate  sum psi*t (intercept), sum Omega'*b (that layer's bias term) and
@@ -277,7 +285,8 @@ struct EpiRelax {
   const float* alpha;
   double alpha_def;
   const float* bprev;
-  const double* wrel;
+  CvProps props;  // error weight wrel of layer `layer` of the row's property
+  int layer;
   double* Om;
   int ldo;
   float* trace;
@@ -285,10 +294,12 @@ struct EpiRelax {
     const float* l;
     const float* u;
     size_t ri;
+    const double* wrel;
   };
   __device__ __forceinline__ Row row(int r) const {
-    const size_t b = (size_t)(r / M);
-    return Row{lz + b * Nh + off, uz + b * Nh + off, (size_t)r * Nh + off};
+    const int b = r / M;
+    return Row{lz + (size_t)b * Nh + off, uz + (size_t)b * Nh + off, (size_t)r * Nh + off,
+               prop_of(props, b).wrel[layer]};
   }
   struct Pre {
     float l, u, al;
@@ -306,7 +317,7 @@ struct EpiRelax {
     if (trace) trace[ri] = trace32(psi);
     s[0] += psi * rl.t;
     s[1] += om * (double)bprev[j];
-    s[2] += fabs(psi) * wrel[j];
+    s[2] += fabs(psi) * w.wrel[j];
   }
 };
 
@@ -318,32 +329,34 @@ struct EpiFinal {
   int M, n0;
   const float* lo;
   const float* hi;
-  const double* X0;
+  CvProps props;  // X0 = max(|lo0|, |hi0|) of the row's property
   double* Ax;
   float* A_out;
   struct Row {
     const float* lo;
     const float* hi;
+    const double* X0;
   };
   __device__ __forceinline__ Row row(int r) const {
-    const size_t b = (size_t)(r / M);
-    return Row{lo + b * n0, hi + b * n0};
+    const int b = r / M;
+    return Row{lo + (size_t)b * n0, hi + (size_t)b * n0, prop_of(props, b).X0};
   }
   struct Pre {
     float xl, xh;
   };
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const { return Pre{w.lo[j], w.hi[j]}; }
-  __device__ __forceinline__ void apply(const Row&, const Pre& p, int r, int j, double a,
+  __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double a,
                                         double* s) const {
     const double xl = (double)p.xl, xh = (double)p.xh;
     s[0] += fmin(a * xl, a * xh);
-    s[1] += fabs(a) * X0[j];
+    s[1] += fabs(a) * w.X0[j];
     if (Ax) Ax[(size_t)r * n0 + j] = a;
     if (A_out) A_out[(size_t)r * n0 + j] = (float)a;
   }
 };
 
-// Re-concretized bound of cached plane column `col` over box r.
+// Re-concretized bound of cached plane column `col` over box b, for the
+// boxes of property p (rows of other properties are left alone).
 struct EpiPlanes {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 4;
@@ -355,12 +368,17 @@ struct EpiPlanes {
   const float* u0;
   float* l;
   float* u;
-  struct Row {};
-  __device__ __forceinline__ Row row(int) const { return Row{}; }
+  CvProps props;
+  int p;
+  struct Row {
+    bool mine;
+  };
+  __device__ __forceinline__ Row row(int b) const { return Row{prop_index(props, b) == p}; }
   struct Pre {};
   __device__ __forceinline__ Pre load(const Row&, int, int) const { return Pre{}; }
-  __device__ __forceinline__ void apply(const Row&, const Pre&, int b, int col, double v,
+  __device__ __forceinline__ void apply(const Row& w, const Pre&, int b, int col, double v,
                                         double*) const {
+    if (!w.mine) return;
     if (col < U) {
       const int j = uidx[col];
       const double x = v + cP[col] - eP[col];
@@ -707,6 +725,40 @@ hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
   return hipGetLastError();
 }
 
+// Plane re-concretization of a batch whose boxes belong to several
+// properties, each with its own packed plane matrix: a row tile is computed
+// once per property present in it (in increasing order; one pass when the
+// boxes are grouped by property), with that property's matrix, and each pass
+// writes only its own rows.
+__device__ __forceinline__ int tile_next_prop(const CvProps& props, int m0, int rows, int after) {
+  const int lane = threadIdx.x & 63;
+  int best = props.P;
+  for (int i = lane; i < rows; i += 64) {
+    const int q = prop_index(props, m0 + i);
+    if (q > after && q < best) best = q;
+  }
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_xor(best, d);
+    best = o < best ? o : best;
+  }
+  return __builtin_amdgcn_readfirstlane(best);
+}
+
+template <class T, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_gemm_planes(int B, int n0, LoadBox la, CvProps props,
+                                                          int Nh, float* l, float* u) {
+  const int m0 = blockIdx.x * T::BM, c0 = blockIdx.y * T::BN;
+  const int rows = min(T::BM, B - m0);
+  for (int p = tile_next_prop(props, m0, rows, -1); p < props.P;
+       p = tile_next_prop(props, m0, rows, p)) {
+    const RootDev& rd = props.tab[p];
+    const int N = 2 * rd.U;
+    if (c0 >= N) continue;
+    EpiPlanes e{rd.U, Nh, rd.cP, rd.eP, rd.uidx, rd.l0, rd.u0, l, u, props, p};
+    gemm_tile<T>(m0, c0, B, 2 * n0, N, la, rd.P, N, e, nullptr, 1);
+  }
+}
+
 template <class T = TileDefault, int OCC = 2, class LoadA, class Epi>
 hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi epi,
                     double* part, hipStream_t s) {
@@ -725,28 +777,29 @@ int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
 hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
-                             double alpha_def, const float* bprev, const double* wrel,
+                             double alpha_def, const float* bprev, CvProps props, int layer,
                              double* Om_out, float* trace, double* part, hipStream_t s) {
-  EpiRelax e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, wrel, Om_out, N, trace};
+  EpiRelax e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props, layer, Om_out, N, trace};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
 hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M,
-                             const float* lo, const float* hi, const double* X0, double* Ax,
+                             const float* lo, const float* hi, CvProps props, double* Ax,
                              float* A_out, double* part, hipStream_t s) {
-  EpiFinal e{M, N, lo, hi, X0, Ax, A_out};
+  EpiFinal e{M, N, lo, hi, props, Ax, A_out};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
-hipError_t launch_gemm_planes(int B, int n0, int U, const float* lo, const float* hi,
-                              const float* P, const double* cP, const double* eP,
-                              const int32_t* uidx, const float* l0, const float* u0, int Nh,
-                              float* l, float* u, hipStream_t s) {
-  EpiPlanes e{U, Nh, cP, eP, uidx, l0, u0, l, u};
-  return run_gemm<TilePlanes>(B, 2 * n0, 2 * U, LoadBox{lo, hi, n0}, P, 2 * U, e, nullptr, s);
+hipError_t launch_gemm_planes(int B, int n0, int Umax, const float* lo, const float* hi,
+                              CvProps props, int Nh, float* l, float* u, hipStream_t s) {
+  if (B <= 0 || Umax <= 0) return hipSuccess;
+  dim3 grid((B + TilePlanes::BM - 1) / TilePlanes::BM, (2 * Umax + TilePlanes::BN - 1) / TilePlanes::BN);
+  hipLaunchKernelGGL((k_gemm_planes<TilePlanes, 2>), grid, dim3(256), 0, s, B, n0,
+                     LoadBox{lo, hi, n0}, props, Nh, l, u);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,

@@ -6,15 +6,17 @@
 
 namespace {
 
-// Psi_T = C W_T (shared by all subdomains), c0 = t + C b_T and the error
-// weight e0 = |C| vT, one workgroup per objective row m.
+// Psi_T = C W_T (shared by the subdomains of a property), c0 = t + C b_T and
+// the error weight e0 = |C| vT, one workgroup per (objective row m, property p);
+// C is [P, M, nT], t [P, M], outputs [P, M, .].
 __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float* __restrict__ C,
                                              const float* __restrict__ t,
                                              const float* __restrict__ W,
-                                             const float* __restrict__ b,
-                                             const double* __restrict__ vT, double* psiT,
-                                             double* c0, double* e0, double* cabs0) {
-  const int m = blockIdx.x;
+                                             const float* __restrict__ b, CvProps props,
+                                             int layer, double* psiT, double* c0, double* e0,
+                                             double* cabs0) {
+  const int m = blockIdx.y * M + blockIdx.x;  // row of the stacked objective
+  const double* __restrict__ vT = props.tab[blockIdx.y].vgemm[layer];
   const float* crow = C + (size_t)m * nT;
   for (int j = threadIdx.x; j < nP; j += blockDim.x) {
     double acc = 0.0;
@@ -38,17 +40,21 @@ __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float*
 }
 
 // First relaxation (ReLU of layer T-1) of every row r = (b, m): one wave
-// per row.  Writes Omega_{T-1} and initialises the row state.
+// per row.  Writes Omega_{T-1} and initialises the row state; the top rows
+// are those of subdomain b's property.
 __global__ __launch_bounds__(256) void k_relax_top(
     int R, int M, int nP, int Nh, int off, const double* __restrict__ psiT,
     const double* __restrict__ c0, const double* __restrict__ e0, const double* __restrict__ cabs0,
     const float* __restrict__ lz, const float* __restrict__ uz, const float* __restrict__ alpha,
-    double alpha_def, const float* __restrict__ bprev, const double* __restrict__ wrel,
+    double alpha_def, const float* __restrict__ bprev, CvProps props, int layer,
     double* Om, float* trace, double* rowc, double* rowerr, double* rowcabs) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= R) return;
-  const int b = r / M, m = r % M;
+  const int b = r / M;
+  const int p = prop_index(props, b);
+  const int m = p * M + r % M;
+  const double* __restrict__ wrel = props.tab[p].wrel[layer];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int j = lane; j < nP; j += 64) {
     const double psi = psiT[(size_t)m * nP + j];
@@ -115,15 +121,16 @@ __global__ void k_finalize(int R, int M, int ntiles, const double* __restrict__ 
   if (c_out) c_out[r] = rd32(c - eplane - 1.2e-7 * sabs);
 }
 
-__global__ void k_fill_stable(int B, int Nh, int nS, const int32_t* __restrict__ sidx,
-                              const float* __restrict__ l0, const float* __restrict__ u0,
-                              float* l, float* u) {
+// Root-stable neurons of each subdomain's property keep their root bounds.
+__global__ void k_fill_stable(int B, int Nh, int nSmax, CvProps props, float* l, float* u) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * nS) return;
-  const int b = (int)(i / nS), q = (int)(i % nS);
-  const int j = sidx[q];
-  l[(size_t)b * Nh + j] = l0[j];
-  u[(size_t)b * Nh + j] = u0[j];
+  if (i >= (size_t)B * nSmax) return;
+  const int b = (int)(i / nSmax), q = (int)(i % nSmax);
+  const RootDev& rd = prop_of(props, b);
+  if (q >= Nh - rd.U) return;
+  const int j = rd.sidx[q];
+  l[(size_t)b * Nh + j] = rd.l0[j];
+  u[(size_t)b * Nh + j] = rd.u0[j];
 }
 
 // Split neurons are fixed to their branch; l > u marks the subdomain empty.
@@ -142,13 +149,15 @@ __global__ void k_split_fix(int B, int Nh, CvCons sp, float* l, float* u, uint8_
 
 // Complete-clipping results of intermediate neurons: l <- max(l, L_lo),
 // u <- min(u, -L_up); an empty result marks the subdomain.
-__global__ void k_merge_neurons(int B, int U, const int32_t* __restrict__ uidx, int Nh,
+__global__ void k_merge_neurons(int B, int Umax, CvProps props, int Nh,
                                 const float* __restrict__ Ltmp, float* l, float* u,
                                 uint8_t* infeasible) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * U) return;
-  const int b = (int)(i / U), c = (int)(i % U);
-  const int j = uidx[c];
+  if (i >= (size_t)B * Umax) return;
+  const int b = (int)(i / Umax), c = (int)(i % Umax);
+  const RootDev& rd = prop_of(props, b);
+  if (c >= rd.U) return;
+  const int j = rd.uidx[c];
   const float Ll = Ltmp[i * 2], Lu = Ltmp[i * 2 + 1];
   const size_t bi = (size_t)b * Nh + j;
   if (Ll == INFINITY || Lu == INFINITY) { infeasible[b] = 1; return; }
@@ -288,10 +297,11 @@ struct LayerTable {
 constexpr int TOPK_NMAX = 4096;
 __global__ __launch_bounds__(256) void k_select_topk(int Nh, LayerTable lt, const float* __restrict__ l,
                                                      const float* __restrict__ u,
-                                                     const float* __restrict__ weight, int k,
-                                                     uint8_t* select) {
+                                                     const float* __restrict__ wall, CvProps props,
+                                                     int k, uint8_t* select) {
   __shared__ double ssc[TOPK_NMAX];
   const int b = blockIdx.x, layer = blockIdx.y;
+  const float* __restrict__ weight = wall + (size_t)prop_index(props, b) * Nh;  // [P, Nh]
   const int off = lt.off[layer], n = lt.size[layer];
   const float* lb = l + (size_t)b * Nh + off;
   const float* ub = u + (size_t)b * Nh + off;
@@ -338,23 +348,24 @@ __global__ void k_merge_layer(int B, int n, int Nh, int off, const float* __rest
 
 }  // namespace
 
-hipError_t launch_top(int M, int nT, int nP, const float* C, const float* t, const float* W,
-                      const float* b, const double* vT, double* psiT, double* c0, double* e0,
-                      double* cabs0, hipStream_t s) {
-  hipLaunchKernelGGL(k_top, dim3(M), dim3(256), 0, s, M, nT, nP, C, t, W, b, vT, psiT, c0, e0, cabs0);
+hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float* t,
+                      const float* W, const float* b, CvProps props, int layer, double* psiT,
+                      double* c0, double* e0, double* cabs0, hipStream_t s) {
+  hipLaunchKernelGGL(k_top, dim3(M, P), dim3(256), 0, s, M, nT, nP, C, t, W, b, props, layer,
+                     psiT, c0, e0, cabs0);
   return hipGetLastError();
 }
 
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
                             const float* lz, const float* uz, const float* alpha,
-                            double alpha_def, const float* bprev, const double* wrel, double* Om,
-                            float* trace, double* rowc, double* rowerr, double* rowcabs,
-                            hipStream_t s) {
+                            double alpha_def, const float* bprev, CvProps props, int layer,
+                            double* Om, float* trace, double* rowc, double* rowerr,
+                            double* rowcabs, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_relax_top, dim3((R + 3) / 4), dim3(256), 0, s, R, M, nP, Nh, off, psiT, c0,
-                     e0, cabs0, lz, uz, alpha, alpha_def, bprev, wrel, Om, trace, rowc, rowerr,
-                     rowcabs);
+                     e0, cabs0, lz, uz, alpha, alpha_def, bprev, props, layer, Om, trace, rowc,
+                     rowerr, rowcabs);
   return hipGetLastError();
 }
 
@@ -375,12 +386,12 @@ hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const d
   return hipGetLastError();
 }
 
-hipError_t launch_fill_stable(int B, int Nh, int nS, const int32_t* sidx, const float* l0,
-                              const float* u0, float* l, float* u, hipStream_t s) {
-  const size_t tot = (size_t)B * nS;
+hipError_t launch_fill_stable(int B, int Nh, int nSmax, CvProps props, float* l, float* u,
+                              hipStream_t s) {
+  const size_t tot = (size_t)B * nSmax;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_stable, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, Nh,
-                     nS, sidx, l0, u0, l, u);
+                     nSmax, props, l, u);
   return hipGetLastError();
 }
 
@@ -393,12 +404,12 @@ hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float
   return hipGetLastError();
 }
 
-hipError_t launch_merge_neurons(int B, int U, const int32_t* uidx, int Nh, const float* Ltmp,
+hipError_t launch_merge_neurons(int B, int Umax, CvProps props, int Nh, const float* Ltmp,
                                 float* l, float* u, uint8_t* infeasible, hipStream_t s) {
-  const size_t tot = (size_t)B * U;
+  const size_t tot = (size_t)B * Umax;
   if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_merge_neurons, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, U,
-                     uidx, Nh, Ltmp, l, u, infeasible);
+  hipLaunchKernelGGL(k_merge_neurons, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, B, Umax,
+                     props, Nh, Ltmp, l, u, infeasible);
   return hipGetLastError();
 }
 
@@ -442,8 +453,8 @@ hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight,
 }
 
 hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const int* size,
-                              const float* l, const float* u, const float* weight, int k,
-                              uint8_t* select, hipStream_t s) {
+                              const float* l, const float* u, const float* weight, CvProps props,
+                              int k, uint8_t* select, hipStream_t s) {
   if (B <= 0 || nlayers <= 0) return hipSuccess;
   LayerTable lt{};
   lt.count = nlayers;
@@ -452,8 +463,8 @@ hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const 
     lt.off[i] = off[i];
     lt.size[i] = size[i];
   }
-  hipLaunchKernelGGL(k_select_topk, dim3(B, nlayers), dim3(256), 0, s, Nh, lt, l, u, weight, k,
-                     select);
+  hipLaunchKernelGGL(k_select_topk, dim3(B, nlayers), dim3(256), 0, s, Nh, lt, l, u, weight, props,
+                     k, select);
   return hipGetLastError();
 }
 

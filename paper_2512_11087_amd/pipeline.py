@@ -1,4 +1,5 @@
-"""The batched clip-and-verify pass over one property, sequenced on the
+"""The batched clip-and-verify pass over one property or a set of
+properties (Batch.pid: the property of each subdomain), sequenced on the
 device through the C ABI:
 
   split halfspaces + relaxed clipping     (clip_domains)
@@ -32,6 +33,8 @@ class PassConfig:
 class Property:
     """A network, root box and specification resident on the device."""
 
+    P = 1
+
     def __init__(self, layers, lo0, hi0, C, t, alpha0=0.5):
         self.net = api.Net(layers)
         self.root = api.Root(self.net, lo0, hi0, alpha0)
@@ -58,23 +61,65 @@ class Property:
         return lo, hi
 
 
+class PropertySet:
+    """P properties over one network (each its own root box and objective),
+    bounded in the same launches: ``root`` is an api.RootSet, C [P, M, n_out],
+    t [P, M]; a batch's ``pid`` gives each subdomain's property."""
+
+    def __init__(self, layers, lo0s, hi0s, Cs, ts, alpha0=0.5):
+        self.net = api.Net(layers)
+        self.roots = [api.Root(self.net, lo, hi, alpha0) for lo, hi in zip(lo0s, hi0s)]
+        self.root = api.RootSet(self.roots)
+        self.P = len(self.roots)
+        self.C = api._f32(np.stack([np.asarray(c, np.float32) for c in Cs]))
+        self.t = api._f32(np.stack([np.asarray(x, np.float32) for x in ts]))
+        self.M = self.C.shape[1]
+        self.ws = api.Workspace()
+        self.ws2 = api.Workspace()
+        self._babsr = None
+
+    def babsr_weight(self):
+        """Per-property weights of the selection score [P, n_hidden]."""
+        if self._babsr is None:
+            self._babsr = api.babsr_weights(self.net, self.root, self.C, self.t, self.ws)
+        return self._babsr
+
+    @classmethod
+    def from_workload(cls, w):
+        """From a workload with extra["properties"] = list of (lo0, hi0, C, t)."""
+        ps = w.extra["properties"]
+        return cls(list(w.net.layers), [p[0] for p in ps], [p[1] for p in ps],
+                   [p[2] for p in ps], [p[3] for p in ps], w.alpha0)
+
+    def boxes(self, counts):
+        """Root boxes of counts[p] subdomains of each property, grouped by
+        property, and their pid [B]."""
+        counts = [int(c) for c in counts]
+        lo = torch.cat([r.lo0.expand(c, -1) for r, c in zip(self.roots, counts)]).contiguous()
+        hi = torch.cat([r.hi0.expand(c, -1) for r, c in zip(self.roots, counts)]).contiguous()
+        pid = torch.repeat_interleave(torch.arange(self.P, dtype=torch.int32),
+                                      torch.tensor(counts)).to("cuda")
+        return lo, hi, pid
+
+
 @dataclass
 class Batch:
     lo: torch.Tensor
     hi: torch.Tensor
     splits: api.Constraints
     ordered: api.Constraints = None   # splits in importance order over the clipped box
+    pid: torch.Tensor = None          # int32 [B] property of each subdomain (property sets)
 
     def cons(self):
         """The constraints as complete clipping takes them."""
         return self.ordered if self.ordered is not None else self.splits
 
 
-def make_batch(prop, neuron, sign, count, lo=None, hi=None):
+def make_batch(prop, neuron, sign, count, lo=None, hi=None, pid=None):
     B = neuron.shape[0]
     if lo is None:
         lo, hi = prop.boxes(B)
-    return Batch(lo, hi, api.Constraints.splits(neuron, sign, count))
+    return Batch(lo, hi, api.Constraints.splits(neuron, sign, count), pid=pid)
 
 
 def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
@@ -87,11 +132,12 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
     if cfg.order and cfg.clip == "sequential" and batch.splits is not None:
         # sequential clipping takes the constraints closest to the box centre first
         clip_cons = batch.splits.with_order(
-            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order0")))
+            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order0"),
+                                 pid=batch.pid))
         out["order0"] = clip_cons.order
     if cfg.clip != "none" and batch.splits is not None:
         inf = api.clip_domains(prop.root, batch.lo, batch.hi, clip_cons, cfg.clip,
-                               infeasible=out.get("infeasible"))
+                               infeasible=out.get("infeasible"), pid=batch.pid)
     else:
         inf = out.get("infeasible")
         if inf is None:
@@ -102,7 +148,8 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
     if cfg.order and batch.splits is not None:
         # complete clipping: the order over the clipped box
         batch.ordered = batch.splits.with_order(
-            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order1")))
+            api.constraint_order(prop.root, batch.lo, batch.hi, batch.splits, out.get("order1"),
+                                 pid=batch.pid))
         out["order1"] = batch.ordered.order
     weight, select = None, None
     if cfg.complete_intermediate and cfg.topk >= 0:
@@ -113,10 +160,12 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
         out["select"] = select
     l, u, inf = api.concretize_planes(prop.root, batch.lo, batch.hi, batch.cons(),
                                       cfg.complete_intermediate, cfg.passes, inf,
-                                      out.get("l"), out.get("u"), prop.ws2, cfg.topk, weight, select)
+                                      out.get("l"), out.get("u"), prop.ws2, cfg.topk, weight, select,
+                                      pid=batch.pid)
     cons = batch.cons() if cfg.complete_final else None
     res = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, l, u, batch.lo, batch.hi,
-                              None, cfg.alpha, inf, cons, cfg.passes, want_plane=planes, ws=prop.ws)
+                              None, cfg.alpha, inf, cons, cfg.passes, want_plane=planes, ws=prop.ws,
+                              pid=batch.pid)
     if planes:
         lb, A, c = res
         out.update(A=A, c=c)
@@ -153,7 +202,7 @@ def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0
     for s in range(1, steps + 1):
         lb, _ = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha, batch.lo,
                                batch.hi, infeasible, cons, passes, state["m"], state["v"], s,
-                               lr * decay ** (s - 1), ws=prop.ws)
+                               lr * decay ** (s - 1), ws=prop.ws, pid=batch.pid)
         torch.maximum(best, lb, out=best)
     return best, alpha
 
@@ -166,6 +215,8 @@ def input_pass(prop, batch, cfg=PassConfig(), out=None):
     against the constraints.  Returns dict(infeasible, l, u, lb, A, c)."""
     B = batch.lo.shape[0]
     out = out if out is not None else {}
+    if prop.P != 1:
+        raise ValueError("input_pass bounds one property (fresh-box intermediate bounds)")
     if cfg.clip != "none" and batch.splits is not None:
         inf = api.clip_domains(prop.root, batch.lo, batch.hi, batch.splits, cfg.clip,
                                infeasible=out.get("infeasible"))
@@ -195,7 +246,7 @@ class AlphaBound(torch.autograd.Function):
         cons = batch.cons() if complete else None
         lb, grad = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha.detach(),
                                   batch.lo, batch.hi, infeasible, cons, passes, want_grad=True,
-                                  ws=prop.ws)
+                                  ws=prop.ws, pid=batch.pid)
         ctx.save_for_backward(grad)
         return lb
 
@@ -229,7 +280,7 @@ class AlphaOptGraph:
         cons = batch.cons() if complete else None
         # size the workspace outside the capture
         api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, self.alpha, batch.lo, batch.hi,
-                       infeasible, cons, passes, self.m, self.v, 1, 0.0, ws=prop.ws)
+                       infeasible, cons, passes, self.m, self.v, 1, 0.0, ws=prop.ws, pid=batch.pid)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream()
@@ -243,7 +294,8 @@ class AlphaOptGraph:
                 for s in range(1, steps + 1):
                     api.alpha_step_into(prop.net, prop.root, prop.C, prop.t, l, u, self.alpha,
                                         batch.lo, batch.hi, infeasible, cons, passes, self.m,
-                                        self.v, s, lr * decay ** (s - 1), self.lbs[s - 1], prop.ws)
+                                        self.v, s, lr * decay ** (s - 1), self.lbs[s - 1], prop.ws,
+                                        pid=batch.pid)
                     torch.maximum(self.best, self.lbs[s - 1], out=self.best)
         torch.cuda.current_stream().wait_stream(side)
 

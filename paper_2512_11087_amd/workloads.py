@@ -352,6 +352,90 @@ def wide_cnn(B: int = 32, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
     return Workload("cnn4x24x24-c16-c8-10-3", net, lo, hi, C, t, B, counts.astype(np.int32))
 
 
+@dataclass
+class WorkloadSet:
+    """Several properties over one network (own box centre, label and
+    subdomain count each).  ``counts[p]`` subdomains of property p, grouped by
+    property in order; ``split_counts`` [sum(counts)] split depth of each;
+    ``member(p)`` is property p alone as a Workload."""
+
+    name: str
+    net: Network
+    lo0s: List[np.ndarray]
+    hi0s: List[np.ndarray]
+    Cs: List[np.ndarray]
+    ts: List[np.ndarray]
+    counts: np.ndarray
+    split_counts: np.ndarray
+    alpha0: float = 0.5
+
+    @property
+    def P(self) -> int:
+        return len(self.lo0s)
+
+    @property
+    def B(self) -> int:
+        return int(self.counts.sum())
+
+    def pid(self) -> np.ndarray:
+        return np.repeat(np.arange(self.P, dtype=np.int32), self.counts)
+
+    def member(self, p: int) -> Workload:
+        start = int(self.counts[:p].sum())
+        sc = self.split_counts[start:start + int(self.counts[p])]
+        return Workload(f"{self.name}[{p}]", self.net, self.lo0s[p], self.hi0s[p], self.Cs[p],
+                        self.ts[p], int(self.counts[p]), sc, self.alpha0)
+
+
+def property_set(net: Network, n_in: int, centre_range, eps: float, clip, counts,
+                 depth, name: str, seed_offset: int = 0) -> WorkloadSet:
+    """Properties of one network: centre p ~ U(centre_range)^n_in (seed 1,
+    the p-th draw), box centre +- eps (clipped to ``clip``), label = argmax
+    of the network at the centre, margin rows; split depth of every
+    subdomain ~ U{depth[0]..depth[1]} (seed 4)."""
+    counts = np.asarray(counts, np.int64)
+    P = counts.size
+    cs = centres(n_in, P + seed_offset, centre_range[0], centre_range[1])[seed_offset:]
+    lo0s, hi0s, Cs, ts = [], [], [], []
+    for p in range(P):
+        lo, hi = box_around(cs[p], eps, clip=clip)
+        label = int(np.argmax(forward(net, cs[p][None, :].astype(np.float32))[0]))
+        C, t = margin_spec(net.n_out, label)
+        lo0s.append(lo)
+        hi0s.append(hi)
+        Cs.append(C)
+        ts.append(t)
+    rng = np.random.default_rng(SEED_SIZES)
+    sc = rng.integers(depth[0], depth[1] + 1, size=int(counts.sum())).astype(np.int32)
+    return WorkloadSet(name, net, lo0s, hi0s, Cs, ts, counts, sc)
+
+
+def geometric_counts(P: int, p: float, cap: int, seed: int = SEED_SIZES) -> np.ndarray:
+    """Subdomain count per property ~ Geometric(p) clipped to [1, cap]."""
+    rng = np.random.default_rng(seed + 100)
+    return np.clip(rng.geometric(p, size=P), 1, cap).astype(np.int64)
+
+
+def cifar_cnn_set(P: int = 64, seed: int = SEED_WEIGHTS, counts=None) -> WorkloadSet:
+    """The CNN of ``cifar_cnn`` with P properties (own image centre U[0,1]^3072
+    and label, eps 2/255 clipped to [0,1]); subdomains per property ~
+    Geometric(0.002) clipped to [1, 4096] unless ``counts`` is given; split
+    depth ~ U{1..12}."""
+    net = he_cnn((3, 32, 32), [(16, 4, 2, 1), (32, 4, 2, 1)], [100, 10], seed)
+    if counts is None:
+        counts = geometric_counts(P, 0.002, 4096)
+    return property_set(net, 3072, (0.0, 1.0), 2.0 / 255.0, (0.0, 1.0), counts, (1, 12),
+                        f"cnn3x32x32-c16-c32-100-10 x {len(counts)} properties")
+
+
+def mnist_mlp_set(counts, seed: int = SEED_WEIGHTS, k: int = 4) -> WorkloadSet:
+    """The 784-256x6-10 MLP with len(counts) properties (centre U[0,1]^784,
+    eps 0.02 clipped to [0,1]), ``k`` splits per subdomain."""
+    net = he_mlp([784] + [256] * 6 + [10], seed)
+    return property_set(net, 784, (0.0, 1.0), 0.02, (0.0, 1.0), counts, (k, k),
+                        f"mlp784-256x6-10 x {len(counts)} properties")
+
+
 def random_boxes_and_constraints(B: int, n: int, k: int, seed: int, width=0.5,
                                  p_zero_coef=0.1, p_flat=0.05, slack=0.5, nnz=8):
     """Random boxes [B, n] and dense constraints G [B, k, n], h [B, k] with

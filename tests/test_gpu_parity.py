@@ -342,10 +342,10 @@ def test_invalid_arguments_are_rejected_before_launch():
     import ctypes as C
     st = N.lib().cv_bound_propagate(prop.net.handle, 2, 5, api._p(prop.C), api._p(prop.t),
                                     api._p(l), api._p(l), None, C.c_float(0.5), api._p(lo),
-                                    api._p(hi), None, prop.root.handle, None, 1, api._p(lb),
+                                    api._p(hi), None, prop.root.handle, None, None, 1, api._p(lb),
                                     None, None, None, C.c_size_t(0), api._stream())
     assert st == -4   # workspace too small
-    st = N.lib().cv_clip_domains(prop.root.handle, 2, 5, None, api._p(lo), api._p(hi), None, 7,
+    st = N.lib().cv_clip_domains(prop.root.handle, None, 2, 5, None, api._p(lo), api._p(hi), None, 7,
                                  api._stream())
     assert st == -1
 

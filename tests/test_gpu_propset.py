@@ -1,0 +1,178 @@
+"""Batching of several properties (a RootSet and a per-subdomain property
+index): each subdomain's results must equal the oracle run of its own
+property, whether the subdomains are grouped by property or interleaved,
+and equal what the same calls give on each property alone."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import pipeline as opipe  # noqa: E402
+from paper_2512_11087_amd import api, pipeline as gpipe, workloads as wl  # noqa: E402
+from helpers import OracleProp, assert_close  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def T(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+def _setup(ws, order_seed=None, k=4):
+    """GPU property set, oracle per property, split lists per property over
+    its own root-unstable neurons; subdomains grouped by property, or
+    permuted (order_seed)."""
+    ps = gpipe.PropertySet(list(ws.net.layers), ws.lo0s, ws.hi0s, ws.Cs, ws.ts)
+    ops = [OracleProp(ws.member(p)) for p in range(ws.P)]
+    sps = [wl.draw_splits(int(ws.counts[p]), np.minimum(ws.member(p).split_counts, k),
+                          ops[p].unstable(), seed=30 + p, kmax=k) for p in range(ws.P)]
+    neuron = np.concatenate([s.neuron for s in sps])
+    sign = np.concatenate([s.sign for s in sps])
+    count = np.concatenate([s.count for s in sps])
+    pid = ws.pid()
+    lo = np.concatenate([np.broadcast_to(ws.lo0s[p], (int(ws.counts[p]), ws.net.n_in))
+                         for p in range(ws.P)])
+    hi = np.concatenate([np.broadcast_to(ws.hi0s[p], (int(ws.counts[p]), ws.net.n_in))
+                         for p in range(ws.P)])
+    perm = np.arange(ws.B)
+    if order_seed is not None:
+        perm = np.random.default_rng(order_seed).permutation(ws.B)
+    batch = gpipe.Batch(T(lo[perm]), T(hi[perm]),
+                        api.Constraints.splits(neuron[perm], sign[perm], count[perm]),
+                        pid=T(pid[perm], torch.int32))
+    return ps, ops, sps, perm, batch
+
+
+def _rows_of(ws, perm, p):
+    """Positions in the (permuted) batch of property p's subdomains, in the
+    property's own order."""
+    start = int(ws.counts[:p].sum())
+    inv = np.argsort(perm)
+    return inv[start:start + int(ws.counts[p])]
+
+
+@pytest.mark.parametrize("order_seed", [None, 7], ids=["grouped", "interleaved"])
+def test_property_set_pass_matches_oracle_per_property(order_seed):
+    # 4 properties of uneven size; the first 64-row tile of the plane GEMM
+    # holds 3 of them
+    ws = wl.mnist_mlp_set([37, 1, 70, 12])
+    ps, ops, sps, perm, batch = _setup(ws, order_seed)
+    gw = H(ps.babsr_weight())
+    cfg_g = gpipe.PassConfig(clip="sequential", order=True, complete_intermediate=True, topk=10)
+    out = gpipe.plain_pass(ps, batch, cfg_g)
+    best, _ = gpipe.alpha_opt(ps, batch, out["l"], out["u"], out["infeasible"], steps=3, lr=0.1)
+    sync()
+    ginf = H(out["infeasible"]).astype(bool)
+    for p in range(ws.P):
+        op, w = ops[p], ws.member(p)
+        ow = opipe.babsr_weights(op.layers, w.C, w.t, op.root)
+        assert_close(gw[p], ow, 1e-5, f"babsr weights of property {p}")
+        cfg_o = opipe.Config(relaxed="sequential", order=True, complete_intermediate=True, topk=10,
+                             babsr_weight=ow)
+        ref = op.run(sps[p], cfg=cfg_o)
+        rows = _rows_of(ws, perm, p)
+        gi = ginf[rows]
+        assert not (gi & ~ref["infeasible"]).any(), f"property {p}: GPU pruned a subdomain"
+        fe = ~ref["infeasible"] & ~gi
+        assert_close(H(batch.lo)[rows][fe], ref["lo"][fe], 1e-5, f"lo of property {p}")
+        assert_close(H(batch.hi)[rows][fe], ref["hi"][fe], 1e-5, f"hi of property {p}")
+        unst = op.unstable()
+        assert_close(H(out["l"])[rows][fe][:, unst], ref["l"][fe][:, unst], 1e-5, f"l of {p}")
+        assert_close(H(out["u"])[rows][fe][:, unst], ref["u"][fe][:, unst], 1e-5, f"u of {p}")
+        assert_close(H(out["lb"])[rows][fe], ref["lb"][fe], 1e-5, f"lb of property {p}")
+        # slope optimisation, on a few subdomains of the property
+        idx = np.nonzero(fe)[0][:6]
+        if idx.size == 0:
+            continue
+        l_list = opipe.split_layers(op.layers, ref["l"][idx])
+        u_list = opipe.split_layers(op.layers, ref["u"][idx])
+        obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][idx],
+                                      ref["hi"][idx], ref["G"][idx], ref["h"][idx],
+                                      ref["active"][idx], steps=3, lr=0.1)
+        assert_close(H(best)[rows][idx], obest, 1e-4, f"alpha-opt of property {p}")
+
+
+def test_property_set_equals_single_property_calls():
+    # the same kernels on a set and on each property alone: identical results
+    ws = wl.mnist_mlp_set([20, 45, 9])
+    ps, ops, sps, perm, batch = _setup(ws, order_seed=3)
+    out = gpipe.plain_pass(ps, batch, gpipe.PassConfig())
+    lbs, _ = api.alpha_step(ps.net, ps.root, ps.C, ps.t, out["l"], out["u"],
+                            torch.full((ws.B, ps.M, ps.net.n_hidden), 0.3, device="cuda"),
+                            batch.lo, batch.hi, out["infeasible"], batch.cons(), want_grad=True,
+                            ws=ps.ws, pid=batch.pid)
+    sync()
+    for p in range(ws.P):
+        rows = _rows_of(ws, perm, p)
+        single = gpipe.Property(list(ws.net.layers), ws.lo0s[p], ws.hi0s[p], ws.Cs[p], ws.ts[p])
+        b1 = gpipe.make_batch(single, sps[p].neuron, sps[p].sign, sps[p].count)
+        o1 = gpipe.plain_pass(single, b1, gpipe.PassConfig())
+        l1, _ = api.alpha_step(single.net, single.root, single.C, single.t, o1["l"], o1["u"],
+                               torch.full((len(rows), single.M, single.net.n_hidden), 0.3,
+                                          device="cuda"),
+                               b1.lo, b1.hi, o1["infeasible"], b1.cons(), want_grad=True,
+                               ws=single.ws)
+        sync()
+        assert np.array_equal(H(out["lb"])[rows], H(o1["lb"])), f"plain bound of property {p}"
+        assert np.array_equal(H(out["l"])[rows], H(o1["l"])), f"intermediate bounds of {p}"
+        assert np.array_equal(H(batch.lo)[rows], H(b1.lo)), f"clipped boxes of {p}"
+        assert np.array_equal(H(lbs)[rows], H(l1)), f"alpha-step bound of property {p}"
+    # branching reads each subdomain's row of the per-property weights
+    weight = ps.babsr_weight()
+    chosen, ccons, _, _ = api.branch_relu(ps.root, out["l"], out["u"], weight, batch.splits,
+                                          batch.lo, batch.hi, 8, pid=batch.pid)
+    sync()
+    for p in range(ws.P):
+        rows = _rows_of(ws, perm, p)
+        wp = weight[p].contiguous()
+        c1, _, _, _ = api.branch_relu(ps.roots[p], out["l"][rows].contiguous(),
+                                      out["u"][rows].contiguous(), wp,
+                                      api.Constraints.splits(sps[p].neuron, sps[p].sign,
+                                                             sps[p].count),
+                                      batch.lo[rows].contiguous(), batch.hi[rows].contiguous(), 8)
+        sync()
+        assert np.array_equal(H(chosen)[rows], H(c1)), f"branching of property {p}"
+
+
+def test_property_set_cnn_matches_oracle_per_property():
+    # conv layers, 3 properties of the CIFAR CNN (complete clipping of the
+    # 3072-dimensional final planes), interleaved
+    ws = wl.cifar_cnn_set(counts=[9, 3, 14])
+    ps, ops, sps, perm, batch = _setup(ws, order_seed=11, k=6)
+    out = gpipe.plain_pass(ps, batch, gpipe.PassConfig())
+    sync()
+    ginf = H(out["infeasible"]).astype(bool)
+    for p in range(ws.P):
+        op = ops[p]
+        ref = op.run(sps[p])
+        rows = _rows_of(ws, perm, p)
+        fe = ~ref["infeasible"] & ~ginf[rows]
+        assert not (ginf[rows] & ~ref["infeasible"]).any()
+        assert_close(H(out["lb"])[rows][fe], ref["lb"][fe], 1e-5, f"cnn lb of property {p}")
+
+
+def test_rootset_rejects_single_root_queries():
+    ws = wl.mnist_mlp_set([2, 2])
+    ps = gpipe.PropertySet(list(ws.net.layers), ws.lo0s, ws.hi0s, ws.Cs, ws.ts)
+    from paper_2512_11087_amd import _native as N
+    import ctypes as C
+    cnt = C.c_int()
+    assert N.lib().cv_root_count(ps.root.handle, C.byref(cnt)) == 0 and cnt.value == 2
+    assert N.lib().cv_root_unstable_count(ps.root.handle, C.byref(cnt)) == -1
+    lo, hi, pid = ps.boxes([2, 2])
+    l = torch.zeros(4, ps.net.n_hidden, device="cuda")
+    with pytest.raises(N.CvError) as e:
+        api.intermediate_bounds(ps.net, ps.root, lo, hi, l, l.clone())
+    assert e.value.status == -3
+    # a set of sets is refused
+    arr = (C.c_void_p * 1)(ps.root.handle.value)
+    out = C.c_void_p()
+    assert N.lib().cv_rootset_create(arr, 1, C.byref(out)) == -1

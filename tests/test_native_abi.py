@@ -65,12 +65,18 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.cv_net_create(d2, 2, C.byref(out)) == -2
     d2[0].kind = 7
     assert lib.cv_net_create(d2, 2, C.byref(out)) == -1
-    assert lib.cv_clip_domains(None, -1, 4, None, None, None, None, 0, None) == -2
-    assert lib.cv_clip_domains(None, 0, 4, None, None, None, None, 0, None) == 0   # B == 0
-    assert lib.cv_clip_domains(None, 3, 4, None, None, None, None, 0, None) == -1
-    assert lib.cv_concretize(None, 2, 2, 0, None, 0, None, None, None, None, 1, None, None,
+    assert lib.cv_clip_domains(None, None, -1, 4, None, None, None, None, 0, None) == -2
+    assert lib.cv_clip_domains(None, None, 0, 4, None, None, None, None, 0, None) == 0  # B == 0
+    assert lib.cv_clip_domains(None, None, 3, 4, None, None, None, None, 0, None) == -1
+    assert lib.cv_concretize(None, None, 2, 2, 0, None, 0, None, None, None, None, 1, None, None,
                              None, None, None) == -2
     assert lib.cv_root_create(None, None, None, C.c_float(0.5), None, C.byref(out)) == -1
     n = C.c_size_t()
-    assert lib.cv_bound_propagate_workspace(None, 1, 1, C.byref(n)) == -1
+    assert lib.cv_bound_propagate_workspace(None, 1, 1, 1, C.byref(n)) == -1
+    # property sets: no roots / a null member / P < 1
+    assert lib.cv_rootset_create(None, 2, C.byref(out)) == -1
+    two = (C.c_void_p * 2)(None, None)
+    assert lib.cv_rootset_create(two, 2, C.byref(out)) == -1
+    assert lib.cv_rootset_create(two, 0, C.byref(out)) == -1
+    assert lib.cv_root_count(None, C.byref(C.c_int())) == -1
     assert lib.cv_net_destroy(None) == 0 and lib.cv_root_destroy(None) == 0
