@@ -188,7 +188,9 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, CvProps props
 
 // The property table of `root` with each subdomain's property index.
 CvProps props_of(const cv_root_s* root, const int32_t* pid) {
-  return CvProps{root ? root->dtab : nullptr, pid, root ? root->P : 1};
+  const bool single = root && root->P == 1;
+  return CvProps{root ? root->dtab : nullptr, pid, root ? root->P : 1,
+                 single ? &root->htab : nullptr};
 }
 
 cv_status resolve_cons(const cv_root_s* root, const int32_t* pid, const cv_constraints* c,
@@ -247,8 +249,8 @@ cv_status root_sync_tab(cv_root_s* r) {
       return CV_E_NOMEM;
     }
   }
-  const RootDev d = root_dev(r);
-  if (hipMemcpy(r->dtab, &d, sizeof(RootDev), hipMemcpyHostToDevice) != hipSuccess)
+  r->htab = root_dev(r);
+  if (hipMemcpy(r->dtab, &r->htab, sizeof(RootDev), hipMemcpyHostToDevice) != hipSuccess)
     return hip_fail(hipGetLastError());
   r->Umax = r->U;
   return CV_OK;

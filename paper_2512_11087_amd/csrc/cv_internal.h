@@ -55,6 +55,7 @@ struct CvProps {
   const RootDev* tab;
   const int32_t* pid;
   int P;
+  const RootDev* host;  // host copy of the entry when the call has one property (P == 1), else null
 };
 
 __device__ __forceinline__ int prop_index(const CvProps& p, int b) {
@@ -75,6 +76,7 @@ struct cv_root_s {
   int P = 1;
   std::vector<cv_root_s*> members;
   RootDev* dtab = nullptr;                    // device [P]
+  RootDev htab{};                             // host copy of dtab[0] (single roots)
   int Umax = 0;                               // max U over the members
   int n0 = 0, N = 0, U = 0;
   float alpha0 = 0.5f;

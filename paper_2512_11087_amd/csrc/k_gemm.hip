@@ -23,6 +23,8 @@
 // MFMA operand layout (16x16x4, float64; measured on gfx950): lane L supplies
 // A[L%16][L/16] and B[L/16][L%16]; accumulator element v of lane L is
 // D[L/16 + 4v][L%16] (rows interleaved by 4, unlike the float32 variant).
+#include <type_traits>
+
 #include "cv_common.h"
 #include "cv_internal.h"
 
@@ -276,6 +278,9 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la
 // of post-activation j of the layer below; relax it, store the next Omega and
 // accumulate  sum psi*t (intercept), sum Omega'*b (that layer's bias term) and
 // sum |psi| * wrel (error weight).
+// MULTI: rows of several properties (the error weight of each row's
+// property is looked up); else one property's weight for every row.
+template <bool MULTI>
 struct EpiRelax {
   static constexpr int NSUM = 3;
   static constexpr int VGROUP = 4;
@@ -285,21 +290,36 @@ struct EpiRelax {
   const float* alpha;
   double alpha_def;
   const float* bprev;
-  CvProps props;  // error weight wrel of layer `layer` of the row's property
+  const double* wrel;  // !MULTI: error weight of layer `layer`
+  CvProps props;       // MULTI: per-property error weights
   int layer;
   double* Om;
   int ldo;
   float* trace;
-  struct Row {
+  struct RowS {
     const float* l;
     const float* u;
     size_t ri;
+  };
+  struct RowM : RowS {
     const double* wrel;
   };
+  typedef typename std::conditional<MULTI, RowM, RowS>::type Row;
   __device__ __forceinline__ Row row(int r) const {
     const int b = r / M;
-    return Row{lz + (size_t)b * Nh + off, uz + (size_t)b * Nh + off, (size_t)r * Nh + off,
-               prop_of(props, b).wrel[layer]};
+    const RowS rs{lz + (size_t)b * Nh + off, uz + (size_t)b * Nh + off, (size_t)r * Nh + off};
+    if constexpr (MULTI) {
+      RowM rm;
+      static_cast<RowS&>(rm) = rs;
+      rm.wrel = prop_of(props, b).wrel[layer];
+      return rm;
+    } else {
+      return rs;
+    }
+  }
+  __device__ __forceinline__ const double* wrel_of(const Row& w) const {
+    if constexpr (MULTI) return w.wrel;
+    else return wrel;
   }
   struct Pre {
     float l, u, al;
@@ -317,29 +337,42 @@ struct EpiRelax {
     if (trace) trace[ri] = trace32(psi);
     s[0] += psi * rl.t;
     s[1] += om * (double)bprev[j];
-    s[2] += fabs(psi) * w.wrel[j];
+    s[2] += fabs(psi) * wrel_of(w)[j];
   }
 };
 
 // Input layer: a = (Omega W1)[r, j] is the coefficient of x_j in the final
 // plane; accumulate min(a lo_j, a hi_j) (Lemma A.2) and |a| X0_j (error).
+template <bool MULTI>
 struct EpiFinal {
   static constexpr int NSUM = 2;
   static constexpr int VGROUP = 4;
   int M, n0;
   const float* lo;
   const float* hi;
-  CvProps props;  // X0 = max(|lo0|, |hi0|) of the row's property
+  const double* X0;  // !MULTI: max(|lo0|, |hi0|) of the property
+  CvProps props;     // MULTI: per property
   double* Ax;
   float* A_out;
-  struct Row {
+  struct RowS {
     const float* lo;
     const float* hi;
+  };
+  struct RowM : RowS {
     const double* X0;
   };
+  typedef typename std::conditional<MULTI, RowM, RowS>::type Row;
   __device__ __forceinline__ Row row(int r) const {
     const int b = r / M;
-    return Row{lo + (size_t)b * n0, hi + (size_t)b * n0, prop_of(props, b).X0};
+    const RowS rs{lo + (size_t)b * n0, hi + (size_t)b * n0};
+    if constexpr (MULTI) {
+      RowM rm;
+      static_cast<RowS&>(rm) = rs;
+      rm.X0 = prop_of(props, b).X0;
+      return rm;
+    } else {
+      return rs;
+    }
   }
   struct Pre {
     float xl, xh;
@@ -349,14 +382,16 @@ struct EpiFinal {
                                         double* s) const {
     const double xl = (double)p.xl, xh = (double)p.xh;
     s[0] += fmin(a * xl, a * xh);
-    s[1] += fabs(a) * w.X0[j];
+    if constexpr (MULTI) s[1] += fabs(a) * w.X0[j];
+    else s[1] += fabs(a) * X0[j];
     if (Ax) Ax[(size_t)r * n0 + j] = a;
     if (A_out) A_out[(size_t)r * n0 + j] = (float)a;
   }
 };
 
-// Re-concretized bound of cached plane column `col` over box b, for the
-// boxes of property p (rows of other properties are left alone).
+// Re-concretized bound of cached plane column `col` over box b; MULTI: for
+// the boxes of property p only (rows of other properties are left alone).
+template <bool MULTI>
 struct EpiPlanes {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 4;
@@ -370,15 +405,22 @@ struct EpiPlanes {
   float* u;
   CvProps props;
   int p;
-  struct Row {
+  struct RowS {};
+  struct RowM {
     bool mine;
   };
-  __device__ __forceinline__ Row row(int b) const { return Row{prop_index(props, b) == p}; }
+  typedef typename std::conditional<MULTI, RowM, RowS>::type Row;
+  __device__ __forceinline__ Row row(int b) const {
+    if constexpr (MULTI) return RowM{prop_index(props, b) == p};
+    else return RowS{};
+  }
   struct Pre {};
   __device__ __forceinline__ Pre load(const Row&, int, int) const { return Pre{}; }
   __device__ __forceinline__ void apply(const Row& w, const Pre&, int b, int col, double v,
                                         double*) const {
-    if (!w.mine) return;
+    if constexpr (MULTI) {
+      if (!w.mine) return;
+    }
     if (col < U) {
       const int j = uidx[col];
       const double x = v + cP[col] - eP[col];
@@ -754,7 +796,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_planes(int B, int n0, LoadBox
     const RootDev& rd = props.tab[p];
     const int N = 2 * rd.U;
     if (c0 >= N) continue;
-    EpiPlanes e{rd.U, Nh, rd.cP, rd.eP, rd.uidx, rd.l0, rd.u0, l, u, props, p};
+    EpiPlanes<true> e{rd.U, Nh, rd.cP, rd.eP, rd.uidx, rd.l0, rd.u0, l, u, props, p};
     gemm_tile<T>(m0, c0, B, 2 * n0, N, la, rd.P, N, e, nullptr, 1);
   }
 }
@@ -779,7 +821,14 @@ hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float*
                              int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, CvProps props, int layer,
                              double* Om_out, float* trace, double* part, hipStream_t s) {
-  EpiRelax e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props, layer, Om_out, N, trace};
+  if (props.host) {  // one property: its error weight for every row
+    EpiRelax<false> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props.host->wrel[layer], props,
+                      layer, Om_out, N, trace};
+    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+    return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+  }
+  EpiRelax<true> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, nullptr, props, layer, Om_out, N,
+                   trace};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
@@ -788,7 +837,12 @@ hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float*
                              const ConvDesc* conv, int M,
                              const float* lo, const float* hi, CvProps props, double* Ax,
                              float* A_out, double* part, hipStream_t s) {
-  EpiFinal e{M, N, lo, hi, props, Ax, A_out};
+  if (props.host) {
+    EpiFinal<false> e{M, N, lo, hi, props.host->X0, props, Ax, A_out};
+    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+    return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+  }
+  EpiFinal<true> e{M, N, lo, hi, nullptr, props, Ax, A_out};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
   return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
@@ -796,6 +850,12 @@ hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float*
 hipError_t launch_gemm_planes(int B, int n0, int Umax, const float* lo, const float* hi,
                               CvProps props, int Nh, float* l, float* u, hipStream_t s) {
   if (B <= 0 || Umax <= 0) return hipSuccess;
+  if (props.host) {  // one property: the plain tiled GEMM with its plane matrix
+    const RootDev& rd = *props.host;
+    EpiPlanes<false> e{rd.U, Nh, rd.cP, rd.eP, rd.uidx, rd.l0, rd.u0, l, u, props, 0};
+    return run_gemm<TilePlanes>(B, 2 * n0, 2 * rd.U, LoadBox{lo, hi, n0}, rd.P, 2 * rd.U, e,
+                                nullptr, s);
+  }
   dim3 grid((B + TilePlanes::BM - 1) / TilePlanes::BM, (2 * Umax + TilePlanes::BN - 1) / TilePlanes::BN);
   hipLaunchKernelGGL((k_gemm_planes<TilePlanes, 2>), grid, dim3(256), 0, s, B, n0,
                      LoadBox{lo, hi, n0}, props, Nh, l, u);
