@@ -208,6 +208,18 @@ __device__ __forceinline__ double buf_f64(cv_buf r, int byte_off) {
 // hoisted conversions and per-element offsets would stay live in registers
 // for the whole loop (and offsets hoisted that way no longer fold into the
 // immediate offset field of the loads).
+// Logical workgroup index for launches whose neighbouring workgroups share
+// data (rows of one subdomain, their constraint rows): the hardware hands
+// workgroup i to XCD i mod 8, each XCD with its own L2, so renumber the
+// workgroups that one XCD runs into a contiguous range of logical indices.
+// A bijection of [0, nblocks).
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblocks) {
+  constexpr unsigned NX = 8;
+  const unsigned per = nblocks / NX, rem = nblocks % NX;
+  const unsigned x = bid % NX, q = bid / NX;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
 __device__ __forceinline__ void cv_opaque(float& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void cv_opaque(int& v) { asm volatile("" : "+v"(v)); }
 

@@ -40,47 +40,53 @@ struct BlockTeam {
   static constexpr int SIZE = 256;
   static constexpr int PER_BLOCK = 1;
   int t;
-  double* red;          // LDS [12]
+  double* red;          // LDS [24]: two banks of 12, used alternately
   const float** mrow;   // LDS [CV_TEAM_KMAX]
   float* mscale;        // LDS [CV_TEAM_KMAX]
   double* mh;           // LDS [CV_TEAM_KMAX]
+  mutable int bank = 0;
   __device__ static int index_in_block() { return 0; }
-  __device__ double sum(double v) const {
-    v = wave_sum(v);
-    if ((t & 63) == 0) red[t >> 6] = v;
-    __syncthreads();
-    const double r = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
+  // One barrier per reduction: successive reductions write alternate banks,
+  // and a thread reaching reduction i+1's barrier implies every thread has
+  // read reduction i-1's bank (it wrote bank i first).
+  __device__ double* next_bank() const {
+    double* r = red + 12 * bank;
+    bank ^= 1;
     return r;
+  }
+  __device__ double sum(double v) const {
+    double* rb = next_bank();
+    v = wave_sum(v);
+    if ((t & 63) == 0) rb[t >> 6] = v;
+    __syncthreads();
+    return (rb[0] + rb[1]) + (rb[2] + rb[3]);
   }
   __device__ void sum3(double& a, double& b, double& c) const {
+    double* rb = next_bank();
     wave_sum3(a, b, c);
     if ((t & 63) == 0) {
-      red[t >> 6] = a;
-      red[4 + (t >> 6)] = b;
-      red[8 + (t >> 6)] = c;
+      rb[t >> 6] = a;
+      rb[4 + (t >> 6)] = b;
+      rb[8 + (t >> 6)] = c;
     }
     __syncthreads();
-    a = (red[0] + red[1]) + (red[2] + red[3]);
-    b = (red[4] + red[5]) + (red[6] + red[7]);
-    c = (red[8] + red[9]) + (red[10] + red[11]);
-    __syncthreads();
+    a = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+    b = (rb[4] + rb[5]) + (rb[6] + rb[7]);
+    c = (rb[8] + rb[9]) + (rb[10] + rb[11]);
   }
   __device__ double max(double v) const {
+    double* rb = next_bank();
     v = wave_max(v);
-    if ((t & 63) == 0) red[t >> 6] = v;
+    if ((t & 63) == 0) rb[t >> 6] = v;
     __syncthreads();
-    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    __syncthreads();
-    return r;
+    return fmax(fmax(rb[0], rb[1]), fmax(rb[2], rb[3]));
   }
   __device__ double min(double v) const {
+    double* rb = next_bank();
     v = wave_min(v);
-    if ((t & 63) == 0) red[t >> 6] = v;
+    if ((t & 63) == 0) rb[t >> 6] = v;
     __syncthreads();
-    const double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-    __syncthreads();
-    return r;
+    return fmin(fmin(rb[0], rb[1]), fmin(rb[2], rb[3]));
   }
   __device__ void publish(const float* my_row, float my_scale, double my_h, int cnt) const {
     if (t < cnt) {

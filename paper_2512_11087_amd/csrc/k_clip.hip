@@ -27,7 +27,7 @@ namespace {
 template <class Team, int EPL>
 __global__ __launch_bounds__(256) void k_clip(int B, int n, CvCons cons, float* lo, float* hi,
                                               uint8_t* infeasible, int mode) {
-  __shared__ double red[12];
+  __shared__ double red[24];
   __shared__ const float* mrow[CV_TEAM_KMAX];
   __shared__ float mscale[CV_TEAM_KMAX];
   __shared__ double mh[CV_TEAM_KMAX];

@@ -296,7 +296,7 @@ struct CaShared {
   double beta[Team::PER_BLOCK * CA_KMAX];
   double q[Team::PER_BLOCK * Team::SIZE * EPL];
   float w[Team::PER_BLOCK * Team::SIZE * EPL];
-  double red[12];
+  double red[24];
   const float* mrow[CA_KMAX];
   float mscale[CA_KMAX];
   double mh[CA_KMAX];
@@ -332,7 +332,9 @@ __global__ __launch_bounds__(256, 3) void k_ca_rows(int R, int M, int n, CvCons 
   __shared__ CaShared<Team, EPL> sh;
   const Team tm = team_of(sh);
   constexpr int T = Team::SIZE;
-  const int r = blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
+  // the M rows of a subdomain share its box and constraint rows: keep
+  // neighbouring rows on one XCD
+  const int r = xcd_block(blockIdx.x, gridDim.x) * Team::PER_BLOCK + Team::index_in_block();
   if (r >= R) return;
   const int b = r / M;
   double* arow = Ax + (size_t)r * n;
@@ -425,7 +427,8 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int Umax, int n, C
   __shared__ CaShared<Team, EPL> sh;
   const Team tm = team_of(sh);
   constexpr int T = Team::SIZE;
-  const long long id = (long long)blockIdx.x * Team::PER_BLOCK + Team::index_in_block();
+  const long long id =
+      (long long)xcd_block(blockIdx.x, gridDim.x) * Team::PER_BLOCK + Team::index_in_block();
   if (id >= (long long)B * Umax * 2) return;
   const int side = (int)(id & 1);
   const long long bc = id >> 1;
