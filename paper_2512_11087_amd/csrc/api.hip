@@ -119,9 +119,13 @@ double layer_wbytes(const cv_net_s* net, int i) {
 }
 
 // Workspace of one backward pass (rows R = B*M, objective rows M).
+// Constraint slots of complete clipping (CV_TEAM_KMAX of the kernels).
+constexpr int CA_SLOTS = 64;
+
 struct Bwd {
   double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
   float* trace;
+  double2* kst;  // [B, CA_SLOTS] per-constraint box statistics for complete clipping
 };
 
 size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool keepAx, bool trace,
@@ -144,6 +148,7 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool ke
   x.e0 = cv.take<double>((size_t)P * M);
   x.cabs0 = cv.take<double>((size_t)P * M);
   x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
+  x.kst = cv.take<double2>((size_t)B * CA_SLOTS);
   if (w) *w = x;
   return cv.off + 256;
 }
@@ -731,7 +736,9 @@ cv_status cv_constraint_order(cv_root root, const int32_t* pid, int B, int n,
 
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes) {
   if (!root || !bytes || B < 0) return CV_E_INVALID;
-  *bytes = complete ? (size_t)B * root->Umax * 2 * sizeof(float) + (size_t)B * root->N + 512 : 0;
+  *bytes = complete ? (size_t)B * root->Umax * 2 * sizeof(float) + (size_t)B * root->N +
+                         (size_t)B * CA_SLOTS * sizeof(double2) + 1024
+                   : 0;
   return CV_OK;
 }
 
@@ -773,6 +780,11 @@ cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const fl
       const cv_net_s* net = root->net;
       const int nl = net->L - 1;
       PLAUNCH("select_topk", 0, 8.0 * B * Nh + 1.0 * B * Nh, launch_select_topk(B, Nh, nl, net->off, net->n + 1, l, u, weight, props, topk, sel, s));
+    }
+    if (sp.kmax <= CA_SLOTS) {  // statistics of each (subdomain, constraint), shared by its neurons
+      double2* kst = cv.take<double2>((size_t)B * CA_SLOTS);
+      PLAUNCH("cons_stats", 0, 8.0 * B * root->n0 + 4.0 * B * sp.kmax * root->n0, launch_cons_stats(B, root->n0, sp, lo, hi, kst, s));
+      sp.kstats = kst;
     }
     PLAUNCH("ca_neurons", 0, 8.0 * B * U * root->n0, launch_ca_neurons(B, U, root->n0, props, sp, passes, lo, hi, l, u, Nh, infeasible, sel, Ltmp, s));
     PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, props, Nh, Ltmp, l, u, infeasible, s));
@@ -940,6 +952,10 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
   st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u, alpha,
                     alpha_default, lo, hi, infeasible, w, lb, A_out, c_out, s);
   if (st) return st;
+  if (cons && cons->kmax > 0 && cc.kmax <= CA_SLOTS) {
+    PLAUNCH("cons_stats", 0, 8.0 * B * net->n[0] + 4.0 * B * cc.kmax * net->n[0], launch_cons_stats(B, net->n[0], cc, lo, hi, w.kst, s));
+    cc.kstats = w.kst;
+  }
   if (cons && cons->kmax > 0)
     PLAUNCH("ca_rows", 0, 8.0 * B * M * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
                           infeasible, lb, nullptr, 0, s));
@@ -983,6 +999,10 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   // complete clipping (or plain concretization) leaves the minimising corner
   // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane
   CvCons none{};
+  if (cons && cons->kmax > 0 && cc.kmax <= CA_SLOTS) {
+    PLAUNCH("cons_stats", 0, 8.0 * B * net->n[0] + 4.0 * B * cc.kmax * net->n[0], launch_cons_stats(B, net->n[0], cc, lo, hi, w.kst, s));
+    cc.kstats = w.kst;
+  }
   PLAUNCH("ca_rows", 0, 16.0 * R * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes < 1 ? 1 : passes,
                         w.Ax, w.rowc, w.rowerr, lo, hi, infeasible, lb, nullptr, 1, s));
   const double dlr = lr;

@@ -111,6 +111,10 @@ struct CvCons {  // device view of cv_constraints (resolved)
   CvProps props;  // split form: the planes of each subdomain's property (eqs. 9-10)
   int nplanes;    // rows of the plane table; split slots with other indices are ignored
   const int32_t* order;  // [B, kmax] position -> slot, or null (list order)
+  // [B, kmax] per position, or null: (min over the box of the constraint's
+  // g.x without h, sum_j |g_j| max(|lo_j|,|hi_j|)), shared by every objective
+  // row of the subdomain (launch_cons_stats)
+  const double2* kstats;
 };
 
 // Number of used slots of subdomain b, clamped to [0, kmax].
@@ -212,6 +216,8 @@ hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float
                             uint8_t* infeasible, hipStream_t s);
 
 // complete clipping (coordinate ascent over the 1-D duals)
+hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, const float* hi,
+                             double2* stats, hipStream_t s);
 hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
                           const double* rowc, const double* rowerr, const float* lo,
                           const float* hi, uint8_t* infeasible, float* lb, float* beta_out,

@@ -175,17 +175,31 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       // (products of float32 values are exact in float64, so
       // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly)
       double m = 0.0, em = 0.0, wsg = 0.0;
+      if (cons->kstats) {  // m and em of this (subdomain, constraint) computed once
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const double gg = (double)g[e];
-        const float xs = g[e] >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
-        m += gg * (double)xs;
-        em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
-        const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
-        const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
-        if (opp && wf > 0.0f) wsg += (double)wf;
+        for (int e = 0; e < EPL; ++e) {
+          const double gg = (double)g[e];
+          const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+          const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
+          if (opp && wf > 0.0f) wsg += (double)wf;
+        }
+        wsg = tm.sum(wsg);
+        const double2 st = cons->kstats[(size_t)b * cons->kmax + k];
+        m = st.x;
+        em = st.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const double gg = (double)g[e];
+          const float xs = g[e] >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
+          m += gg * (double)xs;
+          em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+          const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+          const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
+          if (opp && wf > 0.0f) wsg += (double)wf;
+        }
+        tm.sum3(m, em, wsg);
       }
-      tm.sum3(m, em, wsg);
       m += h;
       if (bold != 0.0) {
         c -= bold * h;
@@ -287,6 +301,62 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
     }
   }
   return d - err;
+}
+
+// Per (subdomain, constraint position): m = min over the box of g.x (h not
+// included) and em = sum_j |g_j| max(|lo_j|,|hi_j|), with the same team
+// shape and summation order as ca_core computes them (so both give the same
+// values); complete clipping of every objective row of the subdomain reads
+// them instead of recomputing them.
+template <class Team, int EPL>
+__global__ __launch_bounds__(256) void k_cons_stats(int B, int n, CvCons cons,
+                                                    const float* __restrict__ lo,
+                                                    const float* __restrict__ hi,
+                                                    double2* stats) {
+  __shared__ double red[24];
+  __shared__ const float* mrow[CV_TEAM_KMAX];
+  __shared__ float mscale[CV_TEAM_KMAX];
+  __shared__ double mh[CV_TEAM_KMAX];
+  const Team tm = make_team<Team>(red, mrow, mscale, mh);
+  constexpr int T = Team::SIZE;
+  const int b = xcd_block(blockIdx.x, gridDim.x) * Team::PER_BLOCK + Team::index_in_block();
+  if (b >= B) return;
+  float xl[EPL], xh[EPL];
+  const cv_buf blo = cv_buffer(lo + (size_t)b * n, 4u * n), bhi = cv_buffer(hi + (size_t)b * n, 4u * n);
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const int j = tm.t + T * e;
+    xl[e] = buf_f32(blo, 4 * j);
+    xh[e] = buf_f32(bhi, 4 * j);
+  }
+  const int cnt = cons_count(cons, b);
+  const float* my_row = nullptr;
+  float my_scale = 0.0f;
+  double my_h = 0.0;
+  if (tm.t < cnt) cons_row(cons, b, tm.t, n, my_row, my_scale, my_h);
+  tm.publish(my_row, my_scale, my_h, cnt);
+#pragma unroll 1
+  for (int k = 0; k < cnt; ++k) {
+    const float* row;
+    float scale;
+    double h;
+    tm.meta(my_row, my_scale, my_h, k, row, scale, h);
+    if (!row) continue;
+    const cv_buf brow = cv_buffer(row, 4u * n);
+    int vb = 4 * tm.t;
+    cv_opaque(vb);
+    double m = 0.0, em = 0.0, z = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const float g = scale * buf_f32(brow, vb + 4 * T * e);
+      const double gg = (double)g;
+      const float xs = g >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
+      m += gg * (double)xs;
+      em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+    }
+    tm.sum3(m, em, z);
+    if (tm.t == 0) stats[(size_t)b * cons.kmax + k] = make_double2(m, em);
+  }
 }
 
 // LDS of a workgroup: beta, the search slices and the team scratch, with
@@ -463,6 +533,15 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int Umax, int n, C
 }
 
 }  // namespace
+
+hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, const float* hi,
+                             double2* stats, hipStream_t s) {
+  if (B <= 0 || cons.kmax <= 0) return hipSuccess;
+  if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
+  CV_DISPATCH_TEAM(n, hipLaunchKernelGGL((k_cons_stats<TM, E>), dim3(team_blocks(B, TM::PER_BLOCK)),
+                                       dim3(256), 0, s, B, n, cons, lo, hi, stats));
+  return hipGetLastError();
+}
 
 hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
                           const double* rowc, const double* rowerr, const float* lo,
