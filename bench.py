@@ -119,6 +119,9 @@ def main():
                     help="replay the slope iterations as one captured HIP graph (their kernels "
                          "are then not timed one by one, so the roofline entry covers the "
                          "plain pass only)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in kernel variants instead of timing the variants of "
+                         "every layer at set-up (the choice never changes a result)")
     ap.add_argument("--kernels-json", default=None, help="write the per-kernel timing table here")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB and exit "
@@ -193,6 +196,11 @@ def main():
         name, split_counts = wset.name, wset.split_counts
         w = wset
     lo_init, hi_init = batch.lo.clone(), batch.hi.clone()
+    tuned = None
+    if not args.no_autotune:
+        tuned = prop.net.autotune(B, prop.M)
+        log("autotuned variants: " + ", ".join(f"{k}{l}={v}" for (k, l), (v, c) in
+                                                sorted(tuned.items()) if c > 1))
     torch.cuda.synchronize()
     log(f"set-up (root pass, {n_unst} unstable of {w.net.n_hidden}) "
         f"{time.perf_counter() - t0:.2f} s")
@@ -298,7 +306,8 @@ def main():
         "config": {"workload": f"{name}: {B} subdomains x {'<=' if split_counts.min() < ksplit else ''}{ksplit} splits, 9 margin rows, "
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
                    "global_batch": B, "alpha_steps": T, "io_dtype": "f32",
-                   "launch": "hip graph (slope iterations)" if args.graph else "eager"},
+                   "launch": "hip graph (slope iterations)" if args.graph else "eager",
+                   "kernel_variants": "autotuned" if tuned is not None else "built-in"},
         "plain": {"value": round(B / plain_s, 1), "unit": "subdomains/s",
                   "ms_per_pass": round(1e3 * plain_s, 3)},
         "alpha_vs_plain": {"throughput_ratio": round(value / (B / plain_s), 5),

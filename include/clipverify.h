@@ -92,6 +92,25 @@ cv_status cv_net_destroy(cv_net net);
 /* Host outputs: input dim, output dim, total hidden neurons, layer count. */
 cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_layers);
 
+/* Kernel variants of each layer, kind CV_TUNE_RELAX (backward step through
+ * W_layer, 2 <= layer <= n_layers-1), CV_TUNE_FINAL (layer 1) or
+ * CV_TUNE_ADJOINT (1 <= layer <= n_layers-1): the output tile of the GEMM
+ * (0: 32 x 128, 1: 64 x 128, 2: 128 x 128 rows x columns) or, for the
+ * adjoint's forward convolution, its channel block (0: built-in, 1/2/3:
+ * 4/8/16 channels); a transposed convolution has the one variant 0.  Every
+ * variant gives the same results (the same accumulation order per element).
+ * cv_net_autotune times each variant of every layer once on synthetic
+ * operands of B subdomains x M objective rows (allocating its own scratch,
+ * synchronising `stream`) and keeps the fastest; the choice then applies to
+ * every call with this net.  It changes the net: do not call it while the
+ * net is in use on another stream.  cv_net_tuning reads a layer's variant
+ * and variant count (host outputs, either may be NULL); cv_net_set_tuning
+ * sets it (CV_E_INVALID for a kind, layer or variant out of range). */
+enum { CV_TUNE_RELAX = 0, CV_TUNE_FINAL = 1, CV_TUNE_ADJOINT = 2 };
+cv_status cv_net_autotune(cv_net net, int B, int M, hipStream_t stream);
+cv_status cv_net_tuning(cv_net net, int kind, int layer, int* variant, int* count);
+cv_status cv_net_set_tuning(cv_net net, int kind, int layer, int variant);
+
 /* ---------------------------------------------------------- root state */
 
 typedef struct cv_root_s* cv_root;

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libclipverify.so")
 
 CV_LINEAR, CV_CONV2D = 0, 1
 CV_CLIP_PARALLEL, CV_CLIP_SEQUENTIAL = 0, 1
+CV_TUNE_RELAX, CV_TUNE_FINAL, CV_TUNE_ADJOINT = 0, 1, 2
 
 STATUS = {0: "CV_OK", -1: "CV_E_INVALID", -2: "CV_E_SHAPE", -3: "CV_E_UNSUPPORTED",
           -4: "CV_E_WORKSPACE", -5: "CV_E_HIP", -6: "CV_E_NOMEM"}
@@ -19,6 +20,7 @@ STATUS = {0: "CV_OK", -1: "CV_E_INVALID", -2: "CV_E_SHAPE", -3: "CV_E_UNSUPPORTE
 EXPORTS = [
     "cv_status_string", "cv_last_hip_error", "cv_version",
     "cv_net_create", "cv_net_destroy", "cv_net_info",
+    "cv_net_autotune", "cv_net_tuning", "cv_net_set_tuning",
     "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
     "cv_root_unstable_count", "cv_rootset_create", "cv_root_count",
     "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
@@ -72,6 +74,9 @@ def lib():
         "cv_net_create": (I, [P, I, P]),
         "cv_net_destroy": (I, [P]),
         "cv_net_info": (I, [P, P, P, P, P]),
+        "cv_net_autotune": (I, [P, I, I, P]),
+        "cv_net_tuning": (I, [P, I, I, P, P]),
+        "cv_net_set_tuning": (I, [P, I, I, I]),
         "cv_root_create": (I, [P, P, P, F, P, P]),
         "cv_root_destroy": (I, [P]),
         "cv_root_bounds": (I, [P, P, P, P]),

@@ -79,6 +79,28 @@ class Net:
         """From an object with ``.layers`` (see the class docstring)."""
         return cls(list(net.layers))
 
+    TUNE_KINDS = {"relax": N.CV_TUNE_RELAX, "final": N.CV_TUNE_FINAL,
+                  "adjoint": N.CV_TUNE_ADJOINT}
+
+    def autotune(self, B, M):
+        """Time every kernel variant of every layer on B x M synthetic rows and
+        keep the fastest (cv_net_autotune); results do not depend on it."""
+        N.call("cv_net_autotune", self.handle, int(B), int(M), _stream())
+        return self.tuning()
+
+    def tuning(self):
+        """{(kind, layer): (variant, count)} for every tunable layer."""
+        out = {}
+        v, c = C.c_int(), C.c_int()
+        for name, kind in self.TUNE_KINDS.items():
+            for layer in range(1, self.n_layers + 1):
+                if N.lib().cv_net_tuning(self.handle, kind, layer, C.byref(v), C.byref(c)) == 0:
+                    out[(name, layer)] = (v.value, c.value)
+        return out
+
+    def set_tuning(self, kind, layer, variant):
+        N.call("cv_net_set_tuning", self.handle, self.TUNE_KINDS[kind], int(layer), int(variant))
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and N._lib is not None:

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <functional>
+
 #include "clipverify.h"
 #include "cv_common.h"
 #include "cv_internal.h"
@@ -179,13 +181,13 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, CvProps props
     const int K = net->n[i], N = net->n[i - 1];
     const ConvDesc* cd = conv_of(net, i);
     PLAUNCH(cd ? "conv_relax" : "gemm_relax", layer_flops(net, i, R), 8.0 * R * (K + N) + layer_wbytes(net, i), launch_gemm_relax(R, K, N, cur, net->W[i - 1], cd, M, Nh, net->off[i - 2], l, u, alpha,
-                             alpha_def, net->b[i - 2], props, i - 2, nxt, w.trace, w.part, s));
+                             alpha_def, net->b[i - 2], props, i - 2, nxt, w.trace, w.part, net->tune[CV_TUNE_RELAX][i - 1], s));
     PLAUNCH("rowacc", 0, 8.0 * R * (3 * gemm_ntiles(N) + 6), launch_rowacc(R, gemm_ntiles(N), w.part, w.rowc, w.rowerr, w.rowcabs, s));
     std::swap(cur, nxt);
   }
   const int n0 = net->n[0];
   PLAUNCH(conv_of(net, 1) ? "conv_final" : "gemm_final", layer_flops(net, 1, R), 8.0 * R * net->n[1] + (w.Ax ? 8.0 * R * n0 : 0.0) + layer_wbytes(net, 1), launch_gemm_final(R, net->n[1], n0, cur, net->W[0], conv_of(net, 1), M, lo, hi, props, w.Ax, A_out,
-                           w.part, s));
+                           w.part, net->tune[CV_TUNE_FINAL][0], s));
   PLAUNCH("finalize", 0, 8.0 * R * (2 * gemm_ntiles(n0) + 3), launch_finalize(R, M, gemm_ntiles(n0), w.part, w.rowc, w.rowerr, w.rowcabs,
                          root->gamma_big, infeasible, lb, c_out, s));
   return CV_OK;
@@ -319,6 +321,7 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
     net->W[i] = net->Wt[i] = net->b[i] = nullptr;
     net->is_conv[i] = false;
     net->conv[i] = ConvDesc{};
+    for (int k = 0; k < 3; ++k) net->tune[k][i] = 0;
     std::vector<float> W, Wt((size_t)no * ni), bb;
     if (d.kind == CV_LINEAR) {
       W.assign(d.W, d.W + (size_t)no * ni);
@@ -415,6 +418,144 @@ cv_status cv_net_destroy(cv_net net) {
     }
   }
   delete net;
+  return CV_OK;
+}
+
+// Variants a layer offers: GEMM tiles 32/64/128 x 128; the forward
+// convolution of the adjoint a channel block (built-in, 4, 8, 16); the
+// transposed convolutions one (their row sums depend on the block).
+static int tune_variants(const cv_net_s* net, int kind, int layer) {
+  if (net->is_conv[layer - 1]) return kind == CV_TUNE_ADJOINT ? 4 : 1;
+  return 3;
+}
+
+static bool tune_layer_valid(const cv_net_s* net, int kind, int layer) {
+  if (kind == CV_TUNE_RELAX) return layer >= 2 && layer <= net->L - 1;
+  if (kind == CV_TUNE_FINAL) return layer == 1;
+  if (kind == CV_TUNE_ADJOINT) return layer >= 1 && layer <= net->L - 1;
+  return false;
+}
+
+cv_status cv_net_tuning(cv_net net, int kind, int layer, int* variant, int* count) {
+  if (!net || !tune_layer_valid(net, kind, layer)) return CV_E_INVALID;
+  if (variant) *variant = net->tune[kind][layer - 1];
+  if (count) *count = tune_variants(net, kind, layer);
+  return CV_OK;
+}
+
+cv_status cv_net_set_tuning(cv_net net, int kind, int layer, int variant) {
+  if (!net || !tune_layer_valid(net, kind, layer)) return CV_E_INVALID;
+  if (variant < 0 || variant >= tune_variants(net, kind, layer)) return CV_E_INVALID;
+  net->tune[kind][layer - 1] = (int8_t)variant;
+  return CV_OK;
+}
+
+cv_status cv_net_autotune(cv_net net, int B, int M, hipStream_t s) {
+  if (!net || B <= 0 || M <= 0) return CV_E_INVALID;
+  const long long R = (long long)B * M;
+  const int L = net->L, Nh = net->n_hidden, n0 = net->n[0];
+  int nmax = n0;
+  for (int i = 1; i <= L; ++i) nmax = std::max(nmax, net->n[i]);
+  int ntmax = 1;
+  for (int i = 0; i <= L; ++i) ntmax = std::max(ntmax, gemm_ntiles(net->n[i]));
+  double *A0 = nullptr, *A1 = nullptr, *part = nullptr, *wr = nullptr, *X0 = nullptr;
+  float *l = nullptr, *u = nullptr, *trace = nullptr, *lo = nullptr, *hi = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    double* ds[] = {A0, A1, part, wr, X0};
+    for (double* p : ds)
+      if (p) (void)hipFree(p);
+    float* fs[] = {l, u, trace, lo, hi};
+    for (float* p : fs)
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (dev_alloc(&A0, (size_t)R * nmax) || dev_alloc(&A1, (size_t)R * nmax) ||
+      dev_alloc(&part, (size_t)R * ntmax * 3) || dev_alloc(&wr, nmax) || dev_alloc(&X0, n0) ||
+      dev_alloc(&l, (size_t)B * Nh) || dev_alloc(&u, (size_t)B * Nh) ||
+      dev_alloc(&trace, (size_t)R * Nh) || dev_alloc(&lo, (size_t)B * n0) ||
+      dev_alloc(&hi, (size_t)B * n0)) {
+    cleanup();
+    return CV_E_NOMEM;
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return hip_fail(hipGetLastError());
+  }
+  // synthetic operands: coefficients in [-1, 1), bounds with unstable neurons
+  if (launch_fill_pattern(A0, (size_t)R * nmax, -1.0, 1.0, 1u, s) ||
+      launch_fill_pattern(wr, nmax, 0.5, 1.5, 2u, s) || launch_fill_pattern(X0, n0, 0.0, 1.0, 3u, s) ||
+      launch_fill_pattern(l, (size_t)B * Nh, -1.0, 0.2, 4u, s) ||
+      launch_fill_pattern(u, (size_t)B * Nh, 0.3, 1.5, 5u, s) ||
+      launch_fill_pattern(trace, (size_t)R * Nh, -1.0, 1.0, 6u, s) ||
+      launch_fill_pattern(lo, (size_t)B * n0, 0.0, 0.4, 7u, s) ||
+      launch_fill_pattern(hi, (size_t)B * n0, 0.5, 1.0, 8u, s)) {
+    cleanup();
+    return hip_fail(hipGetLastError());
+  }
+  RootDev tmp{};
+  tmp.X0 = X0;
+  for (int i = 0; i < CV_MAX_LAYERS; ++i) tmp.wrel[i] = wr;
+  const CvProps props{nullptr, nullptr, 1, &tmp};
+  // average time of 3 launches after a warm-up one
+  auto timed = [&](const std::function<hipError_t()>& launch, float* ms) -> hipError_t {
+    hipError_t e = launch();
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    for (int rep = 0; rep < 3; ++rep)
+      if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+    return hipEventElapsedTime(ms, e0, e1);
+  };
+  for (int kind = 0; kind < 3; ++kind) {
+    for (int layer = 1; layer <= L; ++layer) {
+      if (!tune_layer_valid(net, kind, layer)) continue;
+      const int nv = tune_variants(net, kind, layer);
+      if (nv < 2) continue;
+      const ConvDesc* cd = conv_of(net, layer);
+      float best = 0.0f;
+      int bestv = 0;
+      for (int v = 0; v < nv; ++v) {
+        std::function<hipError_t()> launch;
+        if (kind == CV_TUNE_RELAX) {
+          const int K = net->n[layer], N = net->n[layer - 1];
+          launch = [=]() {
+            return launch_gemm_relax((int)R, K, N, A0, net->W[layer - 1], cd, M, Nh,
+                                     net->off[layer - 2], l, u, nullptr, 0.5, net->b[layer - 2],
+                                     props, layer - 2, A1, nullptr, part, v, s);
+          };
+        } else if (kind == CV_TUNE_FINAL) {
+          launch = [=]() {
+            return launch_gemm_final((int)R, net->n[1], n0, A0, net->W[0], cd, M, lo, hi, props,
+                                     A1, nullptr, part, v, s);
+          };
+        } else {
+          const int K = net->n[layer - 1], N = net->n[layer];
+          double* out = layer < L - 1 ? A1 : nullptr;
+          launch = [=]() {
+            return launch_gemm_adjoint((int)R, K, N, A0, net->Wt[layer - 1], cd, net->b[layer - 1],
+                                       M, Nh, net->off[layer - 1], l, u, nullptr, 0.5, trace,
+                                       nullptr, nullptr, nullptr, nullptr, 0.0, 0.9, 0.999, 1e-8, 1,
+                                       out, v, s);
+          };
+        }
+        float ms = 0.0f;
+        const hipError_t e = timed(launch, &ms);
+        if (e != hipSuccess) {
+          cleanup();
+          return hip_fail(e);
+        }
+        if (v == 0 || ms < best) {
+          best = ms;
+          bestv = v;
+        }
+      }
+      net->tune[kind][layer - 1] = (int8_t)bestv;
+    }
+  }
+  cleanup();
   return CV_OK;
 }
 
@@ -1015,7 +1156,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
     PLAUNCH(cd ? "conv_adjoint" : "gemm_adjoint", layer_flops(net, k, R), 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N + layer_wbytes(net, k), launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], cd, net->b[k - 1], M, net->n_hidden,
                                net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
                                adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
-                               s));
+                               net->tune[CV_TUNE_ADJOINT][k - 1], s));
     cur = out;
   }
   return CV_OK;

@@ -24,6 +24,10 @@ struct cv_net_s {
   float* b[CV_MAX_LAYERS];    // device [n_i] (conv: the bias repeated over positions)
   ConvDesc conv[CV_MAX_LAYERS];  // conv layers: kernels of the direct convolutions
   bool is_conv[CV_MAX_LAYERS];
+  // kernel variants per layer (index i-1 for W_i) chosen by cv_net_autotune:
+  // tile of the backward (relax, final) and adjoint GEMMs, channel block of
+  // the forward convolution; 0 = the built-in choice
+  int8_t tune[3][CV_MAX_LAYERS];
   int off[CV_MAX_LAYERS];     // global offset of hidden layer i (index i-1)
   int n_hidden = 0;
   int nmax_hidden = 0;
@@ -187,13 +191,14 @@ hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float*
                              const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, CvProps props, int layer,
-                             double* Om_out, float* trace, double* part, hipStream_t s);
+                             double* Om_out, float* trace, double* part, int variant,
+                             hipStream_t s);
 hipError_t launch_rowacc(int R, int ntiles, const double* part, double* rowc, double* rowerr,
                          double* rowcabs, hipStream_t s);
 hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M,
                              const float* lo, const float* hi, CvProps props, double* Ax,
-                             float* A_out, double* part, hipStream_t s);
+                             float* A_out, double* part, int variant, hipStream_t s);
 int gemm_ntiles(int N);
 hipError_t launch_finalize(int R, int M, int ntiles, const double* part, const double* rowc,
                            double* rowerr, const double* rowcabs, double gamma_big,
@@ -205,7 +210,8 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
                                float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
-                               double eps, int step, double* Psibar_out, hipStream_t s);
+                               double eps, int step, double* Psibar_out, int variant,
+                               hipStream_t s);
 
 // re-concretization of the cached planes
 hipError_t launch_fill_stable(int B, int Nh, int nSmax, CvProps props, float* l, float* u,
@@ -239,6 +245,10 @@ hipError_t launch_branch_input(int B, int M, int n0, const float* lo, const floa
                                const float* A, int32_t* dim, float* lo2, float* hi2,
                                hipStream_t s);
 hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s);
+hipError_t launch_fill_pattern(double* p, size_t n, double lo, double hi, uint32_t seed,
+                               hipStream_t s);
+hipError_t launch_fill_pattern(float* p, size_t n, double lo, double hi, uint32_t seed,
+                               hipStream_t s);
 hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, const float* lbn,
                               float* l, float* u, uint8_t* infeasible, hipStream_t s);
 hipError_t launch_babsr_weight(int M, int Nh, const float* trace, float* weight, hipStream_t s);

@@ -755,11 +755,16 @@ hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
   return hipGetLastError();
 }
 
+// variant: 0 the block size of conv_block, 1/2/3 blocks of 4/8/16 channels
+// (the forward convolution has no row sums, so the choice does not change
+// any result).
 template <class Epi>
 hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
-                     hipStream_t s) {
+                     hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
-  switch (conv_block(cd.co, (cd.ho * cd.wo + 63) / 64)) {
+  const int cb = variant == 1 ? 4 : variant == 2 ? 8 : variant == 3 ? 16
+                                                                     : conv_block(cd.co, (cd.ho * cd.wo + 63) / 64);
+  switch (cb) {
     case 4: launch_convf_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s); break;
     case 8: launch_convf_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s); break;
     default: launch_convf_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s); break;
@@ -812,6 +817,19 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
   return hipGetLastError();
 }
 
+// Tile variants the autotuner chooses among for the backward and adjoint
+// GEMMs.  All have 128 columns (the row-sum partials' layout) and accumulate
+// every element over K in the same order, so they give identical results.
+template <class LoadA, class Epi>
+hipError_t run_gemm_v(int variant, int R, int K, int N, LoadA la, const float* Bm, int ldb,
+                      Epi epi, double* part, hipStream_t s) {
+  switch (variant) {
+    case 1: return run_gemm<Tile<64, 128>, 2>(R, K, N, la, Bm, ldb, epi, part, s);
+    case 2: return run_gemm<Tile<128, 128>, 1>(R, K, N, la, Bm, ldb, epi, part, s);
+    default: return run_gemm<TileDefault, 2>(R, K, N, la, Bm, ldb, epi, part, s);
+  }
+}
+
 }  // namespace
 
 int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
@@ -820,31 +838,32 @@ hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float*
                              const ConvDesc* conv, int M, int Nh,
                              int off, const float* lz, const float* uz, const float* alpha,
                              double alpha_def, const float* bprev, CvProps props, int layer,
-                             double* Om_out, float* trace, double* part, hipStream_t s) {
+                             double* Om_out, float* trace, double* part, int variant,
+                             hipStream_t s) {
   if (props.host) {  // one property: its error weight for every row
     EpiRelax<false> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props.host->wrel[layer], props,
                       layer, Om_out, N, trace};
     if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
-    return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+    return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
   }
   EpiRelax<true> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, nullptr, props, layer, Om_out, N,
                    trace};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
-  return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+  return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
 hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float* W,
                              const ConvDesc* conv, int M,
                              const float* lo, const float* hi, CvProps props, double* Ax,
-                             float* A_out, double* part, hipStream_t s) {
+                             float* A_out, double* part, int variant, hipStream_t s) {
   if (props.host) {
     EpiFinal<false> e{M, N, lo, hi, props.host->X0, props, Ax, A_out};
     if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
-    return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+    return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
   }
   EpiFinal<true> e{M, N, lo, hi, nullptr, props, Ax, A_out};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
-  return run_gemm(R, K, N, LoadF64{Om, K}, W, N, e, part, s);
+  return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
 hipError_t launch_gemm_planes(int B, int n0, int Umax, const float* lo, const float* hi,
@@ -868,10 +887,11 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
                                float* alpha, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
-                               double eps, int step, double* Psibar_out, hipStream_t s) {
+                               double eps, int step, double* Psibar_out, int variant,
+                               hipStream_t s) {
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
   EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N};
-  if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s);
-  return run_gemm(R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
+  if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s, variant);
+  return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

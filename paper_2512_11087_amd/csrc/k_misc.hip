@@ -346,6 +346,21 @@ __global__ void k_merge_layer(int B, int n, int Nh, int off, const float* __rest
   if (nl > nu && infeasible) infeasible[b] = 1;  // both bounds valid: the box is empty
 }
 
+// Deterministic filler in [lo, hi) (a 32-bit integer hash of the index):
+// synthetic operands for timing kernel variants.
+template <class T>
+__global__ void k_fill_pattern(T* p, size_t n, double lo, double hi, uint32_t seed) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  p[i] = (T)(lo + (hi - lo) * (double)x * 2.3283064365386963e-10);
+}
+
 }  // namespace
 
 hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float* t,
@@ -465,6 +480,22 @@ hipError_t launch_select_topk(int B, int Nh, int nlayers, const int* off, const 
   }
   hipLaunchKernelGGL(k_select_topk, dim3(B, nlayers), dim3(256), 0, s, Nh, lt, l, u, weight, props,
                      k, select);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(double* p, size_t n, double lo, double hi, uint32_t seed,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_pattern<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p,
+                     n, lo, hi, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(float* p, size_t n, double lo, double hi, uint32_t seed,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_pattern<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p,
+                     n, lo, hi, seed);
   return hipGetLastError();
 }
 

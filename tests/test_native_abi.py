@@ -79,4 +79,7 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.cv_rootset_create(two, 2, C.byref(out)) == -1
     assert lib.cv_rootset_create(two, 0, C.byref(out)) == -1
     assert lib.cv_root_count(None, C.byref(C.c_int())) == -1
+    assert lib.cv_net_autotune(None, 4, 4, None) == -1
+    assert lib.cv_net_tuning(None, 0, 2, None, None) == -1
+    assert lib.cv_net_set_tuning(None, 0, 2, 0) == -1
     assert lib.cv_net_destroy(None) == 0 and lib.cv_root_destroy(None) == 0
