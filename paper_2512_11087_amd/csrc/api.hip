@@ -421,12 +421,13 @@ cv_status cv_net_destroy(cv_net net) {
   return CV_OK;
 }
 
-// Variants a layer offers: GEMM tiles 32/64/128 x 128; the forward
+// Variants a layer offers: GEMM tiles 32/64/128 x 128 (the adjoint also
+// 32 x 256); the forward
 // convolution of the adjoint a channel block (built-in, 4, 8, 16); the
 // transposed convolutions one (their row sums depend on the block).
 static int tune_variants(const cv_net_s* net, int kind, int layer) {
   if (net->is_conv[layer - 1]) return kind == CV_TUNE_ADJOINT ? 4 : 1;
-  return 3;
+  return kind == CV_TUNE_ADJOINT ? 4 : 3;
 }
 
 static bool tune_layer_valid(const cv_net_s* net, int kind, int layer) {

@@ -818,14 +818,18 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
 }
 
 // Tile variants the autotuner chooses among for the backward and adjoint
-// GEMMs.  All have 128 columns (the row-sum partials' layout) and accumulate
-// every element over K in the same order, so they give identical results.
+// GEMMs.  The backward ones have 128 columns (the row-sum partials' layout);
+// the adjoint may also take 256.  All accumulate every element over K in the
+// same order, so they give identical results.
 template <class LoadA, class Epi>
 hipError_t run_gemm_v(int variant, int R, int K, int N, LoadA la, const float* Bm, int ldb,
                       Epi epi, double* part, hipStream_t s) {
   switch (variant) {
     case 1: return run_gemm<Tile<64, 128>, 2>(R, K, N, la, Bm, ldb, epi, part, s);
     case 2: return run_gemm<Tile<128, 128>, 1>(R, K, N, la, Bm, ldb, epi, part, s);
+    case 3:  // 256 columns: each row of A read once at N = 256 (no row sums to lay out)
+      if constexpr (Epi::NSUM == 0) return run_gemm<Tile<32, 256>, 2>(R, K, N, la, Bm, ldb, epi, part, s);
+      return hipErrorInvalidValue;
     default: return run_gemm<TileDefault, 2>(R, K, N, la, Bm, ldb, epi, part, s);
   }
 }
