@@ -96,10 +96,11 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
  * W_layer, 2 <= layer <= n_layers-1), CV_TUNE_FINAL (layer 1) or
  * CV_TUNE_ADJOINT (1 <= layer <= n_layers-1): the output tile of the GEMM
  * (0: 32 x 128, 1: 64 x 128, 2: 128 x 128 rows x columns; the adjoint also
- * 3: 32 x 256) or, for the
- * adjoint's forward convolution, its channel block (0: built-in, 1/2/3:
- * 4/8/16 channels); a transposed convolution has the one variant 0.  Every
- * variant gives the same results (the same accumulation order per element).
+ * 3: 32 x 256) or, for the adjoint's forward convolution, the vector kernel
+ * with a channel block (0: built-in, 1/2/3: 4/8/16 channels) or the
+ * matrix-core kernel (4; layers with at least 16 output channels); a
+ * transposed convolution has the one variant 0.  Every variant gives the
+ * same results (the same accumulation order per element).
  * cv_net_autotune times each variant of every layer once on synthetic
  * operands of B subdomains x M objective rows (allocating its own scratch,
  * synchronising `stream`) and keeps the fastest; the choice then applies to

@@ -14,6 +14,14 @@ struct ConvDesc {
   int ptp, pfp;      // ci and co rounded up to a multiple of 16 (weight padding)
   double* Wb;        // device [co][k][k][ptp]: transposed convolution (blocks of ci)
   double* Wf;        // device [ci][k][k][pfp]: forward convolution (blocks of co)
+  // Matrix-core forward convolution (k_convf_mfma): the kernel as MFMA
+  // A-fragments Af [tap][channel group of 4][row tile of 16 co][64 lanes],
+  // and the zero-padded staging of the input row
+  int ci16;          // ci rounded up to a multiple of 16 (staged channels)
+  bool mf;           // the layer has the matrix-core variant
+  double* Af;
+  int fPT, fHP, fWP, fPL; // zero pad before, padded height and width, channel
+                          // stride (HP*WP rounded up to 16 mod 32 doubles)
 };
 
 struct cv_net_s {

@@ -705,6 +705,109 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
   conv_row_sums<NS>(sums, sred, part, r, ntiles);
 }
 
+// Matrix-core forward convolution of one row per workgroup, as an implicit
+// GEMM  D[co, pos] = sum_(tap, ci) W[co, ci, tap] X[ci, pos + tap]  (the
+// adjoint's convolution; an autotuner variant beside the vector kernel).
+// The row X is staged once in LDS with a zero border wide enough that every
+// tap reads inside it, so no load is masked (channels padded to 16, the
+// channel stride padded to 16 mod 32 doubles so that a fragment's four lane
+// groups read disjoint LDS banks); the kernel comes as pre-laid-out
+// A-fragments (coalesced 512-byte loads, four issued together, each shared
+// by NQ column tiles).  A wave owns a 16-row tile of output channels and NQ
+// 16-column tiles of positions: lane L feeds B[L/16][L%16] = X[channel group
+// + L/16, position L%16 of the tile] and receives D[L/16 + 4v][L%16].  The
+// contraction accumulates every output in the same order as the vector
+// kernel (tap-major, then input channel), so the two give identical results.
+template <class Epi, int NQ>
+__global__ __launch_bounds__(256, 4) void k_convf_mfma(int R, ConvDesc cd, const double* __restrict__ in,
+                                                       Epi epi) {
+  extern __shared__ double xs[];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lk = lane >> 4, lc = lane & 15;
+  const int H = cd.hi, W = cd.wi, PT = cd.fPT, HP = cd.fHP, WP = cd.fWP, plane = cd.fPL;
+  {
+    const double* row = in + (size_t)r * cd.ci * H * W;
+    const int nst = cd.ci16 * plane;
+    for (int i = threadIdx.x; i < nst; i += 256) {
+      const int c = i / plane, o = i % plane, y = o / WP, x = o % WP;
+      const int yy = y - PT, xx = x - PT;
+      double v = 0.0;
+      if (c < cd.ci && y < HP && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        v = row[((size_t)c * H + yy) * W + xx];
+      xs[i] = v;
+    }
+  }
+  __syncthreads();
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+  const int MT = (cd.co + 15) / 16;
+  const int CG = cd.ci16 / 4;  // channel groups of 4, a multiple of 4
+  const int npos = cd.ho * cd.wo;
+  const int NG = ((npos + 15) / 16 + NQ - 1) / NQ;
+  // work units: (row tile, NQ column tiles); column tiles past the last
+  // position compute clamped copies that are not stored
+  for (int u = wave; u < MT * NG; u += 4) {
+    const int mt = u / NG, nt0 = (u % NG) * NQ;
+    int pb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int pos = (nt0 + q) * 16 + lc;
+      pos = pos < npos ? pos : npos - 1;
+      pb[q] = lk * plane + (pos / cd.wo * cd.s) * WP + (pos % cd.wo) * cd.s;
+    }
+    d4_t acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+    const double* Ab = cd.Af + (size_t)mt * 64 + lane;
+    const size_t astep = (size_t)MT * 64;
+    for (int t = 0; t < cd.k * cd.k; ++t) {
+      const int toff = (t / cd.k) * WP + t % cd.k;
+      const double* At_ = Ab + (size_t)t * CG * astep;
+      for (int g0 = 0; g0 < CG; g0 += 4) {
+        double af[4], bf[4][NQ];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) af[j] = At_[(size_t)(g0 + j) * astep];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) bf[j][q] = xs[pb[q] + (g0 + j) * 4 * plane + toff];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bf[j][q], acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int pos = (nt0 + q) * 16 + lc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ch = mt * 16 + lk + 4 * v;
+        if (ch < cd.co && pos < npos) {
+          const int c = ch * npos + pos;
+          const auto pre = epi.load(w, r, c);
+          epi.apply(w, pre, r, c, acc[q][v], sums);
+        }
+      }
+    }
+  }
+}
+
+template <class Epi>
+void launch_convf_mfma(int R, const ConvDesc& cd, const double* in, Epi epi, hipStream_t s) {
+  static_assert(Epi::NSUM == 0, "forward convolution: no row sums");
+  const size_t lds = (size_t)cd.ci16 * cd.fPL * 8;
+  const int MT = (cd.co + 15) / 16, NT = (cd.ho * cd.wo + 15) / 16;
+  // four column tiles per unit unless that leaves a wave without work
+  if (MT * ((NT + 3) / 4) >= 4)
+    hipLaunchKernelGGL((k_convf_mfma<Epi, 4>), dim3(R), dim3(256), lds, s, R, cd, in, epi);
+  else
+    hipLaunchKernelGGL((k_convf_mfma<Epi, 2>), dim3(R), dim3(256), lds, s, R, cd, in, epi);
+}
+
 // Channel block of a convolution: the largest of 16, 8, 4 that still gives
 // every wave of a row a task (fewer channels: the smallest block covering them).
 inline int conv_block(int ch, int tasks_per_block) {
@@ -755,13 +858,18 @@ hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
   return hipGetLastError();
 }
 
-// variant: 0 the block size of conv_block, 1/2/3 blocks of 4/8/16 channels
-// (the forward convolution has no row sums, so the choice does not change
-// any result).
+// variant: 0 the vector kernel with the block size of conv_block, 1/2/3
+// with blocks of 4/8/16 channels, 4 the matrix-core kernel (where the layer
+// has one).  The forward convolution has no row sums and every variant
+// accumulates each output in the same order, so the choice changes no result.
 template <class Epi>
 hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
+  if (variant == 4 && cd.mf) {
+    launch_convf_mfma(R, cd, in, epi, s);
+    return hipGetLastError();
+  }
   const int cb = variant == 1 ? 4 : variant == 2 ? 8 : variant == 3 ? 16
                                                                      : conv_block(cd.co, (cd.ho * cd.wo + 63) / 64);
   switch (cb) {
