@@ -176,3 +176,86 @@ def test_rootset_rejects_single_root_queries():
     arr = (C.c_void_p * 1)(ps.root.handle.value)
     out = C.c_void_p()
     assert N.lib().cv_rootset_create(arr, 1, C.byref(out)) == -1
+
+
+def test_full_size_cnn_set_bench_schedule_sampled():
+    # config 3's batching as bench.py times it: the CIFAR CNN with 64 properties
+    # (32414 subdomains, Geometric(0.002) counts, split depth 1..12), one plain
+    # pass and 20 slope iterations over the whole set; the oracle repeats the
+    # schedule on sampled subdomains of sampled properties (a subdomain's
+    # iterations do not depend on the others)
+    from helpers import subset_splits
+    ws = wl.cifar_cnn_set(64)
+    ps = gpipe.PropertySet(list(ws.net.layers), ws.lo0s, ws.hi0s, ws.Cs, ws.ts)
+    ksplit = int(ws.split_counts.max())
+    sps = []
+    for p, root in enumerate(ps.roots):
+        l0, u0 = (H(x) for x in root.bounds())
+        cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
+        sps.append(wl.draw_splits(int(ws.counts[p]), ws.member(p).split_counts, cand,
+                                  seed=wl.SEED_SPLITS + p, kmax=ksplit))
+    sp = wl.Splits(np.concatenate([x.neuron for x in sps]), np.concatenate([x.sign for x in sps]),
+                   np.concatenate([x.count for x in sps]))
+    lo, hi, pid = ps.boxes(ws.counts)
+    assert lo.shape[0] == ws.B == 32414
+    batch = gpipe.make_batch(ps, sp.neuron, sp.sign, sp.count, lo, hi, pid)
+    out = gpipe.plain_pass(ps, batch, gpipe.PassConfig())
+    best, _ = gpipe.alpha_opt(ps, batch, out["l"], out["u"], out["infeasible"], steps=20, lr=0.1)
+    sync()
+    rng = np.random.default_rng(13)
+    checked = 0
+    for p in sorted(rng.choice(ws.P, 3, replace=False)):
+        w = ws.member(p)
+        op = OracleProp(w)
+        n = int(ws.counts[p])
+        local = np.sort(rng.choice(n, min(3, n), replace=False))
+        rows = int(ws.counts[:p].sum()) + local
+        ref = op.run(subset_splits(sps[p], local))
+        assert np.array_equal(H(out["infeasible"])[rows].astype(bool), ref["infeasible"])
+        assert_close(H(out["lb"])[rows], ref["lb"], 1e-5, f"plain lb, property {p}")
+        fe = ~ref["infeasible"]
+        if not fe.any():
+            continue
+        l_list = opipe.split_layers(op.layers, ref["l"][fe])
+        u_list = opipe.split_layers(op.layers, ref["u"][fe])
+        obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe],
+                                      ref["hi"][fe], ref["G"][fe], ref["h"][fe], ref["active"][fe],
+                                      steps=20, lr=0.1)
+        assert_close(H(best)[rows][fe], obest, 1e-4, f"alpha-opt best bound, property {p}")
+        checked += int(fe.sum())
+    assert checked >= 3
+
+
+def _tiny_set(specs):
+    """Properties y_row >= thr of the tiny net over its root box, one per
+    (row, frac): thr = L + frac (m - L), L the root CROWN bound of the row and
+    m its minimum over 2e5 samples (frac < 1 true but not verified at the
+    root, frac > 1 false)."""
+    w = wl.tiny_mlp(8)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 1, bias="uniform")
+    x = np.random.default_rng(wl.SEED_SAMPLES).uniform(w.lo0, w.hi0, size=(200000, 5))
+    y = wl.forward(w.net, x)
+    Cs, ts = [], []
+    for row, frac in specs:
+        C = np.zeros((1, 5), np.float32)
+        C[0, row] = 1.0
+        p1 = gpipe.Property(list(w.net.layers), w.lo0, w.hi0, C, np.zeros(1, np.float32))
+        L = float(H(gpipe.plain_pass(p1, gpipe.Batch(*p1.boxes(1), None))["lb"])[0, 0])
+        thr = L + frac * (y[:, row].min() - L)
+        Cs.append(C)
+        ts.append(np.array([-thr], np.float32))
+    n = len(specs)
+    return gpipe.PropertySet(list(w.net.layers), [w.lo0] * n, [w.hi0] * n, Cs, ts)
+
+
+def test_activation_bab_over_a_property_set():
+    from paper_2512_11087_amd import bab
+    # two true properties (rows 0 and 2), bounded in one pool
+    ps = _tiny_set([(0, 0.3), (2, 0.3)])
+    res = bab.activation_bab(ps, batch=8192, max_iters=300)
+    assert res.verified and res.per_property == [True, True], res
+    assert res.iterations >= 1
+    # a false property among true ones is never reported verified
+    ps = _tiny_set([(0, 0.3), (0, 1.02), (2, 0.3)])
+    res = bab.activation_bab(ps, batch=512, max_iters=12)
+    assert not res.verified and res.per_property[1] is False, res
