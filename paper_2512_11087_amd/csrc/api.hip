@@ -160,17 +160,22 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool ke
 // over each box; the root-derived error weights are those of each subdomain's
 // property.  Leaves the intercept and the plane's error bound in w.rowc /
 // w.rowerr and, when w.Ax is set, the input plane in w.Ax.
+// eye = +-1: the objective is +-I with t = 0 (C and t are then not read).
 cv_status backward_run(const cv_net_s* net, const cv_root_s* root, CvProps props, int T, int B,
                        int M,
                        const float* C, const float* t, const float* l, const float* u,
                        const float* alpha, double alpha_def, const float* lo, const float* hi,
                        const uint8_t* infeasible, const Bwd& w, float* lb, float* A_out,
-                       float* c_out, hipStream_t s) {
+                       float* c_out, hipStream_t s, int eye = 0) {
   const int R = B * M;
   const int Nh = net->n_hidden;
   const int nP = net->n[T - 1];
-  PLAUNCH("top", 2.0 * props.P * M * net->n[T] * nP, 8.0 * props.P * M * nP, launch_top(props.P, M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], props, T - 1,
-                    w.psiT, w.c0, w.e0, w.cabs0, s));
+  if (eye)
+    PLAUNCH("top", 0, 8.0 * props.P * M * nP, launch_top_eye(props.P, M, nP, (double)eye, net->W[T - 1], net->b[T - 1], props, T - 1,
+                          w.psiT, w.c0, w.e0, w.cabs0, s));
+  else
+    PLAUNCH("top", 2.0 * props.P * M * net->n[T] * nP, 8.0 * props.P * M * nP, launch_top(props.P, M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], props, T - 1,
+                      w.psiT, w.c0, w.e0, w.cabs0, s));
   // ReLU of hidden layer T-1 (array index T-2)
   PLAUNCH("relax_top", 0, 8.0 * R * nP, launch_relax_top(R, M, nP, Nh, net->off[T - 2], w.psiT, w.c0, w.e0, w.cabs0, l, u, alpha,
                           alpha_def, net->b[T - 2], props, T - 2, w.Om0, w.trace, w.rowc,
@@ -744,11 +749,9 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
 
   // deeper hidden layers: CROWN with objectives +I (lower) and -I (upper)
   void* ws = nullptr;
-  float *Cdev = nullptr, *tdev = nullptr, *lbtmp = nullptr;
+  float* lbtmp = nullptr;
   auto cleanup = [&]() {
     if (ws) (void)hipFree(ws);
-    if (Cdev) (void)hipFree(Cdev);
-    if (tdev) (void)hipFree(tdev);
     if (lbtmp) (void)hipFree(lbtmp);
   };
   for (int i = 2; i <= L - 1; ++i) {
@@ -760,25 +763,17 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
     ws = nullptr;
     if (hipMalloc(&ws, bytes) != hipSuccess) { cleanup(); return fail(CV_E_NOMEM); }
     bwd_layout(net, i, ni, ni, 1, true, false, ws, &w);
-    if (Cdev) (void)hipFree(Cdev);
-    if (tdev) (void)hipFree(tdev);
     if (lbtmp) (void)hipFree(lbtmp);
-    Cdev = tdev = lbtmp = nullptr;
-    if (dev_alloc(&Cdev, (size_t)ni * ni) || dev_alloc(&tdev, ni) || dev_alloc(&lbtmp, ni)) {
+    lbtmp = nullptr;
+    if (dev_alloc(&lbtmp, ni)) {
       cleanup();
       return fail(CV_E_NOMEM);
     }
-    std::vector<float> I((size_t)ni * ni, 0.0f), z(ni, 0.0f);
     for (int side = 0; side < 2; ++side) {
-      for (int k = 0; k < ni; ++k) I[(size_t)k * ni + k] = side ? -1.0f : 1.0f;
-      if (hipMemcpy(Cdev, I.data(), I.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(tdev, z.data(), ni * 4, hipMemcpyHostToDevice) != hipSuccess) {
-        cleanup();
-        return fail(hip_fail(hipGetLastError()));
-      }
       if ((st = root_sync_tab(r))) { cleanup(); return fail(st); }
-      st = backward_run(net, r, props_of(r, nullptr), i, 1, ni, Cdev, tdev, r->l0, r->u0,
-                        nullptr, alpha0, r->lo0, r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s);
+      st = backward_run(net, r, props_of(r, nullptr), i, 1, ni, nullptr, nullptr, r->l0, r->u0,
+                        nullptr, alpha0, r->lo0, r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s,
+                        side ? -1 : 1);
       if (st) { cleanup(); return fail(st); }
       float* Adst = (side ? r->A_hi : r->A_lo) + (size_t)off * n0;
       double* cdst = (side ? r->c_hi : r->c_lo) + off;
@@ -1017,7 +1012,7 @@ cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes) {
     nmax = std::max(nmax, ni);
     best = std::max(best, bwd_layout(net, i, (long long)B * ni, ni, 1, false, false, nullptr, nullptr));
   }
-  *bytes = best + (size_t)nmax * nmax * 4 + (size_t)nmax * 4 + 2 * (size_t)B * nmax * 4 + 1024;
+  *bytes = best + 2 * (size_t)B * nmax * 4 + 1024;
   return CV_OK;
 }
 
@@ -1038,15 +1033,12 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
     Bwd w;
     const size_t used = bwd_layout(net, i, (long long)B * ni, ni, 1, false, false, ws, &w);
     Carve cv((char*)ws + used);
-    float* C = cv.take<float>((size_t)ni * ni);
-    float* t = cv.take<float>(ni);
     float* lbl = cv.take<float>((size_t)B * ni);
     float* lbn = cv.take<float>((size_t)B * ni);
-    for (int side = 0; side < 2; ++side) {
-      CV_HIP(launch_fill_eye(ni, side ? -1.0f : 1.0f, C, t, s));
-      cv_status st = backward_run(net, root, props_of(root, nullptr), i, B, ni, C, t, l, u,
+    for (int side = 0; side < 2; ++side) {  // objectives +I, then -I
+      cv_status st = backward_run(net, root, props_of(root, nullptr), i, B, ni, nullptr, nullptr, l, u,
                                   nullptr, root->alpha0, lo, hi, infeasible, w,
-                                  side ? lbn : lbl, nullptr, nullptr, s);
+                                  side ? lbn : lbl, nullptr, nullptr, s, side ? -1 : 1);
       if (st) return st;
     }
     PLAUNCH("merge_layer", 0, 16.0 * B * ni, launch_merge_layer(B, ni, Nh, net->off[i - 1], lbl, lbn, l, u, infeasible, s));

@@ -188,6 +188,9 @@ hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, u
 hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float* t,
                       const float* W, const float* b, CvProps props, int layer, double* psiT,
                       double* c0, double* e0, double* cabs0, hipStream_t s);
+hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const float* b,
+                          CvProps props, int layer, double* psiT, double* c0, double* e0,
+                          double* cabs0, hipStream_t s);
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
                             const float* lz, const float* uz, const float* alpha,
@@ -252,7 +255,6 @@ hipError_t launch_branch_relu(int B, int Nh, const float* l, const float* u, con
 hipError_t launch_branch_input(int B, int M, int n0, const float* lo, const float* hi,
                                const float* A, int32_t* dim, float* lo2, float* hi2,
                                hipStream_t s);
-hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s);
 hipError_t launch_fill_pattern(double* p, size_t n, double lo, double hi, uint32_t seed,
                                hipStream_t s);
 hipError_t launch_fill_pattern(float* p, size_t n, double lo, double hi, uint32_t seed,

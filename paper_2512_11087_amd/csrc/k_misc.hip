@@ -39,6 +39,26 @@ __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float*
   }
 }
 
+// The same for the objective C = eye * I (eye = +-1), t = 0 (intermediate
+// bounds of a layer): Psi_T is row m of W_T times eye, c0 = eye b_T[m], e0 =
+// vT[m] -- what k_top computes for that C, exactly, without its dense loop.
+__global__ void k_top_eye(int M, int nP, double eye, const float* __restrict__ W,
+                          const float* __restrict__ b, CvProps props, int layer, double* psiT,
+                          double* c0, double* e0, double* cabs0) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t tot = (size_t)props.P * M * nP;
+  if (i >= tot) return;
+  const int p = (int)(i / ((size_t)M * nP));
+  const int m = (int)((i / nP) % M), j = (int)(i % nP);
+  psiT[i] = eye * (double)W[(size_t)m * nP + j];
+  if (j == 0) {
+    const size_t row = (size_t)p * M + m;
+    c0[row] = eye * (double)b[m];
+    e0[row] = props.tab[p].vgemm[layer][m];
+    cabs0[row] = fabs((double)b[m]);
+  }
+}
+
 // First relaxation (ReLU of layer T-1) of every row r = (b, m): one wave
 // per row.  Writes Omega_{T-1} and initialises the row state; the top rows
 // are those of subdomain b's property.
@@ -322,13 +342,6 @@ __global__ __launch_bounds__(256) void k_select_topk(int Nh, LayerTable lt, cons
   }
 }
 
-// Objective +-I (n x n) for the intermediate bounds of one layer.
-__global__ void k_fill_eye(int n, float v, float* C, float* t) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < (size_t)n * n) C[i] = (i / n == i % n) ? v : 0.0f;
-  if (i < (size_t)n) t[i] = 0.0f;
-}
-
 // l[b, off + m] = max(l, lbl[b, m]) and u[b, off + m] = min(u, -lbn[b, m]):
 // the CROWN bounds of one layer over each box (objective +I: lower bound,
 // objective -I: minus the upper bound), intersected with the bounds at hand.
@@ -368,6 +381,16 @@ hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float*
                       double* c0, double* e0, double* cabs0, hipStream_t s) {
   hipLaunchKernelGGL(k_top, dim3(M, P), dim3(256), 0, s, M, nT, nP, C, t, W, b, props, layer,
                      psiT, c0, e0, cabs0);
+  return hipGetLastError();
+}
+
+hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const float* b,
+                          CvProps props, int layer, double* psiT, double* c0, double* e0,
+                          double* cabs0, hipStream_t s) {
+  const size_t tot = (size_t)P * M * nP;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_top_eye, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, nP, eye, W,
+                     b, props, layer, psiT, c0, e0, cabs0);
   return hipGetLastError();
 }
 
@@ -496,12 +519,6 @@ hipError_t launch_fill_pattern(float* p, size_t n, double lo, double hi, uint32_
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_pattern<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p,
                      n, lo, hi, seed);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_eye(int n, float v, float* C, float* t, hipStream_t s) {
-  const size_t tot = (size_t)n * n;
-  hipLaunchKernelGGL(k_fill_eye, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, v, C, t);
   return hipGetLastError();
 }
 
