@@ -100,19 +100,27 @@ def cpu_baseline(w, sp, sample, alpha_steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 3; 1 for cnn3x32x32-conv64-set256)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mlp784-256x6-10",
                     choices=["mlp784-256x6-10", "mlp784-1024x4-10", "cnn3x32x32",
-                             "cnn3x32x32-set64"],
+                             "cnn3x32x32-set64", "cnn3x32x32-conv64-set256"],
                     help="784-256x6-10 (16384 x 4 splits, the metric's workload), "
                          "784-1024x4-10 (8192 x 6 splits, slope optimisation at width 1024), "
                          "cnn3x32x32 (conv16-conv32-100-10 on 3x32x32 inputs, one property, "
-                         "4096 subdomains, split depth 1..12) or cnn3x32x32-set64 (the same "
+                         "4096 subdomains, split depth 1..12), cnn3x32x32-set64 (the same "
                          "CNN, 64 properties of Geometric(0.002) subdomains each, 32414 in all, "
-                         "bounded together)")
+                         "bounded together) or cnn3x32x32-conv64-set256 (four 64-channel 3x3 "
+                         "convolutions -> 512 -> 10, 256 properties of Zipf(1.2) subdomain "
+                         "counts, 32768 in all, 10 slope steps, bounded in chunks)")
     ap.add_argument("--batch", type=int, default=None)
-    ap.add_argument("--alpha-steps", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="bound the batch in chunks of this many subdomains (default: one call; "
+                         "1024 for cnn3x32x32-conv64-set256, whose per-row matrices are 65536 "
+                         "wide)")
+    ap.add_argument("--alpha-steps", type=int, default=None,
+                    help="slope iterations per step (default 20; 10 for cnn3x32x32-conv64-set256)")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
@@ -148,6 +156,16 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: 5 copies of {n} bytes")
         return
+    big = args.workload == "cnn3x32x32-conv64-set256"
+    if args.steps is None:
+        args.steps = 1 if big else 3
+    if args.alpha_steps is None:
+        args.alpha_steps = 10 if big else 20
+    chunk = args.chunk if args.chunk is not None else (1024 if big else None)
+    if chunk is not None and args.graph:
+        print("bench.py: --graph captures one batch; it does not combine with --chunk",
+              file=sys.stderr)
+        sys.exit(2)
     T = args.alpha_steps
     wset = None
     if args.workload == "mlp784-256x6-10":
@@ -159,8 +177,11 @@ def main():
     elif args.workload == "cnn3x32x32":
         B = args.batch or 4096
         w = wl.cifar_cnn(B)
-    else:
+    elif args.workload == "cnn3x32x32-set64":
         wset = wl.cifar_cnn_set(64)
+        B = wset.B
+    else:
+        wset = wl.cifar_conv64_set(256)
         B = wset.B
     t0 = time.perf_counter()
     if wset is None:
@@ -179,7 +200,14 @@ def main():
         ksplit = int(wset.split_counts.max())
         log(f"workload {wset.name}: B={B} over {wset.P} properties "
             f"(sizes {wset.counts.min()}..{wset.counts.max()}), k<={ksplit}, alpha steps={T}")
-        prop = gpipe.PropertySet(list(wset.net.layers), wset.lo0s, wset.hi0s, wset.Cs, wset.ts)
+        t_roots = time.perf_counter()
+
+        def made(k):
+            if k % 16 == 0 or k == wset.P:
+                log(f"  root pass {k}/{wset.P} ({time.perf_counter() - t_roots:.1f} s)")
+
+        prop = gpipe.PropertySet(list(wset.net.layers), wset.lo0s, wset.hi0s, wset.Cs, wset.ts,
+                                 progress=made)
         sps, unst = [], []
         for p_, r in enumerate(prop.roots):
             l0, u0 = (x.cpu().numpy() for x in r.bounds())
@@ -198,18 +226,20 @@ def main():
     lo_init, hi_init = batch.lo.clone(), batch.hi.clone()
     tuned = None
     if not args.no_autotune:
-        tuned = prop.net.autotune(B, prop.M)
+        tuned = prop.net.autotune(min(B, chunk) if chunk else B, prop.M)
         log("autotuned variants: " + ", ".join(f"{k}{l}={v}" for (k, l), (v, c) in
                                                 sorted(tuned.items()) if c > 1))
     torch.cuda.synchronize()
     log(f"set-up (root pass, {n_unst} unstable of {w.net.n_hidden}) "
         f"{time.perf_counter() - t0:.2f} s")
 
-    state, pstate = {}, {}
+    state, pstate, cstate, cpstate = {}, {}, {}, {}
 
     def plain_step():
         batch.lo.copy_(lo_init)
         batch.hi.copy_(hi_init)
+        if chunk:
+            return gpipe.chunked_verify(prop, batch, chunk, steps=0, state=cpstate)
         return gpipe.plain_pass(prop, batch, gpipe.PassConfig(), pstate)
 
     graph = None
@@ -221,6 +251,11 @@ def main():
                                     steps=T, lr=0.1)
 
     def full_step():
+        if chunk:
+            batch.lo.copy_(lo_init)
+            batch.hi.copy_(hi_init)
+            res = gpipe.chunked_verify(prop, batch, chunk, steps=T, lr=0.1, state=cstate)
+            return res, res["best"]
         out = plain_step()
         if graph is not None:
             return out, graph.run()
@@ -287,7 +322,11 @@ def main():
             f"avg {v['ms'] / v['launches']:8.4f} ms  share {v['ms'] / (1e3 * wall):6.1%}")
 
     cpu = None
-    if not args.no_cpu_baseline and args.cpu_sample > 0:
+    if big and not args.no_cpu_baseline:
+        # the oracle's root pass for this network (dense matrices of 10^9
+        # entries, a CROWN pass per hidden neuron) does not fit a bounded sample
+        log("cpu baseline: not run for this network (the oracle's root pass alone is hours)")
+    elif not args.no_cpu_baseline and args.cpu_sample > 0:
         log(f"cpu baseline: oracle on {args.cpu_sample} subdomains ...")
         if wset is None:
             cpu = cpu_baseline(w, sp, args.cpu_sample, T)
@@ -307,6 +346,7 @@ def main():
                                f"plain pass + {T} alpha-opt Adam steps (lr 0.1)",
                    "global_batch": B, "alpha_steps": T, "io_dtype": "f32",
                    "launch": "hip graph (slope iterations)" if args.graph else "eager",
+                   "chunk": chunk,
                    "kernel_variants": "autotuned" if tuned is not None else "built-in"},
         "plain": {"value": round(B / plain_s, 1), "unit": "subdomains/s",
                   "ms_per_pass": round(1e3 * plain_s, 3)},

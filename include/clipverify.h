@@ -82,11 +82,13 @@ typedef struct cv_net_s* cv_net;
 /* Copies the weights to the current device.  n_layers >= 2 (one hidden ReLU
  * layer at least).  A conv layer (in_features = in_c*in_h*in_w, out_features
  * = out_c*out_h*out_w, out_h = (in_h + 2 pad - kernel)/stride + 1, likewise
- * out_w, activations flattened channel-major) is kept twice: as the dense
- * matrix of its linear map (root planes, objective layer) and as its kernel,
- * with which the backward passes and the adjoint run direct (transposed)
- * convolutions.  Layers whose dense matrix exceeds 2^28 entries return
- * CV_E_UNSUPPORTED, inconsistent sizes CV_E_SHAPE. */
+ * out_w, activations flattened channel-major) is kept as its kernel only:
+ * the backward passes and the adjoint run it as a direct (transposed)
+ * convolution, and the root pass takes the rows of its matrix from the
+ * kernel.  The last (objective) layer must be linear.  CV_E_UNSUPPORTED for
+ * a conv as the last layer, a linear layer of more than 2^28 entries or a
+ * conv layer of more than 2^26 inputs or outputs; CV_E_SHAPE for
+ * inconsistent sizes. */
 cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out);
 cv_status cv_net_destroy(cv_net net);
 /* Host outputs: input dim, output dim, total hidden neurons, layer count. */
@@ -131,13 +133,30 @@ typedef struct cv_root_s* cv_root;
  * lo0, hi0: device [n_in].  Synchronises `stream` before returning. */
 cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
                          hipStream_t stream, cv_root* out);
+/* The same with a choice of which planes stay cached (the root pass computes
+ * them all; the bounds are the same either way):
+ *   CV_ROOT_PLANES_ALL: every hidden neuron's planes, [n_hidden, n_in] per
+ *     side;
+ *   CV_ROOT_PLANES_UNSTABLE: only those of the root-unstable neurons
+ *     (l0 < 0 < u0), [U, n_in] per side -- the memory answer for large
+ *     networks, where the others cannot be split by a branch-and-bound
+ *     anyway.  A split constraint on a neuron without a kept plane is then
+ *     ignored (dropping a constraint can only loosen a bound, so results stay
+ *     sound); cv_root_planes returns CV_E_UNSUPPORTED;
+ *   CV_ROOT_PLANES_AUTO (what cv_root_create does): ALL unless n_hidden *
+ *     n_in exceeds 2^28, then UNSTABLE.
+ * Other values: CV_E_INVALID. */
+enum { CV_ROOT_PLANES_AUTO = 0, CV_ROOT_PLANES_ALL = 1, CV_ROOT_PLANES_UNSTABLE = 2 };
+cv_status cv_root_create_ex(cv_net net, const float* lo0, const float* hi0, float alpha0,
+                            int planes, hipStream_t stream, cv_root* out);
 cv_status cv_root_destroy(cv_root root);
 /* Device outputs [n_hidden]: root pre-activation bounds (global neuron
  * order = layer by layer). */
 cv_status cv_root_bounds(cv_root root, float* l0, float* u0, hipStream_t stream);
 /* Device outputs: A_lo, A_hi [n_hidden, n_in], c_lo, c_hi [n_hidden]:
  * z_j >= A_lo[j].x + c_lo[j] and z_j <= A_hi[j].x + c_hi[j] on the root box
- * (intercepts rounded outward to float32). */
+ * (intercepts rounded outward to float32).  CV_E_UNSUPPORTED for a root that
+ * keeps the unstable neurons' planes only. */
 cv_status cv_root_planes(cv_root root, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
                          hipStream_t stream);
 /* Host output: number of root-unstable neurons (l0 < 0 < u0). */

@@ -21,7 +21,7 @@ EXPORTS = [
     "cv_status_string", "cv_last_hip_error", "cv_version",
     "cv_net_create", "cv_net_destroy", "cv_net_info",
     "cv_net_autotune", "cv_net_tuning", "cv_net_set_tuning",
-    "cv_root_create", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
+    "cv_root_create", "cv_root_create_ex", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
     "cv_root_unstable_count", "cv_rootset_create", "cv_root_count",
     "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
     "cv_concretize_planes_workspace", "cv_babsr_weights", "cv_babsr_weights_workspace",
@@ -78,6 +78,7 @@ def lib():
         "cv_net_tuning": (I, [P, I, I, P, P]),
         "cv_net_set_tuning": (I, [P, I, I, I]),
         "cv_root_create": (I, [P, P, P, F, P, P]),
+        "cv_root_create_ex": (I, [P, P, P, F, I, P, P]),
         "cv_root_destroy": (I, [P]),
         "cv_root_bounds": (I, [P, P, P, P]),
         "cv_root_planes": (I, [P, P, P, P, P, P]),

@@ -103,7 +103,7 @@ class Net:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and N._lib is not None:
+        if h is not None and h.value and N is not None and N._lib is not None:
             N._lib.cv_net_destroy(h)
             self.handle = None
 
@@ -113,12 +113,17 @@ class Root:
 
     P = 1
 
-    def __init__(self, net, lo0, hi0, alpha0=0.5):
+    PLANES = {"auto": 0, "all": 1, "unstable": 2}
+
+    def __init__(self, net, lo0, hi0, alpha0=0.5, planes="auto"):
+        """planes: which cached planes stay on the device -- "all", "unstable"
+        (root-unstable neurons only; splits of other neurons are then
+        ignored) or "auto" (all unless they pass 2^28 coefficients a side)."""
         self.net = net
         self.lo0, self.hi0 = _f32(lo0), _f32(hi0)
         h = C.c_void_p()
-        N.call("cv_root_create", net.handle, _p(self.lo0), _p(self.hi0), float(alpha0), _stream(),
-               C.byref(h))
+        N.call("cv_root_create_ex", net.handle, _p(self.lo0), _p(self.hi0), float(alpha0),
+               self.PLANES[planes], _stream(), C.byref(h))
         self.handle = h
         cnt = C.c_int()
         N.call("cv_root_unstable_count", h, C.byref(cnt))
@@ -141,7 +146,7 @@ class Root:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and N._lib is not None:
+        if h is not None and h.value and N is not None and N._lib is not None:
             N._lib.cv_root_destroy(h)
             self.handle = None
 
@@ -166,7 +171,7 @@ class RootSet:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and N._lib is not None:
+        if h is not None and h.value and N is not None and N._lib is not None:
             N._lib.cv_root_destroy(h)
             self.handle = None
 

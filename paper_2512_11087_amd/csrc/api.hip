@@ -130,6 +130,15 @@ struct Bwd {
   double2* kst;  // [B, CA_SLOTS] per-constraint box statistics for complete clipping
 };
 
+// Row counts a backward pass supports: every per-layer matrix of R rows
+// (widest layer below T, and the [R, n_hidden] slope trace) stays under 2^31
+// entries; larger batches are split by the caller.
+bool rows_fit(const cv_net_s* net, int T, long long R) {
+  long long nmax = net->n_hidden;
+  for (int i = 0; i < T; ++i) nmax = std::max<long long>(nmax, net->n[i]);
+  return R * nmax <= 0x7fffffffLL;
+}
+
 size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool keepAx, bool trace,
                   void* ws, Bwd* w) {
   const long long B = R / M;
@@ -170,8 +179,9 @@ cv_status backward_run(const cv_net_s* net, const cv_root_s* root, CvProps props
   const int R = B * M;
   const int Nh = net->n_hidden;
   const int nP = net->n[T - 1];
+  if (!eye && conv_of(net, T)) return CV_E_UNSUPPORTED;  // a general objective needs a linear layer
   if (eye)
-    PLAUNCH("top", 0, 8.0 * props.P * M * nP, launch_top_eye(props.P, M, nP, (double)eye, net->W[T - 1], net->b[T - 1], props, T - 1,
+    PLAUNCH("top", 0, 8.0 * props.P * M * nP, launch_top_eye(props.P, M, nP, (double)eye, net->W[T - 1], conv_of(net, T), net->b[T - 1], props, T - 1,
                           w.psiT, w.c0, w.e0, w.cabs0, s));
   else
     PLAUNCH("top", 2.0 * props.P * M * net->n[T] * nP, 8.0 * props.P * M * nP, launch_top(props.P, M, net->n[T], nP, C, t, net->W[T - 1], net->b[T - 1], props, T - 1,
@@ -235,6 +245,7 @@ RootDev root_dev(const cv_root_s* r) {
   RootDev d{};
   d.A_lo = r->A_lo;
   d.A_hi = r->A_hi;
+  d.prow = r->prow;
   d.c_lo = r->c_lo;
   d.c_hi = r->c_hi;
   d.l0 = r->l0;
@@ -349,8 +360,12 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
         return CV_E_SHAPE;
     }
     if (d.in_features <= 0 || d.out_features <= 0) return CV_E_INVALID;
-    // conv layers are stored as their dense matrices (below): cap the size
-    if ((long long)d.in_features * d.out_features > (1LL << 28)) return CV_E_UNSUPPORTED;
+    if (d.kind == CV_LINEAR) {  // kept as a dense matrix and its transpose
+      if ((long long)d.in_features * d.out_features > (1LL << 28)) return CV_E_UNSUPPORTED;
+    } else {  // kept as its kernel; the objective layer must be linear
+      if (i == n_layers - 1) return CV_E_UNSUPPORTED;
+      if (d.in_features > (1 << 26) || d.out_features > (1 << 26)) return CV_E_UNSUPPORTED;
+    }
     if (i > 0 && d.in_features != layers[i - 1].out_features) return CV_E_SHAPE;
   }
   cv_net_s* net = new cv_net_s();
@@ -365,45 +380,33 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
     net->is_conv[i] = false;
     net->conv[i] = ConvDesc{};
     for (int k = 0; k < 3; ++k) net->tune[k][i] = 0;
-    std::vector<float> W, Wt((size_t)no * ni), bb;
+    std::vector<float> W, Wt, K, bb;
     if (d.kind == CV_LINEAR) {
       W.assign(d.W, d.W + (size_t)no * ni);
       bb.assign(d.b, d.b + no);
+      Wt.resize((size_t)no * ni);
+      for (int r = 0; r < no; ++r)
+        for (int c = 0; c < ni; ++c) Wt[(size_t)c * no + r] = W[(size_t)r * ni + c];
+      if (dev_alloc(&net->W[i], W.size()) || dev_alloc(&net->Wt[i], Wt.size())) {
+        cv_net_destroy(net);
+        return CV_E_NOMEM;
+      }
+      if (hipMemcpy(net->W[i], W.data(), W.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(net->Wt[i], Wt.data(), Wt.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        cv_net_destroy(net);
+        return hip_fail(hipGetLastError());
+      }
     } else {
-      // The convolution as the dense matrix of the same linear map: output
-      // (co, oy, ox) takes input (ci, oy*stride - pad + ky, ox*stride - pad + kx)
-      // with weight W[co, ci, ky, kx] (cross-correlation, zero padding, maps
-      // flattened channel-major); the bias repeats over output positions.
-      W.assign((size_t)no * ni, 0.0f);
+      // the bias repeats over the output positions (maps flattened channel-major)
+      K.assign(d.W, d.W + (size_t)d.out_c * d.in_c * d.kernel * d.kernel);
       bb.resize(no);
-      const int K = d.kernel, ic = d.in_c, ih = d.in_h, iw = d.in_w, oh = d.out_h, ow = d.out_w;
-      for (int co = 0; co < d.out_c; ++co)
-        for (int oy = 0; oy < oh; ++oy)
-          for (int ox = 0; ox < ow; ++ox) {
-            const size_t r = ((size_t)co * oh + oy) * ow + ox;
-            bb[r] = d.b[co];
-            for (int ci = 0; ci < ic; ++ci)
-              for (int ky = 0; ky < K; ++ky) {
-                const int iy = oy * d.stride - d.pad + ky;
-                if (iy < 0 || iy >= ih) continue;
-                for (int kx = 0; kx < K; ++kx) {
-                  const int ix = ox * d.stride - d.pad + kx;
-                  if (ix < 0 || ix >= iw) continue;
-                  W[r * ni + ((size_t)ci * ih + iy) * iw + ix] = d.W[(((size_t)co * ic + ci) * K + ky) * K + kx];
-                }
-              }
-          }
+      for (int r = 0; r < no; ++r) bb[r] = d.b[r / (d.out_h * d.out_w)];
     }
-    for (int r = 0; r < no; ++r)
-      for (int c = 0; c < ni; ++c) Wt[(size_t)c * no + r] = W[(size_t)r * ni + c];
-    if (dev_alloc(&net->W[i], W.size()) || dev_alloc(&net->Wt[i], Wt.size()) ||
-        dev_alloc(&net->b[i], bb.size())) {
+    if (dev_alloc(&net->b[i], bb.size())) {
       cv_net_destroy(net);
       return CV_E_NOMEM;
     }
-    if (hipMemcpy(net->W[i], W.data(), W.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(net->Wt[i], Wt.data(), Wt.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(net->b[i], bb.data(), bb.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(net->b[i], bb.data(), bb.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
       cv_net_destroy(net);
       return hip_fail(hipGetLastError());
     }
@@ -441,8 +444,9 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
         return cst;
       }
     }
-    net->hW.push_back(W);
-    net->hb.push_back(bb);
+    net->hW.push_back(std::move(W));
+    net->hK.push_back(std::move(K));
+    net->hb.push_back(std::move(bb));
     if (i < n_layers - 1) {
       net->off[i] = acc;
       acc += no;
@@ -636,6 +640,7 @@ cv_status cv_root_destroy(cv_root r) {
   if (r->eP) (void)hipFree(r->eP);
   if (r->uidx) (void)hipFree(r->uidx);
   if (r->sidx) (void)hipFree(r->sidx);
+  if (r->prow) (void)hipFree(r->prow);
   for (int i = 0; i < CV_MAX_LAYERS; ++i) {
     if (r->vgemm[i]) (void)hipFree(r->vgemm[i]);
     if (r->wrel[i]) (void)hipFree(r->wrel[i]);
@@ -646,8 +651,16 @@ cv_status cv_root_destroy(cv_root r) {
 
 cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
                          hipStream_t s, cv_root* out) {
+  return cv_root_create_ex(net, lo0, hi0, alpha0, CV_ROOT_PLANES_AUTO, s, out);
+}
+
+cv_status cv_root_create_ex(cv_net net, const float* lo0, const float* hi0, float alpha0,
+                            int planes, hipStream_t s, cv_root* out) {
   if (!net || !lo0 || !hi0 || !out) return CV_E_INVALID;
   if (!finite01(alpha0)) return CV_E_INVALID;
+  if (planes != CV_ROOT_PLANES_AUTO && planes != CV_ROOT_PLANES_ALL &&
+      planes != CV_ROOT_PLANES_UNSTABLE)
+    return CV_E_INVALID;
   *out = nullptr;
   const int n0 = net->n[0], N = net->n_hidden, L = net->L;
   cv_root_s* r = new cv_root_s();
@@ -705,12 +718,35 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
   auto make_vgemm = [&](int i) -> cv_status {
     const int no = net->n[i], ni = net->n[i - 1];
     std::vector<double> v(no);
-    const std::vector<float>& W = net->hW[i - 1];
     const std::vector<float>& b = net->hb[i - 1];
-    for (int k = 0; k < no; ++k) {
-      double s_ = fabs((double)b[k]);
-      for (int j = 0; j < ni; ++j) s_ += fabs((double)W[(size_t)k * ni + j]) * H[j];
-      v[k] = s_ * (1.0 + 1e-12);
+    if (const ConvDesc* c = conv_of(net, i)) {  // the taps of each output position
+      const std::vector<float>& Kw = net->hK[i - 1];
+      const int K = c->k;
+      for (int co = 0; co < c->co; ++co)
+        for (int oy = 0; oy < c->ho; ++oy)
+          for (int ox = 0; ox < c->wo; ++ox) {
+            const int k = (co * c->ho + oy) * c->wo + ox;
+            double s_ = fabs((double)b[k]);
+            for (int ci = 0; ci < c->ci; ++ci)
+              for (int ky = 0; ky < K; ++ky) {
+                const int iy = oy * c->s - c->p + ky;
+                if (iy < 0 || iy >= c->hi) continue;
+                for (int kx = 0; kx < K; ++kx) {
+                  const int ix = ox * c->s - c->p + kx;
+                  if (ix < 0 || ix >= c->wi) continue;
+                  s_ += fabs((double)Kw[(((size_t)co * c->ci + ci) * K + ky) * K + kx]) *
+                        H[((size_t)ci * c->hi + iy) * c->wi + ix];
+                }
+              }
+            v[k] = s_ * (1.0 + 1e-12);
+          }
+    } else {
+      const std::vector<float>& W = net->hW[i - 1];
+      for (int k = 0; k < no; ++k) {
+        double s_ = fabs((double)b[k]);
+        for (int j = 0; j < ni; ++j) s_ += fabs((double)W[(size_t)k * ni + j]) * H[j];
+        v[k] = s_ * (1.0 + 1e-12);
+      }
     }
     return upload_vec(&r->vgemm[i - 1], v);
   };
@@ -736,8 +772,10 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
   const int n1 = net->n[1];
   if ((st = make_vgemm(1))) return fail(st);
   std::vector<double> hb1(net->hb[0].begin(), net->hb[0].end());
-  if (hipMemcpyAsync(r->A_lo, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
-      hipMemcpyAsync(r->A_hi, net->W[0], (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
+  if ((conv_of(net, 1) ? launch_conv_dense(*conv_of(net, 1), n1, r->A_lo, s)
+                       : hipMemcpyAsync(r->A_lo, net->W[0], (size_t)n1 * n0 * 4,
+                                        hipMemcpyDeviceToDevice, s)) ||
+      hipMemcpyAsync(r->A_hi, r->A_lo, (size_t)n1 * n0 * 4, hipMemcpyDeviceToDevice, s) ||
       hipMemcpy(r->c_lo, hb1.data(), n1 * 8, hipMemcpyHostToDevice) ||
       hipMemcpy(r->c_hi, hb1.data(), n1 * 8, hipMemcpyHostToDevice))
     return fail(hip_fail(hipGetLastError()));
@@ -756,6 +794,7 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
   };
   for (int i = 2; i <= L - 1; ++i) {
     const int ni = net->n[i], off = net->off[i - 1];
+    if (!rows_fit(net, i, ni)) { cleanup(); return fail(CV_E_UNSUPPORTED); }
     if ((st = make_vgemm(i))) { cleanup(); return fail(st); }
     Bwd w;
     const size_t bytes = bwd_layout(net, i, ni, ni, 1, true, false, nullptr, nullptr);
@@ -811,6 +850,33 @@ cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float a
                      r->cP, r->eP, s) ||
       hipStreamSynchronize(s))
     return fail(hip_fail(hipGetLastError()));
+  // keep the planes of the root-unstable neurons only (row q: neuron uidx[q])
+  // when asked, or by default when all planes would pass 2^28 coefficients
+  // per side
+  const bool compact = planes == CV_ROOT_PLANES_UNSTABLE ||
+                       (planes == CV_ROOT_PLANES_AUTO && (long long)N * n0 > (1LL << 28));
+  if (compact) {
+    std::vector<int32_t> prow(N, -1);
+    for (int q = 0; q < r->U; ++q) prow[us[q]] = q;
+    float *clo = nullptr, *chi = nullptr;
+    if ((st = dev_alloc(&r->prow, N)) || (st = dev_alloc(&clo, (size_t)r->U * n0)) ||
+        (st = dev_alloc(&chi, (size_t)r->U * n0))) {
+      if (clo) (void)hipFree(clo);
+      return fail(st);
+    }
+    if (hipMemcpy(r->prow, prow.data(), (size_t)N * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_gather_rows(r->U, n0, r->uidx, r->A_lo, clo, s) != hipSuccess ||
+        launch_gather_rows(r->U, n0, r->uidx, r->A_hi, chi, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      if (clo) (void)hipFree(clo);
+      if (chi) (void)hipFree(chi);
+      return fail(hip_fail(hipGetLastError()));
+    }
+    (void)hipFree(r->A_lo);
+    (void)hipFree(r->A_hi);
+    r->A_lo = clo;
+    r->A_hi = chi;
+  }
   if ((st = root_sync_tab(r))) return fail(st);
   *out = r;
   return CV_OK;
@@ -836,6 +902,9 @@ cv_status cv_rootset_create(const cv_root* roots, int P, cv_root* out) {
   r->gamma_big = r0->gamma_big;  // depends on the layer widths only
   r->P = P;
   r->U = -1;
+  // a set of one property takes the single-property launch paths, which
+  // read the host copy of its table entry
+  r->htab = tab[0];
   for (int p = 0; p < P; ++p) {
     r->members.push_back(roots[p]);
     r->Umax = std::max(r->Umax, roots[p]->U);
@@ -869,6 +938,7 @@ cv_status cv_root_bounds(cv_root r, float* l0, float* u0, hipStream_t s) {
 cv_status cv_root_planes(cv_root r, float* A_lo, float* c_lo, float* A_hi, float* c_hi,
                          hipStream_t s) {
   if (!r || !A_lo || !c_lo || !A_hi || !c_hi || !r->members.empty()) return CV_E_INVALID;
+  if (r->prow) return CV_E_UNSUPPORTED;  // only the unstable neurons' planes are kept
   const size_t na = (size_t)r->N * r->n0 * 4;
   CV_HIP(hipMemcpyAsync(A_lo, r->A_lo, na, hipMemcpyDeviceToDevice, s));
   CV_HIP(hipMemcpyAsync(A_hi, r->A_hi, na, hipMemcpyDeviceToDevice, s));
@@ -1009,6 +1079,7 @@ cv_status cv_intermediate_bounds_workspace(cv_net net, int B, size_t* bytes) {
   int nmax = 1;
   for (int i = 2; i <= net->L - 1; ++i) {
     const int ni = net->n[i];
+    if (!rows_fit(net, i, (long long)B * ni)) return CV_E_UNSUPPORTED;
     nmax = std::max(nmax, ni);
     best = std::max(best, bwd_layout(net, i, (long long)B * ni, ni, 1, false, false, nullptr, nullptr));
   }
@@ -1025,7 +1096,7 @@ cv_status cv_intermediate_bounds(cv_net net, cv_root root, int B, const float* l
   if (B == 0) return CV_OK;
   if (!lo || !hi || !l || !u) return CV_E_INVALID;
   size_t need = 0;
-  cv_intermediate_bounds_workspace(net, B, &need);
+  if (cv_status e = cv_intermediate_bounds_workspace(net, B, &need)) return e;
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   const int Nh = net->n_hidden;
   for (int i = 2; i <= net->L - 1; ++i) {
@@ -1106,6 +1177,7 @@ static cv_status check_prop(cv_net net, cv_root root, int B, int M, const float*
 
 cv_status cv_bound_propagate_workspace(cv_net net, int P, int B, int M, size_t* bytes) {
   if (!net || !bytes || B < 0 || M <= 0 || P < 1) return CV_E_INVALID;
+  if (!rows_fit(net, net->L, (long long)B * M)) return CV_E_UNSUPPORTED;
   *bytes = bwd_layout(net, net->L, (long long)B * M, M, P, true, false, nullptr, nullptr);
   return CV_OK;
 }
@@ -1122,7 +1194,7 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
   if (cons && passes < 1) return CV_E_INVALID;
   if ((A_out == nullptr) != (c_out == nullptr)) return CV_E_INVALID;
   size_t need = 0;
-  cv_bound_propagate_workspace(net, root->P, B, M, &need);
+  if ((st = cv_bound_propagate_workspace(net, root->P, B, M, &need))) return st;
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
   if ((st = resolve_cons(root, pid, cons, &cc))) return st;
@@ -1143,6 +1215,7 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
 
 cv_status cv_alpha_step_workspace(cv_net net, int P, int B, int M, size_t* bytes) {
   if (!net || !bytes || B < 0 || M <= 0 || P < 1) return CV_E_INVALID;
+  if (!rows_fit(net, net->L, (long long)B * M)) return CV_E_UNSUPPORTED;
   *bytes = bwd_layout(net, net->L, (long long)B * M, M, P, true, true, nullptr, nullptr);
   return CV_OK;
 }
@@ -1165,7 +1238,7 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
       return CV_E_INVALID;
   }
   size_t need = 0;
-  cv_alpha_step_workspace(net, root->P, B, M, &need);
+  if ((st = cv_alpha_step_workspace(net, root->P, B, M, &need))) return st;
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
   if ((st = resolve_cons(root, pid, cons, &cc))) return st;

@@ -39,13 +39,17 @@ struct cv_net_s {
   int off[CV_MAX_LAYERS];     // global offset of hidden layer i (index i-1)
   int n_hidden = 0;
   int nmax_hidden = 0;
-  std::vector<std::vector<float>> hW, hb;  // host copies (root set-up; conv: the dense matrix)
+  // host copies for the root set-up: hW the matrix of a linear layer (empty
+  // for a conv layer), hK the kernel of a conv layer [co][ci][k][k] (empty
+  // for a linear layer), hb the bias (conv: repeated over positions)
+  std::vector<std::vector<float>> hW, hK, hb;
 };
 
 // Device view of one property's root state: pointers into its cv_root_s.
 struct RootDev {
-  const float* A_lo;      // [N, n0] cached planes (float32 coefficients)
-  const float* A_hi;
+  const float* A_lo;      // cached planes (float32 coefficients): row prow[j] of neuron j,
+  const float* A_hi;      // [N, n0] (prow null: row j) or [U, n0] (root-unstable neurons only)
+  const int32_t* prow;    // [N] plane row of each neuron, -1: none kept; null: row j
   const double* c_lo;     // [N] float64 intercepts
   const double* c_hi;
   const float* l0;        // [N] root bounds
@@ -92,7 +96,8 @@ struct cv_root_s {
   int Umax = 0;                               // max U over the members
   int n0 = 0, N = 0, U = 0;
   float alpha0 = 0.5f;
-  float *A_lo = nullptr, *A_hi = nullptr;    // [N, n0] float32 plane coefficients
+  float *A_lo = nullptr, *A_hi = nullptr;    // [N, n0] or [U, n0] float32 plane coefficients
+  int32_t* prow = nullptr;                   // [N] plane row of each neuron (null: all kept)
   double *c_lo = nullptr, *c_hi = nullptr;   // [N] intercepts (float64, see k_root_store)
   double* xc0 = nullptr;                     // [n0] centre of the root box
   double* rad0 = nullptr;                    // [n0] half-width of the root box
@@ -157,12 +162,16 @@ __device__ __forceinline__ void cons_row_slot(const CvCons& c, int b, int k, int
     const int j = c.neuron[s];
     if (j < 0 || j >= c.nplanes) return;  // not a hidden neuron: slot ignored
     const RootDev& rd = prop_of(c.props, b);
+    // a root where only unstable neurons keep planes ignores splits of the
+    // others (a dropped constraint only loosens the bounds)
+    const int q = rd.prow ? rd.prow[j] : j;
+    if (q < 0) return;
     if (c.sign[s] < 0) {
-      row = rd.A_lo + (size_t)j * n;
+      row = rd.A_lo + (size_t)q * n;
       scale = 1.0f;
       h = rd.c_lo[j];
     } else {
-      row = rd.A_hi + (size_t)j * n;
+      row = rd.A_hi + (size_t)q * n;
       scale = -1.0f;
       h = -rd.c_hi[j];
     }
@@ -188,9 +197,14 @@ hipError_t launch_clip(int B, int n, const CvCons& cons, float* lo, float* hi, u
 hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float* t,
                       const float* W, const float* b, CvProps props, int layer, double* psiT,
                       double* c0, double* e0, double* cabs0, hipStream_t s);
-hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const float* b,
-                          CvProps props, int layer, double* psiT, double* c0, double* e0,
-                          double* cabs0, hipStream_t s);
+hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const ConvDesc* conv,
+                          const float* b, CvProps props, int layer, double* psiT, double* c0,
+                          double* e0, double* cabs0, hipStream_t s);
+// Rows [0, rows) of the dense matrix of a convolution layer (float32).
+hipError_t launch_conv_dense(const ConvDesc& cd, int rows, float* out, hipStream_t s);
+// dst[q, :] = src[idx[q], :], rows of n floats.
+hipError_t launch_gather_rows(int rows, int n, const int32_t* idx, const float* src, float* dst,
+                              hipStream_t s);
 hipError_t launch_relax_top(int R, int M, int nP, int Nh, int off, const double* psiT,
                             const double* c0, const double* e0, const double* cabs0,
                             const float* lz, const float* uz, const float* alpha,

@@ -39,24 +39,56 @@ __global__ __launch_bounds__(256) void k_top(int M, int nT, int nP, const float*
   }
 }
 
+// Entry (m, j) of the dense matrix of convolution layer cd: output m =
+// (co, oy, ox) reads input j = (ci, iy, ix) through the kernel tap (ky, kx) =
+// (iy - oy*s + p, ix - ox*s + p) when that tap exists, else 0 (kernel from the
+// transposed-convolution layout Wb [co][k][k][ptp], which holds the float32
+// weights exactly).
+__device__ __forceinline__ double conv_entry(const ConvDesc& cd, size_t m, size_t j) {
+  const int hw = cd.ho * cd.wo, ihw = cd.hi * cd.wi;
+  const int co = (int)(m / hw), oy = (int)((m % hw) / cd.wo), ox = (int)(m % cd.wo);
+  const int ci = (int)(j / ihw), iy = (int)((j % ihw) / cd.wi), ix = (int)(j % cd.wi);
+  const int ky = iy - oy * cd.s + cd.p, kx = ix - ox * cd.s + cd.p;
+  if (ky < 0 || ky >= cd.k || kx < 0 || kx >= cd.k) return 0.0;
+  return cd.Wb[(((size_t)co * cd.k + ky) * cd.k + kx) * cd.ptp + ci];
+}
+
 // The same for the objective C = eye * I (eye = +-1), t = 0 (intermediate
 // bounds of a layer): Psi_T is row m of W_T times eye, c0 = eye b_T[m], e0 =
 // vT[m] -- what k_top computes for that C, exactly, without its dense loop.
-__global__ void k_top_eye(int M, int nP, double eye, const float* __restrict__ W,
-                          const float* __restrict__ b, CvProps props, int layer, double* psiT,
-                          double* c0, double* e0, double* cabs0) {
+// A conv layer T (conv = 1) gives its rows from the kernel.
+__global__ void k_top_eye(int M, int nP, double eye, const float* __restrict__ W, ConvDesc cd,
+                          int conv, const float* __restrict__ b, CvProps props, int layer,
+                          double* psiT, double* c0, double* e0, double* cabs0) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t tot = (size_t)props.P * M * nP;
   if (i >= tot) return;
   const int p = (int)(i / ((size_t)M * nP));
   const int m = (int)((i / nP) % M), j = (int)(i % nP);
-  psiT[i] = eye * (double)W[(size_t)m * nP + j];
+  psiT[i] = eye * (conv ? conv_entry(cd, m, j) : (double)W[(size_t)m * nP + j]);
   if (j == 0) {
     const size_t row = (size_t)p * M + m;
     c0[row] = eye * (double)b[m];
     e0[row] = props.tab[p].vgemm[layer][m];
     cabs0[row] = fabs((double)b[m]);
   }
+}
+
+// Rows [0, rows) of the dense matrix of convolution layer cd, float32.
+__global__ void k_conv_dense(ConvDesc cd, int rows, float* out) {
+  const size_t ncol = (size_t)cd.ci * cd.hi * cd.wi;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)rows * ncol) return;
+  out[i] = (float)conv_entry(cd, i / ncol, i % ncol);
+}
+
+// dst[q, :] = src[idx[q], :] for q < rows (rows of n floats).
+__global__ void k_gather_rows(int rows, int n, const int32_t* __restrict__ idx,
+                              const float* __restrict__ src, float* dst) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)rows * n) return;
+  const size_t q = i / n, c = i % n;
+  dst[i] = src[(size_t)idx[q] * n + c];
 }
 
 // First relaxation (ReLU of layer T-1) of every row r = (b, m): one wave
@@ -384,13 +416,34 @@ hipError_t launch_top(int P, int M, int nT, int nP, const float* C, const float*
   return hipGetLastError();
 }
 
-hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const float* b,
-                          CvProps props, int layer, double* psiT, double* c0, double* e0,
-                          double* cabs0, hipStream_t s) {
+hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, const ConvDesc* conv,
+                          const float* b, CvProps props, int layer, double* psiT, double* c0,
+                          double* e0, double* cabs0, hipStream_t s) {
   const size_t tot = (size_t)P * M * nP;
   if (tot == 0) return hipSuccess;
+  if ((tot + 255) / 256 > 0x7fffffffu) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_top_eye, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, nP, eye, W,
-                     b, props, layer, psiT, c0, e0, cabs0);
+                     conv ? *conv : ConvDesc{}, conv ? 1 : 0, b, props, layer, psiT, c0, e0,
+                     cabs0);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_dense(const ConvDesc& cd, int rows, float* out, hipStream_t s) {
+  const size_t tot = (size_t)rows * cd.ci * cd.hi * cd.wi;
+  if (tot == 0) return hipSuccess;
+  if ((tot + 255) / 256 > 0x7fffffffu) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_conv_dense, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, cd, rows,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int rows, int n, const int32_t* idx, const float* src, float* dst,
+                              hipStream_t s) {
+  const size_t tot = (size_t)rows * n;
+  if (tot == 0) return hipSuccess;
+  if ((tot + 255) / 256 > 0x7fffffffu) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, rows, n,
+                     idx, src, dst);
   return hipGetLastError();
 }
 

@@ -35,9 +35,9 @@ class Property:
 
     P = 1
 
-    def __init__(self, layers, lo0, hi0, C, t, alpha0=0.5):
+    def __init__(self, layers, lo0, hi0, C, t, alpha0=0.5, planes="auto"):
         self.net = api.Net(layers)
-        self.root = api.Root(self.net, lo0, hi0, alpha0)
+        self.root = api.Root(self.net, lo0, hi0, alpha0, planes)
         self.C = api._f32(C)
         self.t = api._f32(t)
         self.M = self.C.shape[0]
@@ -66,9 +66,15 @@ class PropertySet:
     bounded in the same launches: ``root`` is an api.RootSet, C [P, M, n_out],
     t [P, M]; a batch's ``pid`` gives each subdomain's property."""
 
-    def __init__(self, layers, lo0s, hi0s, Cs, ts, alpha0=0.5):
-        self.net = api.Net(layers)
-        self.roots = [api.Root(self.net, lo, hi, alpha0) for lo, hi in zip(lo0s, hi0s)]
+    def __init__(self, layers, lo0s, hi0s, Cs, ts, alpha0=0.5, planes="auto", net=None,
+                 progress=None):
+        """progress: called with the number of roots made so far after each."""
+        self.net = net if net is not None else api.Net(layers)
+        self.roots = []
+        for lo, hi in zip(lo0s, hi0s):
+            self.roots.append(api.Root(self.net, lo, hi, alpha0, planes))
+            if progress is not None:
+                progress(len(self.roots))
         self.root = api.RootSet(self.roots)
         self.P = len(self.roots)
         self.C = api._f32(np.stack([np.asarray(c, np.float32) for c in Cs]))
@@ -302,3 +308,43 @@ class AlphaOptGraph:
     def run(self):
         self.graph.replay()
         return self.best
+
+
+def chunked_verify(prop, batch, chunk, steps=10, lr=0.1, cfg=PassConfig(), state=None):
+    """The plain pass and ``steps`` slope iterations over a batch too large
+    for one call (the per-row matrices of a wide network), in consecutive
+    chunks of at most ``chunk`` subdomains.  Subdomains are independent, so
+    every result equals that of one call over the whole batch.  Boxes are
+    clipped in place.  Returns dict(infeasible [B], lb [B, M] plain bound,
+    best [B, M] best bound over the slope iterations (the plain bound when
+    steps = 0)).  ``state`` keeps the per-chunk buffers between calls."""
+    B, M = batch.lo.shape[0], prop.M
+    state = state if state is not None else {}
+    res = state.get("res")
+    if res is None or res["lb"].shape[0] != B:
+        res = dict(infeasible=torch.empty(B, dtype=torch.uint8, device="cuda"),
+                   lb=torch.empty(B, M, device="cuda"), best=torch.empty(B, M, device="cuda"))
+        state["res"] = res
+    for s0 in range(0, B, chunk):
+        s1 = min(B, s0 + chunk)
+        sp = batch.splits
+        cons = None
+        if sp is not None:
+            cons = api.Constraints.splits(sp.neuron[s0:s1], sp.sign[s0:s1],
+                                          None if sp.count is None else sp.count[s0:s1])
+        sub = Batch(batch.lo[s0:s1], batch.hi[s0:s1], cons,
+                    pid=None if batch.pid is None else batch.pid[s0:s1])
+        key = s1 - s0
+        bufs = state.setdefault(("out", key), {})
+        out = plain_pass(prop, sub, cfg, out=bufs)
+        res["infeasible"][s0:s1] = out["infeasible"]
+        res["lb"][s0:s1] = out["lb"]
+        if steps > 0:
+            ast = state.setdefault(("alpha", key), {})
+            best, _ = alpha_opt(prop, sub, out["l"], out["u"], out["infeasible"], steps=steps,
+                                lr=lr, alpha0=cfg.alpha, complete=cfg.complete_final,
+                                passes=cfg.passes, state=ast)
+            res["best"][s0:s1] = best
+        else:
+            res["best"][s0:s1] = out["lb"]
+    return res

@@ -428,6 +428,56 @@ def cifar_cnn_set(P: int = 64, seed: int = SEED_WEIGHTS, counts=None) -> Workloa
                         f"cnn3x32x32-c16-c32-100-10 x {len(counts)} properties")
 
 
+def zipf_counts(P: int, s: float, total: int) -> np.ndarray:
+    """Subdomain counts of P properties proportional to r^-s over the ranks
+    r = 1..P (property p has rank p + 1), rounded by largest remainder to sum
+    to ``total``, with at least 1 each."""
+    w = np.arange(1, P + 1, dtype=np.float64) ** (-s)
+    q = total * w / w.sum()
+    base = np.maximum(np.floor(q).astype(np.int64), 1)
+    left = total - int(base.sum())
+    if left > 0:
+        order = np.argsort(-(q - np.floor(q)), kind="stable")
+        base[order[:left]] += 1
+    elif left < 0:  # the minimum of 1 overshot: take from the largest counts
+        order = np.argsort(-base, kind="stable")
+        i = 0
+        while left < 0:
+            if base[order[i % P]] > 1:
+                base[order[i % P]] -= 1
+                left += 1
+            i += 1
+    return base
+
+
+CONV64_CONVS = [(64, 3, 1, 1), (64, 3, 2, 1), (64, 3, 1, 1), (64, 3, 2, 1)]
+
+
+def cifar_conv64_set(P: int = 256, total: int = 32768, seed: int = SEED_WEIGHTS,
+                     counts=None) -> WorkloadSet:
+    """CNN 3x32x32 -> four 64-channel 3x3 convolutions (strides 1, 2, 1, 2,
+    pad 1) -> linear 512 -> linear 10, He-normal, zero biases; P properties
+    (own image centre U[0,1]^3072 and label, eps 2/255 clipped to [0,1]);
+    subdomain counts Zipf(1.2) over the properties summing to ``total``
+    unless ``counts`` is given; split depth ~ U{1..12}."""
+    net = he_cnn((3, 32, 32), CONV64_CONVS, [512, 10], seed)
+    if counts is None:
+        counts = zipf_counts(P, 1.2, total)
+    return property_set(net, 3072, (0.0, 1.0), 2.0 / 255.0, (0.0, 1.0), counts, (1, 12),
+                        f"cnn3x32x32-4xc64-512-10 x {len(counts)} properties")
+
+
+def small_conv4_set(P: int = 3, B: int = 48, seed: int = SEED_WEIGHTS) -> WorkloadSet:
+    """The layer pattern of ``cifar_conv64_set`` at a size the oracle bounds in
+    seconds: 3x8x8 -> four 8-channel 3x3 convolutions (strides 1, 2, 1, 2,
+    pad 1) -> linear 32 -> linear 10, uniform biases; eps 0.02 around U[0,1]
+    centres; Zipf(1.2) counts summing to B; split depth ~ U{1..6}."""
+    net = he_cnn((3, 8, 8), [(8, 3, 1, 1), (8, 3, 2, 1), (8, 3, 1, 1), (8, 3, 2, 1)], [32, 10],
+                 seed, bias="uniform")
+    return property_set(net, 192, (0.0, 1.0), 0.02, (0.0, 1.0), zipf_counts(P, 1.2, B), (1, 6),
+                        f"cnn3x8x8-4xc8-32-10 x {P} properties")
+
+
 def mnist_mlp_set(counts, seed: int = SEED_WEIGHTS, k: int = 4) -> WorkloadSet:
     """The 784-256x6-10 MLP with len(counts) properties (centre U[0,1]^784,
     eps 0.02 clipped to [0,1]), ``k`` splits per subdomain."""

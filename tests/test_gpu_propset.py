@@ -159,6 +159,24 @@ def test_property_set_cnn_matches_oracle_per_property():
         assert_close(H(out["lb"])[rows][fe], ref["lb"][fe], 1e-5, f"cnn lb of property {p}")
 
 
+def test_set_of_one_property_equals_its_root():
+    # a set of one takes the single-property launch paths (the host copy of
+    # its table entry): the same results as the root alone
+    ws = wl.mnist_mlp_set([23])
+    ps, ops, sps, perm, batch = _setup(ws)
+    out = gpipe.plain_pass(ps, batch, gpipe.PassConfig())
+    best, _ = gpipe.alpha_opt(ps, batch, out["l"], out["u"], out["infeasible"], steps=2, lr=0.1)
+    single = gpipe.Property(list(ws.net.layers), ws.lo0s[0], ws.hi0s[0], ws.Cs[0], ws.ts[0])
+    b1 = gpipe.make_batch(single, sps[0].neuron, sps[0].sign, sps[0].count)
+    o1 = gpipe.plain_pass(single, b1, gpipe.PassConfig())
+    best1, _ = gpipe.alpha_opt(single, b1, o1["l"], o1["u"], o1["infeasible"], steps=2, lr=0.1)
+    sync()
+    assert ps.P == 1
+    assert np.array_equal(H(out["lb"]), H(o1["lb"]))
+    assert np.array_equal(H(out["l"]), H(o1["l"]))
+    assert np.array_equal(H(best), H(best1))
+
+
 def test_rootset_rejects_single_root_queries():
     ws = wl.mnist_mlp_set([2, 2])
     ps = gpipe.PropertySet(list(ws.net.layers), ws.lo0s, ws.hi0s, ws.Cs, ws.ts)

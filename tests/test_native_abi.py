@@ -65,12 +65,24 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.cv_net_create(d2, 2, C.byref(out)) == -2
     d2[0].kind = 7
     assert lib.cv_net_create(d2, 2, C.byref(out)) == -1
+    # a conv as the last (objective) layer is not supported
+    d3 = (N.LayerDesc * 2)()
+    W0, b0 = np.zeros(48 * 4, np.float32), np.zeros(48, np.float32)
+    W1, b1 = np.zeros(2 * 3 * 9, np.float32), np.zeros(2, np.float32)
+    d3[0].kind, d3[0].in_features, d3[0].out_features = N.CV_LINEAR, 4, 48
+    d3[0].W, d3[0].b = W0.ctypes.data, b0.ctypes.data
+    d3[1].kind, d3[1].in_features, d3[1].out_features = N.CV_CONV2D, 48, 32
+    d3[1].in_c, d3[1].in_h, d3[1].in_w, d3[1].kernel, d3[1].stride, d3[1].pad = 3, 4, 4, 3, 1, 1
+    d3[1].out_c, d3[1].out_h, d3[1].out_w = 2, 4, 4
+    d3[1].W, d3[1].b = W1.ctypes.data, b1.ctypes.data
+    assert lib.cv_net_create(d3, 2, C.byref(out)) == -3
     assert lib.cv_clip_domains(None, None, -1, 4, None, None, None, None, 0, None) == -2
     assert lib.cv_clip_domains(None, None, 0, 4, None, None, None, None, 0, None) == 0  # B == 0
     assert lib.cv_clip_domains(None, None, 3, 4, None, None, None, None, 0, None) == -1
     assert lib.cv_concretize(None, None, 2, 2, 0, None, 0, None, None, None, None, 1, None, None,
                              None, None, None) == -2
     assert lib.cv_root_create(None, None, None, C.c_float(0.5), None, C.byref(out)) == -1
+    assert lib.cv_root_create_ex(None, None, None, C.c_float(0.5), 2, None, C.byref(out)) == -1
     n = C.c_size_t()
     assert lib.cv_bound_propagate_workspace(None, 1, 1, 1, C.byref(n)) == -1
     # property sets: no roots / a null member / P < 1
