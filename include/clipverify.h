@@ -130,7 +130,11 @@ typedef struct cv_root_s* cv_root;
  * intercepts float64, corrected at the root box centre and moved outward by
  * the rounding of the coefficients over the box radius, so the stored planes
  * are valid on the whole root box.
- * lo0, hi0: device [n_in].  Synchronises `stream` before returning. */
+ * lo0, hi0: device [n_in].  Synchronises `stream` before returning.  The
+ * pass's working memory (the backward-pass workspace of its widest layer,
+ * one row per neuron of that layer) stays on the net for the next root and
+ * is freed by cv_net_destroy, so roots of one net are created one at a time
+ * (not concurrently from several threads). */
 cv_status cv_root_create(cv_net net, const float* lo0, const float* hi0, float alpha0,
                          hipStream_t stream, cv_root* out);
 /* The same with a choice of which planes stay cached (the root pass computes

@@ -470,6 +470,7 @@ cv_status cv_net_destroy(cv_net net) {
       if (net->conv[i].Af) (void)hipFree(net->conv[i].Af);
     }
   }
+  if (net->root_ws) (void)hipFree(net->root_ws);
   delete net;
   return CV_OK;
 }
@@ -785,54 +786,52 @@ cv_status cv_root_create_ex(cv_net net, const float* lo0, const float* hi0, floa
     return fail(hip_fail(hipGetLastError()));
   if ((st = finish_layer(1))) return fail(st);
 
-  // deeper hidden layers: CROWN with objectives +I (lower) and -I (upper)
-  void* ws = nullptr;
-  float* lbtmp = nullptr;
-  auto cleanup = [&]() {
-    if (ws) (void)hipFree(ws);
-    if (lbtmp) (void)hipFree(lbtmp);
-  };
+  // deeper hidden layers: CROWN with objectives +I (lower) and -I (upper),
+  // in the net's cached working memory (sized for the largest layer once,
+  // then reused by every root of the net)
+  size_t need = 0;
   for (int i = 2; i <= L - 1; ++i) {
-    const int ni = net->n[i], off = net->off[i - 1];
-    if (!rows_fit(net, i, ni)) { cleanup(); return fail(CV_E_UNSUPPORTED); }
-    if ((st = make_vgemm(i))) { cleanup(); return fail(st); }
-    Bwd w;
-    const size_t bytes = bwd_layout(net, i, ni, ni, 1, true, false, nullptr, nullptr);
-    if (ws) (void)hipFree(ws);
-    ws = nullptr;
-    if (hipMalloc(&ws, bytes) != hipSuccess) { cleanup(); return fail(CV_E_NOMEM); }
-    bwd_layout(net, i, ni, ni, 1, true, false, ws, &w);
-    if (lbtmp) (void)hipFree(lbtmp);
-    lbtmp = nullptr;
-    if (dev_alloc(&lbtmp, ni)) {
-      cleanup();
+    if (!rows_fit(net, i, net->n[i])) return fail(CV_E_UNSUPPORTED);
+    need = std::max(need, bwd_layout(net, i, net->n[i], net->n[i], 1, true, false, nullptr,
+                                     nullptr) + (size_t)net->n[i] * 4 + 256);
+  }
+  if (need > net->root_ws_bytes) {
+    if (net->root_ws) (void)hipFree(net->root_ws);
+    net->root_ws = nullptr;
+    net->root_ws_bytes = 0;
+    if (hipMalloc(&net->root_ws, need) != hipSuccess) {
+      net->root_ws = nullptr;
       return fail(CV_E_NOMEM);
     }
+    net->root_ws_bytes = need;
+  }
+  for (int i = 2; i <= L - 1; ++i) {
+    const int ni = net->n[i], off = net->off[i - 1];
+    if ((st = make_vgemm(i))) return fail(st);
+    Bwd w;
+    const size_t used = bwd_layout(net, i, ni, ni, 1, true, false, net->root_ws, &w);
+    Carve cv((char*)net->root_ws + used);
+    float* lbtmp = cv.take<float>(ni);
     for (int side = 0; side < 2; ++side) {
-      if ((st = root_sync_tab(r))) { cleanup(); return fail(st); }
+      if ((st = root_sync_tab(r))) return fail(st);
       st = backward_run(net, r, props_of(r, nullptr), i, 1, ni, nullptr, nullptr, r->l0, r->u0,
                         nullptr, alpha0, r->lo0, r->hi0, nullptr, w, lbtmp, nullptr, nullptr, s,
                         side ? -1 : 1);
-      if (st) { cleanup(); return fail(st); }
+      if (st) return fail(st);
       float* Adst = (side ? r->A_hi : r->A_lo) + (size_t)off * n0;
       double* cdst = (side ? r->c_hi : r->c_lo) + off;
       if (launch_root_store_planes(ni, n0, w.Ax, w.rowc, w.rowerr, r->xc0, r->rad0, side, Adst,
-                                   cdst, s)) {
-        cleanup();
+                                   cdst, s))
         return fail(hip_fail(hipGetLastError()));
-      }
     }
     if (launch_concretize_rows(ni, n0, r->A_lo + (size_t)off * n0, r->c_lo + off, r->lo0, r->hi0,
                                0, r->l0 + off, s) ||
         launch_concretize_rows(ni, n0, r->A_hi + (size_t)off * n0, r->c_hi + off, r->lo0, r->hi0,
                                1, r->u0 + off, s) ||
-        hipStreamSynchronize(s)) {
-      cleanup();
+        hipStreamSynchronize(s))
       return fail(hip_fail(hipGetLastError()));
-    }
-    if ((st = finish_layer(i))) { cleanup(); return fail(st); }
+    if ((st = finish_layer(i))) return fail(st);
   }
-  cleanup();
   if ((st = make_vgemm(L))) return fail(st);
 
   // unstable / stable lists and the packed plane matrix

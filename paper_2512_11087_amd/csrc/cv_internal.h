@@ -43,6 +43,10 @@ struct cv_net_s {
   // for a conv layer), hK the kernel of a conv layer [co][ci][k][k] (empty
   // for a linear layer), hb the bias (conv: repeated over positions)
   std::vector<std::vector<float>> hW, hK, hb;
+  // working memory of the root pass, kept between cv_root_create calls on
+  // this net (grown as needed, freed with the net)
+  void* root_ws = nullptr;
+  size_t root_ws_bytes = 0;
 };
 
 // Device view of one property's root state: pointers into its cv_root_s.
