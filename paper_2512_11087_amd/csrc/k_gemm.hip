@@ -25,6 +25,7 @@
 // D[L/16 + 4v][L%16] (rows interleaved by 4, unlike the float32 variant).
 #include <type_traits>
 
+#include <algorithm>
 #include "cv_common.h"
 #include "cv_internal.h"
 
@@ -560,12 +561,16 @@ __device__ __forceinline__ void conv_stage(double* __restrict__ dst, const doubl
   __syncthreads();
 }
 
-template <class Epi, int CB, bool STAGE>
+// P positions per lane (lanes take consecutive positions, P groups of 64
+// apart): each weight a scalar load brings feeds P * CB FMAs and each wave
+// has P input loads in flight per step.
+template <class Epi, int CB, bool STAGE, int P>
 __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
   extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
   constexpr int NS = Epi::NSUM;
+  constexpr int CH = 64 * P;  // positions per task
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -577,12 +582,12 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
   const int nblk = (cd.ci + CB - 1) / CB;
   const auto w = epi.row(r);
   double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
-  // tasks: (block, parity class, chunk of 64 positions of that class)
+  // tasks: (block, parity class, chunk of CH positions of that class)
   int per_blk = 0;
   for (int cy = 0; cy < cd.s; ++cy)
     for (int cx = 0; cx < cd.s; ++cx) {
       const int ny = (cd.hi - cy + cd.s - 1) / cd.s, nx = (cd.wi - cx + cd.s - 1) / cd.s;
-      per_blk += (ny * nx + 63) / 64;
+      per_blk += (ny * nx + CH - 1) / CH;
     }
   const int ntask = per_blk * nblk;
   for (int task = wave; task < ntask; task += 4) {
@@ -593,48 +598,72 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
     for (int c = 0; c < cd.s * cd.s; ++c) {
       const int y = c / cd.s, x = c % cd.s;
       const int yy = (cd.hi - y + cd.s - 1) / cd.s, xx = (cd.wi - x + cd.s - 1) / cd.s;
-      const int nch = (yy * xx + 63) / 64;
+      const int nch = (yy * xx + CH - 1) / CH;
       if (rem < nch) {
         cy = y; cx = x; ny = yy; nx = xx;
         break;
       }
       rem -= nch;
     }
-    const int idx = rem * 64 + lane;
-    const bool live = idx < ny * nx;
-    const int iy = cy + cd.s * (live ? idx / nx : 0), ix = cx + cd.s * (live ? idx % nx : 0);
-    const int ci0 = blk * CB;
-    double acc[CB];
+    bool live[P];
+    int iy[P], ix[P];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int p = 0; p < P; ++p) {
+      const int idx = rem * CH + 64 * p + lane;
+      live[p] = idx < ny * nx;
+      iy[p] = cy + cd.s * (live[p] ? idx / nx : 0);
+      ix[p] = cx + cd.s * (live[p] ? idx % nx : 0);
+    }
+    const int ci0 = blk * CB;
+    double acc[P][CB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < CB; ++q) acc[p][q] = 0.0;
     const int ky0 = (cy + cd.p) % cd.s, kx0 = (cx + cd.p) % cd.s;
     for (int ky = ky0; ky < cd.k; ky += cd.s) {
-      const int oy = (iy + cd.p - ky) / cd.s;  // exact when >= 0: iy + p - ky = s * oy (same class)
-      const bool vy = live && iy + cd.p - ky >= 0 && oy < cd.ho;
       for (int kx = kx0; kx < cd.k; kx += cd.s) {
-        const int ox = (ix + cd.p - kx) / cd.s;
-        const bool v = vy && ix + cd.p - kx >= 0 && ox < cd.wo;
-        const int base = v ? oy * cd.wo + ox : 0;
+        int base[P];
+        bool v[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          // exact when >= 0: iy + p - ky = s * oy (same class)
+          const int oy = (iy[p] + cd.p - ky) / cd.s, ox = (ix[p] + cd.p - kx) / cd.s;
+          v[p] = live[p] && iy[p] + cd.p - ky >= 0 && oy < cd.ho && ix[p] + cd.p - kx >= 0 &&
+                 ox < cd.wo;
+          base[p] = v[p] ? oy * cd.wo + ox : 0;
+        }
         const conv_wptr wk = (conv_wptr)(cd.Wb + (ky * cd.k + kx) * cpad + ci0);
         const int wstep = cd.k * cd.k * cpad;
 #pragma unroll 2
         for (int co = 0; co < cd.co; ++co) {
-          const double x0 = src[co * (int)cin + base];
-          const double x = v ? x0 : 0.0;
+          double x[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const double x0 = src[co * (int)cin + base[p]];
+            x[p] = v[p] ? x0 : 0.0;
+          }
           const conv_wptr wq = wk + co * wstep;
 #pragma unroll
-          for (int q = 0; q < CB; ++q) acc[q] += x * wq[q];
+          for (int q = 0; q < CB; ++q) {
+            const double wv = wq[q];
+#pragma unroll
+            for (int p = 0; p < P; ++p) acc[p][q] += x[p] * wv;
+          }
         }
       }
     }
-    if (live) {
 #pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        const int ci = ci0 + q;
-        if (ci < cd.ci) {
-          const int c = (ci * cd.hi + iy) * cd.wi + ix;
-          const auto pre = epi.load(w, r, c);
-          epi.apply(w, pre, r, c, acc[q], sums);
+    for (int p = 0; p < P; ++p) {
+      if (live[p]) {
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+          const int ci = ci0 + q;
+          if (ci < cd.ci) {
+            const int c = (ci * cd.hi + iy[p]) * cd.wi + ix[p];
+            const auto pre = epi.load(w, r, c);
+            epi.apply(w, pre, r, c, acc[p][q], sums);
+          }
         }
       }
     }
@@ -644,12 +673,13 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
 
 // Forward convolution of each row (adjoint): out (co, oy, ox) =
 // sum over ci and taps of in (ci, oy*s - p + ky, ox*s - p + kx) * W (co, ci, ky, kx).
-template <class Epi, int CB, bool STAGE>
+template <class Epi, int CB, bool STAGE, int P>
 __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
   extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
   constexpr int NS = Epi::NSUM;
+  constexpr int CH = 64 * P;  // positions per task
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -659,45 +689,67 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
   const double* src = STAGE ? srow : row;
   const int cpad = cd.pfp;
   const int nblk = (cd.co + CB - 1) / CB;
-  const int npos = cd.ho * cd.wo, nchunk = (npos + 63) / 64;
+  const int npos = cd.ho * cd.wo, nchunk = (npos + CH - 1) / CH;
   const auto w = epi.row(r);
   double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
   for (int task = wave; task < nblk * nchunk; task += 4) {
     const int blk = task / nchunk, chunk = task % nchunk;
-    const int pos = chunk * 64 + lane;
-    const bool live = pos < npos;
-    const int oy = live ? pos / cd.wo : 0, ox = live ? pos % cd.wo : 0;
-    const int co0 = blk * CB;
-    double acc[CB];
+    bool live[P];
+    int oy[P], ox[P];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int p = 0; p < P; ++p) {
+      const int pos = chunk * CH + 64 * p + lane;
+      live[p] = pos < npos;
+      oy[p] = live[p] ? pos / cd.wo : 0;
+      ox[p] = live[p] ? pos % cd.wo : 0;
+    }
+    const int co0 = blk * CB;
+    double acc[P][CB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < CB; ++q) acc[p][q] = 0.0;
     for (int ky = 0; ky < cd.k; ++ky) {
-      const int iy = oy * cd.s - cd.p + ky;
-      const bool vy = live && iy >= 0 && iy < cd.hi;
       for (int kx = 0; kx < cd.k; ++kx) {
-        const int ix = ox * cd.s - cd.p + kx;
-        const bool v = vy && ix >= 0 && ix < cd.wi;
-        const int base = v ? iy * cd.wi + ix : 0;
+        int base[P];
+        bool v[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const int iy = oy[p] * cd.s - cd.p + ky, ix = ox[p] * cd.s - cd.p + kx;
+          v[p] = live[p] && iy >= 0 && iy < cd.hi && ix >= 0 && ix < cd.wi;
+          base[p] = v[p] ? iy * cd.wi + ix : 0;
+        }
         const conv_wptr wk = (conv_wptr)(cd.Wf + (ky * cd.k + kx) * cpad + co0);
         const int wstep = cd.k * cd.k * cpad;
 #pragma unroll 2
         for (int ci = 0; ci < cd.ci; ++ci) {
-          const double x0 = src[ci * (int)cin + base];
-          const double x = v ? x0 : 0.0;
+          double x[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            const double x0 = src[ci * (int)cin + base[p]];
+            x[p] = v[p] ? x0 : 0.0;
+          }
           const conv_wptr wq = wk + ci * wstep;
 #pragma unroll
-          for (int q = 0; q < CB; ++q) acc[q] += x * wq[q];
+          for (int q = 0; q < CB; ++q) {
+            const double wv = wq[q];
+#pragma unroll
+            for (int p = 0; p < P; ++p) acc[p][q] += x[p] * wv;
+          }
         }
       }
     }
-    if (live) {
 #pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        const int co = co0 + q;
-        if (co < cd.co) {
-          const int c = (co * cd.ho + oy) * cd.wo + ox;
-          const auto pre = epi.load(w, r, c);
-          epi.apply(w, pre, r, c, acc[q], sums);
+    for (int p = 0; p < P; ++p) {
+      if (live[p]) {
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+          const int co = co0 + q;
+          if (co < cd.co) {
+            const int c = (co * cd.ho + oy[p]) * cd.wo + ox[p];
+            const auto pre = epi.load(w, r, c);
+            epi.apply(w, pre, r, c, acc[p][q], sums);
+          }
         }
       }
     }
@@ -818,42 +870,84 @@ inline int conv_block(int ch, int tasks_per_block) {
   return cb;
 }
 
-template <class Epi, int CB>
-void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
-                     hipStream_t s) {
+// Positions per lane of a direct convolution: 2 where a block's positions
+// fill at least two full chunks of 64 per task and the accumulators stay
+// within 32 doubles, else 1 (blocks of one position each task would leave
+// lanes idle).  `per_blk64` counts a block's tasks at one position per lane.
+inline int conv_positions(int cb, int nblk, int npos_min, int per_blk64) {
+  if (cb * 2 <= 32 && npos_min >= 128 && nblk * ((per_blk64 + 1) / 2) >= 4) return 2;
+  return 1;
+}
+
+template <class Epi, int CB, int P>
+void launch_convt_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                    hipStream_t s) {
   const int n = cd.co * cd.ho * cd.wo;
   if (n <= CONV_STAGE_MAX)
-    hipLaunchKernelGGL((k_convt<Epi, CB, true>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
+    hipLaunchKernelGGL((k_convt<Epi, CB, true, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
                        epi, part, ntiles);
   else
-    hipLaunchKernelGGL((k_convt<Epi, CB, false>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
+    hipLaunchKernelGGL((k_convt<Epi, CB, false, P>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
+                       ntiles);
+}
+
+// variant 0: positions per lane by conv_positions; 1 or 2: that many.
+template <class Epi, int CB>
+void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s, int variant) {
+  // smallest stride-parity class and the tasks of a block at one position per lane
+  int per_blk = 0, cls_min = 1 << 30;
+  for (int cy = 0; cy < cd.s; ++cy)
+    for (int cx = 0; cx < cd.s; ++cx) {
+      const int ncls = ((cd.hi - cy + cd.s - 1) / cd.s) * ((cd.wi - cx + cd.s - 1) / cd.s);
+      per_blk += (ncls + 63) / 64;
+      cls_min = std::min(cls_min, ncls);
+    }
+  const int P = variant == 1 ? 1 : variant == 2 ? 2
+                                  : conv_positions(CB, (cd.ci + CB - 1) / CB, cls_min, per_blk);
+  if (P == 2)
+    launch_convt_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
+  else
+    launch_convt_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
+}
+
+template <class Epi, int CB, int P>
+void launch_convf_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                    hipStream_t s) {
+  const int n = cd.ci * cd.hi * cd.wi;
+  if (n <= CONV_STAGE_MAX)
+    hipLaunchKernelGGL((k_convf<Epi, CB, true, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
+                       epi, part, ntiles);
+  else
+    hipLaunchKernelGGL((k_convf<Epi, CB, false, P>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
                        ntiles);
 }
 
 template <class Epi, int CB>
 void launch_convf_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s) {
-  const int n = cd.ci * cd.hi * cd.wi;
-  if (n <= CONV_STAGE_MAX)
-    hipLaunchKernelGGL((k_convf<Epi, CB, true>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
-                       epi, part, ntiles);
+  const int npos = cd.ho * cd.wo;
+  if (conv_positions(CB, (cd.co + CB - 1) / CB, npos, (npos + 63) / 64) == 2)
+    launch_convf_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
   else
-    hipLaunchKernelGGL((k_convf<Epi, CB, false>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
-                       ntiles);
+    launch_convf_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
 }
 
+// Transposed convolution; variant (autotuner) 0: positions per lane by the
+// shape heuristic, 1/2: one or two positions per lane.  Every variant
+// accumulates each output in the same order.
 template <class Epi>
 hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
-                     hipStream_t s) {
+                     hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
   int per_blk = 0;
   for (int cy = 0; cy < cd.s; ++cy)
     for (int cx = 0; cx < cd.s; ++cx)
       per_blk += (((cd.hi - cy + cd.s - 1) / cd.s) * ((cd.wi - cx + cd.s - 1) / cd.s) + 63) / 64;
   switch (conv_block(cd.ci, per_blk)) {
-    case 4: launch_convt_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s); break;
-    case 8: launch_convt_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s); break;
-    default: launch_convt_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s); break;
+    case 4: launch_convt_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, variant); break;
+    case 8: launch_convt_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, variant); break;
+    default: launch_convt_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, variant); break;
   }
   return hipGetLastError();
 }
@@ -955,12 +1049,12 @@ hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float*
   if (props.host) {  // one property: its error weight for every row
     EpiRelax<false> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props.host->wrel[layer], props,
                       layer, Om_out, N, trace};
-    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
     return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
   }
   EpiRelax<true> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, nullptr, props, layer, Om_out, N,
                    trace};
-  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
   return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
@@ -970,11 +1064,11 @@ hipError_t launch_gemm_final(int R, int K, int N, const double* Om, const float*
                              float* A_out, double* part, int variant, hipStream_t s) {
   if (props.host) {
     EpiFinal<false> e{M, N, lo, hi, props.host->X0, props, Ax, A_out};
-    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+    if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
     return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
   }
   EpiFinal<true> e{M, N, lo, hi, nullptr, props, Ax, A_out};
-  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s);
+  if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
   return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 

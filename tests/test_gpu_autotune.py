@@ -1,7 +1,7 @@
-"""Kernel variants (GEMM tiles, convolution channel blocks) and the
-autotuner that picks among them: every variant of every layer must give
-bit-identical bounds, gradients and slope updates, so tuning never changes
-a result."""
+"""Kernel variants (GEMM tiles, convolution channel blocks and positions
+per lane) and the autotuner that picks among them: every variant of every
+layer must give bit-identical bounds, gradients and slope updates, so tuning
+never changes a result."""
 import numpy as np
 import pytest
 
@@ -16,8 +16,9 @@ def H(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("make", [lambda: wl.mnist_mlp(B=96), lambda: wl.ragged_cnn(B=40)],
-                         ids=["mlp784-256x6-10", "cnn5x9x7"])
+@pytest.mark.parametrize("make", [lambda: wl.mnist_mlp(B=96), lambda: wl.ragged_cnn(B=40),
+                                  lambda: wl.small_conv4_set().member(0)],
+                         ids=["mlp784-256x6-10", "cnn5x9x7", "cnn3x8x8-4xc8"])
 def test_every_kernel_variant_gives_identical_results(make):
     w = make()
     prop = gpipe.Property.from_workload(w)
