@@ -99,8 +99,9 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
  * CV_TUNE_ADJOINT (1 <= layer <= n_layers-1): the output tile of the GEMM
  * (0: 32 x 128, 1: 64 x 128, 2: 128 x 128 rows x columns; the adjoint also
  * 3: 32 x 256) or, for the adjoint's forward convolution, the vector kernel
- * with a channel block (0: built-in, 1/2/3: 4/8/16 channels) or the
- * matrix-core kernel (4; layers with at least 16 output channels); a
+ * with a channel block (0: built-in, 1/2/3: 4/8/16 channels; 4/5: 8/16
+ * channels with four output positions per lane) or the matrix-core kernel
+ * (6; layers with at least 16 output channels); a
  * transposed convolution (CV_TUNE_RELAX / CV_TUNE_FINAL of a conv layer) the
  * output positions per lane (0: by shape, 1 or 2).  Every variant gives the
  * same results (the same accumulation order per element).

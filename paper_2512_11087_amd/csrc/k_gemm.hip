@@ -925,9 +925,12 @@ void launch_convf_p(int R, const ConvDesc& cd, const double* in, Epi epi, double
 
 template <class Epi, int CB>
 void launch_convf_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
-                     hipStream_t s) {
+                     hipStream_t s, int P = 0) {
   const int npos = cd.ho * cd.wo;
-  if (conv_positions(CB, (cd.co + CB - 1) / CB, npos, (npos + 63) / 64) == 2)
+  if (P == 0) P = conv_positions(CB, (cd.co + CB - 1) / CB, npos, (npos + 63) / 64);
+  if (P == 4)
+    launch_convf_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
+  else if (P == 2)
     launch_convf_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
   else
     launch_convf_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
@@ -953,23 +956,27 @@ hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
 }
 
 // variant: 0 the vector kernel with the block size of conv_block, 1/2/3
-// with blocks of 4/8/16 channels, 4 the matrix-core kernel (where the layer
-// has one).  The forward convolution has no row sums and every variant
-// accumulates each output in the same order, so the choice changes no result.
+// with blocks of 4/8/16 channels (positions per lane by shape), 4/5 blocks
+// of 8/16 channels with four positions per lane, 6 the matrix-core kernel
+// (where the layer has one).  The forward convolution has no row sums and
+// every variant accumulates each output in the same order, so the choice
+// changes no result.
 template <class Epi>
 hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
-  if (variant == 4 && cd.mf) {
+  if (variant == 6 && cd.mf) {
     launch_convf_mfma(R, cd, in, epi, s);
     return hipGetLastError();
   }
-  const int cb = variant == 1 ? 4 : variant == 2 ? 8 : variant == 3 ? 16
-                                                                     : conv_block(cd.co, (cd.ho * cd.wo + 63) / 64);
+  const int cb = variant == 1 ? 4 : (variant == 2 || variant == 4) ? 8
+                                  : (variant == 3 || variant == 5) ? 16
+                                                                   : conv_block(cd.co, (cd.ho * cd.wo + 63) / 64);
+  const int P = variant >= 4 ? 4 : 0;
   switch (cb) {
-    case 4: launch_convf_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s); break;
-    case 8: launch_convf_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s); break;
-    default: launch_convf_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s); break;
+    case 4: launch_convf_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, P); break;
+    case 8: launch_convf_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, P); break;
+    default: launch_convf_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, P); break;
   }
   return hipGetLastError();
 }
