@@ -310,6 +310,63 @@ class AlphaOptGraph:
         return self.best
 
 
+class StepGraph:
+    """One whole step -- reset the boxes to ``lo0``/``hi0``, the plain pass
+    (clipping, plane re-concretization, bound with complete clipping) and
+    ``steps`` slope iterations -- captured once into a HIP graph and replayed.
+    The calls only launch kernels into buffers allocated by an eager warm-up
+    run (workspaces, outputs, slope state), so the graph holds the step's
+    whole launch sequence.  ``run()`` returns (out, best): the plain pass's
+    dict (infeasible, l, u, lb) and the best bound over the iterations; both
+    are buffers the graph rewrites on every replay."""
+
+    def __init__(self, prop, batch, lo0, hi0, steps=20, lr=0.1, decay=1.0, cfg=PassConfig()):
+        self.prop, self.batch, self.lo0, self.hi0 = prop, batch, lo0, hi0
+        B, M, nh = batch.lo.shape[0], prop.M, prop.net.n_hidden
+        self.out = {}
+        self.alpha = torch.full((B, M, nh), cfg.alpha, device="cuda")
+        self.m = torch.zeros_like(self.alpha)
+        self.v = torch.zeros_like(self.alpha)
+        self.best = torch.full((B, M), -float("inf"), device="cuda")
+        self.lbs = [torch.empty(B, M, device="cuda") for _ in range(steps)]
+
+        def body():
+            batch.lo.copy_(lo0)
+            batch.hi.copy_(hi0)
+            out = plain_pass(prop, batch, cfg, out=self.out)
+            cons = batch.cons() if cfg.complete_final else None
+            self.alpha.fill_(cfg.alpha)
+            self.m.fill_(0.0)
+            self.v.fill_(0.0)
+            self.best.fill_(-float("inf"))
+            for s in range(1, steps + 1):
+                api.alpha_step_into(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"],
+                                    self.alpha, batch.lo, batch.hi, out["infeasible"], cons,
+                                    cfg.passes, self.m, self.v, s, lr * decay ** (s - 1),
+                                    self.lbs[s - 1], prop.ws, pid=batch.pid)
+                torch.maximum(self.best, self.lbs[s - 1], out=self.best)
+
+        # eager warm-up: sizes every workspace and output buffer
+        out = plain_pass(prop, batch, cfg, out=self.out)
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], self.alpha,
+                       batch.lo, batch.hi, out["infeasible"],
+                       batch.cons() if cfg.complete_final else None, cfg.passes, self.m, self.v, 1,
+                       0.0, ws=prop.ws, pid=batch.pid)
+        body()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(self.graph, stream=side):
+                body()
+        torch.cuda.current_stream().wait_stream(side)
+
+    def run(self):
+        self.graph.replay()
+        return self.out, self.best
+
+
 def chunked_verify(prop, batch, chunk, steps=10, lr=0.1, cfg=PassConfig(), state=None):
     """The plain pass and ``steps`` slope iterations over a batch too large
     for one call (the per-row matrices of a wide network), in consecutive

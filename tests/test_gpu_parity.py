@@ -626,6 +626,36 @@ def test_input_pass_matches_oracle():
                                         ref["lb_unclipped"][~ref["infeasible"]] + 1e-6).any()
 
 
+def test_step_graph_replays_match_eager():
+    # the whole step (box reset, plain pass, slope iterations) captured once,
+    # replayed several times with eager work in between: the eager step's
+    # boxes, intermediate bounds, plain bound and best bound every time
+    w = wl.mnist_mlp(B=160)
+    prop = gpipe.Property.from_workload(w)
+    l0, u0 = (H(x) for x in prop.root.bounds())
+    cand = np.nonzero((l0 < 0) & (u0 > 0))[0]
+    sp = wl.draw_splits(w.B, w.split_counts, cand)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    lo0, hi0 = batch.lo.clone(), batch.hi.clone()
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    best_e, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=5,
+                                lr=0.1)
+    ref = [H(x).copy() for x in (batch.lo, batch.hi, out["l"], out["u"], out["lb"],
+                                 out["infeasible"], best_e)]
+    g = gpipe.StepGraph(prop, batch, lo0, hi0, steps=5, lr=0.1)
+    for rep in range(3):
+        o, best = g.run()
+        sync()
+        got = [H(x).copy() for x in (batch.lo, batch.hi, o["l"], o["u"], o["lb"], o["infeasible"],
+                                     best)]
+        for a, b, name in zip(ref, got, ("lo", "hi", "l", "u", "lb", "infeasible", "best")):
+            assert np.array_equal(a, b), f"replay {rep}: {name}"
+        # unrelated eager work between replays, on other buffers
+        b2 = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+        gpipe.alpha_opt(prop, b2, out["l"], out["u"], out["infeasible"], steps=2, lr=0.3)
+        sync()
+
+
 def test_alpha_opt_graph_replays_match_eager():
     # the captured slope optimisation, replayed several times with eager work
     # in between, gives the eager result bit for bit every time
