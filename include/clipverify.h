@@ -101,10 +101,10 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
  * 3: 32 x 256) or, for the adjoint's forward convolution, the vector kernel
  * with a channel block (0: built-in, 1/2/3: 4/8/16 channels; 4/5: 8/16
  * channels with four output positions per lane) or the matrix-core kernel
- * (6; layers with at least 16 output channels); a
- * transposed convolution (CV_TUNE_RELAX / CV_TUNE_FINAL of a conv layer) the
- * output positions per lane (0: by shape, 1 or 2).  Every variant gives the
- * same results (the same accumulation order per element).
+ * (6; layers with at least 16 output channels); for a transposed
+ * convolution (CV_TUNE_RELAX / CV_TUNE_FINAL of a conv layer) the output
+ * positions per lane (0: by shape, 1: one, 2: two, 3: four).  Every variant
+ * gives the same results (the same accumulation order per element).
  * cv_net_autotune times each variant of every layer once on synthetic
  * operands of B subdomains x M objective rows (allocating its own scratch,
  * synchronising `stream`) and keeps the fastest; the choice then applies to

@@ -481,7 +481,7 @@ cv_status cv_net_destroy(cv_net net) {
 // convolutions one (their row sums depend on the block).
 static int tune_variants(const cv_net_s* net, int kind, int layer) {
   if (net->is_conv[layer - 1])
-    return kind == CV_TUNE_ADJOINT ? (net->conv[layer - 1].mf ? 7 : 6) : 3;
+    return kind == CV_TUNE_ADJOINT ? (net->conv[layer - 1].mf ? 7 : 6) : 4;
   return kind == CV_TUNE_ADJOINT ? 4 : 3;
 }
 

@@ -891,7 +891,7 @@ void launch_convt_p(int R, const ConvDesc& cd, const double* in, Epi epi, double
                        ntiles);
 }
 
-// variant 0: positions per lane by conv_positions; 1 or 2: that many.
+// variant 0: positions per lane by conv_positions; 1, 2, 3: one, two, four.
 template <class Epi, int CB>
 void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant) {
@@ -903,9 +903,11 @@ void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
       per_blk += (ncls + 63) / 64;
       cls_min = std::min(cls_min, ncls);
     }
-  const int P = variant == 1 ? 1 : variant == 2 ? 2
+  const int P = variant == 1 ? 1 : variant == 2 ? 2 : variant == 3 ? 4
                                   : conv_positions(CB, (cd.ci + CB - 1) / CB, cls_min, per_blk);
-  if (P == 2)
+  if (P == 4)
+    launch_convt_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
+  else if (P == 2)
     launch_convt_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
   else
     launch_convt_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
@@ -937,7 +939,7 @@ void launch_convf_cb(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
 }
 
 // Transposed convolution; variant (autotuner) 0: positions per lane by the
-// shape heuristic, 1/2: one or two positions per lane.  Every variant
+// shape heuristic, 1/2/3: one, two or four positions per lane.  Every variant
 // accumulates each output in the same order.
 template <class Epi>
 hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
