@@ -79,6 +79,23 @@ class Net:
         """From an object with ``.layers`` (see the class docstring)."""
         return cls(list(net.layers))
 
+    def max_batch(self, M, P=1):
+        """Largest number of subdomains with M objective rows that one
+        bound_propagate / alpha_step call takes for this network (the
+        library's own size check, asked by bisection; host only)."""
+        need = C.c_size_t()
+        ok = lambda B: N.lib().cv_alpha_step_workspace(self.handle, P, B, M, C.byref(need)) == 0
+        lo, hi = 1, 1 << 30
+        if not ok(lo):
+            return 0
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if ok(mid):
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
+
     TUNE_KINDS = {"relax": N.CV_TUNE_RELAX, "final": N.CV_TUNE_FINAL,
                   "adjoint": N.CV_TUNE_ADJOINT}
 

@@ -370,12 +370,15 @@ class StepGraph:
 def chunked_verify(prop, batch, chunk, steps=10, lr=0.1, cfg=PassConfig(), state=None):
     """The plain pass and ``steps`` slope iterations over a batch too large
     for one call (the per-row matrices of a wide network), in consecutive
-    chunks of at most ``chunk`` subdomains.  Subdomains are independent, so
-    every result equals that of one call over the whole batch.  Boxes are
+    chunks of at most ``chunk`` subdomains (0 or None: the most one call
+    takes, ``Net.max_batch``).  Subdomains are independent, so every result
+    equals that of one call over the whole batch.  Boxes are
     clipped in place.  Returns dict(infeasible [B], lb [B, M] plain bound,
     best [B, M] best bound over the slope iterations (the plain bound when
     steps = 0)).  ``state`` keeps the per-chunk buffers between calls."""
     B, M = batch.lo.shape[0], prop.M
+    if not chunk:
+        chunk = prop.net.max_batch(M, prop.P)
     state = state if state is not None else {}
     res = state.get("res")
     if res is None or res["lb"].shape[0] != B:

@@ -122,6 +122,18 @@ def test_full_size_conv64_roots_chunks_and_soundness():
     sync()
     with pytest.raises(Exception):
         ps.roots[0].planes()
+    # size limits: one call takes at most 2^31 / 102912 rows (2318 subdomains
+    # of 9 rows); beyond, the workspace query and the call refuse (no launch)
+    from paper_2512_11087_amd import _native as N
+    import ctypes as C
+    assert ps.net.max_batch(9) == (2 ** 31 - 1) // (9 * 102912)
+    n = C.c_size_t()
+    assert N.lib().cv_alpha_step_workspace(ps.net.handle, 2, 4096, 9, C.byref(n)) == -3
+    assert N.lib().cv_bound_propagate_workspace(ps.net.handle, 2, 2318, 9, C.byref(n)) == 0
+    # an unknown plane mode is refused
+    h = C.c_void_p()
+    assert N.lib().cv_root_create_ex(ps.net.handle, api._p(ps.roots[0].lo0), api._p(ps.roots[0].hi0),
+                                     C.c_float(0.5), 7, None, C.byref(h)) == -1
 
     # root bounds: every layer-1 neuron and 24 layer-2 neurons of each
     # property against the oracle (layer 2: CROWN with objective e_j over
