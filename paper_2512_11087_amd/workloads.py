@@ -352,6 +352,22 @@ def wide_cnn(B: int = 32, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
     return Workload("cnn4x24x24-c16-c8-10-3", net, lo, hi, C, t, B, counts.astype(np.int32))
 
 
+def edge_cnn(B: int = 48, seed: int = SEED_WEIGHTS, depth=(1, 6)) -> Workload:
+    """Convolution edge cases: 3x7x7 -> conv 4 (1x1, stride 2, pad 0: in the
+    transposed convolution the odd positions take no tap at all) -> conv 5
+    (2x2, stride 2, pad 0: non-overlapping taps) -> conv 3 (3x3, stride 1,
+    pad 2: the output grows) -> linear 6 -> linear 3, uniform biases; box =
+    centre U[-1,1]^147 +- 0.05, the 3 outputs as objectives."""
+    net = he_cnn((3, 7, 7), [(4, 1, 2, 0), (5, 2, 2, 0), (3, 3, 1, 2)], [6, 3], seed,
+                 bias="uniform")
+    c = centres(147, 1, -1.0, 1.0)[0]
+    lo, hi = box_around(c, 0.05)
+    C, t = identity_spec(3)
+    counts = np.random.default_rng(SEED_SIZES).integers(depth[0], depth[1] + 1, size=B)
+    return Workload("cnn3x7x7-c4k1s2-c5k2s2-c3k3p2-6-3", net, lo, hi, C, t, B,
+                    counts.astype(np.int32))
+
+
 @dataclass
 class WorkloadSet:
     """Several properties over one network (own box centre, label and

@@ -17,8 +17,9 @@ def H(t):
 
 
 @pytest.mark.parametrize("make", [lambda: wl.mnist_mlp(B=96), lambda: wl.ragged_cnn(B=40),
-                                  lambda: wl.small_conv4_set().member(0)],
-                         ids=["mlp784-256x6-10", "cnn5x9x7", "cnn3x8x8-4xc8"])
+                                  lambda: wl.small_conv4_set().member(0),
+                                  lambda: wl.edge_cnn(B=40)],
+                         ids=["mlp784-256x6-10", "cnn5x9x7", "cnn3x8x8-4xc8", "cnn3x7x7-edge"])
 def test_every_kernel_variant_gives_identical_results(make):
     w = make()
     prop = gpipe.Property.from_workload(w)
