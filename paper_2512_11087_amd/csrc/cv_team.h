@@ -23,6 +23,12 @@ struct WaveTeam {
   __device__ void sum3(double& a, double& b, double& c) const { wave_sum3(a, b, c); }
   __device__ double max(double v) const { return wave_max(v); }
   __device__ double min(double v) const { return wave_min(v); }
+  // two maxima and a sum in one pass
+  __device__ void max_max_sum(double& a, double& b, double& c) const {
+    a = wave_max(a);
+    b = wave_max(b);
+    c = wave_sum(c);
+  }
   // member k < cnt holds constraint k's row pointer, scale and offset
   __device__ void publish(const float*, float, double, int) const {}
   __device__ void meta(const float* my_row, float my_scale, double my_h, int k, const float*& row,
@@ -80,6 +86,23 @@ struct BlockTeam {
     if ((t & 63) == 0) rb[t >> 6] = v;
     __syncthreads();
     return fmax(fmax(rb[0], rb[1]), fmax(rb[2], rb[3]));
+  }
+  // two maxima and a sum through one barrier (each combined as max, max
+  // and sum would combine it)
+  __device__ void max_max_sum(double& a, double& b, double& c) const {
+    double* rb = next_bank();
+    a = wave_max(a);
+    b = wave_max(b);
+    c = wave_sum(c);
+    if ((t & 63) == 0) {
+      rb[t >> 6] = a;
+      rb[4 + (t >> 6)] = b;
+      rb[8 + (t >> 6)] = c;
+    }
+    __syncthreads();
+    a = fmax(fmax(rb[0], rb[1]), fmax(rb[2], rb[3]));
+    b = fmax(fmax(rb[4], rb[5]), fmax(rb[6], rb[7]));
+    c = (rb[8] + rb[9]) + (rb[10] + rb[11]);
   }
   __device__ double min(double v) const {
     double* rb = next_bank();

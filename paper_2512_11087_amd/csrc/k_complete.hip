@@ -43,19 +43,12 @@ constexpr int CA_KMAX = CV_TEAM_KMAX;
 // The breakpoints and weights sit in the team's LDS slice (element e of
 // member t at e*T + t; non-candidates hold -inf), which keeps them out of the
 // registers of the common path that needs no search.
+// qmax, qmin: the largest and smallest candidate (team-wide), wpos the sum
+// of the candidates' weights.
 template <class Team, int EPL>
 __device__ double ca_select(const Team& tm, const double* sq, const float* sw, double S,
-                            double wpos) {
+                            double wpos, double qmax, double qmin) {
   constexpr int T = Team::SIZE;
-  double qmax = -INFINITY, qmin = INFINITY;
-#pragma unroll
-  for (int e = 0; e < EPL; ++e) {
-    const double q = sq[e * T + tm.t];
-    qmax = fmax(qmax, q);
-    if (q > 0.0) qmin = fmin(qmin, q);
-  }
-  qmax = tm.max(qmax);
-  qmin = tm.min(qmin);
   unsigned long long blo = (unsigned long long)__double_as_longlong(qmin) - 1ull;
   unsigned long long bhi = (unsigned long long)__double_as_longlong(qmax) + 1ull;
   double wlo = wpos, whi = 0.0;  // W(> lo), W(>= hi)
@@ -83,7 +76,8 @@ __device__ double ca_select(const Team& tm, const double* sq, const float* sw, d
       blo += off;
       continue;
     }
-    double wg = 0.0, wge = 0.0;
+    // W(> p) and W(>= p) in one reduction
+    double wg = 0.0, wge = 0.0, zero = 0.0;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const double q = sq[e * T + tm.t];
@@ -91,13 +85,12 @@ __device__ double ca_select(const Team& tm, const double* sq, const float* sw, d
       if (q > p) wg += w;
       if (q >= p) wge += w;
     }
-    wg = tm.sum(wg);
+    tm.sum3(wg, wge, zero);
     if (wg > S) {  // q* > p, and nothing lies in (p, mv]
       blo += off;
       wlo = wg;
       continue;
     }
-    wge = tm.sum(wge);
     if (wge > S) return p;
     bhi = (unsigned long long)__double_as_longlong(p);
     whi = wge;
@@ -218,7 +211,8 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       if (wsg > S) {
         // breakpoints and the exact candidate set (a division may underflow
         // to q = 0, which is not a candidate), staged in LDS for the search
-        double wpos = 0.0;
+        // the candidates' total weight and their range, reduced together
+        double wpos = 0.0, qmax = -INFINITY, nqmin = -INFINITY;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           double qe = -INFINITY;
@@ -230,13 +224,15 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
               qe = q;
               we = w;
               wpos += (double)w;
+              qmax = fmax(qmax, q);
+              nqmin = fmax(nqmin, -q);
             }
           }
           sq[e * T + t] = qe;
           sw[e * T + t] = we;
         }
-        wpos = tm.sum(wpos);
-        if (wpos > S) bk = ca_select<Team, EPL>(tm, sq, sw, S, wpos);
+        tm.max_max_sum(qmax, nqmin, wpos);
+        if (wpos > S) bk = ca_select<Team, EPL>(tm, sq, sw, S, wpos, qmax, -nqmin);
       }
       beta[k] = bk;
       if (bk != 0.0) {
