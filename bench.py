@@ -137,7 +137,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU; the batch shards over subdomains across "
+        print("bench.py: measures one GPU; the batch shards over subdomains across "
               "GPUs but no multi-GPU path is built, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 

@@ -31,7 +31,7 @@
  *   +inf lower bounds (case 1 of the proof of Thm 3.1).
  * - Handles are immutable after creation: concurrent calls on different
  *   streams may share them; calls sharing one workspace must not overlap.
- * - Limits of this build: input dimension n <= 4096 and, for complete
+ * - Limits of this library: input dimension n <= 4096 and, for complete
  *   clipping and the constraint order, kmax <= 64 (CV_E_UNSUPPORTED beyond).
  */
 #ifndef CLIPVERIFY_H
@@ -49,7 +49,7 @@ typedef enum {
   CV_OK = 0,
   CV_E_INVALID = -1,     /* null pointer / invalid value (e.g. alpha outside [0,1]) */
   CV_E_SHAPE = -2,       /* sizes inconsistent with the handle or each other */
-  CV_E_UNSUPPORTED = -3, /* valid request this build does not implement */
+  CV_E_UNSUPPORTED = -3, /* valid request this library does not implement */
   CV_E_WORKSPACE = -4,   /* ws_bytes smaller than the reported requirement */
   CV_E_HIP = -5,         /* a HIP runtime call failed (see cv_last_hip_error) */
   CV_E_NOMEM = -6        /* device allocation inside a create call failed */

@@ -1,6 +1,6 @@
 """FP64 CPU oracle for the clip-and-verify hot path (test infrastructure).
 
-This package is the reference that the GPU path is judged against.  It is a
+This package is the reference that the GPU path is checked against.  It is a
 plain, slow, float64 NumPy restatement of what the paper (Clip-and-Verify:
 linear constraint-driven domain clipping, arXiv 2512.11087) computes:
 

@@ -197,7 +197,7 @@ def test_rootset_rejects_single_root_queries():
 
 
 def test_full_size_cnn_set_bench_schedule_sampled():
-    # config 3's batching as bench.py times it: the CIFAR CNN with 64 properties
+    # the 64-property batching as bench.py times it: the CIFAR CNN with 64 properties
     # (32414 subdomains, Geometric(0.002) counts, split depth 1..12), one plain
     # pass and 20 slope iterations over the whole set; the oracle repeats the
     # schedule on sampled subdomains of sampled properties (a subdomain's
