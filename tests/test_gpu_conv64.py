@@ -107,6 +107,55 @@ def test_small_conv4_set_unstable_planes_match_oracle():
     assert np.array_equal(H(b_ch.lo), H(batch.lo))
 
 
+def test_unstable_planes_ignore_splits_of_stable_neurons():
+    # a root that keeps only its unstable neurons' planes drops a split on a
+    # root-stable neuron (no plane to clip with): the result is the oracle's
+    # for the same subdomains without those splits (intermediate-bound fixes
+    # of the split neuron still apply, as they need no plane)
+    ws = wl.small_conv4_set(P=1, B=40)
+    w = ws.member(0)
+    op = OracleProp(w)
+    prop = gpipe.Property(list(w.net.layers), w.lo0, w.hi0, w.C, w.t, planes="unstable")
+    un = op.unstable()
+    stable = np.setdiff1d(np.arange(w.net.n_hidden), un)
+    sp = wl.draw_splits(w.B, np.minimum(w.split_counts, 4), un, seed=77, kmax=5)
+    # append one stable-neuron split (with the sign of its fixed regime, so
+    # the subdomain stays non-empty) to every subdomain
+    rng = np.random.default_rng(78)
+    for b in range(w.B):
+        j = int(rng.choice(stable))
+        k = int(sp.count[b])
+        sp.neuron[b, k] = j
+        sp.sign[b, k] = 1 if op.l0[j] >= 0 else -1
+        sp.count[b] = k + 1
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    sync()
+    ref = op.run(sp)            # every split, the stable ones included
+    keep = sp.neuron.copy()     # the same lists without the stable-neuron splits
+    cnt = sp.count.copy()
+    for b in range(w.B):
+        k = int(cnt[b]) - 1
+        keep[b, k] = -1
+        cnt[b] = k
+    ref_drop = op.run(wl.Splits(keep, sp.sign, cnt))
+    fe = ~ref_drop["infeasible"]
+    assert not (H(out["infeasible"]).astype(bool) & ~ref_drop["infeasible"]).any()
+    assert_close(H(batch.lo)[fe], ref_drop["lo"][fe], 1e-5, "lo without the stable splits")
+    assert_close(H(out["lb"])[fe], ref_drop["lb"][fe], 1e-5, "lb without the stable splits")
+    # a stable neuron's split in its own regime clips nothing either way
+    assert_close(ref["lb"][fe], ref_drop["lb"][fe], 1e-9, "oracle: the regime split is redundant")
+    # and a root keeping every plane (which applies those splits) gives the
+    # same GPU results bit for bit
+    prop_all = gpipe.Property(list(w.net.layers), w.lo0, w.hi0, w.C, w.t, planes="all")
+    b_all = gpipe.make_batch(prop_all, sp.neuron, sp.sign, sp.count)
+    o_all = gpipe.plain_pass(prop_all, b_all, gpipe.PassConfig())
+    sync()
+    assert np.array_equal(H(o_all["lb"]), H(out["lb"]))
+    assert np.array_equal(H(b_all.lo), H(batch.lo)) and np.array_equal(H(b_all.hi), H(batch.hi))
+    assert np.array_equal(H(o_all["infeasible"]), H(out["infeasible"]))
+
+
 def test_full_size_conv64_roots_chunks_and_soundness():
     ws = wl.cifar_conv64_set(256)
     net = ws.net
