@@ -177,6 +177,25 @@ def test_set_of_one_property_equals_its_root():
     assert np.array_equal(H(best), H(best1))
 
 
+def test_property_set_step_graph_replays_match_eager():
+    # many properties through one captured graph: the whole step (box reset,
+    # plain pass, slope iterations) over a 3-property set, replayed, equals
+    # the eager step bit for bit
+    ws = wl.mnist_mlp_set([30, 7, 19])
+    ps, ops, sps, perm, batch = _setup(ws, order_seed=9)
+    lo0, hi0 = batch.lo.clone(), batch.hi.clone()
+    out = gpipe.plain_pass(ps, batch, gpipe.PassConfig())
+    best_e, _ = gpipe.alpha_opt(ps, batch, out["l"], out["u"], out["infeasible"], steps=4, lr=0.1)
+    ref = [H(x).copy() for x in (batch.lo, out["l"], out["lb"], best_e)]
+    g = gpipe.StepGraph(ps, batch, lo0, hi0, steps=4, lr=0.1)
+    for rep in range(2):
+        o, best = g.run()
+        sync()
+        got = [H(x).copy() for x in (batch.lo, o["l"], o["lb"], best)]
+        for a, b, name in zip(ref, got, ("lo", "l", "lb", "best")):
+            assert np.array_equal(a, b), f"replay {rep}: {name}"
+
+
 def test_rootset_rejects_single_root_queries():
     ws = wl.mnist_mlp_set([2, 2])
     ps = gpipe.PropertySet(list(ws.net.layers), ws.lo0s, ws.hi0s, ws.Cs, ws.ts)
