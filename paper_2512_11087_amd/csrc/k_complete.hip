@@ -145,6 +145,10 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       double h;
       tm.meta(my_row, my_scale, my_h, k, row, scale, h);
       if (!row) continue;
+      // the shared statistics of this (subdomain, constraint), loaded first so
+      // their latency overlaps the row's
+      double2 st = make_double2(0.0, 0.0);
+      if (cons->kstats) st = cons->kstats[(size_t)b * cons->kmax + k];
       const cv_buf brow = cv_buffer(row, 4u * n);
       int vb = 4 * t;
       cv_opaque(vb);
@@ -166,18 +170,19 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       // weight exceeds -m, i.e. when beta* > 0 is possible.  The weights only
       // steer the choice of beta, so float32 suffices (any beta >= 0 is valid).
       // (products of float32 values are exact in float64, so
-      // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly)
+      // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly;
+      // the opposite-sign test is branch-free, and a skipped weight adds +0.0
+      // to a non-negative sum, which leaves it unchanged)
       double m = 0.0, em = 0.0, wsg = 0.0;
       if (cons->kstats) {  // m and em of this (subdomain, constraint) computed once
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           const double gg = (double)g[e];
           const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
-          const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
-          if (opp && wf > 0.0f) wsg += (double)wf;
+          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
+          wsg += (opp & (wf > 0.0f)) ? (double)wf : 0.0;
         }
         wsg = tm.sum(wsg);
-        const double2 st = cons->kstats[(size_t)b * cons->kmax + k];
         m = st.x;
         em = st.y;
       } else {
@@ -188,8 +193,8 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
           m += gg * (double)xs;
           em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
           const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
-          const bool opp = g[e] != 0.0f && a[e] != 0.0 && (signbit(a[e]) != signbit(g[e]));
-          if (opp && wf > 0.0f) wsg += (double)wf;
+          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
+          wsg += (opp & (wf > 0.0f)) ? (double)wf : 0.0;
         }
         tm.sum3(m, em, wsg);
       }
@@ -387,9 +392,20 @@ __device__ __forceinline__ float* w_slice(CaShared<Team, EPL>& sh) {
   return sh.w + Team::index_in_block() * Team::SIZE * EPL;
 }
 
+// Workgroups per CU that k_ca_rows asks the register allocator for.  A
+// workgroup team of up to 12 coordinates per lane fits four workgroups' LDS
+// and spills only a few registers at that target, which pays for itself
+// (3072-wide rows); wave teams stay at three: at four, a 13-coordinate wave
+// spills its objective row inside the constraint loop, and that costs more
+// than the fourth wave gains.
+template <class Team, int EPL>
+constexpr int ca_rows_blocks() {
+  return (Team::PER_BLOCK == 1 && EPL <= 12) ? 4 : 3;
+}
+
 // Final planes: rows r = (b, m) of the backward pass output.
 template <class Team, int EPL>
-__global__ __launch_bounds__(256, 3) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
+__global__ __launch_bounds__(256, (ca_rows_blocks<Team, EPL>())) void k_ca_rows(int R, int M, int n, CvCons cons, int passes,
                                                  double* Ax, const double* __restrict__ rowc,
                                                  const double* __restrict__ rowerr,
                                                  const float* __restrict__ lo,
