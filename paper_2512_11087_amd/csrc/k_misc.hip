@@ -91,6 +91,49 @@ __global__ void k_gather_rows(int rows, int n, const int32_t* __restrict__ idx,
   dst[i] = src[(size_t)idx[q] * n + c];
 }
 
+// One lane's share of a top row: elements j = lane, lane + 64, ... in
+// chunks of four per lane, every load of a chunk issued before the first is
+// used; the sums accumulate the elements in increasing j.  HAS_ALPHA is a
+// template flag so no branch on it sits between the loads.
+template <bool HAS_ALPHA>
+__device__ __forceinline__ void relax_top_lane(int lane, int nP, const double* __restrict__ psirow,
+                                               const float* __restrict__ lzb,
+                                               const float* __restrict__ uzb,
+                                               const float* __restrict__ alr, double alpha_def,
+                                               const float* __restrict__ bprev,
+                                               const double* __restrict__ wrel, double* omr,
+                                               float* trr, double& s1, double& s2, double& s3) {
+  constexpr int U = 4;
+  for (int j0 = lane; j0 < nP; j0 += 64 * U) {
+    double psi[U], wr[U];
+    float lv[U], uv[U], av[U], bp[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      // past the end: a valid index whose values go unused (j0 < nP here)
+      const int j = min(j0 + 64 * q, nP - 1);
+      psi[q] = psirow[j];
+      lv[q] = lzb[j];
+      uv[q] = uzb[j];
+      av[q] = HAS_ALPHA ? alr[j] : 0.0f;
+      bp[q] = bprev[j];
+      wr[q] = wrel[j];
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + 64 * q;
+      if (j >= nP) break;
+      const double al = HAS_ALPHA ? (double)av[q] : alpha_def;
+      const Relax rl = relax_apply(psi[q], relax_line(lv[q], uv[q]), al);
+      const double om = psi[q] * rl.s;
+      omr[j] = om;
+      if (trr) trr[j] = trace32(psi[q]);
+      s1 += psi[q] * rl.t;
+      s2 += om * (double)bp[q];
+      s3 += fabs(psi[q]) * wr[q];
+    }
+  }
+}
+
 // First relaxation (ReLU of layer T-1) of every row r = (b, m): one wave
 // per row.  Writes Omega_{T-1} and initialises the row state; the top rows
 // are those of subdomain b's property.
@@ -108,19 +151,16 @@ __global__ __launch_bounds__(256) void k_relax_top(
   const int m = p * M + r % M;
   const double* __restrict__ wrel = props.tab[p].wrel[layer];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int j = lane; j < nP; j += 64) {
-    const double psi = psiT[(size_t)m * nP + j];
-    const size_t bi = (size_t)b * Nh + off + j;
-    const size_t ri = (size_t)r * Nh + off + j;
-    const double al = alpha ? (double)alpha[ri] : alpha_def;
-    const Relax rl = relax_apply(psi, relax_line(lz[bi], uz[bi]), al);
-    const double om = psi * rl.s;
-    Om[(size_t)r * nP + j] = om;
-    if (trace) trace[ri] = trace32(psi);
-    s1 += psi * rl.t;
-    s2 += om * (double)bprev[j];
-    s3 += fabs(psi) * wrel[j];
-  }
+  const double* psirow = psiT + (size_t)m * nP;
+  const size_t bbase = (size_t)b * Nh + off, rbase = (size_t)r * Nh + off;
+  double* omr = Om + (size_t)r * nP;
+  float* trr = trace ? trace + rbase : nullptr;
+  if (alpha)
+    relax_top_lane<true>(lane, nP, psirow, lz + bbase, uz + bbase, alpha + rbase, alpha_def, bprev,
+                         wrel, omr, trr, s1, s2, s3);
+  else
+    relax_top_lane<false>(lane, nP, psirow, lz + bbase, uz + bbase, nullptr, alpha_def, bprev,
+                          wrel, omr, trr, s1, s2, s3);
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);
   s3 = wave_sum(s3);
