@@ -51,9 +51,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, workload, batch):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the kernels changed since it was taken."""
+    or None when there is none, when it was counted on another workload or
+    batch, or when the kernels changed since it was taken."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -62,6 +63,8 @@ def traffic_for(kernel):
     except Exception:
         return None
     if d.get("source_hash") != kernel_source_hash():
+        return None
+    if d.get("workload_id") != workload or d.get("global_batch") != batch:
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -325,7 +328,7 @@ def main():
                 "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4)}
     roof["kernel"] = dom
     roof["avg_launch_ms"] = round(avg_ms, 4)
-    roof["traffic"] = traffic_for(dom)
+    roof["traffic"] = traffic_for(dom, args.workload, B)
     if args.kernels_json:
         with open(args.kernels_json, "w") as f:
             json.dump({"steps": args.steps if graph is None else 1, "wall_s": kern_wall,
