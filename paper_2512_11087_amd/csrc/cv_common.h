@@ -123,23 +123,8 @@ struct Relax {
   double s, t;
   bool lower;
 };
-__device__ __forceinline__ Relax relu_relax(double psi, float lf, float uf, double alpha) {
-  Relax r;
-  const double l = (double)lf, u = (double)uf;
-  r.lower = false;
-  if (l >= 0.0) { r.s = 1.0; r.t = 0.0; return r; }
-  if (u <= 0.0) { r.s = 0.0; r.t = 0.0; return r; }
-  if (psi >= 0.0) { r.s = alpha; r.t = 0.0; r.lower = true; return r; }
-  const double s = u / (u - l);
-  const double t1 = -s * l;
-  const double t2 = u - s * u;
-  const double t = fmax(t1, t2);
-  r.s = s;
-  r.t = t + (u - l) * (4.0 * CV_U64);
-  return r;
-}
 
-// The same relaxation split into a per-neuron part -- (slope, intercept) of
+// Computed in two parts: a per-neuron part -- (slope, intercept) of
 // the line used when alpha does not apply: (1, 0) active, (0, 0) inactive,
 // the upper line of an unstable neuron (intercept > 0, which marks it
 // unstable) -- and the per-row choice by the sign of psi.  Evaluated in
@@ -164,7 +149,7 @@ __device__ __forceinline__ Relax relax_apply(double psi, cv_line line, double al
 }
 
 // float32 image of a float64 coefficient that keeps the sign decision
-// psi >= 0 of relu_relax (a negative value never becomes -0.0).
+// psi >= 0 of relax_apply (a negative value never becomes -0.0).
 __device__ __forceinline__ float trace32(double psi) {
   float f = (float)psi;
   if (psi < 0.0 && !(f < 0.0f)) f = -1.17549435e-38f;
