@@ -116,6 +116,33 @@ def test_complete_clip_single_constraint_is_exact_lp():
             assert g[b] <= v + 1e-9 and g[b] == pytest.approx(v, rel=1e-6, abs=1e-6)
 
 
+@pytest.mark.parametrize("n", [784, 3072], ids=["wave-team", "workgroup-team"])
+def test_complete_clip_search_with_skewed_breakpoints_and_weights(n):
+    # the weighted-quantile search on inputs that interpolation serves badly:
+    # breakpoints q_j = -a_j/g_j spread log-uniformly over 12 decades, weights
+    # |g_j| (hi_j - lo_j) over 6 decades plus one weight far above the rest,
+    # and the crossing placed at varying depths; every coordinate is a
+    # candidate.  Thm 3.1: the bound at the exact quantile is the oracle's.
+    B = 24
+    rng = np.random.default_rng(2512)
+    lo = np.full((B, n), -1.0, np.float32)
+    hi = np.full((B, n), 1.0, np.float32)
+    mag = (10.0 ** rng.uniform(-3, 3, (B, n))).astype(np.float32)
+    mag[np.arange(B), rng.integers(0, n, B)] = 1e5          # one dominant weight
+    g = (mag * rng.choice([-1.0, 1.0], (B, n))).astype(np.float32)
+    q = 10.0 ** rng.uniform(-6, 6, (B, n))
+    A = (-q * g).astype(np.float32)                          # opposite signs: all candidates
+    depth = np.linspace(0.05, 0.95, B)                       # where the crossing falls
+    h = (depth * np.abs(g.astype(np.float64)).sum(1)).astype(np.float32)
+    c = np.zeros((B, 1), np.float32)
+    cons = api.Constraints.dense(g[:, None, :], h[:, None], np.ones(B, np.int32))
+    lbc, _, _ = api.concretize(T(A[:, None, :]), T(c), T(lo), T(hi), cons)
+    L, beta, inf = complete.single_sort(A, c[:, 0], g, h, lo, hi)
+    assert not inf.any() and (beta > 0).all()                # every problem searches
+    assert_close(H(lbc)[:, 0], L, 1e-5, "skewed search")
+    assert np.all(H(lbc)[:, 0] <= L + 1e-6 * np.maximum(np.abs(L), 1.0))
+
+
 # ---------------------------------------------------------------- root pass
 
 @pytest.mark.parametrize("make", [lambda: wl.tiny_mlp(8), lambda: wl.mnist_mlp(8),
