@@ -39,10 +39,11 @@ Readings taken:
 * Optimised alpha is one value per (subdomain, objective row, neuron), the
   loss is the sum of the rows' bounds (separable per row).  Root planes use a
   fixed alpha (0.5).
-* At a kink of the final dual (a coefficient of A + beta^T G that is zero up
-  to rounding, which happens at the breakpoint chosen by (7)) the subgradient
-  uses the box midpoint for that coordinate: any point of [lo_j, hi_j] is a
-  valid subgradient there; the midpoint is the symmetric choice.
+* At a kink of the final dual (a coefficient of A + beta^T G that is zero in
+  exact arithmetic, which happens at the breakpoint chosen by (7)) the
+  subgradient uses the box midpoint for that coordinate: any point of
+  [lo_j, hi_j] is a valid subgradient there; the midpoint is the symmetric
+  choice.  ``kink_tol`` bounds the float64 residue such a zero leaves.
 """
 from dataclasses import dataclass
 
@@ -53,7 +54,18 @@ from . import complete as cc
 from . import crown
 from .box import f64, concretize_min, concretize_min_shared, concretize_max_shared
 
-KINK_REL = 2.0 ** -40
+U64 = 2.0 ** -53   # unit roundoff of float64
+
+
+def kink_tol(k):
+    """Relative bound on the float64 residue of a coefficient of
+    A + beta^T G that exact arithmetic makes zero.  beta_k = -a'_j / g_kj is
+    formed from a'_j = A_j + sum_{p != k} beta_p G_pj (off by at most
+    gamma_k s_j, s_j = |A_j| + sum_p beta_p |G_pj|) and one rounded division;
+    A_j + sum_p beta_p G_pj is then summed again (gamma_{k+1} s_j).  Together
+    at most (2k + 2) u s_j (1 + 1%); (2k + 8) u leaves room.  k: number of
+    constraint slots."""
+    return (2 * k + 8) * U64
 
 
 @dataclass
@@ -349,7 +361,7 @@ def bound_and_grad(layers, C, t, l_list, u_list, alpha, lo, hi, G, h, active,
     scale = np.abs(A)
     if beta is not None:
         scale = scale + np.einsum("bmk,bkn->bmn", beta, np.abs(G))
-    kink = np.abs(Af) <= KINK_REL * scale
+    kink = np.abs(Af) <= kink_tol(G.shape[1]) * scale
     xstar = np.where(kink, (lo[:, None, :] + hi[:, None, :]) / 2.0,
                      np.where(Af > 0.0, lo[:, None, :], hi[:, None, :]))
     grads = [None] * (len(layers) - 1)

@@ -141,7 +141,7 @@ def test_single_constraint_solvers_agree_with_exact_lp(seed):
         n = int(rng.integers(1, 6))
         a, c, G, h, lo, hi = rand_problem(rng, n, 1)
         Le, be = complete.single_enum(a, c, G[0], h[0], lo, hi)
-        Ls, bs, infs = complete.single_sort(a[None], np.array([c]), G, h, lo[None], hi[None])
+        Ls, bs, infs = complete.single_max(a[None], np.array([c]), G, h, lo[None], hi[None])
         Lk, infk = complete.knapsack_greedy(a, c, G[0], h[0], lo, hi)
         Lv = exact.lp_vertices(a, c, G, h, lo, hi)[0]
         if Lv == np.inf:
@@ -173,7 +173,7 @@ def test_redundant_constraint_gives_zero_multiplier():
     a = np.array([1.0, -2.0, 0.5])
     G = np.array([[1.0, 1.0, 1.0]])
     h = np.array([-5.0])           # max over the box is -2 <= 0: redundant
-    L, beta, inf = complete.single_sort(a[None], np.array([0.0]), G, h, lo[None], hi[None])
+    L, beta, inf = complete.single_max(a[None], np.array([0.0]), G, h, lo[None], hi[None])
     assert beta[0] == 0.0 and not inf[0]
     assert L[0] == pytest.approx(box.concretize_min(a[None], np.array([0.0]), lo, hi)[0])
 

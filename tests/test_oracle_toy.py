@@ -69,7 +69,7 @@ def test_complete_clip_upper_z2():
     L, beta = complete.single_enum(-W1[1], -b1[1], W1[0], b1[0], lo, hi)
     assert -L == pytest.approx(fr(V["z2_upper_cc"]))
     assert beta == pytest.approx(fr(V["beta_star_z2"]))
-    Ls, bs, inf = complete.single_sort(-W1[1][None], -b1[1:2], W1[0][None], b1[0:1], lo[None], hi[None])
+    Ls, bs, inf = complete.single_max(-W1[1][None], -b1[1:2], W1[0][None], b1[0:1], lo[None], hi[None])
     assert -Ls[0] == pytest.approx(fr(V["z2_upper_cc"])) and bs[0] == pytest.approx(5.0)
     assert exact.lp_simplex(-W1[1], -b1[1], W1[0:1], b1[0:1], lo, hi) == -Fraction(V["z2_upper_cc"])
 
