@@ -392,10 +392,16 @@ def adam_ascent(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def alpha_opt(layers, C, t, l_list, u_list, lo, hi, G, h, active, steps=20,
-              lr=0.1, alpha0=0.5, decay=1.0, complete=True, passes=1):
+              lr=0.1, alpha0=0.5, decay=1.0, complete=True, passes=1, b1=0.9, b2=0.999,
+              eps=1e-8, state32=False):
     """Step (8) repeated: ``steps`` iterations of (bound, gradient, Adam) starting
     from alpha0 everywhere.  Returns (best lb over the iterations [B, M],
-    per-iteration lb list, final alpha list)."""
+    per-iteration lb list, final alpha list).
+
+    state32: the slopes and Adam moments are carried from one iteration to
+    the next as float32 values (rounded to nearest after each update), which
+    is how they cross the library's interface between its steps; every
+    iteration still computes in float64 on the widened values."""
     B = lo.shape[0]
     M = C.shape[0]
     alpha = [np.full((B, M, W.shape[0]), alpha0) for W, _ in layers[:-1]]
@@ -410,5 +416,9 @@ def alpha_opt(layers, C, t, l_list, u_list, lo, hi, G, h, active, steps=20,
         best = np.maximum(best, lb)
         lr_s = lr * decay ** (s - 1)
         for kk in range(len(alpha)):
-            alpha[kk], ms[kk], vs[kk] = adam_ascent(alpha[kk], grads[kk], ms[kk], vs[kk], s, lr_s)
+            alpha[kk], ms[kk], vs[kk] = adam_ascent(alpha[kk], grads[kk], ms[kk], vs[kk], s, lr_s,
+                                                    b1, b2, eps)
+            if state32:
+                alpha[kk], ms[kk], vs[kk] = (x.astype(np.float32).astype(np.float64)
+                                             for x in (alpha[kk], ms[kk], vs[kk]))
     return best, hist, alpha

@@ -127,7 +127,7 @@ constexpr int CA_SLOTS = 64;
 struct Bwd {
   double *Om0, *Om1, *Ax, *part, *rowc, *rowerr, *rowcabs, *psiT, *c0, *e0, *cabs0;
   float* trace;
-  double2* kst;  // [B, CA_SLOTS] per-constraint box statistics for complete clipping
+  CvKStat* kst;  // [B, CA_SLOTS] per-constraint box statistics for complete clipping
 };
 
 // Row counts a backward pass supports: every per-layer matrix of R rows
@@ -159,7 +159,7 @@ size_t bwd_layout(const cv_net_s* net, int T, long long R, int M, int P, bool ke
   x.e0 = cv.take<double>((size_t)P * M);
   x.cabs0 = cv.take<double>((size_t)P * M);
   x.trace = trace ? cv.take<float>((size_t)R * net->n_hidden) : nullptr;
-  x.kst = cv.take<double2>((size_t)B * CA_SLOTS);
+  x.kst = cv.take<CvKStat>((size_t)B * CA_SLOTS);
   if (w) *w = x;
   return cv.off + 256;
 }
@@ -988,7 +988,7 @@ cv_status cv_constraint_order(cv_root root, const int32_t* pid, int B, int n,
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes) {
   if (!root || !bytes || B < 0) return CV_E_INVALID;
   *bytes = complete ? (size_t)B * root->Umax * 2 * sizeof(float) + (size_t)B * root->N +
-                         (size_t)B * CA_SLOTS * sizeof(double2) + 1024
+                         (size_t)B * CA_SLOTS * sizeof(CvKStat) + 1024
                    : 0;
   return CV_OK;
 }
@@ -1033,7 +1033,7 @@ cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const fl
       PLAUNCH("select_topk", 0, 8.0 * B * Nh + 1.0 * B * Nh, launch_select_topk(B, Nh, nl, net->off, net->n + 1, l, u, weight, props, topk, sel, s));
     }
     if (sp.kmax <= CA_SLOTS) {  // statistics of each (subdomain, constraint), shared by its neurons
-      double2* kst = cv.take<double2>((size_t)B * CA_SLOTS);
+      CvKStat* kst = cv.take<CvKStat>((size_t)B * CA_SLOTS);
       PLAUNCH("cons_stats", 0, 8.0 * B * root->n0 + 4.0 * B * sp.kmax * root->n0, launch_cons_stats(B, root->n0, sp, lo, hi, kst, s));
       sp.kstats = kst;
     }

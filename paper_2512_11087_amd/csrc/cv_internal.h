@@ -122,6 +122,16 @@ struct cv_root_s {
 // ----------------------------------------------------------- launchers
 // All return hipError_t of the launch.
 
+// Per (subdomain, constraint position) statistics of a constraint over the
+// box, shared by every objective row of the subdomain (launch_cons_stats):
+// m = min over the box of g.x (h not included), em = sum_j |g_j| max(|lo_j|,
+// |hi_j|) and tmax = max_j |g_j| max(|lo_j|,|hi_j|) (rounded up to float32:
+// it only scales a tolerance).
+struct __align__(8) CvKStat {
+  double m, em;
+  float tmax, unused;
+};
+
 struct CvCons {  // device view of cv_constraints (resolved)
   int kmax;
   const int32_t* count;
@@ -132,10 +142,8 @@ struct CvCons {  // device view of cv_constraints (resolved)
   CvProps props;  // split form: the planes of each subdomain's property (eqs. 9-10)
   int nplanes;    // rows of the plane table; split slots with other indices are ignored
   const int32_t* order;  // [B, kmax] position -> slot, or null (list order)
-  // [B, kmax] per position, or null: (min over the box of the constraint's
-  // g.x without h, sum_j |g_j| max(|lo_j|,|hi_j|)), shared by every objective
-  // row of the subdomain (launch_cons_stats)
-  const double2* kstats;
+  // [B, kmax] per position, or null: the constraint's box statistics
+  const CvKStat* kstats;
 };
 
 // Number of used slots of subdomain b, clamped to [0, kmax].
@@ -252,7 +260,7 @@ hipError_t launch_split_fix(int B, int Nh, const CvCons& splits, float* l, float
 
 // complete clipping (coordinate ascent over the 1-D duals)
 hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, const float* hi,
-                             double2* stats, hipStream_t s);
+                             CvKStat* stats, hipStream_t s);
 hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
                           const double* rowc, const double* rowerr, const float* lo,
                           const float* hi, uint8_t* infeasible, float* lb, float* beta_out,

@@ -29,6 +29,12 @@ struct WaveTeam {
     b = wave_max(b);
     c = wave_sum(c);
   }
+  // two sums and a maximum in one pass
+  __device__ void sum_sum_max(double& a, double& b, double& c) const {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_max(c);
+  }
   // member k < cnt holds constraint k's row pointer, scale and offset
   __device__ void publish(const float*, float, double, int) const {}
   __device__ void meta(const float* my_row, float my_scale, double my_h, int k, const float*& row,
@@ -103,6 +109,22 @@ struct BlockTeam {
     a = fmax(fmax(rb[0], rb[1]), fmax(rb[2], rb[3]));
     b = fmax(fmax(rb[4], rb[5]), fmax(rb[6], rb[7]));
     c = (rb[8] + rb[9]) + (rb[10] + rb[11]);
+  }
+  // two sums and a maximum through one barrier
+  __device__ void sum_sum_max(double& a, double& b, double& c) const {
+    double* rb = next_bank();
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_max(c);
+    if ((t & 63) == 0) {
+      rb[t >> 6] = a;
+      rb[4 + (t >> 6)] = b;
+      rb[8 + (t >> 6)] = c;
+    }
+    __syncthreads();
+    a = (rb[0] + rb[1]) + (rb[2] + rb[3]);
+    b = (rb[4] + rb[5]) + (rb[6] + rb[7]);
+    c = fmax(fmax(rb[8], rb[9]), fmax(rb[10], rb[11]));
   }
   __device__ double min(double v) const {
     double* rb = next_bank();

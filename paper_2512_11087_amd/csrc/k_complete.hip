@@ -8,9 +8,9 @@
 // w_j = |g_j| (hi_j - lo_j).  So beta* = 0 when the slope at 0+ is <= 0, else
 // beta* is the breakpoint q* where the slope changes sign: the smallest
 // positive breakpoint with  sum_{q_j > q*} w_j <= -m  (a weighted quantile).
-// m > 0 means the constraint is empty over the box (+inf).  Supergradients
-// within a small tolerance of zero count as zero, so near-ties between
-// maximisers go to the smallest one.
+// m > 0 means the constraint is empty over the box (+inf).  Slopes within a
+// small tolerance of zero count as zero, so near-ties between maximisers go
+// to the smallest one (see the tolerance at its use).
 //
 // GPU mapping: one team per problem -- a wave64 for n <= 1024, a 256-thread
 // workgroup for n <= 4096 -- whose member t owns coordinates t, t + T, ...
@@ -44,13 +44,17 @@ constexpr int CA_KMAX = CV_TEAM_KMAX;
 // on every early round takes 15-20 % fewer than alternating from the start).
 // A probe takes the largest candidate p at or below the split point; W(> p)
 // decides the side and, only when W(> p) <= S, W(>= p) > S identifies p = q*.
-// The breakpoints and weights sit in the team's LDS slice (element e of
-// member t at e*T + t; non-candidates hold -inf), which keeps them out of the
-// registers of the common path that needs no search.
+// The breakpoints and the candidates' |g_j| sit in the team's LDS slice
+// (element e of member t at e*T + t; non-candidates hold -inf and 0), which
+// keeps them out of the registers of the common path that needs no search;
+// each weight |g_j| (hi_j - lo_j) is formed in float64 from |g_j| and the box
+// in registers, the same value the caller summed, so every decision is taken
+// on exact float64 weights.
 // qmax, qmin: the largest and smallest candidate (team-wide), wpos the sum
 // of the candidates' weights.
 template <class Team, int EPL>
-__device__ double ca_select(const Team& tm, const double* sq, const float* sw, double S,
+__device__ double ca_select(const Team& tm, const double* sq, const float* sg,
+                            const float (&xl)[EPL], const float (&xh)[EPL], double S,
                             double wpos, double qmax, double qmin) {
   constexpr int T = Team::SIZE;
   unsigned long long blo = (unsigned long long)__double_as_longlong(qmin) - 1ull;
@@ -85,7 +89,7 @@ __device__ double ca_select(const Team& tm, const double* sq, const float* sw, d
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const double q = sq[e * T + tm.t];
-      const double w = (double)sw[e * T + tm.t];
+      const double w = (double)sg[e * T + tm.t] * ((double)xh[e] - (double)xl[e]);
       if (q > p) wg += w;
       if (q >= p) wge += w;
     }
@@ -151,7 +155,7 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       if (!row) continue;
       // the shared statistics of this (subdomain, constraint), loaded first so
       // their latency overlaps the row's
-      double2 st = make_double2(0.0, 0.0);
+      CvKStat st{};
       if (cons->kstats) st = cons->kstats[(size_t)b * cons->kmax + k];
       const cv_buf brow = cv_buffer(row, 4u * n);
       int vb = 4 * t;
@@ -168,39 +172,46 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
 #pragma unroll
         for (int e = 0; e < EPL; ++e) a[e] -= bold * (double)g[e];
       }
-      // m, its error scale, and the weight of the coordinates whose
+      // m, its error scales, and the weight of the coordinates whose
       // breakpoint q_j = -a_j/g_j is positive (a_j and g_j of opposite
       // signs), without dividing; breakpoints are formed only when that
-      // weight exceeds -m, i.e. when beta* > 0 is possible.  The weights only
-      // steer the choice of beta, so float32 suffices (any beta >= 0 is valid).
-      // (products of float32 values are exact in float64, so
-      // min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi)) exactly;
-      // the opposite-sign test is branch-free, and a skipped weight adds +0.0
-      // to a non-negative sum, which leaves it unchanged)
-      double m = 0.0, em = 0.0, wsg = 0.0;
-      if (cons->kstats) {  // m and em of this (subdomain, constraint) computed once
+      // weight exceeds -m, i.e. when beta* > 0 is possible.  Weights are
+      // summed in float64 (products of float32 values are exact in float64,
+      // so min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi))
+      // exactly; the opposite-sign test is branch-free, and a skipped weight
+      // adds +0.0 to a non-negative sum, which leaves it unchanged).
+      double m = 0.0, em = 0.0, tmax = 0.0, wsg = 0.0;
+      if (cons->kstats) {  // m, em and tmax of this (subdomain, constraint) computed once
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           const double gg = (double)g[e];
-          const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
+          const double wd = fabs(gg) * ((double)xh[e] - (double)xl[e]);
           const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
-          wsg += (opp & (wf > 0.0f)) ? (double)wf : 0.0;
+          wsg += opp ? wd : 0.0;
         }
         wsg = tm.sum(wsg);
-        m = st.x;
-        em = st.y;
+        m = st.m;
+        em = st.em;
+        tmax = (double)st.tmax;
       } else {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           const double gg = (double)g[e];
           const float xs = g[e] >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
           m += gg * (double)xs;
-          em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
-          const float wf = (float)(fabs(gg) * ((double)xh[e] - (double)xl[e]));
-          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
-          wsg += (opp & (wf > 0.0f)) ? (double)wf : 0.0;
+          const double te = fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+          em += te;
+          tmax = fmax(tmax, te);
         }
-        tm.sum3(m, em, wsg);
+        tm.sum_sum_max(m, em, tmax);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const double gg = (double)g[e];
+          const double wd = fabs(gg) * ((double)xh[e] - (double)xl[e]);
+          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
+          wsg += opp ? wd : 0.0;
+        }
+        wsg = tm.sum(wsg);
       }
       m += h;
       if (bold != 0.0) {
@@ -212,36 +223,42 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
         empty = true;
         break;
       }
-      // slopes within 2^-18 sum_j |g_j| max(|lo_j|,|hi_j|) of zero count as
-      // zero: near-ties go to the smaller multiplier (the dual is exactly flat
-      // on [0, q] after relaxed clipping by the same constraint)
-      const double S = -m + 3.814697265625e-06 * em;
+      // Slopes within `tol` of zero count as zero, so near-ties go to the
+      // smaller multiplier.  Relaxed clipping by this constraint leaves the
+      // dual exactly flat where only the clipped coordinate i's breakpoint is
+      // ahead (its weight is -m), but the float32 end of that coordinate is
+      // rounded outward, which leaves a slope of up to one float32 ulp of the
+      // end times |g_i| <= 2^-23 tmax; the float64 sums add at most
+      // gamma_{2n+8} (em + |h| + wsg).
+      const double tol = 2.384185791015625e-07 * tmax + cv_gamma(2 * n + 8) * (em + fabs(h) + wsg);
+      const double S = -m + tol;
       double bk = 0.0;
       if (wsg > S) {
         // breakpoints and the exact candidate set (a division may underflow
         // to q = 0, which is not a candidate), staged in LDS for the search
-        // the candidates' total weight and their range, reduced together
+        // with |g_j|; the candidates' total weight and their range, reduced
+        // together
         double wpos = 0.0, qmax = -INFINITY, nqmin = -INFINITY;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           double qe = -INFINITY;
-          float we = 0.0f;
+          float ge = 0.0f;
           if (g[e] != 0.0f) {
             const double q = -a[e] / (double)g[e];
-            const float w = (float)(fabs((double)g[e]) * ((double)xh[e] - (double)xl[e]));
-            if (q > 0.0 && w > 0.0f) {
+            const double w = (double)fabsf(g[e]) * ((double)xh[e] - (double)xl[e]);
+            if (q > 0.0 && w > 0.0) {
               qe = q;
-              we = w;
-              wpos += (double)w;
+              ge = fabsf(g[e]);
+              wpos += w;
               qmax = fmax(qmax, q);
               nqmin = fmax(nqmin, -q);
             }
           }
           sq[e * T + t] = qe;
-          sw[e * T + t] = we;
+          sw[e * T + t] = ge;
         }
         tm.max_max_sum(qmax, nqmin, wpos);
-        if (wpos > S) bk = ca_select<Team, EPL>(tm, sq, sw, S, wpos, qmax, -nqmin);
+        if (wpos > S) bk = ca_select<Team, EPL>(tm, sq, sw, xl, xh, S, wpos, qmax, -nqmin);
       }
       beta[k] = bk;
       if (bk != 0.0) {
@@ -309,15 +326,15 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
 }
 
 // Per (subdomain, constraint position): m = min over the box of g.x (h not
-// included) and em = sum_j |g_j| max(|lo_j|,|hi_j|), with the same team
-// shape and summation order as ca_core computes them (so both give the same
-// values); complete clipping of every objective row of the subdomain reads
-// them instead of recomputing them.
+// included), em = sum_j |g_j| max(|lo_j|,|hi_j|) and the largest of those
+// terms, with the same team shape and summation order as ca_core computes
+// them (so both give the same values); complete clipping of every objective
+// row of the subdomain reads them instead of recomputing them.
 template <class Team, int EPL>
 __global__ __launch_bounds__(256) void k_cons_stats(int B, int n, CvCons cons,
                                                     const float* __restrict__ lo,
                                                     const float* __restrict__ hi,
-                                                    double2* stats) {
+                                                    CvKStat* stats) {
   __shared__ double red[24];
   __shared__ const float* mrow[CV_TEAM_KMAX];
   __shared__ float mscale[CV_TEAM_KMAX];
@@ -350,17 +367,19 @@ __global__ __launch_bounds__(256) void k_cons_stats(int B, int n, CvCons cons,
     const cv_buf brow = cv_buffer(row, 4u * n);
     int vb = 4 * tm.t;
     cv_opaque(vb);
-    double m = 0.0, em = 0.0, z = 0.0;
+    double m = 0.0, em = 0.0, tmax = 0.0;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const float g = scale * buf_f32(brow, vb + 4 * T * e);
       const double gg = (double)g;
       const float xs = g >= 0.0f ? fminf(xl[e], xh[e]) : fmaxf(xl[e], xh[e]);
       m += gg * (double)xs;
-      em += fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+      const double te = fabs(gg) * (double)fmaxf(fabsf(xl[e]), fabsf(xh[e]));
+      em += te;
+      tmax = fmax(tmax, te);
     }
-    tm.sum3(m, em, z);
-    if (tm.t == 0) stats[(size_t)b * cons.kmax + k] = make_double2(m, em);
+    tm.sum_sum_max(m, em, tmax);
+    if (tm.t == 0) stats[(size_t)b * cons.kmax + k] = CvKStat{m, em, ru32(tmax), 0.0f};
   }
 }
 
@@ -551,7 +570,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int Umax, int n, C
 }  // namespace
 
 hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, const float* hi,
-                             double2* stats, hipStream_t s) {
+                             CvKStat* stats, hipStream_t s) {
   if (B <= 0 || cons.kmax <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
   CV_DISPATCH_TEAM(n, hipLaunchKernelGGL((k_cons_stats<TM, E>), dim3(team_blocks(B, TM::PER_BLOCK)),

@@ -542,3 +542,49 @@ def random_alpha(B: int, M: int, n_hidden: int, seed: int):
     """Slopes in [0, 1] for every (subdomain, objective row, hidden neuron)."""
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, (B, M, n_hidden)), np.float32)
+
+
+def tie_problems(B: int, n: int, k: int, P: int, seed: int):
+    """Boxes, constraints and objective rows arranged so that complete
+    clipping after relaxed clipping meets ties (float32; values on coarse
+    dyadic grids, so products of inputs are exact).
+
+    Each constraint has one dominant coefficient (+-8 against normal(0, 1)
+    entries rounded to 1/16), which makes relaxed clipping tighten that
+    coordinate; 30 % of the subdomains repeat constraint 0 as constraint 1.
+    Each objective row puts the first constraint's dominant coordinate's
+    breakpoint -A_j / G_0j far out (64) and makes about a third of the other
+    coordinates share one breakpoint (1/4, 1/2, 1 or 2) against constraint 0;
+    the rest are normal(0, 1) rounded to 1/16.  Each constraint's hyperplane
+    passes through the box corner where g.x is smallest, moved into the box
+    by a fraction (0.2 to 0.9) of what the dominant coordinate spans.
+    Returns lo, hi [B, n], G [B, k, n], h [B, k], count [B], A [B, P, n],
+    c [B, P]."""
+    rng = np.random.default_rng(seed)
+    grid = lambda x, s: np.round(x * s) / s
+    lo = grid(rng.uniform(-1.0, 0.5, (B, n)), 64)
+    hi = lo + grid(rng.uniform(0.25, 1.0, (B, n)), 64)
+    G = grid(rng.normal(0.0, 1.0, (B, k, n)), 16)
+    G[rng.random((B, k, n)) < 0.1] = 0.0
+    dom = rng.integers(0, n, (B, k))
+    bi, ki = np.meshgrid(np.arange(B), np.arange(k), indexing="ij")
+    G[bi, ki, dom] = 8.0 * rng.choice([-1.0, 1.0], (B, k))
+    if k >= 2:
+        dup = rng.random(B) < 0.3
+        G[dup, 1] = G[dup, 0]
+    corner = np.where(G > 0.0, lo[:, None, :], hi[:, None, :])
+    span = 8.0 * (hi[bi, dom] - lo[bi, dom])
+    h = -np.einsum("bkn,bkn->bk", G, corner) - rng.uniform(0.2, 0.9, (B, k)) * span
+    if k >= 2:
+        h[dup, 1] = h[dup, 0]
+    A = grid(rng.normal(0.0, 1.0, (B, P, n)), 16)
+    g0 = G[:, 0][:, None, :]
+    tie_q = rng.choice([0.25, 0.5, 1.0, 2.0], (B, P))[..., None]
+    tied = (rng.random((B, P, n)) < 0.33) & (g0 != 0.0)
+    A = np.where(tied, -tie_q * g0, A)
+    A[np.arange(B)[:, None], np.arange(P)[None, :], dom[:, 0][:, None]] = \
+        -64.0 * G[np.arange(B), 0, dom[:, 0]][:, None]
+    c = np.zeros((B, P))
+    count = np.full(B, k, np.int32)
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return f(lo), f(hi), f(G), f(h), count, f(A), f(c)

@@ -6,6 +6,12 @@ from paper_2512_11087_amd import workloads as wl
 
 REL = 1e-5   # parity band: |gpu - oracle| <= REL * max(|oracle|, 1)
 
+# Adam's hyperparameters as the library receives them (float32 through the C
+# ABI), widened to float64 for the oracle like every other input: 0.999 in
+# float32 is 0.99900001287..., which moves 1 - beta2 by 1.3e-5 relative.
+F32 = lambda x: float(np.float32(x))
+ADAM = dict(lr=F32(0.1), b1=F32(0.9), b2=F32(0.999), eps=F32(1e-8))
+
 
 def assert_close(gpu, ref, rel=REL, what=""):
     gpu = np.asarray(gpu, np.float64)
@@ -45,3 +51,63 @@ class OracleProp:
 
 def subset_splits(sp, idx):
     return wl.Splits(sp.neuron[idx], sp.sign[idx], sp.count[idx])
+
+
+# The kernel's documented near-tie rule for complete clipping: a right slope
+# of the 1-D dual within 2^-22 sum_j |g_j| max(|lo_j|, |hi_j|) of zero counts
+# as zero, and the smallest such point is taken.  It is the kernel's own
+# choice (its breakpoint weights are float32); the oracle uses a float64
+# bound of its own.  Tests use this constant only to judge the kernel's
+# multipliers where several points maximise the dual.
+KERNEL_TIE = 2.0 ** -22
+
+
+def check_multipliers(a, c, G, h, lo, hi, beta, lb, tie=KERNEL_TIE):
+    """Judge one coordinate-ascent pass of kernel multipliers (float32, as
+    returned) with the oracle's dual slopes (Thm 3.1), constraint by
+    constraint in order, each against the objective with the earlier
+    multipliers in place: beta_k must be a maximiser of its 1-D dual up to
+    the kernel's tie rule (right slope <= tie threshold) and the smallest
+    such point (left slope above it), allowing for the float32 rounding of
+    beta and of the kernel's weights; then the bound lb must equal
+    max(plain concretization, D(beta)) within 1e-5 and not exceed it beyond
+    rounding.  a [R, n], c [R], G [R, k, n], h [R, k], lo, hi [R, n],
+    beta [R, k], lb [R].  Returns counts of the ties met."""
+    from oracle import complete
+    f = lambda x: np.asarray(x, np.float64)
+    ak, ck = f(a).copy(), f(c).copy()
+    G, h, lo, hi, beta = f(G), f(h), f(lo), f(hi), f(beta)
+    R, k, n = G.shape
+    flat = flat0 = 0
+    drift = np.zeros(R)
+    for kk in range(k):
+        g, hh, b = G[:, kk], h[:, kk], beta[:, kk]
+        em = (np.abs(g) * np.maximum(np.abs(lo), np.abs(hi))).sum(-1)
+        W = (np.abs(g) * (hi - lo)).sum(-1)
+        slack = 2.0 ** -23 * W + complete.slope_tol(g, hh, lo, hi)
+        thr = tie * em
+        left, _ = complete.dual_slopes(ak, g, hh, lo, hi, b * (1.0 - 2.0 ** -22))
+        _, right = complete.dual_slopes(ak, g, hh, lo, hi, b * (1.0 + 2.0 ** -22))
+        bad = right > thr + slack
+        assert not bad.any(), f"constraint {kk}: {bad.sum()} multipliers are not maximisers"
+        pos = b > 0.0
+        bad = pos & ~(left > thr - slack)
+        assert not bad.any(), f"constraint {kk}: {bad.sum()} multipliers past the smallest maximiser"
+        near = np.abs(right) <= thr + slack
+        flat += int((pos & near).sum())
+        flat0 += int((~pos & near).sum())
+        drift += 2.0 ** -22 * b * (em + np.abs(hh))
+        ak += b[:, None] * g
+        ck += b * hh
+    D = box_min(ak, ck, lo, hi)
+    plain = box_min(f(a), f(c), lo, hi)
+    ref = np.maximum(plain, D)
+    scale = (np.abs(f(a)) * np.maximum(np.abs(lo), np.abs(hi))).sum(-1) + np.abs(f(c)) + 1.0
+    assert np.all(f(lb) <= ref + drift + 1e-9 * scale), "bound above D at the kernel's multipliers"
+    assert_close(lb, ref, REL, "bound vs D at the kernel's multipliers")
+    return {"flat": flat, "flat_at_zero": flat0}
+
+
+def box_min(a, c, lo, hi):
+    from oracle import box
+    return box.concretize_min(a[:, None, :], c[:, None], lo, hi)[:, 0]

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import complete, crown, pipeline as opipe, relaxed  # noqa: E402
 from paper_2512_11087_amd import api, pipeline as gpipe, workloads as wl  # noqa: E402
-from helpers import OracleProp, assert_close, subset_splits  # noqa: E402
+from helpers import ADAM, OracleProp, assert_close, subset_splits  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -137,7 +137,7 @@ def test_complete_clip_search_with_skewed_breakpoints_and_weights(n):
     c = np.zeros((B, 1), np.float32)
     cons = api.Constraints.dense(g[:, None, :], h[:, None], np.ones(B, np.int32))
     lbc, _, _ = api.concretize(T(A[:, None, :]), T(c), T(lo), T(hi), cons)
-    L, beta, inf = complete.single_sort(A, c[:, 0], g, h, lo, hi)
+    L, beta, inf = complete.single_max(A, c[:, 0], g, h, lo, hi)
     assert not inf.any() and (beta > 0).all()                # every problem searches
     assert_close(H(lbc)[:, 0], L, 1e-5, "skewed search")
     assert np.all(H(lbc)[:, 0] <= L + 1e-6 * np.maximum(np.abs(L), 1.0))
@@ -188,19 +188,33 @@ def run_both(w, sp, cfg_g, cfg_o, op=None):
 
 
 def compare_pass(out, batch, ref, op, rel=1e-5):
+    """Whole pass, each side with its own intermediate steps: every result
+    within ``rel`` of the oracle's, and the GPU's never the tighter one
+    beyond the oracle's own rounding (its boxes contain the oracle's, its
+    bounds are not above them)."""
     ginf = H(out["infeasible"]).astype(bool)
     oinf = ref["infeasible"]
     assert not (ginf & ~oinf).any(), "GPU pruned a subdomain the oracle keeps"
     assert (ginf == oinf).mean() > 0.999
     fe = ~oinf & ~ginf
-    assert_close(H(batch.lo)[fe], ref["lo"][fe], 1e-5, "clipped lo")
-    assert_close(H(batch.hi)[fe], ref["hi"][fe], 1e-5, "clipped hi")
+    glo, ghi = H(batch.lo)[fe].astype(np.float64), H(batch.hi)[fe].astype(np.float64)
+    assert np.all(glo <= ref["lo"][fe] + DIR * np.maximum(np.abs(ref["lo"][fe]), 1.0)), "box tighter"
+    assert np.all(ghi >= ref["hi"][fe] - DIR * np.maximum(np.abs(ref["hi"][fe]), 1.0)), "box tighter"
+    assert_close(glo, ref["lo"][fe], 1e-5, "clipped lo")
+    assert_close(ghi, ref["hi"][fe], 1e-5, "clipped hi")
     unst = op.unstable()
-    assert_close(H(out["l"])[fe][:, unst], ref["l"][fe][:, unst], rel, "l")
-    assert_close(H(out["u"])[fe][:, unst], ref["u"][fe][:, unst], rel, "u")
+    gl, gu = H(out["l"])[fe][:, unst], H(out["u"])[fe][:, unst]
+    ol, ou = ref["l"][fe][:, unst], ref["u"][fe][:, unst]
+    assert np.all(gl <= ol + 1e-9 * np.maximum(np.abs(ol), 1.0)), "intermediate l above the oracle's"
+    assert np.all(gu >= ou - 1e-9 * np.maximum(np.abs(ou), 1.0)), "intermediate u below the oracle's"
+    assert_close(gl, ol, rel, "l")
+    assert_close(gu, ou, rel, "u")
     glb = H(out["lb"])
     assert np.all(np.isinf(glb[ginf]))
-    return assert_close(glb[fe], ref["lb"][fe], rel, "lb")
+    olb = ref["lb"][fe]
+    above = glb[fe] > olb + 1e-9 * np.maximum(np.abs(olb), 1.0)
+    assert not above.any(), f"GPU bound above the oracle's on {above.sum()} rows"
+    return assert_close(glb[fe], olb, rel, "lb")
 
 
 @pytest.mark.parametrize("mode", ["parallel", "sequential"])
@@ -261,6 +275,10 @@ def test_pass_sound_on_sampled_points_of_each_subdomain():
 # ------------------------------------------------------------------ slopes
 
 def test_alpha_gradient_matches_oracle():
+    # the bound and its slope gradient at random slopes, with the GPU's own
+    # intermediate bounds handed to the oracle as data (and the oracle's own
+    # clipped box and halfspaces, see test_gpu_sameinput): every gradient
+    # entry within 1e-5 of the largest of its row
     w = wl.tiny_mlp(64)
     w.net = wl.he_mlp([5] + [50] * 6 + [5], 2, bias="uniform")
     op = OracleProp(w)
@@ -275,20 +293,25 @@ def test_alpha_gradient_matches_oracle():
     fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
     al = [alpha[:, :, o:o + n].astype(np.float64) for o, n in
           zip(w.net.hidden_offsets, w.net.hidden_sizes)]
-    l_list = opipe.split_layers(op.layers, ref["l"])
-    u_list = opipe.split_layers(op.layers, ref["u"])
+    l_list = opipe.split_layers(op.layers, H(out["l"]).astype(np.float64))
+    u_list = opipe.split_layers(op.layers, H(out["u"]).astype(np.float64))
     olb, ograds, _, _ = opipe.bound_and_grad(op.layers, w.C, w.t, l_list, u_list, al, ref["lo"],
                                             ref["hi"], ref["G"], ref["h"], ref["active"])
     assert_close(H(lb)[fe], olb[fe], 1e-5, "alpha-step bound")
+    assert np.all(H(lb)[fe] <= olb[fe] + 1e-9 * np.maximum(np.abs(olb[fe]), 1.0))
     og = np.concatenate(ograds, axis=2)[fe]
     gg = H(grad)[fe]
     scale = np.abs(og).max(axis=2, keepdims=True) + 1e-30
-    bad = np.abs(gg - og) > 1e-5 * scale + 1e-5 * np.abs(og)
-    assert bad.mean() < 1e-3, f"{bad.sum()} gradient entries differ"
+    bad = np.abs(gg - og) > 1e-5 * scale
+    assert not bad.any(), f"{bad.sum()} gradient entries differ"
     assert (og != 0).sum() > 100
 
 
 def test_alpha_opt_matches_oracle_and_improves():
+    # six slope iterations on the tiny net: the oracle on the GPU's float32
+    # intermediate bounds, with its slopes and moments carried as float32
+    # between iterations (as through the library's interface), within 1e-5;
+    # on its own float64 bounds as well here (no discrete choice flips)
     w = wl.tiny_mlp(48)
     w.net = wl.he_mlp([5] + [50] * 6 + [5], 3, bias="uniform")
     op = OracleProp(w)
@@ -297,14 +320,16 @@ def test_alpha_opt_matches_oracle_and_improves():
     best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=6, lr=0.1)
     sync()
     fe = ~ref["infeasible"] & ~H(out["infeasible"]).astype(bool)
-    l_list = opipe.split_layers(op.layers, ref["l"][fe])
-    u_list = opipe.split_layers(op.layers, ref["u"][fe])
-    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
-                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=6, lr=0.1)
     g = H(best)[fe]
     assert np.all(g >= H(out["lb"])[fe] - 1e-6 * np.maximum(np.abs(g), 1))
     assert (g > H(out["lb"])[fe] + 1e-4).any()
-    assert_close(g, obest, 1e-4, "alpha-opt best bound")
+    for l, u in ((H(out["l"])[fe].astype(np.float64), H(out["u"])[fe].astype(np.float64)),
+                 (ref["l"][fe], ref["u"][fe])):
+        obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, opipe.split_layers(op.layers, l),
+                                      opipe.split_layers(op.layers, u), ref["lo"][fe], ref["hi"][fe],
+                                      ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=6,
+                                      state32=True, **ADAM)
+        assert_close(g, obest, 1e-5, "alpha-opt best bound")
 
 
 # ---------------------------------------------- full size, bench configuration
@@ -377,46 +402,6 @@ def test_invalid_arguments_are_rejected_before_launch():
     assert st == -1
 
 
-def _alpha_opt_sampled(w, n_sample, steps, seed, rel_plain=1e-5, rel_alpha=1e-4):
-    """The bench schedule (plain pass + `steps` slope iterations, lr 0.1) on the
-    whole batch; the oracle repeats it on sampled subdomains (the iterations
-    of one subdomain do not depend on the others)."""
-    op = OracleProp(w)
-    sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
-    prop = gpipe.Property.from_workload(w)
-    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
-    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
-    best, _ = gpipe.alpha_opt(prop, batch, out["l"], out["u"], out["infeasible"], steps=steps,
-                              lr=0.1)
-    sync()
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(w.B, n_sample, replace=False))
-    ref = op.run(subset_splits(sp, idx))
-    assert_close(H(out["lb"])[idx], ref["lb"], rel_plain, "plain lb (sampled)")
-    fe = ~ref["infeasible"]
-    assert np.array_equal(H(out["infeasible"])[idx].astype(bool), ref["infeasible"])
-    l_list = opipe.split_layers(op.layers, ref["l"][fe])
-    u_list = opipe.split_layers(op.layers, ref["u"][fe])
-    obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
-                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=steps, lr=0.1)
-    g = H(best)[idx][fe]
-    assert_close(g, obest, rel_alpha, "alpha-opt best bound (sampled)")
-    assert np.all(g >= H(out["lb"])[idx][fe] - 1e-6 * np.maximum(np.abs(g), 1))
-    return g, H(out["lb"])[idx][fe]
-
-
-def test_full_size_mnist_alpha_opt_sampled():
-    # 784-256x6-10, 16384 subdomains x 4 splits, 20 slope iterations (bench step)
-    g, plain = _alpha_opt_sampled(wl.mnist_mlp(B=16384), 6, 20, seed=11)
-    assert (g > plain + 1.0).any()
-
-
-def test_full_size_alpha_mlp_sampled():
-    # 784-1024x4-10, 8192 subdomains x 6 splits, alpha0 0.5, 20 Adam steps lr 0.1
-    g, plain = _alpha_opt_sampled(wl.alpha_mlp(B=8192), 4, 20, seed=12)
-    assert (g > plain + 1.0).any()
-
-
 def test_autograd_bound_matches_adjoint_and_fused_adam():
     w = wl.tiny_mlp(64)
     w.net = wl.he_mlp([5] + [50] * 6 + [5], 2, bias="uniform")
@@ -485,8 +470,8 @@ def test_pass_with_constraint_order_matches_oracle(make):
     l_list = opipe.split_layers(op.layers, ref["l"][fe])
     u_list = opipe.split_layers(op.layers, ref["u"][fe])
     obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][fe], ref["hi"][fe],
-                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=3, lr=0.1)
-    assert_close(H(best)[fe], obest, 1e-4, "alpha-opt with order")
+                                  ref["G"][fe], ref["h"][fe], ref["active"][fe], steps=3, state32=True, **ADAM)
+    assert_close(H(best)[fe], obest, 1e-5, "alpha-opt with order")
 
 
 # ------------------------------------------------------- conv layers (CNN)
@@ -518,8 +503,8 @@ def test_pass_cnn_matches_oracle(make):
     u_list = opipe.split_layers(op.layers, ref["u"][idx])
     obest, _, _ = opipe.alpha_opt(op.layers, w.C, w.t, l_list, u_list, ref["lo"][idx],
                                   ref["hi"][idx], ref["G"][idx], ref["h"][idx], ref["active"][idx],
-                                  steps=2, lr=0.1)
-    assert_close(H(best)[idx], obest, 1e-4, "cnn alpha-opt")
+                                  steps=2, state32=True, **ADAM)
+    assert_close(H(best)[idx], obest, 1e-5, "cnn alpha-opt")
 
 
 # ------------------------------------- top-k intermediate neurons (BaBSR score)
