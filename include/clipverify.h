@@ -269,6 +269,29 @@ cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const fl
 /* Workspace bytes of cv_concretize_planes (0 unless complete != 0). */
 cv_status cv_concretize_planes_workspace(cv_root root, int B, int complete, size_t* bytes);
 
+/* cv_concretize_planes for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, with the scratch taken from
+ * a static device array of CV_CONCRETIZE_PLANES_STATIC_BYTES (64 MiB) instead
+ * of a caller workspace.  The library holds one such array on every device
+ * it runs on until the process ends; the first call on a device looks up
+ * that device's copy (the current device: the one of `stream` and of every
+ * pointer).  The call itself allocates nothing, and records no timing events
+ * while the kernel-timing instrumentation is on.  Limit: the scratch
+ * cv_concretize_planes_workspace reports for (root, B, complete) must fit in
+ * the array, else CV_E_WORKSPACE and nothing is enqueued (with complete != 0
+ * about B * (8 U + n_hidden + 1536) bytes, U the root-unstable neurons).
+ * Calls on one device share its array and keep no state across calls, but
+ * two calls that overlap in time on one device (other streams, other
+ * threads) race on it: serialise them.  Other arguments, results and errors
+ * as cv_concretize_planes. */
+#define CV_CONCRETIZE_PLANES_STATIC_BYTES (64u << 20)
+cv_status cv_concretize_planes_static(cv_root root, const int32_t* pid, int B, const float* lo,
+                                      const float* hi, const cv_constraints* splits, int complete,
+                                      int passes, int topk, const float* weight, float* l,
+                                      float* u, uint8_t* infeasible, uint8_t* select,
+                                      hipStream_t stream);
+
 /* Weights of the neuron-selection score (heuristics appendix): weight[j] =
  * max(0, -mean over the M objective rows of Psi_mj), the coefficient with
  * which the ReLU output of hidden neuron j enters the CROWN lower bound of

@@ -23,7 +23,7 @@ EXPORTS = [
     "cv_net_autotune", "cv_net_tuning", "cv_net_set_tuning",
     "cv_root_create", "cv_root_create_ex", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
     "cv_root_unstable_count", "cv_rootset_create", "cv_root_count",
-    "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes",
+    "cv_clip_domains", "cv_constraint_order", "cv_concretize_planes", "cv_concretize_planes_static",
     "cv_concretize_planes_workspace", "cv_babsr_weights", "cv_babsr_weights_workspace",
     "cv_concretize", "cv_bound_propagate", "cv_bound_propagate_workspace",
     "cv_branch_relu", "cv_branch_input", "cv_intermediate_bounds",
@@ -88,6 +88,7 @@ def lib():
         "cv_clip_domains": (I, [P, P, I, I, P, P, P, P, I, P]),
         "cv_constraint_order": (I, [P, P, I, I, P, P, P, P, P]),
         "cv_concretize_planes": (I, [P, P, I, P, P, P, I, I, I, P, P, P, P, P, P, S, P]),
+        "cv_concretize_planes_static": (I, [P, P, I, P, P, P, I, I, I, P, P, P, P, P, P]),
         "cv_babsr_weights": (I, [P, P, I, P, P, P, P, S, P]),
         "cv_babsr_weights_workspace": (I, [P, I, P]),
         "cv_branch_relu": (I, [P, P, I, P, P, P, P, P, P, I, P, P, P, P, P, P, P]),

@@ -345,6 +345,22 @@ def concretize_planes(root, lo, hi, splits=None, complete=False, passes=1, infea
     return l, u, infeasible
 
 
+def concretize_planes_static(root, lo, hi, splits=None, complete=False, passes=1, infeasible=None,
+                             l=None, u=None, topk=-1, weight=None, select=None, pid=None):
+    """concretize_planes through the allocation-free entry point (scratch in
+    the library's static per-device array; no workspace)."""
+    B = lo.shape[0]
+    nh = root.net.n_hidden
+    l = torch.empty(B, nh, device="cuda") if l is None else l
+    u = torch.empty(B, nh, device="cuda") if u is None else u
+    if infeasible is None:
+        infeasible = torch.zeros(B, dtype=torch.uint8, device="cuda")
+    N.call("cv_concretize_planes_static", root.handle, _pid(pid), B, _p(lo), _p(hi),
+           _cref(splits), int(bool(complete)), int(passes), int(topk), _p(weight), _p(l), _p(u),
+           _p(infeasible), _p(select), _stream())
+    return l, u, infeasible
+
+
 def babsr_weights(net, root, C_, t, ws=None):
     """Weights of the neuron-selection score (cv_babsr_weights): [n_hidden]
     for a Root and C [M, n_out]; [P, n_hidden] for per-property C [P, M, n_out]."""

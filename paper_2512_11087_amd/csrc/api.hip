@@ -7,6 +7,7 @@
 #include <vector>
 
 #include <functional>
+#include <mutex>
 
 #include "clipverify.h"
 #include "cv_common.h"
@@ -17,6 +18,9 @@
 namespace {
 
 thread_local int g_last_hip = 0;
+// Set while an allocation-free entry point runs on this thread: the timing
+// instrumentation records no events then (creating one may allocate).
+thread_local bool t_noalloc = false;
 
 cv_status hip_fail(hipError_t e) {
   g_last_hip = (int)e;
@@ -64,10 +68,10 @@ struct Prof {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Prof(const char* n, double f, double by, hipStream_t st) : name(n), flops(f), bytes(by), s(st) {
-    if (g_prof_on && (a = prof_event())) (void)hipEventRecord(a, s);
+    if (g_prof_on && !t_noalloc && (a = prof_event())) (void)hipEventRecord(a, s);
   }
   ~Prof() {
-    if (!g_prof_on || !a) return;
+    if (!g_prof_on || t_noalloc || !a) return;
     hipEvent_t b = prof_event();
     if (b && hipEventRecord(b, s) == hipSuccess) g_prof.push_back({name, a, b, flops, bytes});
   }
@@ -314,6 +318,36 @@ cv_status root_sync_tab(cv_root_s* r) {
   if (hipMemcpy(r->dtab, &r->htab, sizeof(RootDev), hipMemcpyHostToDevice) != hipSuccess)
     return hip_fail(hipGetLastError());
   r->Umax = r->U;
+  return CV_OK;
+}
+
+// ---------------------------------------------- allocation-free variant
+// Scratch of cv_concretize_planes_static: a file-scope device array, one copy
+// on every device the library runs on, held until the process ends.  Host
+// code never passes the array's name as an address (in host code it is a
+// host-side stand-in); hipGetSymbolAddress, called once per device with that
+// device current, gives the device copy's address, which is what the kernels
+// receive.
+constexpr size_t kStaticScratchBytes = (size_t)CV_CONCRETIZE_PLANES_STATIC_BYTES;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on
+// that device).
+cv_status static_scratch(void** out) {
+  int dev = -1;
+  CV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CV_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return CV_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
   return CV_OK;
 }
 
@@ -1041,6 +1075,25 @@ cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const fl
     PLAUNCH("merge_neurons", 0, 16.0 * B * U, launch_merge_neurons(B, U, props, Nh, Ltmp, l, u, infeasible, s));
   }
   return CV_OK;
+}
+
+cv_status cv_concretize_planes_static(cv_root root, const int32_t* pid, int B, const float* lo,
+                                      const float* hi, const cv_constraints* splits, int complete,
+                                      int passes, int topk, const float* weight, float* l,
+                                      float* u, uint8_t* infeasible, uint8_t* select,
+                                      hipStream_t s) {
+  if (!root || B < 0) return CV_E_INVALID;
+  size_t need = 0;
+  cv_status st = cv_concretize_planes_workspace(root, B, complete, &need);
+  if (st) return st;
+  if (need > kStaticScratchBytes) return CV_E_WORKSPACE;
+  void* ws = nullptr;
+  if (need > 0 && (st = static_scratch(&ws))) return st;
+  t_noalloc = true;
+  st = cv_concretize_planes(root, pid, B, lo, hi, splits, complete, passes, topk, weight, l, u,
+                            infeasible, select, ws, need > 0 ? kStaticScratchBytes : 0, s);
+  t_noalloc = false;
+  return st;
 }
 
 cv_status cv_babsr_weights_workspace(cv_net net, int M, size_t* bytes) {
