@@ -359,17 +359,25 @@ cv_status cv_bound_propagate_workspace(cv_net net, int P, int B, int M, size_t* 
  * clipping multipliers fixed, by a hand-written adjoint of the backward
  * pass; then, when lr > 0, one projected Adam ascent step (bias-corrected
  * moments with beta1, beta2, eps; `step` >= 1 is the 1-based step index)
- * on alpha, clamped to [0,1].
- * alpha, adam_m, adam_v: device [B, M, n_hidden] in/out (adam_* may be NULL
- * when lr == 0).  grad: device [B, M, n_hidden] out or NULL.
+ * on alpha, clamped to [0,1] (the experimental settings' slope
+ * optimisation: Adam, lr 0.1, 20 iterations).
+ * alpha: device [B, M, n_hidden] in/out.  Step 1 starts an optimisation:
+ * Adam's moments are taken as zero (adam_m, adam_v are written, not read)
+ * and, when alpha_init is in [0, 1], every slope is alpha_init (alpha is
+ * then written, not read); alpha_init < 0 reads alpha at step 1 as well,
+ * and must be < 0 at later steps (CV_E_INVALID otherwise).
+ * adam_m, adam_v: device [B, M, n_hidden] in/out (may be NULL when lr == 0).
+ * best: device [B, M] in/out or NULL: the running best bound over the steps,
+ * max(best, lb) (lb itself at step 1, where best is not read); +inf for an
+ * infeasible subdomain.  grad: device [B, M, n_hidden] out or NULL.
  * ws: at least cv_alpha_step_workspace(...) bytes. */
 cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t,
-                        const float* l, const float* u, float* alpha,
+                        const float* l, const float* u, float* alpha, float alpha_init,
                         const float* lo, const float* hi, uint8_t* infeasible,
                         cv_root root, const int32_t* pid, const cv_constraints* cons,
                         int passes, float* adam_m, float* adam_v, int step, float lr,
                         float beta1, float beta2, float eps,
-                        float* lb, float* grad, void* ws, size_t ws_bytes,
+                        float* lb, float* best, float* grad, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 cv_status cv_alpha_step_workspace(cv_net net, int P, int B, int M, size_t* bytes);
 
@@ -431,6 +439,14 @@ cv_status cv_profile_reset(void);
 cv_status cv_profile_collect(int* entries);
 cv_status cv_profile_entry(int i, const char** name, int* launches, double* ms,
                            double* flops, double* bytes);
+
+/* Roofline denominators measured on the current device (benchmark
+ * instrumentation, not a hot call: it allocates 2 GiB, synchronises `stream`
+ * and frees): the HBM bandwidth of a streaming copy of 1 GiB (bytes read +
+ * written per second) and the float64 matrix-core rate of a loop of
+ * independent v_mfma_f64_16x16x4_f64 on 2048 workgroups, each the best of
+ * five timed runs after one warm-up.  Host outputs in GB/s and TFLOP/s. */
+cv_status cv_measure_peaks(double* hbm_gbs, double* f64_mfma_tflops, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -30,6 +30,7 @@ EXPORTS = [
     "cv_intermediate_bounds_workspace",
     "cv_alpha_step", "cv_alpha_step_workspace",
     "cv_profile_enable", "cv_profile_reset", "cv_profile_collect", "cv_profile_entry",
+    "cv_measure_peaks",
 ]
 
 
@@ -100,10 +101,11 @@ def lib():
         "cv_bound_propagate": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, P, I, P, P, P, P, S,
                                    P]),
         "cv_bound_propagate_workspace": (I, [P, I, I, I, P]),
-        "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, P, P, P, P, P, P, I, P, P, I, F, F, F, F,
-                              P, P, P, S, P]),
+        "cv_alpha_step": (I, [P, I, I, P, P, P, P, P, F, P, P, P, P, P, P, I, P, P, I, F, F, F,
+                              F, P, P, P, P, S, P]),
         "cv_alpha_step_workspace": (I, [P, I, I, I, P]),
         "cv_profile_enable": (I, [I]),
+        "cv_measure_peaks": (I, [P, P, P]),
         "cv_profile_reset": (I, []),
         "cv_profile_collect": (I, [P]),
         "cv_profile_entry": (I, [I, P, P, P, P, P]),
@@ -151,3 +153,11 @@ def profile_collect():
         out[name.value.decode()] = dict(launches=cnt.value, ms=ms.value, flops=fl.value,
                                         bytes=by.value)
     return out
+
+
+def measure_peaks(stream=None):
+    """(HBM GB/s of a streaming copy, FP64 matrix-core TFLOP/s) measured on the
+    current device by cv_measure_peaks."""
+    gbs, tfl = C.c_double(), C.c_double()
+    call("cv_measure_peaks", C.byref(gbs), C.byref(tfl), stream)
+    return gbs.value, tfl.value

@@ -410,10 +410,11 @@ def bound_propagate(net, root, C_, t, l, u, lo, hi, alpha=None, alpha_default=0.
 
 
 def alpha_step_into(net, root, C_, t, l, u, alpha, lo, hi, infeasible, cons, passes, adam_m,
-                    adam_v, step, lr, lb, ws, beta1=0.9, beta2=0.999, eps=1e-8, pid=None):
-    """alpha_step writing the bound into a given buffer lb [B, M] and using a
-    workspace that is already large enough (no allocation: usable under
-    stream capture)."""
+                    adam_v, step, lr, lb, ws, beta1=0.9, beta2=0.999, eps=1e-8, pid=None,
+                    alpha_init=-1.0, best=None):
+    """alpha_step writing the bound into a given buffer lb [B, M] (and the
+    running best into ``best``) with a workspace that is already large
+    enough (no allocation: usable under stream capture)."""
     B = lo.shape[0]
     M = C_.shape[-2]
     need = C.c_size_t()
@@ -421,18 +422,20 @@ def alpha_step_into(net, root, C_, t, l, u, alpha, lo, hi, infeasible, cons, pas
     buf = ws.buf
     if buf is None or buf.numel() < need.value:
         raise RuntimeError("workspace too small for alpha_step_into; size it before capture")
-    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
-           _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons), int(passes), _p(adam_m),
-           _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
-           None, _p(buf), need.value, _stream())
+    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha),
+           float(alpha_init), _p(lo), _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons),
+           int(passes), _p(adam_m), _p(adam_v), int(step), float(lr), float(beta1), float(beta2),
+           float(eps), _p(lb), _p(best), None, _p(buf), need.value, _stream())
     return lb
 
 
 def alpha_step(net, root, C_, t, l, u, alpha, lo, hi, infeasible=None, cons=None, passes=1,
                adam_m=None, adam_v=None, step=1, lr=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
-               want_grad=False, ws=None, pid=None):
+               want_grad=False, ws=None, pid=None, alpha_init=-1.0, best=None):
     """Bound at the current alpha [B, M, n_hidden] and its gradient, then
-    (lr > 0) one Adam ascent step on alpha in place.  Returns (lb, grad)."""
+    (lr > 0) one Adam ascent step on alpha in place; ``best`` [B, M] (if
+    given) becomes max(best, bound), the bound itself at step 1; at step 1
+    an ``alpha_init`` in [0, 1] replaces alpha.  Returns (lb, grad)."""
     B = lo.shape[0]
     M = C_.shape[-2]
     lb = torch.empty(B, M, device="cuda")
@@ -440,8 +443,8 @@ def alpha_step(net, root, C_, t, l, u, alpha, lo, hi, infeasible=None, cons=None
     need = C.c_size_t()
     N.call("cv_alpha_step_workspace", net.handle, root.P, B, M, C.byref(need))
     buf = (ws or Workspace()).get(need.value)
-    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha), _p(lo),
-           _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons), int(passes), _p(adam_m),
-           _p(adam_v), int(step), float(lr), float(beta1), float(beta2), float(eps), _p(lb),
-           _p(grad), _p(buf), need.value, _stream())
+    N.call("cv_alpha_step", net.handle, B, M, _p(C_), _p(t), _p(l), _p(u), _p(alpha),
+           float(alpha_init), _p(lo), _p(hi), _p(infeasible), root.handle, _pid(pid), _cref(cons),
+           int(passes), _p(adam_m), _p(adam_v), int(step), float(lr), float(beta1), float(beta2),
+           float(eps), _p(lb), _p(best), _p(grad), _p(buf), need.value, _stream())
     return lb, grad

@@ -626,9 +626,9 @@ cv_status cv_net_autotune(cv_net net, int B, int M, hipStream_t s) {
           double* out = layer < L - 1 ? A1 : nullptr;
           launch = [=]() {
             return launch_gemm_adjoint((int)R, K, N, A0, net->Wt[layer - 1], cd, net->b[layer - 1],
-                                       M, Nh, net->off[layer - 1], l, u, nullptr, 0.5, trace,
-                                       nullptr, nullptr, nullptr, nullptr, 0.0, 0.9, 0.999, 1e-8, 1,
-                                       out, v, s);
+                                       M, Nh, net->off[layer - 1], l, u, nullptr, nullptr, 0.5,
+                                       trace, nullptr, nullptr, nullptr, nullptr, 0.0, 0.9, 0.999,
+                                       1e-8, 1, false, out, v, s);
           };
         }
         float ms = 0.0f;
@@ -1261,7 +1261,7 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
   }
   if (cons && cons->kmax > 0)
     PLAUNCH("ca_rows", 0, 8.0 * B * M * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(B * M, M, net->n[0], cc, passes, w.Ax, w.rowc, w.rowerr, lo, hi,
-                          infeasible, lb, nullptr, 0, s));
+                          infeasible, lb, nullptr, 0, nullptr, 0, s));
   return CV_OK;
 }
 
@@ -1273,22 +1273,27 @@ cv_status cv_alpha_step_workspace(cv_net net, int P, int B, int M, size_t* bytes
 }
 
 cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t, const float* l,
-                        const float* u, float* alpha, const float* lo, const float* hi,
-                        uint8_t* infeasible, cv_root root, const int32_t* pid,
+                        const float* u, float* alpha, float alpha_init, const float* lo,
+                        const float* hi, uint8_t* infeasible, cv_root root, const int32_t* pid,
                         const cv_constraints* cons, int passes,
                         float* adam_m, float* adam_v, int step, float lr, float beta1, float beta2,
-                        float eps, float* lb, float* grad, void* ws, size_t ws_bytes,
+                        float eps, float* lb, float* best, float* grad, void* ws, size_t ws_bytes,
                         hipStream_t s) {
   cv_status st = check_prop(net, root, B, M, C, t, l, u, lo, hi, lb);
   if (st || B == 0) return st;
   if (!alpha) return CV_E_INVALID;
   if (cons && passes < 1) return CV_E_INVALID;
   if (lr < 0.0f || !(lr == lr)) return CV_E_INVALID;
+  if (step < 1) return CV_E_INVALID;
   if (lr > 0.0f) {
-    if (!adam_m || !adam_v || step < 1) return CV_E_INVALID;
+    if (!adam_m || !adam_v) return CV_E_INVALID;
     if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
       return CV_E_INVALID;
   }
+  // step 1 starts an optimisation: the slopes are alpha_init when it is in
+  // [0, 1] (alpha is then only written) and Adam's moments are zero
+  const bool init = step == 1 && finite01(alpha_init);
+  if (!init && !(alpha_init < 0.0f)) return CV_E_INVALID;
   size_t need = 0;
   if ((st = cv_alpha_step_workspace(net, root->P, B, M, &need))) return st;
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
@@ -1297,18 +1302,21 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   Bwd w;
   const int R = B * M;
   bwd_layout(net, net->L, R, M, root->P, true, true, ws, &w);
-  st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u, alpha, 0.0, lo, hi,
-                    infeasible, w, lb, nullptr, nullptr, s);
+  st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u,
+                    init ? nullptr : alpha, init ? (double)alpha_init : 0.0, lo, hi, infeasible,
+                    w, lb, nullptr, nullptr, s);
   if (st) return st;
   // complete clipping (or plain concretization) leaves the minimising corner
-  // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane
+  // x* of the final dual in w.Ax: the adjoint of the bound w.r.t. the plane;
+  // it also folds the bound into the running best
   CvCons none{};
   if (cons && cons->kmax > 0 && cc.kmax <= CA_SLOTS) {
     PLAUNCH("cons_stats", 0, 8.0 * B * net->n[0] + 4.0 * B * cc.kmax * net->n[0], launch_cons_stats(B, net->n[0], cc, lo, hi, w.kst, s));
     cc.kstats = w.kst;
   }
-  PLAUNCH("ca_rows", 0, 16.0 * R * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes < 1 ? 1 : passes,
-                        w.Ax, w.rowc, w.rowerr, lo, hi, infeasible, lb, nullptr, 1, s));
+  PLAUNCH("ca_rows", 0, 16.0 * R * net->n[0] + 8.0 * B * net->n[0], launch_ca_rows(R, M, net->n[0], (cons && cons->kmax > 0) ? cc : none, passes,
+                        w.Ax, w.rowc, w.rowerr, lo, hi, infeasible, lb, nullptr, 1, best,
+                        step == 1 ? 1 : 0, s));
   const double dlr = lr;
   double* cur = w.Ax;
   double* bufs[2] = {w.Om0, w.Om1};
@@ -1317,12 +1325,61 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
     double* out = (k < net->L - 1) ? bufs[(k - 1) & 1] : nullptr;
     const ConvDesc* cd = conv_of(net, k);
     PLAUNCH(cd ? "conv_adjoint" : "gemm_adjoint", layer_flops(net, k, R), 8.0 * R * (K + (out ? N : 0)) + 28.0 * R * N + layer_wbytes(net, k), launch_gemm_adjoint(R, K, N, cur, net->Wt[k - 1], cd, net->b[k - 1], M, net->n_hidden,
-                               net->off[k - 1], l, u, alpha, 0.0, w.trace, infeasible, grad,
-                               adam_m, adam_v, dlr, beta1, beta2, eps, step < 1 ? 1 : step, out,
+                               net->off[k - 1], l, u, alpha, init ? nullptr : alpha,
+                               init ? (double)alpha_init : 0.0, w.trace, infeasible, grad,
+                               adam_m, adam_v, dlr, beta1, beta2, eps, step, step == 1, out,
                                net->tune[CV_TUNE_ADJOINT][k - 1], s));
     cur = out;
   }
   return CV_OK;
+}
+
+cv_status cv_measure_peaks(double* hbm_gbs, double* f64_mfma_tflops, hipStream_t s) {
+  if (!hbm_gbs || !f64_mfma_tflops) return CV_E_INVALID;
+  const size_t bytes = (size_t)1 << 30;
+  const int blocks = 2048, iters = 20000;
+  void *src = nullptr, *dst = nullptr;
+  double* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  cv_status st = CV_OK;
+  auto fail = [&](hipError_t e) {
+    if (e != hipSuccess && st == CV_OK) st = hip_fail(e);
+    return e != hipSuccess;
+  };
+  if (hipMalloc(&src, bytes) != hipSuccess || hipMalloc(&dst, bytes) != hipSuccess ||
+      hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(double)) != hipSuccess) {
+    st = CV_E_NOMEM;
+  }
+  if (st == CV_OK && !fail(hipEventCreate(&e0)) && !fail(hipEventCreate(&e1)) &&
+      !fail(hipMemsetAsync(src, 0, bytes, s))) {
+    float best = 0.0f;
+    for (int rep = 0; rep < 6 && st == CV_OK; ++rep) {  // first run warms up
+      float ms = 0.0f;
+      if (fail(hipEventRecord(e0, s)) || fail(launch_probe_copy(src, dst, bytes, s)) ||
+          fail(hipEventRecord(e1, s)) || fail(hipEventSynchronize(e1)) ||
+          fail(hipEventElapsedTime(&ms, e0, e1)))
+        break;
+      if (rep > 0 && (best == 0.0f || ms < best)) best = ms;
+    }
+    if (st == CV_OK) *hbm_gbs = 2.0 * (double)bytes / (best * 1e-3) / 1e9;
+    best = 0.0f;
+    for (int rep = 0; rep < 6 && st == CV_OK; ++rep) {
+      float ms = 0.0f;
+      if (fail(hipEventRecord(e0, s)) || fail(launch_probe_mfma(blocks, iters, out, s)) ||
+          fail(hipEventRecord(e1, s)) || fail(hipEventSynchronize(e1)) ||
+          fail(hipEventElapsedTime(&ms, e0, e1)))
+        break;
+      if (rep > 0 && (best == 0.0f || ms < best)) best = ms;
+    }
+    const double flops = (double)blocks * 4.0 * iters * 4.0 * 2048.0;
+    if (st == CV_OK) *f64_mfma_tflops = flops / (best * 1e-3) / 1e12;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  if (out) (void)hipFree(out);
+  return st;
 }
 
 cv_status cv_profile_enable(int on) {

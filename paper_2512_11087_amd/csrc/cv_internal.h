@@ -244,11 +244,15 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
                                const ConvDesc* conv,
                                const float* b, int M, int Nh, int off, const float* lz,
                                const float* uz,
-                               float* alpha, double alpha_def,
+                               float* alpha, const float* alpha_in, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
-                               double eps, int step, double* Psibar_out, int variant,
+                               double eps, int step, bool fresh, double* Psibar_out, int variant,
                                hipStream_t s);
+
+// peak probes (benchmark instrumentation)
+hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_probe_mfma(int blocks, int iters, double* out, hipStream_t s);
 
 // re-concretization of the cached planes
 hipError_t launch_fill_stable(int B, int Nh, int nSmax, CvProps props, float* l, float* u,
@@ -264,7 +268,7 @@ hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, 
 hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
                           const double* rowc, const double* rowerr, const float* lo,
                           const float* hi, uint8_t* infeasible, float* lb, float* beta_out,
-                          int write_xstar, hipStream_t s);
+                          int write_xstar, float* best, int best_init, hipStream_t s);
 hipError_t launch_ca_generic(int B, int P, int n, const float* A, int A_shared, const float* c,
                              const float* lo, const float* hi, const CvCons* cons, int passes,
                              float* lb, float* ub, float* beta_out, uint8_t* infeasible,

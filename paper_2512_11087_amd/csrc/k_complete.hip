@@ -180,16 +180,8 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       // so min(g lo, g hi) = g * (g >= 0 ? min(lo, hi) : max(lo, hi))
       // exactly; the opposite-sign test is branch-free, and a skipped weight
       // adds +0.0 to a non-negative sum, which leaves it unchanged).
-      double m = 0.0, em = 0.0, tmax = 0.0, wsg = 0.0;
+      double m = 0.0, em = 0.0, tmax = 0.0;
       if (cons->kstats) {  // m, em and tmax of this (subdomain, constraint) computed once
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          const double gg = (double)g[e];
-          const double wd = fabs(gg) * ((double)xh[e] - (double)xl[e]);
-          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
-          wsg += opp ? wd : 0.0;
-        }
-        wsg = tm.sum(wsg);
         m = st.m;
         em = st.em;
         tmax = (double)st.tmax;
@@ -204,14 +196,35 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
           tmax = fmax(tmax, te);
         }
         tm.sum_sum_max(m, em, tmax);
+      }
+      // The weight of the coordinates whose breakpoint is positive, W(> 0).
+      // Workgroup teams (rows over 1024 wide, where most constraints need a
+      // search) screen it in float32: each weight |g_j| (hi_j - lo_j) is then
+      // within 2^-23 of its value and a member's sum of up to 16 of them
+      // within 15 * 2^-24 more, so the team sum `ws` is within 2^-19 ws of the
+      // exact one, and only when that does not settle `ws > S` is the exact
+      // float64 sum formed; the decision is the exact one either way.  Wave
+      // teams sum in float64 directly (measured faster there: the screen
+      // costs them registers).
+      constexpr bool SCREEN = Team::PER_BLOCK == 1;
+      double ws = 0.0;
+      if constexpr (SCREEN) {
+        float w32 = 0.0f;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          const double gg = (double)g[e];
-          const double wd = fabs(gg) * ((double)xh[e] - (double)xl[e]);
           const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
-          wsg += opp ? wd : 0.0;
+          const float wf = fabsf(g[e]) * (xh[e] - xl[e]);
+          w32 += opp ? wf : 0.0f;
         }
-        wsg = tm.sum(wsg);
+        ws = tm.sum((double)w32);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const double wd = fabs((double)g[e]) * ((double)xh[e] - (double)xl[e]);
+          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
+          ws += opp ? wd : 0.0;
+        }
+        ws = tm.sum(ws);
       }
       m += h;
       if (bold != 0.0) {
@@ -230,10 +243,21 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
       // rounded outward, which leaves a slope of up to one float32 ulp of the
       // end times |g_i| <= 2^-23 tmax; the float64 sums add at most
       // gamma_{2n+8} (em + |h| + wsg).
-      const double tol = 2.384185791015625e-07 * tmax + cv_gamma(2 * n + 8) * (em + fabs(h) + wsg);
+      const double tol = 2.384185791015625e-07 * tmax + cv_gamma(2 * n + 8) * (em + fabs(h) + ws);
       const double S = -m + tol;
+      bool search = ws > S + (SCREEN ? 0x1p-18 * ws : 0.0);
+      if (SCREEN && !search && ws > S - 0x1p-18 * ws) {  // too close to call in float32
+        double wsg = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const double wd = fabs((double)g[e]) * ((double)xh[e] - (double)xl[e]);
+          const bool opp = (g[e] != 0.0f) & (a[e] != 0.0) & (signbit(a[e]) != signbit(g[e]));
+          wsg += opp ? wd : 0.0;
+        }
+        search = tm.sum(wsg) > S;
+      }
       double bk = 0.0;
-      if (wsg > S) {
+      if (search) {
         // breakpoints and the exact candidate set (a division may underflow
         // to q = 0, which is not a candidate), staged in LDS for the search
         // with |g_j|; the candidates' total weight and their range, reduced
@@ -433,7 +457,8 @@ __global__ __launch_bounds__(256, (ca_rows_blocks<Team, EPL>())) void k_ca_rows(
                                                  const double* __restrict__ rowerr,
                                                  const float* __restrict__ lo,
                                                  const float* __restrict__ hi, uint8_t* infeasible,
-                                                 float* lb, float* beta_out, int write_xstar) {
+                                                 float* lb, float* beta_out, int write_xstar,
+                                                 float* best, int best_init) {
   __shared__ CaShared<Team, EPL> sh;
   const Team tm = team_of(sh);
   constexpr int T = Team::SIZE;
@@ -445,7 +470,10 @@ __global__ __launch_bounds__(256, (ca_rows_blocks<Team, EPL>())) void k_ca_rows(
   double* arow = Ax + (size_t)r * n;
   const cv_buf ba = cv_buffer(arow, 8u * n);
   if (infeasible && infeasible[b]) {
-    if (tm.t == 0) lb[r] = INFINITY;
+    if (tm.t == 0) {
+      lb[r] = INFINITY;
+      if (best) best[r] = INFINITY;
+    }
     return;
   }
   double a[EPL];
@@ -461,12 +489,14 @@ __global__ __launch_bounds__(256, (ca_rows_blocks<Team, EPL>())) void k_ca_rows(
                                       write_xstar ? arow : nullptr, beta_slice(sh), q_slice(sh),
                                       w_slice(sh));
   if (tm.t == 0) {
+    float v = INFINITY;
     if (empty) {
-      lb[r] = INFINITY;
       if (infeasible) infeasible[b] = 1;
     } else {
-      lb[r] = fmaxf(lb[r], rd32(L));
+      v = fmaxf(lb[r], rd32(L));
     }
+    lb[r] = v;
+    if (best) best[r] = best_init ? v : fmaxf(best[r], v);
   }
 }
 
@@ -581,12 +611,13 @@ hipError_t launch_cons_stats(int B, int n, const CvCons& cons, const float* lo, 
 hipError_t launch_ca_rows(int R, int M, int n, const CvCons& cons, int passes, double* Ax,
                           const double* rowc, const double* rowerr, const float* lo,
                           const float* hi, uint8_t* infeasible, float* lb, float* beta_out,
-                          int write_xstar, hipStream_t s) {
+                          int write_xstar, float* best, int best_init, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   if (cons.kmax > CA_KMAX) return hipErrorInvalidValue;
   CV_DISPATCH_TEAM(n, hipLaunchKernelGGL((k_ca_rows<TM, E>), dim3(team_blocks(R, TM::PER_BLOCK)),
                                        dim3(256), 0, s, R, M, n, cons, passes, Ax, rowc, rowerr,
-                                       lo, hi, infeasible, lb, beta_out, write_xstar));
+                                       lo, hi, infeasible, lb, beta_out, write_xstar, best,
+                                       best_init));
   return hipGetLastError();
 }
 

@@ -135,11 +135,11 @@ __device__ __forceinline__ void load_bn(const float* __restrict__ Bm, int ldb, i
 // the global loads of chunk c+1 are in flight into registers; they are
 // written to the other buffer afterwards, one barrier per chunk.
 // One BM x BN output tile at (m0, n0); its row-sum partials go to column
-// tile blockIdx.y.  Ends with LDS free for the next call.
+// tile `tn`.  Ends with LDS free for the next call.
 template <class T, class LoadA, class Epi>
 __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, const LoadA& la,
                                           const float* __restrict__ Bm, int ldb, const Epi& epi,
-                                          double* __restrict__ part, int ntiles) {
+                                          double* __restrict__ part, int ntiles, int tn) {
   constexpr int GBM = T::BM, GBN = T::BN, WN = T::WN, MI = T::MI, NI = T::NI;
   constexpr int SA_LD = T::SA_LD, SB_LD = T::SB_LD, APT = T::APT, BPT = T::BPT;
   __shared__ double sA[2][GBK * SA_LD];
@@ -261,18 +261,31 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
           double t = 0.0;
 #pragma unroll
           for (int w = 0; w < NWAVE; ++w) t += sRed[(w * GBM + tid) * NS + s];
-          part[((size_t)r * ntiles + blockIdx.y) * NS + s] = t;
+          part[((size_t)r * ntiles + tn) * NS + s] = t;
         }
       }
     }
   }
 }
 
+// Tile order: workgroup i runs on XCD i mod 8, each XCD with its own L2, so
+// the linear grid is renumbered (xcd_block) to give every XCD a contiguous
+// range, walked row tile by row tile with all `ntiles` column tiles of a row
+// tile next to each other: they run at about the same time on one XCD, and
+// the rows of A that all of them read come from HBM once.
+__device__ __forceinline__ void tile_of(int ntiles, int& tm, int& tn) {
+  const int t = (int)xcd_block(blockIdx.x, gridDim.x);
+  tm = t / ntiles;
+  tn = t - tm * ntiles;
+}
+
 template <class T, int OCC, class LoadA, class Epi>
 __global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la,
                                                    const float* __restrict__ Bm, int ldb, Epi epi,
                                                    double* __restrict__ part, int ntiles) {
-  gemm_tile<T>(blockIdx.x * T::BM, blockIdx.y * T::BN, R, K, N, la, Bm, ldb, epi, part, ntiles);
+  int tm, tn;
+  tile_of(ntiles, tm, tn);
+  gemm_tile<T>(tm * T::BM, tn * T::BN, R, K, N, la, Bm, ldb, epi, part, ntiles, tn);
 }
 
 // Hidden layer of the backward pass: psi = (Omega W)[r, j] is the coefficient
@@ -455,6 +468,8 @@ struct EpiAdj {
   double lr, b1, b2, eps, bc1, bc2;
   double* out;
   int ldo;
+  const float* alpha_in;  // slopes read (null: alpha_def everywhere); alpha: where they are written
+  bool fresh;             // Adam's moments start at zero (not read)
   struct Row {
     const float* l;
     const float* u;
@@ -471,15 +486,15 @@ struct EpiAdj {
   };
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
     const size_t ri = w.ri + j;
-    const bool adam = lr > 0.0 && alpha;
-    return Pre{w.l[j], w.u[j], trace[ri], alpha ? alpha[ri] : (float)alpha_def,
+    const bool adam = lr > 0.0 && alpha && !fresh;
+    return Pre{w.l[j], w.u[j], trace[ri], alpha_in ? alpha_in[ri] : (float)alpha_def,
                adam ? am[ri] : 0.0f, adam ? av[ri] : 0.0f};
   }
   __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double acc,
                                         double*) const {
     const double om = acc + (double)bias[j];
     const size_t ri = w.ri + j;
-    const double al = alpha ? (double)p.al : alpha_def;
+    const double al = alpha_in ? (double)p.al : alpha_def;
     const double psi = (double)p.psi;
     const Relax rl = relax_apply(psi, relax_line(p.l, p.u), al);
     const bool dead = w.dead;
@@ -1004,8 +1019,10 @@ __device__ __forceinline__ int tile_next_prop(const CvProps& props, int m0, int 
 
 template <class T, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_gemm_planes(int B, int n0, LoadBox la, CvProps props,
-                                                          int Nh, float* l, float* u) {
-  const int m0 = blockIdx.x * T::BM, c0 = blockIdx.y * T::BN;
+                                                          int Nh, float* l, float* u, int ntiles) {
+  int tm, tn;
+  tile_of(ntiles, tm, tn);
+  const int m0 = tm * T::BM, c0 = tn * T::BN;
   const int rows = min(T::BM, B - m0);
   for (int p = tile_next_prop(props, m0, rows, -1); p < props.P;
        p = tile_next_prop(props, m0, rows, p)) {
@@ -1013,7 +1030,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm_planes(int B, int n0, LoadBox
     const int N = 2 * rd.U;
     if (c0 >= N) continue;
     EpiPlanes<true> e{rd.U, Nh, rd.cP, rd.eP, rd.uidx, rd.l0, rd.u0, l, u, props, p};
-    gemm_tile<T>(m0, c0, B, 2 * n0, N, la, rd.P, N, e, nullptr, 1);
+    gemm_tile<T>(m0, c0, B, 2 * n0, N, la, rd.P, N, e, nullptr, 1, 0);
   }
 }
 
@@ -1022,9 +1039,9 @@ hipError_t run_gemm(int R, int K, int N, LoadA la, const float* Bm, int ldb, Epi
                     double* part, hipStream_t s) {
   if (R <= 0 || N <= 0) return hipSuccess;
   const int nt = (N + T::BN - 1) / T::BN;
-  dim3 grid((R + T::BM - 1) / T::BM, nt);
-  hipLaunchKernelGGL((k_gemm<T, OCC, LoadA, Epi>), grid, dim3(256), 0, s, R, K, N, la, Bm, ldb, epi,
-                     part, nt);
+  const long long nblk = (long long)((R + T::BM - 1) / T::BM) * nt;
+  hipLaunchKernelGGL((k_gemm<T, OCC, LoadA, Epi>), dim3((unsigned)nblk), dim3(256), 0, s, R, K, N,
+                     la, Bm, ldb, epi, part, nt);
   return hipGetLastError();
 }
 
@@ -1090,23 +1107,24 @@ hipError_t launch_gemm_planes(int B, int n0, int Umax, const float* lo, const fl
     return run_gemm<TilePlanes>(B, 2 * n0, 2 * rd.U, LoadBox{lo, hi, n0}, rd.P, 2 * rd.U, e,
                                 nullptr, s);
   }
-  dim3 grid((B + TilePlanes::BM - 1) / TilePlanes::BM, (2 * Umax + TilePlanes::BN - 1) / TilePlanes::BN);
-  hipLaunchKernelGGL((k_gemm_planes<TilePlanes, 2>), grid, dim3(256), 0, s, B, n0,
-                     LoadBox{lo, hi, n0}, props, Nh, l, u);
+  const int nt = (2 * Umax + TilePlanes::BN - 1) / TilePlanes::BN;
+  const long long nblk = (long long)((B + TilePlanes::BM - 1) / TilePlanes::BM) * nt;
+  hipLaunchKernelGGL((k_gemm_planes<TilePlanes, 2>), dim3((unsigned)nblk), dim3(256), 0, s, B, n0,
+                     LoadBox{lo, hi, n0}, props, Nh, l, u, nt);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const float* Wt,
                                const ConvDesc* conv, const float* b, int M, int Nh, int off, const float* lz,
                                const float* uz,
-                               float* alpha, double alpha_def,
+                               float* alpha, const float* alpha_in, double alpha_def,
                                const float* trace, const uint8_t* infeasible, float* grad,
                                float* adam_m, float* adam_v, double lr, double b1, double b2,
-                               double eps, int step, double* Psibar_out, int variant,
+                               double eps, int step, bool fresh, double* Psibar_out, int variant,
                                hipStream_t s) {
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
   EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
-           lr, b1, b2, eps, bc1, bc2, Psibar_out, N};
+           lr, b1, b2, eps, bc1, bc2, Psibar_out, N, alpha_in, fresh};
   if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s, variant);
   return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

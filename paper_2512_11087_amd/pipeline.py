@@ -184,32 +184,28 @@ def plain_pass(prop, batch, cfg=PassConfig(), out=None, planes=False):
 def alpha_opt(prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0=0.5,
               complete=True, passes=1, state=None):
     """Slope optimisation: ``steps`` x (bound, adjoint, Adam).  Returns the
-    best bound over the iterations [B, M] and the final alpha."""
+    best bound over the iterations [B, M] and the final alpha.  The first
+    call starts from alpha0 with zero Adam moments and the library keeps the
+    running best, so no other kernel runs between the calls."""
     B = batch.lo.shape[0]
     M, nh = prop.M, prop.net.n_hidden
     if state is None:
         state = {}
-    alpha = state.get("alpha")
-    if alpha is None:
-        alpha = torch.full((B, M, nh), alpha0, device="cuda")
-        m = torch.zeros_like(alpha)
-        v = torch.zeros_like(alpha)
-        state.update(alpha=alpha, m=m, v=v)
-    else:
+    if state.get("alpha") is None:
+        alpha = torch.empty(B, M, nh, device="cuda")
+        state.update(alpha=alpha, m=torch.empty_like(alpha), v=torch.empty_like(alpha),
+                     best=torch.empty(B, M, device="cuda"))
+    alpha, best = state["alpha"], state["best"]
+    if steps < 1:
         alpha.fill_(alpha0)
-        state["m"].zero_()
-        state["v"].zero_()
-    best = state.get("best")
-    if best is None:
-        best = torch.empty(B, M, device="cuda")
-        state["best"] = best
-    best.fill_(-float("inf"))
+        best.fill_(-float("inf"))
+        return best, alpha
     cons = batch.cons() if complete else None
     for s in range(1, steps + 1):
-        lb, _ = api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha, batch.lo,
-                               batch.hi, infeasible, cons, passes, state["m"], state["v"], s,
-                               lr * decay ** (s - 1), ws=prop.ws, pid=batch.pid)
-        torch.maximum(best, lb, out=best)
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, l, u, alpha, batch.lo, batch.hi,
+                       infeasible, cons, passes, state["m"], state["v"], s, lr * decay ** (s - 1),
+                       ws=prop.ws, pid=batch.pid, alpha_init=alpha0 if s == 1 else -1.0,
+                       best=best)
     return best, alpha
 
 
@@ -272,8 +268,9 @@ class AlphaOptGraph:
     captured once into a HIP graph and replayed: the step index and learning
     rate of every iteration are baked into its launches, the buffers are
     allocated before capture (the calls themselves only launch kernels).
-    ``run()`` resets alpha and the Adam moments inside the graph and returns
-    the best bound [B, M] over the iterations (a buffer the graph writes)."""
+    ``run()`` starts from alpha0 with zero Adam moments (the first step's
+    launches do that) and returns the best bound [B, M] over the iterations
+    (a buffer the graph writes)."""
 
     def __init__(self, prop, batch, l, u, infeasible, steps=20, lr=0.1, decay=1.0, alpha0=0.5,
                  complete=True, passes=1):
@@ -293,16 +290,12 @@ class AlphaOptGraph:
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             with torch.cuda.graph(self.graph, stream=side):
-                self.alpha.fill_(alpha0)
-                self.m.fill_(0.0)
-                self.v.fill_(0.0)
-                self.best.fill_(-float("inf"))
                 for s in range(1, steps + 1):
                     api.alpha_step_into(prop.net, prop.root, prop.C, prop.t, l, u, self.alpha,
                                         batch.lo, batch.hi, infeasible, cons, passes, self.m,
                                         self.v, s, lr * decay ** (s - 1), self.lbs[s - 1], prop.ws,
-                                        pid=batch.pid)
-                    torch.maximum(self.best, self.lbs[s - 1], out=self.best)
+                                        pid=batch.pid, alpha_init=alpha0 if s == 1 else -1.0,
+                                        best=self.best)
         torch.cuda.current_stream().wait_stream(side)
 
     def run(self):
@@ -335,16 +328,12 @@ class StepGraph:
             batch.hi.copy_(hi0)
             out = plain_pass(prop, batch, cfg, out=self.out)
             cons = batch.cons() if cfg.complete_final else None
-            self.alpha.fill_(cfg.alpha)
-            self.m.fill_(0.0)
-            self.v.fill_(0.0)
-            self.best.fill_(-float("inf"))
             for s in range(1, steps + 1):
                 api.alpha_step_into(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"],
                                     self.alpha, batch.lo, batch.hi, out["infeasible"], cons,
                                     cfg.passes, self.m, self.v, s, lr * decay ** (s - 1),
-                                    self.lbs[s - 1], prop.ws, pid=batch.pid)
-                torch.maximum(self.best, self.lbs[s - 1], out=self.best)
+                                    self.lbs[s - 1], prop.ws, pid=batch.pid,
+                                    alpha_init=cfg.alpha if s == 1 else -1.0, best=self.best)
 
         # eager warm-up: sizes every workspace and output buffer
         out = plain_pass(prop, batch, cfg, out=self.out)

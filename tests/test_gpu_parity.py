@@ -438,6 +438,47 @@ def test_autograd_bound_matches_adjoint_and_fused_adam():
     assert np.abs(H(a1) - H(a2))[m].max() < 1e-4
 
 
+def test_alpha_step_keeps_the_best_bound_and_starts_from_alpha_init():
+    # the running best and the step-1 start live in the library: slopes,
+    # moments and best filled with NaN are never read at step 1, and the
+    # results equal those of pre-filled buffers with the best taken outside
+    w = wl.tiny_mlp(64)
+    w.net = wl.he_mlp([5] + [50] * 6 + [5], 2, bias="uniform")
+    sp = wl.draw_splits(64, w.split_counts[:64], np.arange(w.net.n_hidden))
+    prop = gpipe.Property.from_workload(w)
+    batch = gpipe.make_batch(prop, sp.neuron, sp.sign, sp.count)
+    out = gpipe.plain_pass(prop, batch, gpipe.PassConfig())
+    B, M, nh = 64, prop.M, prop.net.n_hidden
+    a1 = torch.full((B, M, nh), 0.5, device="cuda")
+    m1, v1 = torch.zeros_like(a1), torch.zeros_like(a1)
+    nan = float("nan")
+    a2, m2, v2 = (torch.full_like(a1, nan) for _ in range(3))
+    best = torch.full((B, M), nan, device="cuda")
+    lbs = []
+    for s in range(1, 6):
+        lb, _ = api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], a1,
+                               batch.lo, batch.hi, out["infeasible"], batch.splits, 1, m1, v1, s,
+                               0.1, ws=prop.ws)
+        lbs.append(H(lb))
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], a2, batch.lo,
+                       batch.hi, out["infeasible"], batch.splits, 1, m2, v2, s, 0.1, ws=prop.ws,
+                       alpha_init=0.5 if s == 1 else -1.0, best=best)
+    sync()
+    ref = np.max(np.stack(lbs), axis=0)
+    assert np.array_equal(H(best), ref)
+    assert np.array_equal(H(a1), H(a2)) and np.array_equal(H(m1), H(m2))
+    inf = H(out["infeasible"]).astype(bool)
+    assert inf.any() and np.isinf(H(best)[inf]).all()
+    assert np.isfinite(H(best)[~inf]).all()
+    # a start value at a later step is refused before launch
+    from paper_2512_11087_amd import _native as N
+    with pytest.raises(N.CvError) as e:
+        api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], a2, batch.lo,
+                       batch.hi, out["infeasible"], batch.splits, 1, m2, v2, 2, 0.1, ws=prop.ws,
+                       alpha_init=0.5)
+    assert e.value.status == -1
+
+
 # ---------------------------------------------------- constraint importance order
 
 def test_constraint_order_matches_oracle():
