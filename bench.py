@@ -70,42 +70,61 @@ def traffic_for(kernel, workload, batch):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(w, sp, sample, alpha_steps):
-    """The FP64 oracle timed on the first `sample` subdomains of the same
-    workload: the same step (plain pass + slope optimisation)."""
-    import numpy as np
-    from oracle import crown, pipeline as opipe
+def blas_info():
+    """(vendor and version, threads) of the BLAS NumPy runs on."""
     try:
         from threadpoolctl import threadpool_info
-        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            i = libs[0]
+            return f"{i.get('internal_api', '?')} {i.get('version', '')}".strip(), int(i.get("num_threads", 1))
     except Exception:
-        blas = None
+        pass
+    return "unknown", None
+
+
+def cpu_baseline(w, sp, sample, alpha_steps, runs=3):
+    """The FP64 oracle timed on the first `sample` subdomains of the same
+    workload: the same step (plain pass + slope optimisation), one warm-up
+    and `runs` timed runs, the median reported."""
+    import numpy as np
+    from oracle import crown, pipeline as opipe
+    vendor, threads = blas_info()
     cores = len(os.sched_getaffinity(0))
     layers = crown.dense_layers(w.net)
     root = crown.root_pass(layers, w.lo0, w.hi0, w.alpha0)   # set-up, not timed (as on the GPU)
     idx = np.arange(sample)
     lo = np.broadcast_to(w.lo0, (sample, w.net.n_in)).astype(np.float64)
     hi = np.broadcast_to(w.hi0, (sample, w.net.n_in)).astype(np.float64)
-    t0 = time.perf_counter()
-    out = opipe.run(layers, root, w.C, w.t, lo, hi, sp.neuron[idx], sp.sign[idx], sp.count[idx])
-    fe = ~out["infeasible"]
-    l_list = opipe.split_layers(layers, out["l"][fe])
-    u_list = opipe.split_layers(layers, out["u"][fe])
-    opipe.alpha_opt(layers, w.C, w.t, l_list, u_list, out["lo"][fe], out["hi"][fe], out["G"][fe],
-                    out["h"][fe], out["active"][fe], steps=alpha_steps, lr=0.1)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "subdomains/s", "cores": int(blas or cores),
-            "kind": "oracle",
+
+    def once():
+        t0 = time.perf_counter()
+        out = opipe.run(layers, root, w.C, w.t, lo, hi, sp.neuron[idx], sp.sign[idx], sp.count[idx])
+        fe = ~out["infeasible"]
+        l_list = opipe.split_layers(layers, out["l"][fe])
+        u_list = opipe.split_layers(layers, out["u"][fe])
+        opipe.alpha_opt(layers, w.C, w.t, l_list, u_list, out["lo"][fe], out["hi"][fe],
+                        out["G"][fe], out["h"][fe], out["active"][fe], steps=alpha_steps, lr=0.1)
+        return time.perf_counter() - t0
+
+    once()
+    dts = sorted(once() for _ in range(runs))
+    dt = dts[len(dts) // 2]
+    return {"value": sample / dt, "unit": "subdomains/s", "cores": int(threads or cores),
+            "kind": "oracle", "blas": vendor,
             "sample": f"first {sample} of the {w.B} subdomains, same step (plain pass + "
-                      f"{alpha_steps} slope iterations), {dt:.1f} s on {cores} host cores"}
+                      f"{alpha_steps} slope iterations): median of {runs} runs after one "
+                      f"warm-up, {dt:.2f} s each (runs {', '.join(f'{x:.2f}' for x in dts)} s), "
+                      f"{cores} host cores, {vendor} with {threads} threads"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 3; 1 for cnn3x32x32-conv64-set256)")
-    ap.add_argument("--warmup", type=int, default=1)
+                    help="timed steps, each timed with HIP events; the median is reported "
+                         "(default 20; 2 for cnn3x32x32-conv64-set256)")
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mlp784-256x6-10",
                     choices=["mlp784-256x6-10", "mlp784-1024x4-10", "cnn3x32x32",
                              "cnn3x32x32-set64", "cnn3x32x32-conv64-set256"],
@@ -124,7 +143,9 @@ def main():
                          "wide)")
     ap.add_argument("--alpha-steps", type=int, default=None,
                     help="slope iterations per step (default 20; 10 for cnn3x32x32-conv64-set256)")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip measuring the HBM and FP64 matrix-core peaks on the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="replay each step (box reset, plain pass, slope iterations) as one "
@@ -161,7 +182,7 @@ def main():
         return
     big = args.workload == "cnn3x32x32-conv64-set256"
     if args.steps is None:
-        args.steps = 1 if big else 3
+        args.steps = 2 if big else 20
     if args.alpha_steps is None:
         args.alpha_steps = 10 if big else 20
     chunk = args.chunk if args.chunk is not None else (1024 if big else None)
@@ -270,20 +291,30 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
 
-    # timed region: K full steps, kernel events recorded on the launch stream
+    # timed region: K full steps, each bracketed by HIP events on the launch
+    # stream (torch's current stream, which every library call is given), and
+    # the kernels' own events recorded on that stream
     _native.profile_reset()
     _native.profile_enable(True)
     torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ev[i][0].record()
         out, best = full_step()
+        ev[i][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _native.profile_enable(False)
     kern = _native.profile_collect()
-    ms_step = 1e3 * wall / args.steps
-    value = B / (wall / args.steps)
-    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step -> {value:.0f} subdomains/s")
+    step_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    ms_step = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else \
+        0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
+    value = B / (ms_step * 1e-3)
+    log(f"timed {args.steps} steps: median {ms_step:.2f} ms/step (min {step_ms[0]:.2f}, "
+        f"max {step_ms[-1]:.2f}; wall mean {1e3 * wall / args.steps:.2f}) -> {value:.0f} "
+        f"subdomains/s")
     kern_wall = wall
     if graph is not None:
         # graph replays record no per-kernel events: time the kernels on one
@@ -329,6 +360,12 @@ def main():
     roof["kernel"] = dom
     roof["avg_launch_ms"] = round(avg_ms, 4)
     roof["traffic"] = traffic_for(dom, args.workload, B)
+    if not args.no_peaks:
+        hbm, mfma = _native.measure_peaks()
+        meas = mfma if roof["unit"] == "TFLOP/s" else hbm
+        roof["peak_measured"] = round(meas, 3 if roof["unit"] == "TFLOP/s" else 1)
+        roof["frac_measured"] = round(roof["achieved"] / meas, 4)
+        log(f"measured peaks: HBM copy {hbm:.0f} GB/s, FP64 MFMA loop {mfma:.2f} TFLOP/s")
     if args.kernels_json:
         with open(args.kernels_json, "w") as f:
             json.dump({"steps": args.steps if graph is None else 1, "wall_s": kern_wall,
@@ -357,6 +394,8 @@ def main():
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "subdomains/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "ms_per_step_min": round(step_ms[0], 3),
+        "timing": f"median of {args.steps} steps, each timed with HIP events on the launch stream",
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{name}: {B} subdomains x {'<=' if split_counts.min() < ksplit else ''}{ksplit} splits, 9 margin rows, "
