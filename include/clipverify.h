@@ -88,7 +88,12 @@ typedef struct cv_net_s* cv_net;
  * kernel.  The last (objective) layer must be linear.  CV_E_UNSUPPORTED for
  * a conv as the last layer, a linear layer of more than 2^28 entries or a
  * conv layer of more than 2^26 inputs or outputs; CV_E_SHAPE for
- * inconsistent sizes. */
+ * inconsistent sizes.  A conv layer whose input row fits 64 KiB runs
+ * whole-row convolution kernels (unless it has 32 or more channels on both
+ * sides), the others tiled kernels; with
+ * CV_CONV_TILED=1 in the environment when the net is made, every conv layer
+ * runs the tiled kernels (a testing aid: it changes the summation order, not
+ * the bounds' soundness). */
 cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out);
 cv_status cv_net_destroy(cv_net net);
 /* Host outputs: input dim, output dim, total hidden neurons, layer count. */
@@ -98,12 +103,15 @@ cv_status cv_net_info(cv_net net, int* n_in, int* n_out, int* n_hidden, int* n_l
  * W_layer, 2 <= layer <= n_layers-1), CV_TUNE_FINAL (layer 1) or
  * CV_TUNE_ADJOINT (1 <= layer <= n_layers-1): the output tile of the GEMM
  * (0: 32 x 128, 1: 64 x 128, 2: 128 x 128 rows x columns; the adjoint also
- * 3: 32 x 256) or, for the adjoint's forward convolution, the vector kernel
- * with a channel block (0: built-in, 1/2/3: 4/8/16 channels; 4/5: 8/16
- * channels with four output positions per lane) or the matrix-core kernel
- * (6; layers with at least 16 output channels); for a transposed
- * convolution (CV_TUNE_RELAX / CV_TUNE_FINAL of a conv layer) the output
- * positions per lane (0: by shape, 1: one, 2: two, 3: four).  Every variant
+ * 3: 32 x 256).  A conv layer runs as a direct convolution: where it runs
+ * the whole-row kernels (see cv_net_create), the transposed
+ * convolution (CV_TUNE_RELAX / CV_TUNE_FINAL) takes 0: positions per lane
+ * by shape, 1/2/3: one, two or four, and the adjoint's forward convolution
+ * 0: built-in, 1/2/3: channel blocks of 4/8/16, 4/5: blocks of 8/16 with
+ * four positions per lane; where it runs the tiled kernels, their
+ * transposed convolution takes the staging depth (0 built-in, 1/2/3: 4/8/16
+ * channels per chunk) and whose forward convolution takes 0: built-in,
+ * 1/2/3: 4/8/16 channels per chunk, 4: the other tile width.  Every variant
  * gives the same results (the same accumulation order per element).
  * cv_net_autotune times each variant of every layer once on synthetic
  * operands of B subdomains x M objective rows (allocating its own scratch,

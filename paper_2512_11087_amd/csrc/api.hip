@@ -7,6 +7,7 @@
 #include <vector>
 
 #include <functional>
+#include <cstdlib>
 #include <mutex>
 
 #include "clipverify.h"
@@ -269,44 +270,6 @@ RootDev root_dev(const cv_root_s* r) {
 }
 
 // (Re)writes the one-entry property table of a single root.
-// Tables of the matrix-core forward convolution of conv layer d (see
-// ConvDesc): the kernel as MFMA A-fragments (lane L holds output channel
-// L%16 of a 16-channel tile at k step L/16) and the zero-padded staging
-// geometry, chosen so that every tap of every output position reads inside
-// the staged row.  A layer with fewer than 16 output channels (a mostly
-// empty tile) or a staged row over 64 KiB has no such variant.
-cv_status conv_mfma_tables(const cv_layer_desc& d, ConvDesc& c) {
-  const int K = c.k, S = c.s, P = c.p;
-  c.ci16 = (c.ci + 15) / 16 * 16;
-  c.Af = nullptr;
-  c.mf = false;
-  // row oy*S + ky of the staged plane is input row oy*S - P + ky
-  c.fPT = P;
-  c.fHP = c.hi + P + std::max(0, (c.ho - 1) * S + K - P - c.hi);
-  c.fWP = c.wi + P + std::max(0, (c.wo - 1) * S + K - P - c.wi);
-  // channel stride = 16 mod 32 doubles: a fragment's four lane groups read
-  // four channels, which then fall on disjoint LDS banks
-  const int hw = c.fHP * c.fWP;
-  c.fPL = hw + ((16 - hw % 32) % 32 + 32) % 32;
-  if (c.co < 16 || (size_t)c.ci16 * c.fPL * 8 > 65536) return CV_OK;
-  const int MT = (c.co + 15) / 16, CG = c.ci16 / 4, taps = K * K;
-  std::vector<double> A((size_t)taps * CG * MT * 64, 0.0);
-  for (int t = 0; t < taps; ++t)
-    for (int cg = 0; cg < CG; ++cg)
-      for (int mt = 0; mt < MT; ++mt)
-        for (int L = 0; L < 64; ++L) {
-          const int co = mt * 16 + L % 16, ci = cg * 4 + L / 16;
-          if (co < c.co && ci < c.ci)
-            A[(((size_t)t * CG + cg) * MT + mt) * 64 + L] =
-                d.W[(((size_t)co * c.ci + ci) * K + t / K) * K + t % K];
-        }
-  if (dev_alloc(&c.Af, A.size())) return CV_E_NOMEM;
-  if (hipMemcpy(c.Af, A.data(), A.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
-    return hip_fail(hipGetLastError());
-  c.mf = true;
-  return CV_OK;
-}
-
 cv_status root_sync_tab(cv_root_s* r) {
   if (!r->dtab) {
     if (hipMalloc((void**)&r->dtab, sizeof(RootDev)) != hipSuccess) {
@@ -445,16 +408,24 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
       return hip_fail(hipGetLastError());
     }
     if (d.kind == CV_CONV2D) {
-      // Kernels of the direct convolutions: Wb [co][k][k][ci padded to 16]
-      // (transposed, blocks of input channels) and Wf [ci][k][k][co padded
-      // to 16] (forward, blocks of output channels); padding is zero.
+      // Kernels of the direct convolutions: Wb [co][k][k][ci padded] (the
+      // transposed convolution's; blocks of its output channels ci are
+      // contiguous) and Wf [ci][k][k][co padded] (the forward one's).  The
+      // contiguous dimension is padded to 16 (to 64 past 64 channels: the
+      // matrix-core tasks take up to 64 output channels), the outer one to a
+      // multiple of 4 (the matrix cores contract four channels per step);
+      // padding is zero.
       ConvDesc& c = net->conv[i];
+      auto pad_out = [](int n) { return n <= 64 ? (n + 15) / 16 * 16 : (n + 63) / 64 * 64; };
+      const char* tiled = std::getenv("CV_CONV_TILED");
       c = ConvDesc{d.in_c, d.in_h, d.in_w, d.out_c, d.out_h, d.out_w, d.kernel, d.stride, d.pad,
-                   (d.in_c + 15) / 16 * 16, (d.out_c + 15) / 16 * 16, nullptr, nullptr};
+                   pad_out(d.in_c), pad_out(d.out_c), nullptr, nullptr,
+                   tiled != nullptr && tiled[0] == '1'};
       net->is_conv[i] = true;
       const int K = c.k;
       const int pt = c.ptp, pf = c.pfp;
-      std::vector<double> Wb((size_t)c.co * K * K * pt, 0.0), Wf((size_t)c.ci * K * K * pf, 0.0);
+      const int co4 = (c.co + 3) / 4 * 4, ci4 = (c.ci + 3) / 4 * 4;
+      std::vector<double> Wb((size_t)co4 * K * K * pt, 0.0), Wf((size_t)ci4 * K * K * pf, 0.0);
       for (int co = 0; co < c.co; ++co)
         for (int ci = 0; ci < c.ci; ++ci)
           for (int ky = 0; ky < K; ++ky)
@@ -471,11 +442,6 @@ cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) 
           hipMemcpy(c.Wf, Wf.data(), Wf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
         cv_net_destroy(net);
         return hip_fail(hipGetLastError());
-      }
-      cv_status cst = conv_mfma_tables(d, c);
-      if (cst) {
-        cv_net_destroy(net);
-        return cst;
       }
     }
     net->hW.push_back(std::move(W));
@@ -501,7 +467,6 @@ cv_status cv_net_destroy(cv_net net) {
     if (net->is_conv[i]) {
       if (net->conv[i].Wb) (void)hipFree(net->conv[i].Wb);
       if (net->conv[i].Wf) (void)hipFree(net->conv[i].Wf);
-      if (net->conv[i].Af) (void)hipFree(net->conv[i].Af);
     }
   }
   if (net->root_ws) (void)hipFree(net->root_ws);
@@ -510,12 +475,17 @@ cv_status cv_net_destroy(cv_net net) {
 }
 
 // Variants a layer offers: GEMM tiles 32/64/128 x 128 (the adjoint also
-// 32 x 256); the forward convolution of the adjoint a channel block
-// (built-in, 4, 8, 16) or the matrix-core kernel; the transposed
-// convolutions one (their row sums depend on the block).
+// 32 x 256).  A conv layer whose input row fits LDS runs the whole-row
+// convolutions: positions per lane of the transposed one (built-in, 1, 2,
+// 4), channel block and positions per lane of the forward one (6); a longer
+// row the tiled convolutions: the depth of the input staging (built-in, 4,
+// 8, 16 channels), the forward one also the other column-tile count.
 static int tune_variants(const cv_net_s* net, int kind, int layer) {
-  if (net->is_conv[layer - 1])
-    return kind == CV_TUNE_ADJOINT ? (net->conv[layer - 1].mf ? 7 : 6) : 4;
+  if (net->is_conv[layer - 1]) {
+    const ConvDesc& c = net->conv[layer - 1];
+    if (kind == CV_TUNE_ADJOINT) return conv_whole_row_layer(c, false) ? 6 : 5;
+    return 4;
+  }
   return kind == CV_TUNE_ADJOINT ? 4 : 3;
 }
 

@@ -11,17 +11,10 @@
 // flattened channel-major): input (ci, hi, wi) -> output (co, ho, wo).
 struct ConvDesc {
   int ci, hi, wi, co, ho, wo, k, s, p;
-  int ptp, pfp;      // ci and co rounded up to a multiple of 16 (weight padding)
-  double* Wb;        // device [co][k][k][ptp]: transposed convolution (blocks of ci)
-  double* Wf;        // device [ci][k][k][pfp]: forward convolution (blocks of co)
-  // Matrix-core forward convolution (k_convf_mfma): the kernel as MFMA
-  // A-fragments Af [tap][channel group of 4][row tile of 16 co][64 lanes],
-  // and the zero-padded staging of the input row
-  int ci16;          // ci rounded up to a multiple of 16 (staged channels)
-  bool mf;           // the layer has the matrix-core variant
-  double* Af;
-  int fPT, fHP, fWP, fPL; // zero pad before, padded height and width, channel
-                          // stride (HP*WP rounded up to 16 mod 32 doubles)
+  int ptp, pfp;      // ci and co rounded up to a multiple of 16 (of 64 past 64 channels)
+  double* Wb;        // device [co rounded up to 4][k][k][ptp]: transposed convolution (blocks of ci)
+  double* Wf;        // device [ci rounded up to 4][k][k][pfp]: forward convolution (blocks of co)
+  bool tiled;        // the tiled kernels also where the whole-row ones would run
 };
 
 struct cv_net_s {
@@ -213,6 +206,9 @@ hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, cons
                           const float* b, CvProps props, int layer, double* psiT, double* c0,
                           double* e0, double* cabs0, hipStream_t s);
 // Rows [0, rows) of the dense matrix of a convolution layer (float32).
+// Whether a conv layer's transposed (or forward) convolution runs the
+// whole-row kernels (its input row fits LDS) rather than the tiled ones.
+bool conv_whole_row_layer(const ConvDesc& cd, bool transposed);
 hipError_t launch_conv_dense(const ConvDesc& cd, int rows, float* out, hipStream_t s);
 // dst[q, :] = src[idx[q], :], rows of n floats.
 hipError_t launch_gather_rows(int rows, int n, const int32_t* idx, const float* src, float* dst,

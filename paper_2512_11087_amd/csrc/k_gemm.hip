@@ -517,23 +517,100 @@ struct EpiAdj {
 // ------------------------------------------------------------ convolutions
 // The backward pass through a conv layer is a transposed convolution of each
 // row of Omega (and the adjoint a forward convolution), computed directly
-// rather than as a product with the layer's dense matrix: float64 FMAs on the
-// vector units (whose float64 rate equals the matrix cores' on gfx950), one
-// workgroup per row, the same fused epilogues as the GEMMs.  A wave takes a
-// task = (channel block, chunk of 64 output positions); the block's weights
-// are wave-uniform (scalar loads), each input value read feeds CB FMAs.  A
-// row that fits is first staged in LDS with wide coalesced loads, so the
-// taps read LDS instead of issuing one dependent global load each.
-// Transposed convolution: the lanes of a task share one stride-parity class
-// of output positions (iy = cy + s a, ix = cx + s b), so for every tap the
-// divisibility (iy + p - ky) % s is uniform and only the ~k^2/s^2 valid taps
-// are visited; borders are masked per lane.
+// rather than as a product with the layer's dense matrix, with the same
+// fused epilogues as the GEMMs.
+//
+// A workgroup takes one row, a band of output rows at full width (a tile)
+// and four tasks, one per wave; a task is a set of output channels times a
+// group of output positions.  In the transposed convolution the positions of
+// a task share one stride-parity class (iy = s a + cy, ix = s b + cx): only
+// the taps ky = cy + p (mod s) reach a class, and its t-th one reaches input
+// row oy = a + dy - t, so the taps are uniform over the wave and only the
+// ~k^2/s^2 of the class are visited.  The input band the tile reads (halo
+// included, zero outside the map) is staged in LDS, CC input channels at a
+// time, so every tap reads LDS.
+//
+// Layers with 16 or more output channels run on the float64 matrix cores
+// (v_mfma_f64_16x16x4_f64) as an implicit GEMM per task, D[out channel,
+// position] = sum over (input channel, tap) of W X: the MFMA's k runs over
+// four input channels at one tap, the B fragment is gathered from the band
+// and the A fragment (the kernel slice) is read from the L2-resident
+// weights.  The contraction order is: groups of four input channels, then
+// taps, then the group's channels.  Narrower layers use the float64 vector
+// units: a wave takes CB output channels times 64 P positions, each band
+// value read feeds CB FMAs whose weights are wave-uniform (scalar loads);
+// order: input channels, then taps.  The staging depth CC (an autotuner
+// variant) changes no result.
 
-// Row sums of a workgroup into the partials of column tile 0 (the other
-// tiles of the row get zeros), the layout the GEMM epilogues write.
+// Kernel weights are read through the constant address space: their
+// addresses are wave-uniform and nothing in these kernels writes them, so
+// they come in by scalar loads and feed the FMAs from SGPRs.
+typedef const __attribute__((address_space(4))) double* conv_wptr;
+
+// Geometry of one tiled convolution launch (computed on the host).
+struct ConvPlan {
+  bool mf;            // matrix-core kernel (else vector)
+  int P, CB;          // vector kernel: positions per lane, channels per block
+  int MT, NQ;         // matrix-core kernel: 16-channel row tiles and 16-position column tiles per task
+  int CC;             // input channels per staged chunk (matrix-core: a multiple of 4)
+  int TA;             // class rows (forward: output rows) per tile
+  int nT;             // tiles per row
+  int nch;            // position groups per class and tile
+  int nblk;           // channel blocks
+  int ntask;          // tasks per tile
+  int wgt;            // workgroups per tile
+  int SH, SW, plane;  // staged band: rows, columns, doubles per channel
+  int dmin;           // transposed: first band row (relative to the tile) and column, input coordinates
+  float inv_sh;       // 1 / SH (band row -> channel in the staging loop)
+};
+
+// Largest staged band, in doubles: 64 KiB of LDS per workgroup.
+constexpr int CONV_BAND_MAX = 8192;
+
+// Stage channels [c0, c0 + nc) of a row (maps Hs x Ws; channels >= nin
+// read as zero) over band rows [R0, R0 + SH) and columns [C0, C0 + SW)
+// into LDS, channel stride `plane`, zero outside the map.  Thread i takes
+// column i mod SW of band rows i / SW, i / SW + 256 / SW, ... (SW <= 256),
+// four rows' loads issued before their stores; a load outside the map
+// reads the row's first value and is replaced by zero (no branch per load).
+__device__ __forceinline__ void conv_band(double* __restrict__ band, const double* __restrict__ src,
+                                          int c0, int nc, int nin, int Hs, int Ws, int R0, int C0,
+                                          int SH, int SW, int plane, float inv_sh) {
+  const int rpp = 256 / SW;
+  const int r0 = threadIdx.x / SW;
+  if (r0 >= rpp) return;
+  const int x = threadIdx.x - r0 * SW;
+  const int gx = C0 + x;
+  const bool xok = gx >= 0 && gx < Ws;
+  const int nrow = nc * SH;
+  for (int rb = r0; rb < nrow; rb += 4 * rpp) {
+    double v[4];
+    int d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = rb + u * rpp;
+      // r / SH exactly: (r + 1/2) / SH is at least 1 / (2 SH) from an integer
+      const int c = (int)(((float)r + 0.5f) * inv_sh);
+      const int y = r - c * SH;
+      const int gy = R0 + y;
+      const bool ok = r < nrow && xok && gy >= 0 && gy < Hs && c0 + c < nin;
+      const size_t gi = ok ? ((size_t)(c0 + c) * Hs + gy) * Ws + gx : 0;
+      const double val = src[gi];
+      v[u] = ok ? val : 0.0;
+      d[u] = r < nrow ? c * plane + y * SW + x : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (d[u] >= 0) band[d[u]] = v[u];
+  }
+}
+
+// Row sums of a workgroup into partial slot `slot` of the row (the GEMM
+// epilogues' layout: ntiles slots per row, summed in order afterwards); the
+// workgroup of slot 0 zeroes the slots past the row's last workgroup.
 template <int NS>
 __device__ __forceinline__ void conv_row_sums(double (&sums)[NSUM_MAX], double* sred, double* part,
-                                              int r, int ntiles) {
+                                              int r, int ntiles, int slot, int nslots) {
   if constexpr (NS > 0) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -544,25 +621,487 @@ __device__ __forceinline__ void conv_row_sums(double (&sums)[NSUM_MAX], double* 
     __syncthreads();
     if (threadIdx.x < NS) {
       const int q = threadIdx.x;
-      part[((size_t)r * ntiles) * NS + q] =
+      part[((size_t)r * ntiles + slot) * NS + q] =
           (sred[q] + sred[NSUM_MAX + q]) + (sred[2 * NSUM_MAX + q] + sred[3 * NSUM_MAX + q]);
     }
-    for (int i = threadIdx.x; i < (ntiles - 1) * NS; i += 256)
-      part[((size_t)r * ntiles + 1) * NS + i] = 0.0;
+    if (slot == 0)
+      for (int i = threadIdx.x; i < (ntiles - nslots) * NS; i += 256)
+        part[((size_t)r * ntiles + nslots) * NS + i] = 0.0;
   }
 }
 
-// Kernel weights are read through the constant address space: their
-// addresses are wave-uniform and nothing in these kernels writes them, so
-// they come in by scalar loads and feed the FMAs from SGPRs.
-typedef const __attribute__((address_space(4))) double* conv_wptr;
+// Workgroup -> (row, tile, workgroup of the tile): the workgroups of a row
+// are consecutive on one XCD (xcd_block), so its input is fetched into one L2.
+__device__ __forceinline__ void conv_wg(const ConvPlan& pl, int& r, int& slot, int& tile, int& g) {
+  const int per_row = pl.nT * pl.wgt;
+  const int id = (int)xcd_block(blockIdx.x, gridDim.x);
+  r = id / per_row;
+  slot = id - r * per_row;
+  tile = slot / pl.wgt;
+  g = slot - tile * pl.wgt;
+}
 
-// Largest input row staged in LDS (doubles): 64 KiB keeps two workgroups
-// per CU; longer rows are read from global memory directly.
+// Sum over n (channel, tap) pairs of a staged chunk, software-pipelined:
+// the LDS inputs and scalar weights of pair j+1 are requested before the
+// FMAs of pair j, so their latency overlaps those FMAs (LDS reads and scalar
+// loads share one wait counter: waiting for either waits for both).  `it`
+// walks the pairs in order: xoff() is the pair's offset in the band,
+// wptr() its CB weights, next() moves on.
+template <int CB, int P, class It>
+__device__ __forceinline__ void conv_pairs(double (&acc)[P][CB], const double* __restrict__ band,
+                                           const int (&base)[P], It& it, int n) {
+  if (n <= 0) return;
+  double xa[P], xb[P], wa[CB], wb[CB];
+  auto ld = [&](double (&x)[P], double (&w)[CB]) {
+    const int o = it.xoff();
+    const conv_wptr wp = it.wptr();
+#pragma unroll
+    for (int p = 0; p < P; ++p) x[p] = band[base[p] + o];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) w[q] = wp[q];
+    it.next();
+  };
+  auto fm = [&](const double (&x)[P], const double (&w)[CB]) {
+#pragma unroll
+    for (int q = 0; q < CB; ++q)
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[p][q] += x[p] * w[q];
+  };
+  ld(xa, wa);
+  for (int j = 0;;) {
+    if (j + 1 < n) ld(xb, wb);
+    fm(xa, wa);
+    if (++j == n) break;
+    if (j + 1 < n) ld(xa, wa);
+    fm(xb, wb);
+    if (++j == n) break;
+  }
+}
+
+// Pairs of the transposed convolution: channel c of the chunk, then the
+// class's taps (t, u) in order; the band offset of tap (t, u) is -(t SW + u).
+struct ConvtPairs {
+  const double* w0;  // weights of the chunk's first channel, block ci0
+  int c, t, u, nty, ntx, SW, plane, k, s, ky0, kx0, ptp, wstep;
+  __device__ __forceinline__ int xoff() const { return c * plane - (t * SW + u); }
+  __device__ __forceinline__ conv_wptr wptr() const {
+    return (conv_wptr)(w0 + c * wstep + ((ky0 + s * t) * k + kx0 + s * u) * ptp);
+  }
+  __device__ __forceinline__ void next() {
+    if (++u == ntx) {
+      u = 0;
+      if (++t == nty) {
+        t = 0;
+        ++c;
+      }
+    }
+  }
+};
+
+// Pairs of the forward convolution: channel, then taps (ky, kx) in order;
+// the weights of consecutive pairs are pfp doubles apart.
+struct ConvfPairs {
+  const double* w;  // weights of the current pair, block co0
+  int c, ky, kx, k, SW, plane, pfp;
+  __device__ __forceinline__ int xoff() const { return c * plane + ky * SW + kx; }
+  __device__ __forceinline__ conv_wptr wptr() const { return (conv_wptr)w; }
+  __device__ __forceinline__ void next() {
+    w += pfp;
+    if (++kx == k) {
+      kx = 0;
+      if (++ky == k) {
+        ky = 0;
+        ++c;
+      }
+    }
+  }
+};
+
+// Transposed convolution of each row: out (ci, iy, ix) = sum over co and the
+// taps with iy + p - ky = s oy, ix + p - kx = s ox of in (co, oy, ox) W (co, ci, ky, kx).
+template <class Epi, int CB, int P>
+__global__ __launch_bounds__(256) void k_convt(ConvDesc cd, ConvPlan pl, const double* __restrict__ in,
+                                               Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double band[];
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int r, slot, tile, g;
+  conv_wg(pl, r, slot, tile, g);
+  const int s = cd.s, k = cd.k;
+  const int A0 = tile * pl.TA;
+  // the wave's task: (class, chunk, block), blocks innermost
+  const int task = g * 4 + wave;
+  const bool has = task < pl.ntask;
+  const int blk = has ? task % pl.nblk : 0;
+  const int qc = has ? task / pl.nblk : 0;
+  const int chunk = qc % pl.nch, cl = qc / pl.nch;
+  const int cy = cl / s, cx = cl - (cl / s) * s;
+  const int ky0 = (cy + cd.p) % s, kx0 = (cx + cd.p) % s;
+  const int nty = ky0 < k ? (k - ky0 + s - 1) / s : 0;
+  const int ntx = kx0 < k ? (k - kx0 + s - 1) / s : 0;
+  const int dy = (cy + cd.p - ky0) / s, dx = (cx + cd.p - kx0) / s;
+  const int ny = (cd.hi - cy + s - 1) / s, nx = (cd.wi - cx + s - 1) / s;
+  bool live[P];
+  int iy[P], ix[P], base[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int idx = chunk * 64 * P + 64 * p + lane;
+    int al = nx > 0 ? idx / nx : 0;
+    int b = idx - al * nx;
+    live[p] = has && nx > 0 && al < pl.TA && A0 + al < ny;
+    if (!live[p]) al = b = 0;
+    iy[p] = s * (A0 + al) + cy;
+    ix[p] = s * b + cx;
+    base[p] = (al + dy - pl.dmin) * pl.SW + (b + dx - pl.dmin);
+  }
+  const int ci0 = blk * CB;
+  const double* row = in + (size_t)r * cd.co * cd.ho * cd.wo;
+  double acc[P][CB];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[p][q] = 0.0;
+  const int wstep = k * k * cd.ptp;
+  for (int c0 = 0; c0 < cd.co; c0 += pl.CC) {
+    const int nc = min(pl.CC, cd.co - c0);
+    if (c0 > 0) __syncthreads();
+    conv_band(band, row, c0, nc, cd.co, cd.ho, cd.wo, A0 + pl.dmin, pl.dmin, pl.SH, pl.SW, pl.plane,
+              pl.inv_sh);
+    __syncthreads();
+    if (!has) continue;
+    ConvtPairs it{cd.Wb + (size_t)c0 * wstep + ci0, 0, 0, 0, nty, ntx, pl.SW, pl.plane, k, s,
+                  ky0, kx0, cd.ptp, wstep};
+    conv_pairs<CB, P>(acc, band, base, it, nc * nty * ntx);
+  }
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (live[p]) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int ci = ci0 + q;
+        if (ci < cd.ci) {
+          const int c = (ci * cd.hi + iy[p]) * cd.wi + ix[p];
+          const auto pre = epi.load(w, r, c);
+          epi.apply(w, pre, r, c, acc[p][q], sums);
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, slot, pl.nT * pl.wgt);
+}
+
+// Forward convolution of each row (the adjoint): out (co, oy, ox) = sum over
+// ci and taps of in (ci, oy s - p + ky, ox s - p + kx) W (co, ci, ky, kx).
+template <class Epi, int CB, int P>
+__global__ __launch_bounds__(256) void k_convf(ConvDesc cd, ConvPlan pl, const double* __restrict__ in,
+                                               Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double band[];
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int r, slot, tile, g;
+  conv_wg(pl, r, slot, tile, g);
+  const int s = cd.s, k = cd.k;
+  const int Y0 = tile * pl.TA;
+  const int task = g * 4 + wave;
+  const bool has = task < pl.ntask;
+  const int blk = has ? task % pl.nblk : 0;
+  const int chunk = has ? task / pl.nblk : 0;
+  bool live[P];
+  int oy[P], ox[P], base[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int idx = chunk * 64 * P + 64 * p + lane;
+    int yl = idx / cd.wo;
+    int x = idx - yl * cd.wo;
+    live[p] = has && yl < pl.TA && Y0 + yl < cd.ho;
+    if (!live[p]) yl = x = 0;
+    oy[p] = Y0 + yl;
+    ox[p] = x;
+    base[p] = yl * s * pl.SW + x * s;
+  }
+  const int co0 = blk * CB;
+  const double* row = in + (size_t)r * cd.ci * cd.hi * cd.wi;
+  double acc[P][CB];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[p][q] = 0.0;
+  const int wstep = k * k * cd.pfp;
+  for (int c0 = 0; c0 < cd.ci; c0 += pl.CC) {
+    const int nc = min(pl.CC, cd.ci - c0);
+    if (c0 > 0) __syncthreads();
+    conv_band(band, row, c0, nc, cd.ci, cd.hi, cd.wi, Y0 * s - cd.p, -cd.p, pl.SH, pl.SW, pl.plane,
+              pl.inv_sh);
+    __syncthreads();
+    if (!has) continue;
+    ConvfPairs it{cd.Wf + (size_t)c0 * wstep + co0, 0, 0, 0, k, pl.SW, pl.plane, cd.pfp};
+    conv_pairs<CB, P>(acc, band, base, it, nc * k * k);
+  }
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (live[p]) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        const int co = co0 + q;
+        if (co < cd.co) {
+          const int c = (co * cd.ho + oy[p]) * cd.wo + ox[p];
+          const auto pre = epi.load(w, r, c);
+          epi.apply(w, pre, r, c, acc[p][q], sums);
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, slot, pl.nT * pl.wgt);
+}
+
+// Matrix-core steps over one staged chunk: n steps of (group of four input
+// channels, tap), each MT x NQ MFMAs; the A and B fragments of step j+1 are
+// requested before the MFMAs of step j (A by vector loads, B from LDS: two
+// wait counters, so each wait covers only its own loads).  `it` walks the
+// steps in order: xoff() is the step's band offset (added to each lane's
+// column offset boff), woff() its offset in the lane's weight stream wl.
+template <int MT, int NQ, class It>
+__device__ __forceinline__ void conv_mfma_steps(d4_t (&acc)[MT][NQ], const double* __restrict__ band,
+                                                const int (&boff)[NQ], const double* __restrict__ wl,
+                                                It& it, int n) {
+  if (n <= 0) return;
+  double a0[MT], b0[NQ], a1[MT], b1[NQ];
+  auto ld = [&](double (&a)[MT], double (&b)[NQ]) {
+    const int xo = it.xoff();
+    const double* w = wl + it.woff();
+#pragma unroll
+    for (int m = 0; m < MT; ++m) a[m] = w[16 * m];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) b[q] = band[boff[q] + xo];
+    it.next();
+  };
+  auto mm = [&](const double (&a)[MT], const double (&b)[NQ]) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
+  };
+  ld(a0, b0);
+  for (int j = 0;;) {
+    if (j + 1 < n) ld(a1, b1);
+    mm(a0, b0);
+    if (++j == n) break;
+    if (j + 1 < n) ld(a0, b0);
+    mm(a1, b1);
+    if (++j == n) break;
+  }
+}
+
+// Steps of the transposed convolution: channel group g, then the class's
+// taps (t, u); band offset 4 g plane - (t SW + u), weights of input channel
+// 4 g + (lane / 16) at tap (ky0 + s t, kx0 + s u).
+struct ConvtSteps {
+  int g, t, u, nty, ntx, SW, plane, k, s, ky0, kx0, ptp;
+  __device__ __forceinline__ int xoff() const { return 4 * g * plane - (t * SW + u); }
+  __device__ __forceinline__ int woff() const {
+    return (4 * g * k * k + (ky0 + s * t) * k + kx0 + s * u) * ptp;
+  }
+  __device__ __forceinline__ void next() {
+    if (++u == ntx) {
+      u = 0;
+      if (++t == nty) {
+        t = 0;
+        ++g;
+      }
+    }
+  }
+};
+
+// Steps of the forward convolution: channel group g, then taps (ky, kx).
+struct ConvfSteps {
+  int g, ky, kx, k, SW, plane, pfp;
+  __device__ __forceinline__ int xoff() const { return 4 * g * plane + ky * SW + kx; }
+  __device__ __forceinline__ int woff() const { return (4 * g * k * k + ky * k + kx) * pfp; }
+  __device__ __forceinline__ void next() {
+    if (++kx == k) {
+      kx = 0;
+      if (++ky == k) {
+        ky = 0;
+        ++g;
+      }
+    }
+  }
+};
+
+// Matrix-core transposed convolution (>= 16 output channels).  A task covers
+// 16 MT output channels (ci) and 16 NQ positions of one class; lane L feeds
+// B[L/16][L%16] = band value of input channel 4g + L/16 for position L%16 of
+// a column tile and receives D[L/16 + 4v][L%16].
+template <class Epi, int MT, int NQ>
+__global__ __launch_bounds__(256) void k_convt_mf(ConvDesc cd, ConvPlan pl, const double* __restrict__ in,
+                                                  Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double band[];
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int lane = threadIdx.x & 63;
+  const int lk = lane >> 4, lc = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int r, slot, tile, g;
+  conv_wg(pl, r, slot, tile, g);
+  const int s = cd.s, k = cd.k;
+  const int A0 = tile * pl.TA;
+  const int task = g * 4 + wave;
+  const bool has = task < pl.ntask;
+  const int blk = has ? task % pl.nblk : 0;
+  const int qc = has ? task / pl.nblk : 0;
+  const int grp = qc % pl.nch, cl = qc / pl.nch;
+  const int cy = cl / s, cx = cl - (cl / s) * s;
+  const int ky0 = (cy + cd.p) % s, kx0 = (cx + cd.p) % s;
+  const int nty = ky0 < k ? (k - ky0 + s - 1) / s : 0;
+  const int ntx = kx0 < k ? (k - kx0 + s - 1) / s : 0;
+  const int dy = (cy + cd.p - ky0) / s, dx = (cx + cd.p - kx0) / s;
+  const int ny = (cd.hi - cy + s - 1) / s, nx = (cd.wi - cx + s - 1) / s;
+  bool live[NQ];
+  int iy[NQ], ix[NQ], boff[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = (grp * NQ + q) * 16 + lc;
+    int al = nx > 0 ? idx / nx : 0;
+    int b = idx - al * nx;
+    live[q] = has && nx > 0 && al < pl.TA && A0 + al < ny;
+    if (!live[q]) al = b = 0;
+    iy[q] = s * (A0 + al) + cy;
+    ix[q] = s * b + cx;
+    boff[q] = lk * pl.plane + (al + dy - pl.dmin) * pl.SW + (b + dx - pl.dmin);
+  }
+  const int ch0 = blk * 16 * MT;
+  const double* row = in + (size_t)r * cd.co * cd.ho * cd.wo;
+  d4_t acc[MT][NQ];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[m][q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < cd.co; c0 += pl.CC) {
+    const int nc4 = (min(pl.CC, cd.co - c0) + 3) & ~3;
+    if (c0 > 0) __syncthreads();
+    conv_band(band, row, c0, nc4, cd.co, cd.ho, cd.wo, A0 + pl.dmin, pl.dmin, pl.SH, pl.SW, pl.plane,
+              pl.inv_sh);
+    __syncthreads();
+    if (!has) continue;
+    ConvtSteps it{0, 0, 0, nty, ntx, pl.SW, pl.plane, k, s, ky0, kx0, cd.ptp};
+    const double* wl = cd.Wb + ((size_t)(c0 + lk) * k * k) * cd.ptp + ch0 + lc;
+    conv_mfma_steps<MT, NQ>(acc, band, boff, wl, it, (nc4 / 4) * nty * ntx);
+  }
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (live[q]) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ci = ch0 + 16 * m + lk + 4 * v;
+          if (ci < cd.ci) {
+            const int c = (ci * cd.hi + iy[q]) * cd.wi + ix[q];
+            const auto pre = epi.load(w, r, c);
+            epi.apply(w, pre, r, c, acc[m][q][v], sums);
+          }
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, slot, pl.nT * pl.wgt);
+}
+
+// Matrix-core forward convolution (>= 16 output channels): a task covers
+// 16 MT output channels (co) and 16 NQ output positions of the tile.
+template <class Epi, int MT, int NQ>
+__global__ __launch_bounds__(256) void k_convf_mf(ConvDesc cd, ConvPlan pl, const double* __restrict__ in,
+                                                  Epi epi, double* __restrict__ part, int ntiles) {
+  extern __shared__ double band[];
+  __shared__ double sred[4 * NSUM_MAX];
+  constexpr int NS = Epi::NSUM;
+  const int lane = threadIdx.x & 63;
+  const int lk = lane >> 4, lc = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int r, slot, tile, g;
+  conv_wg(pl, r, slot, tile, g);
+  const int s = cd.s, k = cd.k;
+  const int Y0 = tile * pl.TA;
+  const int task = g * 4 + wave;
+  const bool has = task < pl.ntask;
+  const int blk = has ? task % pl.nblk : 0;
+  const int grp = has ? task / pl.nblk : 0;
+  bool live[NQ];
+  int oy[NQ], ox[NQ], boff[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = (grp * NQ + q) * 16 + lc;
+    int yl = idx / cd.wo;
+    int x = idx - yl * cd.wo;
+    live[q] = has && yl < pl.TA && Y0 + yl < cd.ho;
+    if (!live[q]) yl = x = 0;
+    oy[q] = Y0 + yl;
+    ox[q] = x;
+    boff[q] = lk * pl.plane + yl * s * pl.SW + x * s;
+  }
+  const int ch0 = blk * 16 * MT;
+  const double* row = in + (size_t)r * cd.ci * cd.hi * cd.wi;
+  d4_t acc[MT][NQ];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[m][q] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < cd.ci; c0 += pl.CC) {
+    const int nc4 = (min(pl.CC, cd.ci - c0) + 3) & ~3;
+    if (c0 > 0) __syncthreads();
+    conv_band(band, row, c0, nc4, cd.ci, cd.hi, cd.wi, Y0 * s - cd.p, -cd.p, pl.SH, pl.SW, pl.plane,
+              pl.inv_sh);
+    __syncthreads();
+    if (!has) continue;
+    ConvfSteps it{0, 0, 0, k, pl.SW, pl.plane, cd.pfp};
+    const double* wl = cd.Wf + ((size_t)(c0 + lk) * k * k) * cd.pfp + ch0 + lc;
+    conv_mfma_steps<MT, NQ>(acc, band, boff, wl, it, (nc4 / 4) * k * k);
+  }
+  const auto w = epi.row(r);
+  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (live[q]) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int co = ch0 + 16 * m + lk + 4 * v;
+          if (co < cd.co) {
+            const int c = (co * cd.ho + oy[q]) * cd.wo + ox[q];
+            const auto pre = epi.load(w, r, c);
+            epi.apply(w, pre, r, c, acc[m][q][v], sums);
+          }
+        }
+      }
+    }
+  }
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, slot, pl.nT * pl.wgt);
+}
+
+// Whole-row convolutions, for rows whose input fits LDS (up to 64 KiB):
+// one workgroup per row stages the whole input row once (no halo, no
+// tiles) and its four waves take tasks = (channel block of 4/8/16, chunk
+// of 64 P output positions); weights come by scalar loads; each output sums
+// over its taps in order and, within a tap, over input channels in order.
+// In the transposed convolution the lanes of a task share one stride-parity
+// class, so a tap's divisibility by the stride is uniform; borders are
+// masked per lane.  Longer rows take the tiled kernels above.
 constexpr int CONV_STAGE_MAX = 8192;
 
 // Copy one row into LDS with many loads in flight per thread.
-__device__ __forceinline__ void conv_stage(double* __restrict__ dst, const double* __restrict__ src,
+__device__ __forceinline__ void conv_stage_row(double* __restrict__ dst, const double* __restrict__ src,
                                            int n) {
   int i = threadIdx.x;
   for (; i + 3 * 256 < n; i += 4 * 256) {
@@ -579,8 +1118,8 @@ __device__ __forceinline__ void conv_stage(double* __restrict__ dst, const doubl
 // P positions per lane (lanes take consecutive positions, P groups of 64
 // apart): each weight a scalar load brings feeds P * CB FMAs and each wave
 // has P input loads in flight per step.
-template <class Epi, int CB, bool STAGE, int P>
-__global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double* __restrict__ in,
+template <class Epi, int CB, int P>
+__global__ __launch_bounds__(256) void k_convt_row(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
   extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
@@ -591,8 +1130,8 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const size_t cin = (size_t)cd.ho * cd.wo;
   const double* row = in + (size_t)r * cd.co * cin;
-  if constexpr (STAGE) conv_stage(srow, row, (int)(cd.co * cin));
-  const double* src = STAGE ? srow : row;
+  conv_stage_row(srow, row, (int)(cd.co * cin));
+  const double* src = srow;
   const int cpad = cd.ptp;
   const int nblk = (cd.ci + CB - 1) / CB;
   const auto w = epi.row(r);
@@ -683,13 +1222,13 @@ __global__ __launch_bounds__(256) void k_convt(int R, ConvDesc cd, const double*
       }
     }
   }
-  conv_row_sums<NS>(sums, sred, part, r, ntiles);
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, 0, 1);
 }
 
 // Forward convolution of each row (adjoint): out (co, oy, ox) =
 // sum over ci and taps of in (ci, oy*s - p + ky, ox*s - p + kx) * W (co, ci, ky, kx).
-template <class Epi, int CB, bool STAGE, int P>
-__global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double* __restrict__ in,
+template <class Epi, int CB, int P>
+__global__ __launch_bounds__(256) void k_convf_row(int R, ConvDesc cd, const double* __restrict__ in,
                                                Epi epi, double* __restrict__ part, int ntiles) {
   extern __shared__ double srow[];
   __shared__ double sred[4 * NSUM_MAX];
@@ -700,8 +1239,8 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const size_t cin = (size_t)cd.hi * cd.wi;
   const double* row = in + (size_t)r * cd.ci * cin;
-  if constexpr (STAGE) conv_stage(srow, row, (int)(cd.ci * cin));
-  const double* src = STAGE ? srow : row;
+  conv_stage_row(srow, row, (int)(cd.ci * cin));
+  const double* src = srow;
   const int cpad = cd.pfp;
   const int nblk = (cd.co + CB - 1) / CB;
   const int npos = cd.ho * cd.wo, nchunk = (npos + CH - 1) / CH;
@@ -769,115 +1308,12 @@ __global__ __launch_bounds__(256) void k_convf(int R, ConvDesc cd, const double*
       }
     }
   }
-  conv_row_sums<NS>(sums, sred, part, r, ntiles);
-}
-
-// Matrix-core forward convolution of one row per workgroup, as an implicit
-// GEMM  D[co, pos] = sum_(tap, ci) W[co, ci, tap] X[ci, pos + tap]  (the
-// adjoint's convolution; an autotuner variant beside the vector kernel).
-// The row X is staged once in LDS with a zero border wide enough that every
-// tap reads inside it, so no load is masked (channels padded to 16, the
-// channel stride padded to 16 mod 32 doubles so that a fragment's four lane
-// groups read disjoint LDS banks); the kernel comes as pre-laid-out
-// A-fragments (coalesced 512-byte loads, four issued together, each shared
-// by NQ column tiles).  A wave owns a 16-row tile of output channels and NQ
-// 16-column tiles of positions: lane L feeds B[L/16][L%16] = X[channel group
-// + L/16, position L%16 of the tile] and receives D[L/16 + 4v][L%16].  The
-// contraction accumulates every output in the same order as the vector
-// kernel (tap-major, then input channel), so the two give identical results.
-template <class Epi, int NQ>
-__global__ __launch_bounds__(256, 4) void k_convf_mfma(int R, ConvDesc cd, const double* __restrict__ in,
-                                                       Epi epi) {
-  extern __shared__ double xs[];
-  const int r = blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lk = lane >> 4, lc = lane & 15;
-  const int H = cd.hi, W = cd.wi, PT = cd.fPT, HP = cd.fHP, WP = cd.fWP, plane = cd.fPL;
-  {
-    const double* row = in + (size_t)r * cd.ci * H * W;
-    const int nst = cd.ci16 * plane;
-    for (int i = threadIdx.x; i < nst; i += 256) {
-      const int c = i / plane, o = i % plane, y = o / WP, x = o % WP;
-      const int yy = y - PT, xx = x - PT;
-      double v = 0.0;
-      if (c < cd.ci && y < HP && yy >= 0 && yy < H && xx >= 0 && xx < W)
-        v = row[((size_t)c * H + yy) * W + xx];
-      xs[i] = v;
-    }
-  }
-  __syncthreads();
-  const auto w = epi.row(r);
-  double sums[NSUM_MAX] = {0.0, 0.0, 0.0};
-  const int MT = (cd.co + 15) / 16;
-  const int CG = cd.ci16 / 4;  // channel groups of 4, a multiple of 4
-  const int npos = cd.ho * cd.wo;
-  const int NG = ((npos + 15) / 16 + NQ - 1) / NQ;
-  // work units: (row tile, NQ column tiles); column tiles past the last
-  // position compute clamped copies that are not stored
-  for (int u = wave; u < MT * NG; u += 4) {
-    const int mt = u / NG, nt0 = (u % NG) * NQ;
-    int pb[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      int pos = (nt0 + q) * 16 + lc;
-      pos = pos < npos ? pos : npos - 1;
-      pb[q] = lk * plane + (pos / cd.wo * cd.s) * WP + (pos % cd.wo) * cd.s;
-    }
-    d4_t acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
-    const double* Ab = cd.Af + (size_t)mt * 64 + lane;
-    const size_t astep = (size_t)MT * 64;
-    for (int t = 0; t < cd.k * cd.k; ++t) {
-      const int toff = (t / cd.k) * WP + t % cd.k;
-      const double* At_ = Ab + (size_t)t * CG * astep;
-      for (int g0 = 0; g0 < CG; g0 += 4) {
-        double af[4], bf[4][NQ];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) af[j] = At_[(size_t)(g0 + j) * astep];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) bf[j][q] = xs[pb[q] + (g0 + j) * 4 * plane + toff];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q)
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], bf[j][q], acc[q], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int pos = (nt0 + q) * 16 + lc;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ch = mt * 16 + lk + 4 * v;
-        if (ch < cd.co && pos < npos) {
-          const int c = ch * npos + pos;
-          const auto pre = epi.load(w, r, c);
-          epi.apply(w, pre, r, c, acc[q][v], sums);
-        }
-      }
-    }
-  }
-}
-
-template <class Epi>
-void launch_convf_mfma(int R, const ConvDesc& cd, const double* in, Epi epi, hipStream_t s) {
-  static_assert(Epi::NSUM == 0, "forward convolution: no row sums");
-  const size_t lds = (size_t)cd.ci16 * cd.fPL * 8;
-  const int MT = (cd.co + 15) / 16, NT = (cd.ho * cd.wo + 15) / 16;
-  // four column tiles per unit unless that leaves a wave without work
-  if (MT * ((NT + 3) / 4) >= 4)
-    hipLaunchKernelGGL((k_convf_mfma<Epi, 4>), dim3(R), dim3(256), lds, s, R, cd, in, epi);
-  else
-    hipLaunchKernelGGL((k_convf_mfma<Epi, 2>), dim3(R), dim3(256), lds, s, R, cd, in, epi);
+  conv_row_sums<NS>(sums, sred, part, r, ntiles, 0, 1);
 }
 
 // Channel block of a convolution: the largest of 16, 8, 4 that still gives
 // every wave of a row a task (fewer channels: the smallest block covering them).
-inline int conv_block(int ch, int tasks_per_block) {
+inline int conv_block_row(int ch, int tasks_per_block) {
   int cb = 16;
   while (cb > 4 && ((ch + cb - 1) / cb) * tasks_per_block < 4) cb >>= 1;
   if (ch <= 4) cb = 4;
@@ -889,26 +1325,22 @@ inline int conv_block(int ch, int tasks_per_block) {
 // fill at least two full chunks of 64 per task and the accumulators stay
 // within 32 doubles, else 1 (blocks of one position each task would leave
 // lanes idle).  `per_blk64` counts a block's tasks at one position per lane.
-inline int conv_positions(int cb, int nblk, int npos_min, int per_blk64) {
+inline int conv_positions_row(int cb, int nblk, int npos_min, int per_blk64) {
   if (cb * 2 <= 32 && npos_min >= 128 && nblk * ((per_blk64 + 1) / 2) >= 4) return 2;
   return 1;
 }
 
 template <class Epi, int CB, int P>
-void launch_convt_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+void launch_convt_row_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                     hipStream_t s) {
   const int n = cd.co * cd.ho * cd.wo;
-  if (n <= CONV_STAGE_MAX)
-    hipLaunchKernelGGL((k_convt<Epi, CB, true, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
-                       epi, part, ntiles);
-  else
-    hipLaunchKernelGGL((k_convt<Epi, CB, false, P>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
-                       ntiles);
+  hipLaunchKernelGGL((k_convt_row<Epi, CB, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in, epi,
+                     part, ntiles);
 }
 
-// variant 0: positions per lane by conv_positions; 1, 2, 3: one, two, four.
+// variant 0: positions per lane by conv_positions_row; 1, 2, 3: one, two, four.
 template <class Epi, int CB>
-void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+void launch_convt_row_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant) {
   // smallest stride-parity class and the tasks of a block at one position per lane
   int per_blk = 0, cls_min = 1 << 30;
@@ -919,81 +1351,301 @@ void launch_convt_cb(int R, const ConvDesc& cd, const double* in, Epi epi, doubl
       cls_min = std::min(cls_min, ncls);
     }
   const int P = variant == 1 ? 1 : variant == 2 ? 2 : variant == 3 ? 4
-                                  : conv_positions(CB, (cd.ci + CB - 1) / CB, cls_min, per_blk);
+                                  : conv_positions_row(CB, (cd.ci + CB - 1) / CB, cls_min, per_blk);
   if (P == 4)
-    launch_convt_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
+    launch_convt_row_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
   else if (P == 2)
-    launch_convt_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
+    launch_convt_row_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
   else
-    launch_convt_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
+    launch_convt_row_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
 }
 
 template <class Epi, int CB, int P>
-void launch_convf_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+void launch_convf_row_p(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                     hipStream_t s) {
   const int n = cd.ci * cd.hi * cd.wi;
-  if (n <= CONV_STAGE_MAX)
-    hipLaunchKernelGGL((k_convf<Epi, CB, true, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in,
-                       epi, part, ntiles);
-  else
-    hipLaunchKernelGGL((k_convf<Epi, CB, false, P>), dim3(R), dim3(256), 0, s, R, cd, in, epi, part,
-                       ntiles);
+  hipLaunchKernelGGL((k_convf_row<Epi, CB, P>), dim3(R), dim3(256), (size_t)n * 8, s, R, cd, in, epi,
+                     part, ntiles);
 }
 
 template <class Epi, int CB>
-void launch_convf_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+void launch_convf_row_cb(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int P = 0) {
   const int npos = cd.ho * cd.wo;
-  if (P == 0) P = conv_positions(CB, (cd.co + CB - 1) / CB, npos, (npos + 63) / 64);
+  if (P == 0) P = conv_positions_row(CB, (cd.co + CB - 1) / CB, npos, (npos + 63) / 64);
   if (P == 4)
-    launch_convf_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
+    launch_convf_row_p<Epi, CB, 4>(R, cd, in, epi, part, ntiles, s);
   else if (P == 2)
-    launch_convf_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
+    launch_convf_row_p<Epi, CB, 2>(R, cd, in, epi, part, ntiles, s);
   else
-    launch_convf_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
+    launch_convf_row_p<Epi, CB, 1>(R, cd, in, epi, part, ntiles, s);
 }
 
 // Transposed convolution; variant (autotuner) 0: positions per lane by the
 // shape heuristic, 1/2/3: one, two or four positions per lane.  Every variant
 // accumulates each output in the same order.
 template <class Epi>
-hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+hipError_t run_convt_row(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
   int per_blk = 0;
   for (int cy = 0; cy < cd.s; ++cy)
     for (int cx = 0; cx < cd.s; ++cx)
       per_blk += (((cd.hi - cy + cd.s - 1) / cd.s) * ((cd.wi - cx + cd.s - 1) / cd.s) + 63) / 64;
-  switch (conv_block(cd.ci, per_blk)) {
-    case 4: launch_convt_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, variant); break;
-    case 8: launch_convt_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, variant); break;
-    default: launch_convt_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, variant); break;
+  switch (conv_block_row(cd.ci, per_blk)) {
+    case 4: launch_convt_row_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, variant); break;
+    case 8: launch_convt_row_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, variant); break;
+    default: launch_convt_row_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, variant); break;
   }
   return hipGetLastError();
 }
 
-// variant: 0 the vector kernel with the block size of conv_block, 1/2/3
-// with blocks of 4/8/16 channels (positions per lane by shape), 4/5 blocks
-// of 8/16 channels with four positions per lane, 6 the matrix-core kernel
-// (where the layer has one).  The forward convolution has no row sums and
+// variant: 0 the block size of conv_block_row, 1/2/3 blocks of 4/8/16
+// channels (positions per lane by shape), 4/5 blocks of 8/16 channels with
+// four positions per lane.  The forward convolution has no row sums and
 // every variant accumulates each output in the same order, so the choice
 // changes no result.
+template <class Epi>
+hipError_t run_convf_row(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s, int variant = 0) {
+  if (R <= 0) return hipSuccess;
+  const int cb = variant == 1 ? 4 : (variant == 2 || variant == 4) ? 8
+                                  : (variant == 3 || variant == 5) ? 16
+                                                                   : conv_block_row(cd.co, (cd.ho * cd.wo + 63) / 64);
+  const int P = variant >= 4 ? 4 : 0;
+  switch (cb) {
+    case 4: launch_convf_row_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, P); break;
+    case 8: launch_convf_row_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, P); break;
+    default: launch_convf_row_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, P); break;
+  }
+  return hipGetLastError();
+}
+
+// Channel block of the vector kernels: 4, 8 or 16 channels, the smallest
+// that covers a layer of up to 8 channels, else 16.
+inline int conv_block(int ch) { return ch <= 4 ? 4 : ch <= 8 ? 8 : 16; }
+
+// Positions per lane (vector kernels): two where the (class, block) pairs of
+// a row times its full chunks of 128 positions per class still give every
+// wave a task, else one (each weight then feeds fewer FMAs, but no wave
+// idles).
+inline int conv_positions(int pairs, int npos_class) { return pairs * (npos_class / 128) >= 4 ? 2 : 1; }
+
+// Band plane: SH x SW doubles, rounded up (matrix-core kernels) to 16 mod
+// 32 doubles so that the four lane groups of a B fragment, which read four
+// consecutive channels, fall on disjoint LDS banks.
+inline int conv_plane(int SH, int SW, bool mf) {
+  const int n = SH * SW;
+  return mf ? n + ((16 - n % 32) + 32) % 32 : n;
+}
+
+// Channels staged per chunk: `cc` if given, else the most of 16, 8, 4
+// (matrix cores; the vector kernels also 2, 1) whose band fits 32 KiB;
+// always within the band budget, and at most the layer's channels (rounded
+// up to 4 on the matrix cores).
+inline int conv_depth(int cc, int plane, int nin, bool mf) {
+  const int lo = mf ? 4 : 1;
+  if (cc <= 0) {
+    cc = 16;
+    while (cc > lo && (size_t)cc * plane * 8 > 32768) cc >>= 1;
+  }
+  while (cc > lo && (size_t)cc * plane > CONV_BAND_MAX) cc >>= 1;
+  const int cap = mf ? (nin + 3) & ~3 : nin;
+  return std::max(lo, std::min(cc, cap));
+}
+
+// Tiles: class rows TA so that a tile's class holds about `target`
+// positions (at least one row), groups of `per` positions per class.
+inline void conv_tiles(ConvPlan& pl, int ncls, int nymax, int nxmax, int per, int target) {
+  pl.TA = std::max(1, std::min(nymax, (target + nxmax - 1) / std::max(1, nxmax)));
+  pl.nch = (pl.TA * nxmax + per - 1) / per;
+  pl.nT = (nymax + pl.TA - 1) / pl.TA;
+  pl.ntask = ncls * pl.nch * pl.nblk;
+  pl.wgt = (pl.ntask + 3) / 4;
+}
+
+// Shape of a task: the matrix cores for 16 or more output channels (up to
+// 64 per task; NQ = 2 column tiles unless that leaves waves idle), else the
+// vector kernel's channel block and positions per lane; then the tiles.
+inline void conv_shape(ConvPlan& pl, int nout, int ncls, int nymax, int nxmax) {
+  pl.mf = nout >= 16;
+  if (pl.mf) {
+    pl.MT = std::min(4, (nout + 15) / 16);
+    pl.nblk = (nout + 16 * pl.MT - 1) / (16 * pl.MT);
+    pl.NQ = ncls * pl.nblk * ((nymax * nxmax) / 32) >= 4 ? 2 : 1;
+    const int per = 16 * pl.NQ;
+    const int want = std::max(1, (4 + ncls * pl.nblk - 1) / (ncls * pl.nblk));
+    conv_tiles(pl, ncls, nymax, nxmax, per, std::max(64, want * per));
+  } else {
+    pl.CB = conv_block(nout);
+    pl.nblk = (nout + pl.CB - 1) / pl.CB;
+    pl.P = conv_positions(ncls * pl.nblk, nymax * nxmax);
+    const int per = 64 * pl.P;
+    const int want = std::max(1, (4 + ncls * pl.nblk - 1) / (ncls * pl.nblk));
+    conv_tiles(pl, ncls, nymax, nxmax, per, want * per);
+  }
+}
+
+// Plan of a transposed convolution (output: ci x hi x wi; input: co x ho x wo).
+inline ConvPlan plan_convt(const ConvDesc& cd, int cc) {
+  ConvPlan pl{};
+  const int s = cd.s, k = cd.k;
+  const int nymax = (cd.hi + s - 1) / s, nxmax = (cd.wi + s - 1) / s;
+  conv_shape(pl, cd.ci, s * s, nymax, nxmax);
+  // band: input rows a + dy - t over the classes that have taps
+  int dmin = 1 << 30, dmax = -(1 << 30);
+  for (int c = 0; c < s; ++c) {
+    const int k0 = (c + cd.p) % s;
+    if (k0 >= k) continue;
+    const int nt = (k - k0 + s - 1) / s, d = (c + cd.p - k0) / s;
+    dmin = std::min(dmin, d - nt + 1);
+    dmax = std::max(dmax, d);
+  }
+  pl.dmin = dmin;
+  pl.SH = pl.TA + dmax - dmin;
+  pl.SW = nxmax + dmax - dmin;
+  pl.plane = conv_plane(pl.SH, pl.SW, pl.mf);
+  pl.CC = conv_depth(cc, pl.plane, cd.co, pl.mf);
+  pl.inv_sh = 1.0f / (float)pl.SH;
+  return pl;
+}
+
+// Plan of a forward convolution (input ci x hi x wi, output co x ho x wo);
+// nq > 0 fixes the matrix-core kernel's column tiles per task.
+inline ConvPlan plan_convf(const ConvDesc& cd, int nq, int cc) {
+  ConvPlan pl{};
+  conv_shape(pl, cd.co, 1, cd.ho, cd.wo);
+  if (pl.mf && nq > 0 && nq != pl.NQ) {
+    pl.NQ = nq;
+    const int per = 16 * nq;
+    const int want = std::max(1, (4 + pl.nblk - 1) / pl.nblk);
+    conv_tiles(pl, 1, cd.ho, cd.wo, per, std::max(64, want * per));
+  }
+  pl.SH = (pl.TA - 1) * cd.s + cd.k;
+  pl.SW = (cd.wo - 1) * cd.s + cd.k;
+  pl.plane = conv_plane(pl.SH, pl.SW, pl.mf);
+  pl.CC = conv_depth(cc, pl.plane, cd.ci, pl.mf);
+  pl.inv_sh = 1.0f / (float)pl.SH;
+  return pl;
+}
+
+template <class Epi, int CB, int P>
+void launch_convt(int R, const ConvDesc& cd, const ConvPlan& pl, const double* in, Epi epi,
+                  double* part, int ntiles, hipStream_t s) {
+  const long long nwg = (long long)R * pl.nT * pl.wgt;
+  hipLaunchKernelGGL((k_convt<Epi, CB, P>), dim3((unsigned)nwg), dim3(256),
+                     (size_t)pl.CC * pl.plane * 8, s, cd, pl, in, epi, part, ntiles);
+}
+
+template <class Epi, int CB, int P>
+void launch_convf(int R, const ConvDesc& cd, const ConvPlan& pl, const double* in, Epi epi,
+                  double* part, int ntiles, hipStream_t s) {
+  const long long nwg = (long long)R * pl.nT * pl.wgt;
+  hipLaunchKernelGGL((k_convf<Epi, CB, P>), dim3((unsigned)nwg), dim3(256),
+                     (size_t)pl.CC * pl.plane * 8, s, cd, pl, in, epi, part, ntiles);
+}
+
+template <class Epi, int MT, int NQ>
+void launch_convt_mf(int R, const ConvDesc& cd, const ConvPlan& pl, const double* in, Epi epi,
+                     double* part, int ntiles, hipStream_t s) {
+  const long long nwg = (long long)R * pl.nT * pl.wgt;
+  hipLaunchKernelGGL((k_convt_mf<Epi, MT, NQ>), dim3((unsigned)nwg), dim3(256),
+                     (size_t)pl.CC * pl.plane * 8, s, cd, pl, in, epi, part, ntiles);
+}
+
+template <class Epi, int MT, int NQ>
+void launch_convf_mf(int R, const ConvDesc& cd, const ConvPlan& pl, const double* in, Epi epi,
+                     double* part, int ntiles, hipStream_t s) {
+  const long long nwg = (long long)R * pl.nT * pl.wgt;
+  hipLaunchKernelGGL((k_convf_mf<Epi, MT, NQ>), dim3((unsigned)nwg), dim3(256),
+                     (size_t)pl.CC * pl.plane * 8, s, cd, pl, in, epi, part, ntiles);
+}
+
+// A plan the kernels can run: a band that fits LDS and the staging loop
+// (SW <= 256), at most `ntiles` row-sum slots per row, a grid within range.
+inline bool conv_plan_ok(const ConvPlan& pl, int R, int ntiles) {
+  return pl.plane * pl.CC <= CONV_BAND_MAX && pl.SW <= 256 && pl.nT * pl.wgt <= ntiles &&
+         (long long)R * pl.nT * pl.wgt < (1ll << 31);
+}
+
+// The whole-row kernels take a layer whose input row (transposed: co x ho x
+// wo, forward: ci x hi x wi) fits their LDS staging, unless it has 32 or
+// more channels on both sides (a contraction the matrix cores of the tiled
+// kernels run faster, measured at the 3x32x32 CNNs) or the net was made to
+// run the tiled kernels everywhere.
+inline bool conv_whole_row(const ConvDesc& cd, bool transposed) {
+  const bool wide = cd.ci >= 32 && cd.co >= 32;
+  return !cd.tiled && !wide &&
+         (transposed ? cd.co * cd.ho * cd.wo : cd.ci * cd.hi * cd.wi) <= CONV_STAGE_MAX;
+}
+
+// Transposed convolution: the whole-row kernels where the input row fits
+// LDS (variants as run_convt_row), else the tiled ones, variant (autotuner)
+// 0: staging depth by the band budget, 1/2/3: 4, 8 or 16 channels per
+// chunk.  No variant changes a result.
+template <class Epi>
+hipError_t run_convt(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
+                     hipStream_t s, int variant = 0) {
+  if (R <= 0) return hipSuccess;
+  if (conv_whole_row(cd, true)) return run_convt_row(R, cd, in, epi, part, ntiles, s, variant);
+  const int cc = variant == 1 ? 4 : variant == 2 ? 8 : variant == 3 ? 16 : 0;
+  const ConvPlan pl = plan_convt(cd, cc);
+  if (!conv_plan_ok(pl, R, Epi::NSUM > 0 ? ntiles : 1 << 30)) return hipErrorInvalidValue;
+  if (pl.mf) {
+    switch (pl.MT * 10 + pl.NQ) {
+      case 11: launch_convt_mf<Epi, 1, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 12: launch_convt_mf<Epi, 1, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 21: launch_convt_mf<Epi, 2, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 22: launch_convt_mf<Epi, 2, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 31: launch_convt_mf<Epi, 3, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 32: launch_convt_mf<Epi, 3, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 41: launch_convt_mf<Epi, 4, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      default: launch_convt_mf<Epi, 4, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+    }
+    return hipGetLastError();
+  }
+  switch (pl.CB * 10 + pl.P) {
+    case 41: launch_convt<Epi, 4, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+    case 42: launch_convt<Epi, 4, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+    case 81: launch_convt<Epi, 8, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+    default: launch_convt<Epi, 8, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+  }
+  return hipGetLastError();
+}
+
+// Forward convolution: the whole-row kernels where the input row fits LDS
+// (variants as run_convf_row), else the tiled ones, variant 0: tiles and
+// staging depth by shape, 1/2/3: 4, 8 or 16 channels per chunk, 4: the
+// other column-tile count (matrix cores; the vector kernel keeps its shape).  The forward convolution has no
+// row sums and accumulates each output in the same order under every
+// variant, so the choice changes no result.
 template <class Epi>
 hipError_t run_convf(int R, const ConvDesc& cd, const double* in, Epi epi, double* part, int ntiles,
                      hipStream_t s, int variant = 0) {
   if (R <= 0) return hipSuccess;
-  if (variant == 6 && cd.mf) {
-    launch_convf_mfma(R, cd, in, epi, s);
+  if (conv_whole_row(cd, false)) return run_convf_row(R, cd, in, epi, part, ntiles, s, variant);
+  const int cc = variant == 1 ? 4 : variant == 2 ? 8 : variant == 3 ? 16 : 0;
+  ConvPlan pl = plan_convf(cd, 0, cc);
+  if (variant == 4 && pl.mf) pl = plan_convf(cd, 3 - pl.NQ, 0);
+  if (!conv_plan_ok(pl, R, Epi::NSUM > 0 ? ntiles : 1 << 30)) return hipErrorInvalidValue;
+  if (pl.mf) {
+    switch (pl.MT * 10 + pl.NQ) {
+      case 11: launch_convf_mf<Epi, 1, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 12: launch_convf_mf<Epi, 1, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 21: launch_convf_mf<Epi, 2, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 22: launch_convf_mf<Epi, 2, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 31: launch_convf_mf<Epi, 3, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 32: launch_convf_mf<Epi, 3, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+      case 41: launch_convf_mf<Epi, 4, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+      default: launch_convf_mf<Epi, 4, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+    }
     return hipGetLastError();
   }
-  const int cb = variant == 1 ? 4 : (variant == 2 || variant == 4) ? 8
-                                  : (variant == 3 || variant == 5) ? 16
-                                                                   : conv_block(cd.co, (cd.ho * cd.wo + 63) / 64);
-  const int P = variant >= 4 ? 4 : 0;
-  switch (cb) {
-    case 4: launch_convf_cb<Epi, 4>(R, cd, in, epi, part, ntiles, s, P); break;
-    case 8: launch_convf_cb<Epi, 8>(R, cd, in, epi, part, ntiles, s, P); break;
-    default: launch_convf_cb<Epi, 16>(R, cd, in, epi, part, ntiles, s, P); break;
+  switch (pl.CB * 10 + pl.P) {
+    case 41: launch_convf<Epi, 4, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+    case 42: launch_convf<Epi, 4, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
+    case 81: launch_convf<Epi, 8, 1>(R, cd, pl, in, epi, part, ntiles, s); break;
+    default: launch_convf<Epi, 8, 2>(R, cd, pl, in, epi, part, ntiles, s); break;
   }
   return hipGetLastError();
 }
@@ -1063,6 +1715,8 @@ hipError_t run_gemm_v(int variant, int R, int K, int N, LoadA la, const float* B
 }
 
 }  // namespace
+
+bool conv_whole_row_layer(const ConvDesc& cd, bool transposed) { return conv_whole_row(cd, transposed); }
 
 int gemm_ntiles(int N) { return (N + TileDefault::BN - 1) / TileDefault::BN; }
 

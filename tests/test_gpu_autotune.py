@@ -1,4 +1,4 @@
-"""Kernel variants (GEMM tiles, convolution channel blocks and positions
+"""Kernel variants (GEMM tiles, convolution staging depth and positions
 per lane) and the autotuner that picks among them: every variant of every
 layer must give bit-identical bounds, gradients and slope updates, so tuning
 never changes a result."""
@@ -20,7 +20,10 @@ def H(t):
                                   lambda: wl.small_conv4_set().member(0),
                                   lambda: wl.edge_cnn(B=40)],
                          ids=["mlp784-256x6-10", "cnn5x9x7", "cnn3x8x8-4xc8", "cnn3x7x7-edge"])
-def test_every_kernel_variant_gives_identical_results(make):
+@pytest.mark.parametrize("kernels", ["auto", "tiled"])
+def test_every_kernel_variant_gives_identical_results(make, kernels, monkeypatch):
+    if kernels == "tiled":   # conv layers on the tiled kernels (no effect on the MLP)
+        monkeypatch.setenv("CV_CONV_TILED", "1")
     w = make()
     prop = gpipe.Property.from_workload(w)
     l0, u0 = (H(x) for x in prop.root.bounds())

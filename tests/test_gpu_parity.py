@@ -517,18 +517,23 @@ def test_pass_with_constraint_order_matches_oracle(make):
 
 # ------------------------------------------------------- conv layers (CNN)
 
+@pytest.mark.parametrize("kernels", ["auto", "tiled"])
 @pytest.mark.parametrize("make", [lambda: wl.cifar_cnn(B=64), lambda: wl.ragged_cnn(B=64),
                                   lambda: wl.wide_cnn(B=32), lambda: wl.edge_cnn(B=64)],
                          ids=["cnn3x32x32", "cnn5x9x7", "cnn4x24x24", "cnn3x7x7-edge"])
-def test_pass_cnn_matches_oracle(make):
+def test_pass_cnn_matches_oracle(make, kernels, monkeypatch):
     # backward passes and the adjoint run direct (transposed) convolutions.
     # 3x32x32 -> conv16 4x4/2 -> conv32 4x4/2 -> 100 -> 10: 3072-dim input
     # boxes take the workgroup-per-row complete clipping.  5x9x7 -> conv6
     # 3x3/1 -> conv17 4x4/3 -> 12 -> 4: ragged channel blocks, stride 3.
     # 4x24x24 -> conv16 3x3/1 -> conv8 4x4/2 -> 10 -> 3: rows of 9216 values
-    # are read from global memory instead of LDS.  3x7x7 -> conv4 1x1/2 ->
+    # (over 64 KiB) take the tiled kernels.  3x7x7 -> conv4 1x1/2 ->
     # conv5 2x2/2 -> conv3 3x3/1 pad 2 -> 6 -> 3: positions without taps,
-    # non-overlapping taps, padding wider than half the kernel.
+    # non-overlapping taps, padding wider than half the kernel.  "tiled":
+    # every conv layer on the tiled kernels (band staging; matrix cores from
+    # 16 output channels), which otherwise run only where a row exceeds LDS.
+    if kernels == "tiled":
+        monkeypatch.setenv("CV_CONV_TILED", "1")
     w = make()
     op = OracleProp(w)
     sp = wl.draw_splits(w.B, w.split_counts, op.unstable())
