@@ -24,6 +24,8 @@
 // The returned bound D(beta) is valid for any beta >= 0 (weak duality); it is
 // evaluated in float64, moved down by a rigorous bound on its rounding (and by
 // the error bound of the objective plane itself) and rounded down to float32.
+#include <type_traits>
+
 #include "cv_common.h"
 #include "cv_internal.h"
 #include "cv_team.h"
@@ -31,6 +33,13 @@
 namespace {
 
 constexpr int CA_KMAX = CV_TEAM_KMAX;
+
+// What the search keeps per candidate beside its breakpoint: workgroup teams
+// (LDS to spare at three workgroups per CU) the float64 weight itself, wave
+// teams |g_j| in float32 (their four teams' slices share one workgroup's
+// LDS), from which each round forms the weight.
+template <class Team>
+using ca_wt = typename std::conditional<Team::PER_BLOCK == 1, double, float>::type;
 
 // Weighted quantile: the smallest candidate q* with W(> q*) <= S, where
 // W(> p) sums the weights of candidates above p.  The search keeps an open
@@ -44,16 +53,17 @@ constexpr int CA_KMAX = CV_TEAM_KMAX;
 // on every early round takes 15-20 % fewer than alternating from the start).
 // A probe takes the largest candidate p at or below the split point; W(> p)
 // decides the side and, only when W(> p) <= S, W(>= p) > S identifies p = q*.
-// The breakpoints and the candidates' |g_j| sit in the team's LDS slice
+// The breakpoints and the candidates' weights sit in the team's LDS slice
 // (element e of member t at e*T + t; non-candidates hold -inf and 0), which
-// keeps them out of the registers of the common path that needs no search;
-// each weight |g_j| (hi_j - lo_j) is formed in float64 from |g_j| and the box
-// in registers, the same value the caller summed, so every decision is taken
-// on exact float64 weights.
+// keeps them out of the registers of the common path that needs no search:
+// the float64 weight |g_j| (hi_j - lo_j) itself (workgroup teams), or |g_j|,
+// from which each round forms that weight with the box in registers (wave
+// teams).  Either way it is the value the caller summed, so every decision
+// is taken on exact float64 weights.
 // qmax, qmin: the largest and smallest candidate (team-wide), wpos the sum
 // of the candidates' weights.
 template <class Team, int EPL>
-__device__ double ca_select(const Team& tm, const double* sq, const float* sg,
+__device__ double ca_select(const Team& tm, const double* sq, const ca_wt<Team>* sg,
                             const float (&xl)[EPL], const float (&xh)[EPL], double S,
                             double wpos, double qmax, double qmin) {
   constexpr int T = Team::SIZE;
@@ -89,7 +99,9 @@ __device__ double ca_select(const Team& tm, const double* sq, const float* sg,
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const double q = sq[e * T + tm.t];
-      const double w = (double)sg[e * T + tm.t] * ((double)xh[e] - (double)xl[e]);
+      double w;
+      if constexpr (Team::PER_BLOCK == 1) w = sg[e * T + tm.t];
+      else w = (double)sg[e * T + tm.t] * ((double)xh[e] - (double)xl[e]);
       if (q > p) wg += w;
       if (q >= p) wge += w;
     }
@@ -120,7 +132,7 @@ template <class Team, int EPL>
 __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, double e_in,
                           const float* lo_b, const float* hi_b, const CvCons* cons, int b,
                           int passes, bool& empty, float* beta_out, double* xstar,
-                          double* beta, double* sq, float* sw) {
+                          double* beta, double* sq, ca_wt<Team>* sw) {
   constexpr int T = Team::SIZE;
   const int t = tm.t;
   float xl[EPL], xh[EPL];
@@ -266,13 +278,14 @@ __device__ double ca_core(const Team& tm, int n, double (&a)[EPL], double c, dou
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
           double qe = -INFINITY;
-          float ge = 0.0f;
+          ca_wt<Team> ge = 0;
           if (g[e] != 0.0f) {
             const double q = -a[e] / (double)g[e];
             const double w = (double)fabsf(g[e]) * ((double)xh[e] - (double)xl[e]);
             if (q > 0.0 && w > 0.0) {
               qe = q;
-              ge = fabsf(g[e]);
+              if constexpr (Team::PER_BLOCK == 1) ge = w;
+              else ge = fabsf(g[e]);
               wpos += w;
               qmax = fmax(qmax, q);
               nqmin = fmax(nqmin, -q);
@@ -413,7 +426,7 @@ template <class Team, int EPL>
 struct CaShared {
   double beta[Team::PER_BLOCK * CA_KMAX];
   double q[Team::PER_BLOCK * Team::SIZE * EPL];
-  float w[Team::PER_BLOCK * Team::SIZE * EPL];
+  ca_wt<Team> w[Team::PER_BLOCK * Team::SIZE * EPL];
   double red[24];
   const float* mrow[CA_KMAX];
   float mscale[CA_KMAX];
@@ -435,19 +448,18 @@ __device__ __forceinline__ double* q_slice(CaShared<Team, EPL>& sh) {
   return sh.q + Team::index_in_block() * Team::SIZE * EPL;
 }
 template <class Team, int EPL>
-__device__ __forceinline__ float* w_slice(CaShared<Team, EPL>& sh) {
+__device__ __forceinline__ ca_wt<Team>* w_slice(CaShared<Team, EPL>& sh) {
   return sh.w + Team::index_in_block() * Team::SIZE * EPL;
 }
 
-// Workgroups per CU that k_ca_rows asks the register allocator for.  A
-// workgroup team of up to 12 coordinates per lane fits four workgroups' LDS
-// and spills only a few registers at that target, which pays for itself
-// (3072-wide rows); wave teams stay at three: at four, a 13-coordinate wave
-// spills its objective row inside the constraint loop, and that costs more
-// than the fourth wave gains.
+// Workgroups per CU that k_ca_rows asks the register allocator for: three.
+// At four, a 13-coordinate wave team spills its objective row inside the
+// constraint loop, and a 12-coordinate workgroup team spills about 40
+// registers to memory (measured on 3072-wide rows: 4.19 ms at four, 3.69 ms
+// at three).
 template <class Team, int EPL>
 constexpr int ca_rows_blocks() {
-  return (Team::PER_BLOCK == 1 && EPL <= 12) ? 4 : 3;
+  return 3;
 }
 
 // Final planes: rows r = (b, m) of the backward pass output.
