@@ -391,6 +391,22 @@ def main():
             cpu["sample"] = f"property {p_}: " + cpu["sample"]
         log(f"cpu baseline {cpu['value']:.2f} subdomains/s ({cpu['sample']})")
 
+    # device memory of the step: the library's workspace for one slope-step
+    # call (a chunk when chunked), the slope and Adam state it carries between
+    # steps (alpha, m, v: 12 bytes per row and hidden neuron), torch's peak
+    # allocation over the run and the device's use after it
+    rows_call = (min(B, chunk) if chunk else B) * prop.M
+    free_b, total_b = torch.cuda.mem_get_info()
+    memory = {
+        "alpha_step_workspace_bytes": prop.net.alpha_step_workspace(
+            min(B, chunk) if chunk else B, prop.M, getattr(prop, "P", 1)),
+        "slope_state_bytes": 12 * rows_call * prop.net.n_hidden,
+        "torch_peak_allocated_bytes": int(torch.cuda.max_memory_allocated()),
+        "device_used_bytes": int(total_b - free_b),
+        "device_total_bytes": int(total_b),
+    }
+    log("memory: " + ", ".join(f"{k} {v / 2**30:.2f} GiB" for k, v in memory.items()))
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "subdomains/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -409,6 +425,7 @@ def main():
         "alpha_vs_plain": {"throughput_ratio": round(value / (B / plain_s), 5),
                            "mean_lb_gain": gain},
         "roofline": roof,
+        "memory": memory,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -52,7 +52,8 @@ typedef enum {
   CV_E_UNSUPPORTED = -3, /* valid request this library does not implement */
   CV_E_WORKSPACE = -4,   /* ws_bytes smaller than the reported requirement */
   CV_E_HIP = -5,         /* a HIP runtime call failed (see cv_last_hip_error) */
-  CV_E_NOMEM = -6        /* device allocation inside a create call failed */
+  CV_E_NOMEM = -6,       /* device allocation inside a create call failed */
+  CV_E_NONFINITE = -7    /* debug build: a floating-point input holds NaN or +-inf */
 } cv_status;
 
 const char* cv_status_string(cv_status s);
@@ -60,6 +61,22 @@ const char* cv_status_string(cv_status s);
 int cv_last_hip_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int cv_version(void);
+
+/* Debug build (libclipverify_debug.so, compiled with CV_DEBUG): 1, else 0.
+ * A debug build also checks what a release build takes on trust, at the
+ * cost of synchronising the stream:
+ * - the floating-point inputs of cv_clip_domains, cv_concretize,
+ *   cv_concretize_planes, cv_bound_propagate and cv_alpha_step (boxes,
+ *   planes and intercepts, objectives, intermediate bounds, slopes read)
+ *   are scanned on the device before any kernel is enqueued; a NaN or
+ *   +-inf returns CV_E_NONFINITE and enqueues nothing;
+ * - every kernel launch is followed by a synchronisation of its stream and
+ *   an error check, so a failing kernel returns CV_E_HIP from the call that
+ *   launched it, and cv_last_kernel names it. */
+int cv_debug_build(void);
+/* Name of the kernel this thread's library calls launched last (NULL
+ * before the first launch).  Host-owned static string. */
+const char* cv_last_kernel(void);
 
 /* ------------------------------------------------------------- network */
 

@@ -1,24 +1,28 @@
 """ctypes view of libclipverify.so (the C ABI declared in include/clipverify.h).
 
 Loading fails loudly: there is no fallback implementation.  Build the
-library first with ``python -m paper_2512_11087_amd.build``.
+library first with ``python -m paper_2512_11087_amd.build``.  With
+CV_DEBUG=1 in the environment the debug build (libclipverify_debug.so:
+input scans, a synchronisation and error check after every kernel) is
+loaded instead.
 """
 import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libclipverify.so")
+DEBUG_LIB_PATH = os.path.join(HERE, "libclipverify_debug.so")
 
 CV_LINEAR, CV_CONV2D = 0, 1
 CV_CLIP_PARALLEL, CV_CLIP_SEQUENTIAL = 0, 1
 CV_TUNE_RELAX, CV_TUNE_FINAL, CV_TUNE_ADJOINT = 0, 1, 2
 
 STATUS = {0: "CV_OK", -1: "CV_E_INVALID", -2: "CV_E_SHAPE", -3: "CV_E_UNSUPPORTED",
-          -4: "CV_E_WORKSPACE", -5: "CV_E_HIP", -6: "CV_E_NOMEM"}
+          -4: "CV_E_WORKSPACE", -5: "CV_E_HIP", -6: "CV_E_NOMEM", -7: "CV_E_NONFINITE"}
 
 # every function the header declares (checked by the CPU test suite)
 EXPORTS = [
-    "cv_status_string", "cv_last_hip_error", "cv_version",
+    "cv_status_string", "cv_last_hip_error", "cv_version", "cv_debug_build", "cv_last_kernel",
     "cv_net_create", "cv_net_destroy", "cv_net_info",
     "cv_net_autotune", "cv_net_tuning", "cv_net_set_tuning",
     "cv_root_create", "cv_root_create_ex", "cv_root_destroy", "cv_root_bounds", "cv_root_planes",
@@ -61,17 +65,24 @@ _lib = None
 def lib():
     """The loaded library (raises if it is not built)."""
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"libclipverify is not built ({LIB_PATH} missing); "
+    if _lib is None:
+        _lib = load(DEBUG_LIB_PATH if os.environ.get("CV_DEBUG") == "1" else LIB_PATH)
+    return _lib
+
+
+def load(path):
+    """Load a build of the library at `path` with the ABI's signatures."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"libclipverify is not built ({path} missing); "
                            "run `python -m paper_2512_11087_amd.build`")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     P, I, F, S, V = C.c_void_p, C.c_int, C.c_float, C.c_size_t, None
     sig = {
         "cv_status_string": (C.c_char_p, [I]),
         "cv_last_hip_error": (I, []),
         "cv_version": (I, []),
+        "cv_debug_build": (I, []),
+        "cv_last_kernel": (C.c_char_p, []),
         "cv_net_create": (I, [P, I, P]),
         "cv_net_destroy": (I, [P]),
         "cv_net_info": (I, [P, P, P, P, P]),
@@ -114,7 +125,6 @@ def lib():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = L
     return L
 
 

@@ -96,6 +96,13 @@ class Net:
                 hi = mid - 1
         return lo
 
+    def alpha_step_workspace(self, B, M, P=1):
+        """Bytes of device workspace one alpha_step call over B subdomains
+        with M objective rows asks for (host only)."""
+        need = C.c_size_t()
+        N.call("cv_alpha_step_workspace", self.handle, P, B, M, C.byref(need))
+        return int(need.value)
+
     TUNE_KINDS = {"relax": N.CV_TUNE_RELAX, "final": N.CV_TUNE_FINAL,
                   "adjoint": N.CV_TUNE_ADJOINT}
 

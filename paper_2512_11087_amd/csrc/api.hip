@@ -7,6 +7,7 @@
 #include <vector>
 
 #include <functional>
+#include <initializer_list>
 #include <cstdlib>
 #include <mutex>
 
@@ -19,6 +20,7 @@
 namespace {
 
 thread_local int g_last_hip = 0;
+thread_local const char* t_last_kernel = nullptr;
 // Set while an allocation-free entry point runs on this thread: the timing
 // instrumentation records no events then (creating one may allocate).
 thread_local bool t_noalloc = false;
@@ -77,11 +79,52 @@ struct Prof {
     if (b && hipEventRecord(b, s) == hipSuccess) g_prof.push_back({name, a, b, flops, bytes});
   }
 };
+// A kernel launch of the hot calls: named (cv_last_kernel) and timed when
+// the instrumentation is on; a debug build synchronises the stream and
+// checks for an error after every launch.
+#ifdef CV_DEBUG
+#define CV_DEBUG_SYNC()                            \
+  do {                                             \
+    CV_HIP(hipStreamSynchronize(s));               \
+    CV_HIP(hipGetLastError());                     \
+  } while (0)
+#else
+#define CV_DEBUG_SYNC() \
+  do {                  \
+  } while (0)
+#endif
 #define PLAUNCH(name, flops, bytes, call)          \
   do {                                             \
-    Prof pf__(name, (double)(flops), (double)(bytes), s); \
-    CV_HIP(call);                                  \
+    t_last_kernel = name;                          \
+    {                                              \
+      Prof pf__(name, (double)(flops), (double)(bytes), s); \
+      CV_HIP(call);                                \
+    }                                              \
+    CV_DEBUG_SYNC();                               \
   } while (0)
+
+// Debug builds: CV_E_NONFINITE if any of the float arrays (pointer, count;
+// null pointers skipped) holds a NaN or +-inf, scanned on the device on
+// stream s (which is synchronised).  Release builds: CV_OK, nothing read.
+struct FArr {
+  const float* p;
+  size_t n;
+};
+cv_status debug_finite(hipStream_t s, std::initializer_list<FArr> arrays) {
+#ifdef CV_DEBUG
+  t_last_kernel = "scan_nonfinite";
+  CV_HIP(launch_nonfinite_reset(s));
+  for (const FArr& a : arrays)
+    if (a.p && a.n) CV_HIP(launch_nonfinite_scan(a.p, a.n, s));
+  unsigned found = 0;
+  CV_HIP(nonfinite_result(&found, s));
+  return found ? CV_E_NONFINITE : CV_OK;
+#else
+  (void)s;
+  (void)arrays;
+  return CV_OK;
+#endif
+}
 
 // Bump allocator over a caller workspace (256-byte aligned slices).
 struct Carve {
@@ -328,12 +371,19 @@ const char* cv_status_string(cv_status s) {
     case CV_E_WORKSPACE: return "workspace too small";
     case CV_E_HIP: return "HIP runtime error";
     case CV_E_NOMEM: return "device allocation failed";
+    case CV_E_NONFINITE: return "non-finite input (debug build)";
   }
   return "unknown status";
 }
 
 int cv_last_hip_error(void) { return g_last_hip; }
 int cv_version(void) { return CV_VERSION; }
+#ifdef CV_DEBUG
+int cv_debug_build(void) { return 1; }
+#else
+int cv_debug_build(void) { return 0; }
+#endif
+const char* cv_last_kernel(void) { return t_last_kernel; }
 
 cv_status cv_net_create(const cv_layer_desc* layers, int n_layers, cv_net* out) {
   if (!layers || !out) return CV_E_INVALID;
@@ -968,6 +1018,7 @@ cv_status cv_clip_domains(cv_root root, const int32_t* pid, int B, int n,
   CvCons c;
   cv_status st = resolve_cons(root, pid, cons, &c);
   if (st) return st;
+  if ((st = debug_finite(s, {{lo, (size_t)B * n}, {hi, (size_t)B * n}}))) return st;
   PLAUNCH("clip", 0, 16.0 * B * n + 4.0 * B * c.kmax * n, launch_clip(B, n, c, lo, hi, infeasible, mode, s));
   return CV_OK;
 }
@@ -1017,6 +1068,7 @@ cv_status cv_concretize_planes(cv_root root, const int32_t* pid, int B, const fl
   CvCons sp;
   cv_status st = resolve_cons(root, pid, splits, &sp);
   if (st) return st;
+  if ((st = debug_finite(s, {{lo, (size_t)B * root->n0}, {hi, (size_t)B * root->n0}}))) return st;
   const CvProps props = props_of(root, pid);
   const int Nh = root->N, U = root->Umax;
   int Umin = U;
@@ -1181,9 +1233,22 @@ cv_status cv_concretize(cv_root root, const int32_t* pid, int B, int P, int n, c
   CvCons cc;
   cv_status st = resolve_cons(root, pid, cons, &cc);
   if (st) return st;
+  const size_t na = (A_shared ? (size_t)P : (size_t)B * P);
+  if ((st = debug_finite(s, {{A, na * n}, {c, na}, {lo, (size_t)B * n}, {hi, (size_t)B * n}})))
+    return st;
   PLAUNCH("ca_generic", 0, 4.0 * B * P * n + 8.0 * B * n, launch_ca_generic(B, P, n, A, A_shared, c, lo, hi, cons ? &cc : nullptr, passes, lb, ub,
                            beta, infeasible, s));
   return CV_OK;
+}
+
+// Debug scan of the inputs of a bound propagation or slope step (alpha only
+// where it is read).
+cv_status debug_prop_inputs(const cv_net_s* net, const cv_root_s* root, int B, int M, const float* C,
+                            const float* t, const float* l, const float* u, const float* alpha,
+                            const float* lo, const float* hi, hipStream_t s) {
+  const size_t PM = (size_t)root->P * M, BH = (size_t)B * net->n_hidden, B0 = (size_t)B * net->n[0];
+  return debug_finite(s, {{C, PM * net->n[net->L]}, {t, PM}, {l, BH}, {u, BH},
+                          {alpha, BH * M}, {lo, B0}, {hi, B0}});
 }
 
 static cv_status check_prop(cv_net net, cv_root root, int B, int M, const float* C, const float* t,
@@ -1220,6 +1285,7 @@ cv_status cv_bound_propagate(cv_net net, int B, int M, const float* C, const flo
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
   if ((st = resolve_cons(root, pid, cons, &cc))) return st;
+  if ((st = debug_prop_inputs(net, root, B, M, C, t, l, u, alpha, lo, hi, s))) return st;
   Bwd w;
   bwd_layout(net, net->L, (long long)B * M, M, root->P, true, false, ws, &w);
   st = backward_run(net, root, props_of(root, pid), net->L, B, M, C, t, l, u, alpha,
@@ -1269,6 +1335,8 @@ cv_status cv_alpha_step(cv_net net, int B, int M, const float* C, const float* t
   if (!ws || ws_bytes < need) return CV_E_WORKSPACE;
   CvCons cc;
   if ((st = resolve_cons(root, pid, cons, &cc))) return st;
+  if ((st = debug_prop_inputs(net, root, B, M, C, t, l, u, init ? nullptr : alpha, lo, hi, s)))
+    return st;
   Bwd w;
   const int R = B * M;
   bwd_layout(net, net->L, R, M, root->P, true, true, ws, &w);

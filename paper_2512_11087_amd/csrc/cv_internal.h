@@ -206,6 +206,11 @@ hipError_t launch_top_eye(int P, int M, int nP, double eye, const float* W, cons
                           const float* b, CvProps props, int layer, double* psiT, double* c0,
                           double* e0, double* cabs0, hipStream_t s);
 // Rows [0, rows) of the dense matrix of a convolution layer (float32).
+// Debug-build input scan: clear the device flag of non-finite values, flag
+// those of p[0, n), read the flag back (synchronises s).
+hipError_t launch_nonfinite_reset(hipStream_t s);
+hipError_t launch_nonfinite_scan(const float* p, size_t n, hipStream_t s);
+hipError_t nonfinite_result(unsigned* found, hipStream_t s);
 // Whether a conv layer's transposed (or forward) convolution runs the
 // whole-row kernels (its input row fits LDS) rather than the tiled ones.
 bool conv_whole_row_layer(const ConvDesc& cd, bool transposed);

@@ -623,3 +623,40 @@ hipError_t launch_merge_layer(int B, int n, int Nh, int off, const float* lbl, c
                      off, lbl, lbn, l, u, infeasible);
   return hipGetLastError();
 }
+
+// ------------------------------------------------ debug-build input scan
+// Flags non-finite values of float arrays in one device word (cleared,
+// set by any wave that sees one -- every writer stores the same value --
+// and read back on the stream).  Only the debug build's entry points call
+// these.
+namespace {
+__device__ unsigned g_nonfinite;
+
+__global__ void k_nonfinite_reset() { g_nonfinite = 0u; }
+
+__global__ __launch_bounds__(256) void k_nonfinite_scan(const float* __restrict__ p, size_t n) {
+  unsigned bad = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    bad |= !isfinite(p[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) g_nonfinite = 1u;
+}
+}  // namespace
+
+hipError_t launch_nonfinite_reset(hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite_reset, dim3(1), dim3(1), 0, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_scan(const float* p, size_t n, hipStream_t s) {
+  const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_nonfinite_scan, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t nonfinite_result(unsigned* found, hipStream_t s) {
+  hipError_t e = hipMemcpyFromSymbolAsync(found, HIP_SYMBOL(g_nonfinite), sizeof(unsigned), 0,
+                                          hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+

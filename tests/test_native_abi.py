@@ -95,3 +95,17 @@ def test_invalid_arguments_are_rejected_on_the_host(lib):
     assert lib.cv_net_tuning(None, 0, 2, None, None) == -1
     assert lib.cv_net_set_tuning(None, 0, 2, 0) == -1
     assert lib.cv_net_destroy(None) == 0 and lib.cv_root_destroy(None) == 0
+
+
+def test_debug_build_loads_and_reports_itself(lib):
+    # the debug build (input scans, a check after every kernel) exports the
+    # same functions and says it is one; the release build says it is not
+    if not os.path.exists(N.DEBUG_LIB_PATH):
+        from paper_2512_11087_amd import build
+        build.build(debug=True)
+    dbg = N.load(N.DEBUG_LIB_PATH)
+    for name in header_functions():
+        assert hasattr(dbg, name), name
+    assert dbg.cv_debug_build() == 1 and lib.cv_debug_build() == 0
+    assert dbg.cv_status_string(-7) == b"non-finite input (debug build)"
+    assert dbg.cv_last_kernel() is None
