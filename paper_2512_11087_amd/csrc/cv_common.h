@@ -48,6 +48,21 @@ __device__ __forceinline__ double lane_f64(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
+// A pointer every lane holds alike, moved to scalar registers (so that a
+// buffer resource built from it is scalar: a resource in vector registers
+// makes the compiler loop over its distinct values around every load).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t u = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (T*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+// A float64 value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
 #define CV_DPP_XOR1 0xB1
 #define CV_DPP_XOR2 0x4E
 #define CV_DPP_HALF_MIRROR 0x141

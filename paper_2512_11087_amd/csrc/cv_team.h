@@ -141,11 +141,16 @@ struct BlockTeam {
     }
     __syncthreads();
   }
+  // Every member reads the same LDS words, so the values are uniform: taking
+  // them through readfirstlane puts them in scalar registers, which lets a
+  // buffer load use the row as its resource directly (a resource the
+  // compiler sees in vector registers costs a loop over its distinct values
+  // around every load, each waiting for the previous).
   __device__ void meta(const float*, float, double, int k, const float*& row, float& scale,
                        double& h) const {
-    row = mrow[k];
-    scale = mscale[k];
-    h = mh[k];
+    row = uniform_ptr(mrow[k]);
+    scale = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(mscale[k])));
+    h = uniform_f64(mh[k]);
   }
 };
 

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_clip(int B, int n, CvCons cons, float* 
       tm.meta(my_row, my_scale, my_h, k, row, scale, h);
     else
       cons_row(cons, b, k, n, row, scale, h);
+    row = uniform_ptr(row);  // the same constraint for the whole team
     if (!row) continue;
     const cv_buf brow = cv_buffer(row, 4u * n);
     float g[EPL];

@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256, 2) void k_ca_neurons(int B, int Umax, int n, C
     if (tm.t == 0) Ltmp[id] = -INFINITY;
     return;
   }
-  const float* ap = (side ? rd.A_hi : rd.A_lo) + (size_t)(rd.prow ? q : j) * n;
+  const float* ap = uniform_ptr((side ? rd.A_hi : rd.A_lo) + (size_t)(rd.prow ? q : j) * n);
   const double c = side ? -rd.c_hi[j] : rd.c_lo[j];
   double a[EPL];
   const cv_buf bap = cv_buffer(ap, 4u * n);
