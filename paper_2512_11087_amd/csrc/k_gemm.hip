@@ -65,9 +65,23 @@ typedef Tile<64, 128> TilePlanes;
 static_assert(TileDefault::BN == TilePlanes::BN, "row-sum partials assume one column tiling");
 
 // A loaders return 4 consecutive k of one row (zeros outside [0,R) x [0,K)).
+// load_in (HAS_IN): the same for a row and chunk known to lie inside, with no
+// test (fast_ok: the loader's own layout allows it).
 struct LoadF64 {
   const double* p;
   int ld;
+  static constexpr bool HAS_IN = true;
+  __device__ __forceinline__ bool fast_ok() const { return (ld & 1) == 0; }
+  template <int NV>
+  __device__ __forceinline__ void load_in(int r, int k, double (&v)[NV]) const {
+    const double2* q = reinterpret_cast<const double2*>(p + (size_t)r * ld + k);
+#pragma unroll
+    for (int t = 0; t < NV / 2; ++t) {
+      const double2 x = q[t];
+      v[2 * t] = x.x;
+      v[2 * t + 1] = x.y;
+    }
+  }
   template <int NV>
   __device__ __forceinline__ void load(int r, int k, int R, int K, double (&v)[NV]) const {
     if (r < R && k + NV - 1 < K && (ld & 1) == 0) {
@@ -90,6 +104,14 @@ struct LoadBox {
   const float* lo;
   const float* hi;
   int n0;
+  // no untested copy of the main loop for this loader (a second loop copy
+  // costs the plane re-concretization a wave per SIMD); load_in exists only
+  // so that the shared loop compiles
+  static constexpr bool HAS_IN = false;
+  template <int NV>
+  __device__ __forceinline__ void load_in(int r, int k, double (&v)[NV]) const {
+    load<NV>(r, k, 0x7fffffff, 0x7fffffff, v);
+  }
   template <int NV>
   __device__ __forceinline__ void load(int r, int k, int R, int K, double (&v)[NV]) const {
     static_assert(NV % 2 == 0, "pairs");
@@ -174,39 +196,66 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
           make_float4(pb[q], pb[q + 1], pb[q + 2], pb[q + 3]);
   };
   const int nch = (K + GBK - 1) / GBK;
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) fetch((c + 1) * GBK);
+  // A tile inside the matrix (every row, column and K chunk in range) runs a
+  // copy of the main loop whose operand loads have no per-lane test: one
+  // uniform branch per tile instead of masked branches around every load.
+  auto main_loop = [&](auto inside) {
+    constexpr bool IN = decltype(inside)::value;
+    auto fetch_c = [&](int k0) {
+      if constexpr (IN) {
+        la.template load_in<APT>(m0 + ar, k0 + akq, pa);
+        const float4* q = reinterpret_cast<const float4*>(Bm + (size_t)(k0 + bk) * ldb + n0 + bc0);
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 4) {
-      double af[MI], bf[NI];
-      const int kr = kk + (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < MI; ++i) af[i] = sA[buf][kr * SA_LD + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < NI; ++j) bf[j] = (double)sB[buf][kr * SB_LD + wave * WN + j * 16 + (lane & 15)];
-      if (nblk == NI) {  // full tile: straight-line MFMA issue
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-#pragma unroll
-          for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int t = 0; t < BPT / 4; ++t) {
+          const float4 x = q[t];
+          pb[4 * t] = x.x; pb[4 * t + 1] = x.y; pb[4 * t + 2] = x.z; pb[4 * t + 3] = x.w;
+        }
       } else {
+        fetch(k0);
+      }
+    };
+    fetch_c(0);
+    stash(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nch) fetch_c((c + 1) * GBK);
 #pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          if (j < nblk) {
+      for (int kk = 0; kk < GBK; kk += 4) {
+        double af[MI], bf[NI];
+        const int kr = kk + (lane >> 4);
 #pragma unroll
-            for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i) af[i] = sA[buf][kr * SA_LD + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) bf[j] = (double)sB[buf][kr * SB_LD + wave * WN + j * 16 + (lane & 15)];
+        if (IN || nblk == NI) {  // full tile: straight-line MFMA issue
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NI; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            if (j < nblk) {
+#pragma unroll
+              for (int i = 0; i < MI; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
           }
         }
       }
+      if (c + 1 < nch) stash(buf ^ 1);
+      __syncthreads();
     }
-    if (c + 1 < nch) stash(buf ^ 1);
-    __syncthreads();
+  };
+  if constexpr (LoadA::HAS_IN) {
+    if (m0 + GBM <= R && n0 + GBN <= N && K > 0 && K % GBK == 0 && la.fast_ok() && (ldb & 3) == 0)
+      main_loop(std::true_type{});
+    else
+      main_loop(std::false_type{});
+  } else {
+    main_loop(std::false_type{});
   }
 
   // Epilogue, in groups of VGROUP accumulator rows: all global loads of a
