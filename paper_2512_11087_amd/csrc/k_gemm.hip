@@ -249,14 +249,6 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
       __syncthreads();
     }
   };
-  if constexpr (LoadA::HAS_IN) {
-    if (m0 + GBM <= R && n0 + GBN <= N && K > 0 && K % GBK == 0 && la.fast_ok() && (ldb & 3) == 0)
-      main_loop(std::true_type{});
-    else
-      main_loop(std::false_type{});
-  } else {
-    main_loop(std::false_type{});
-  }
 
   // Epilogue, in groups of VGROUP accumulator rows: all global loads of a
   // group are issued first (Epi::load), then the group is computed and
@@ -264,6 +256,11 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
   // once per element (the stores could otherwise alias later loads).
   constexpr int NS = Epi::NSUM;
   constexpr int VG = Epi::VGROUP;
+  // Inside a tile that lies in the matrix every element is in range; the
+  // epilogues that gain from it (Epi::UNGUARDED_INSIDE) then run without the
+  // per-element tests.
+  auto epilogue = [&](auto inside) {
+  constexpr bool IN = decltype(inside)::value && Epi::UNGUARDED_INSIDE;
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
 #pragma unroll
@@ -273,11 +270,11 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
 #pragma unroll
       for (int dv = 0; dv < VG; ++dv) {
         const int r = m0 + i * 16 + (lane >> 4) + 4 * (v0 + dv);
-        rw[dv] = epi.row(r < R ? r : R - 1);
+        rw[dv] = epi.row(IN || r < R ? r : R - 1);
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
           const int c = n0 + wave * WN + j * 16 + (lane & 15);
-          if (r < R && j < nblk && c < N) pre[dv][j] = epi.load(rw[dv], r, c);
+          if (IN || (r < R && j < nblk && c < N)) pre[dv][j] = epi.load(rw[dv], r, c);
         }
       }
 #pragma unroll
@@ -288,7 +285,7 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
           const int c = n0 + wave * WN + j * 16 + (lane & 15);
-          if (r < R && j < nblk && c < N) epi.apply(rw[dv], pre[dv][j], r, c, acc[i][j][v0 + dv], sums);
+          if (IN || (r < R && j < nblk && c < N)) epi.apply(rw[dv], pre[dv][j], r, c, acc[i][j][v0 + dv], sums);
         }
         if constexpr (NS > 0) {
 #pragma unroll
@@ -314,6 +311,25 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
         }
       }
     }
+  }
+  };
+  if constexpr (LoadA::HAS_IN) {
+    const bool in = m0 + GBM <= R && n0 + GBN <= N && K > 0 && K % GBK == 0 && la.fast_ok() && (ldb & 3) == 0;
+    if (in)
+      main_loop(std::true_type{});
+    else
+      main_loop(std::false_type{});
+    if constexpr (Epi::UNGUARDED_INSIDE) {
+      if (in)
+        epilogue(std::true_type{});
+      else
+        epilogue(std::false_type{});
+    } else {
+      epilogue(std::false_type{});
+    }
+  } else {
+    main_loop(std::false_type{});
+    epilogue(std::false_type{});
   }
 }
 
@@ -347,6 +363,7 @@ template <bool MULTI>
 struct EpiRelax {
   static constexpr int NSUM = 3;
   static constexpr int VGROUP = 4;
+  static constexpr bool UNGUARDED_INSIDE = true;
   int M, Nh, off;
   const float* lz;   // pre-activation bounds l, u of the layer below [B, Nh]
   const float* uz;
@@ -410,6 +427,7 @@ template <bool MULTI>
 struct EpiFinal {
   static constexpr int NSUM = 2;
   static constexpr int VGROUP = 4;
+  static constexpr bool UNGUARDED_INSIDE = true;
   int M, n0;
   const float* lo;
   const float* hi;
@@ -458,6 +476,7 @@ template <bool MULTI>
 struct EpiPlanes {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 4;
+  static constexpr bool UNGUARDED_INSIDE = false;
   int U, Nh;
   const double* cP;
   const double* eP;
@@ -503,6 +522,9 @@ struct EpiPlanes {
 struct EpiAdj {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 2;
+  // the unguarded form takes 16 more VGPRs here (5 -> 4 waves per SIMD) and
+  // was measured slower (0.624 -> 0.663 ms at the 784-256x6 shapes)
+  static constexpr bool UNGUARDED_INSIDE = false;
   int M, Nh, off;
   const float* bias;
   const float* lz;
