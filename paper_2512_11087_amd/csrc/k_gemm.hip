@@ -519,7 +519,12 @@ struct EpiPlanes {
 // gradient of the alpha of lower-line entries = Omega_bar * Psi (forward
 // trace), Psi_bar of the layer above = Omega_bar * slope + intercept, and the
 // projected Adam ascent step on alpha.
-struct EpiAdj {
+// FULL: the slope step after the first -- slopes read, Adam's moments read
+// and the step taken -- fixed at compile time; otherwise these are tested
+// per call (every other use, the convolutions included).  Both forms compute
+// the same values.
+template <bool FULL>
+struct EpiAdjT {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 2;
   // the unguarded form takes 16 more VGPRs here (5 -> 4 waves per SIMD) and
@@ -555,24 +560,26 @@ struct EpiAdj {
   struct Pre {
     float l, u, psi, al, m, v;
   };
+  __device__ __forceinline__ bool reads_alpha() const { return FULL || alpha_in != nullptr; }
+  __device__ __forceinline__ bool steps() const { return FULL || (lr > 0.0 && alpha); }
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
     const size_t ri = w.ri + j;
-    const bool adam = lr > 0.0 && alpha && !fresh;
-    return Pre{w.l[j], w.u[j], trace[ri], alpha_in ? alpha_in[ri] : (float)alpha_def,
+    const bool adam = FULL || (lr > 0.0 && alpha && !fresh);
+    return Pre{w.l[j], w.u[j], trace[ri], reads_alpha() ? alpha_in[ri] : (float)alpha_def,
                adam ? am[ri] : 0.0f, adam ? av[ri] : 0.0f};
   }
   __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double acc,
                                         double*) const {
     const double om = acc + (double)bias[j];
     const size_t ri = w.ri + j;
-    const double al = alpha_in ? (double)p.al : alpha_def;
+    const double al = reads_alpha() ? (double)p.al : alpha_def;
     const double psi = (double)p.psi;
     const Relax rl = relax_apply(psi, relax_line(p.l, p.u), al);
     const bool dead = w.dead;
     const double g = (rl.lower && !dead) ? om * psi : 0.0;
     if (out) out[(size_t)r * ldo + j] = om * rl.s + rl.t;
     if (grad) grad[ri] = (float)g;
-    if (lr > 0.0 && alpha) {
+    if (steps()) {
       const double m = b1 * (double)p.m + (1.0 - b1) * g;
       const double v = b2 * (double)p.v + (1.0 - b2) * g * g;
       const double mh = m / bc1, vh = v / bc2;
@@ -584,6 +591,8 @@ struct EpiAdj {
     }
   }
 };
+
+typedef EpiAdjT<false> EpiAdj;
 
 // ------------------------------------------------------------ convolutions
 // The backward pass through a conv layer is a transposed convolution of each
@@ -1851,5 +1860,10 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
   EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N, alpha_in, fresh};
   if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s, variant);
+  if (alpha_in && alpha && lr > 0.0 && !fresh && adam_m && adam_v) {
+    EpiAdjT<true> f{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
+                    lr, b1, b2, eps, bc1, bc2, Psibar_out, N, alpha_in, fresh};
+    return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, f, nullptr, s);
+  }
   return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }

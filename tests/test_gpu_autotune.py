@@ -40,11 +40,16 @@ def test_every_kernel_variant_gives_identical_results(make, kernels, monkeypatch
         lb, grad = api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"], alpha,
                                   batch.lo, batch.hi, out["infeasible"], batch.cons(), 1, m, v, 1,
                                   0.1, want_grad=True, ws=prop.ws)
+        # a second step reads the slopes and Adam's moments (the GEMM
+        # epilogue's form for the steps after the first)
+        lb_s2, grad_s2 = api.alpha_step(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"],
+                                        alpha, batch.lo, batch.hi, out["infeasible"], batch.cons(),
+                                        1, m, v, 2, 0.1, want_grad=True, ws=prop.ws)
         lb2, A, c = api.bound_propagate(prop.net, prop.root, prop.C, prop.t, out["l"], out["u"],
                                         batch.lo, batch.hi, infeasible=out["infeasible"],
                                         cons=batch.cons(), want_plane=True, ws=prop.ws)
         torch.cuda.synchronize()
-        return [H(x) for x in (lb, grad, alpha, m, v, lb2, A, c)]
+        return [H(x) for x in (lb, grad, lb_s2, grad_s2, alpha, m, v, lb2, A, c)]
 
     ref = run()
     assert np.isfinite(ref[0]).any()
