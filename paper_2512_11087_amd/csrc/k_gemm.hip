@@ -359,7 +359,9 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int R, int K, int N, LoadA la
 // sum |psi| * wrel (error weight).
 // MULTI: rows of several properties (the error weight of each row's
 // property is looked up); else one property's weight for every row.
-template <bool MULTI>
+// FULL: slopes read and the trace written (the backward pass of a slope
+// step), fixed at compile time; otherwise tested per call.
+template <bool MULTI, bool FULL = false>
 struct EpiRelax {
   static constexpr int NSUM = 3;
   static constexpr int VGROUP = 4;
@@ -405,16 +407,16 @@ struct EpiRelax {
     float l, u, al;
   };
   __device__ __forceinline__ Pre load(const Row& w, int, int j) const {
-    return Pre{w.l[j], w.u[j], alpha ? alpha[w.ri + j] : (float)alpha_def};
+    return Pre{w.l[j], w.u[j], (FULL || alpha) ? alpha[w.ri + j] : (float)alpha_def};
   }
   __device__ __forceinline__ void apply(const Row& w, const Pre& p, int r, int j, double psi,
                                         double* s) const {
     const size_t ri = w.ri + j;
-    const double al = alpha ? (double)p.al : alpha_def;
+    const double al = (FULL || alpha) ? (double)p.al : alpha_def;
     const Relax rl = relax_apply(psi, relax_line(p.l, p.u), al);
     const double om = psi * rl.s;
     Om[(size_t)r * ldo + j] = om;
-    if (trace) trace[ri] = trace32(psi);
+    if (FULL || trace) trace[ri] = trace32(psi);
     s[0] += psi * rl.t;
     s[1] += om * (double)bprev[j];
     s[2] += fabs(psi) * wrel_of(w)[j];
@@ -1806,15 +1808,26 @@ hipError_t launch_gemm_relax(int R, int K, int N, const double* Om, const float*
                              double alpha_def, const float* bprev, CvProps props, int layer,
                              double* Om_out, float* trace, double* part, int variant,
                              hipStream_t s) {
+  const bool full = alpha && trace;
   if (props.host) {  // one property: its error weight for every row
     EpiRelax<false> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props.host->wrel[layer], props,
                       layer, Om_out, N, trace};
     if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
+    if (full) {
+      EpiRelax<false, true> f{M, Nh, off, lz, uz, alpha, alpha_def, bprev, props.host->wrel[layer],
+                              props, layer, Om_out, N, trace};
+      return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, f, part, s);
+    }
     return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
   }
   EpiRelax<true> e{M, Nh, off, lz, uz, alpha, alpha_def, bprev, nullptr, props, layer, Om_out, N,
                    trace};
   if (conv) return run_convt(R, *conv, Om, e, part, gemm_ntiles(N), s, variant);
+  if (full) {
+    EpiRelax<true, true> f{M, Nh, off, lz, uz, alpha, alpha_def, bprev, nullptr, props, layer,
+                           Om_out, N, trace};
+    return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, f, part, s);
+  }
   return run_gemm_v(variant, R, K, N, LoadF64{Om, K}, W, N, e, part, s);
 }
 
