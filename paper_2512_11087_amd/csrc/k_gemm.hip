@@ -1872,11 +1872,15 @@ hipError_t launch_gemm_adjoint(int R, int K, int N, const double* Abar, const fl
   const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
   EpiAdj e{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
            lr, b1, b2, eps, bc1, bc2, Psibar_out, N, alpha_in, fresh};
-  if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s, variant);
-  if (alpha_in && alpha && lr > 0.0 && !fresh && adam_m && adam_v) {
+  const bool full = alpha_in && alpha && lr > 0.0 && !fresh && adam_m && adam_v;
+  if (full) {
     EpiAdjT<true> f{M, Nh, off, b, lz, uz, alpha, alpha_def, trace, infeasible, grad, adam_m, adam_v,
                     lr, b1, b2, eps, bc1, bc2, Psibar_out, N, alpha_in, fresh};
-    return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, f, nullptr, s);
+    // the whole-row forward convolutions gain from the fixed form (config 3's
+    // layers 1.765 -> 1.690 ms); the tiled ones lost (4.14 -> 4.23 ms)
+    if (conv && conv_whole_row(*conv, false)) return run_convf_row(R, *conv, Abar, f, nullptr, 1, s, variant);
+    if (!conv) return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, f, nullptr, s);
   }
+  if (conv) return run_convf(R, *conv, Abar, e, nullptr, 1, s, variant);
   return run_gemm_v(variant, R, K, N, LoadF64{Abar, K}, Wt, N, e, nullptr, s);
 }
