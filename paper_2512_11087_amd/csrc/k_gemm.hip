@@ -265,6 +265,9 @@ __device__ __forceinline__ void gemm_tile(int m0, int n0, int R, int K, int N, c
   for (int i = 0; i < MI; ++i) {
 #pragma unroll
     for (int v0 = 0; v0 < 4; v0 += VG) {
+      // (FENCE_GROUPS: each group's loads stay in the group, which bounds the
+      // registers the epilogue holds)
+      if constexpr (Epi::FENCE_GROUPS) __builtin_amdgcn_sched_barrier(0);
       typename Epi::Row rw[VG];
       typename Epi::Pre pre[VG][NI];
 #pragma unroll
@@ -366,6 +369,7 @@ struct EpiRelax {
   static constexpr int NSUM = 3;
   static constexpr int VGROUP = 4;
   static constexpr bool UNGUARDED_INSIDE = true;
+  static constexpr bool FENCE_GROUPS = false;
   int M, Nh, off;
   const float* lz;   // pre-activation bounds l, u of the layer below [B, Nh]
   const float* uz;
@@ -430,6 +434,7 @@ struct EpiFinal {
   static constexpr int NSUM = 2;
   static constexpr int VGROUP = 4;
   static constexpr bool UNGUARDED_INSIDE = true;
+  static constexpr bool FENCE_GROUPS = false;
   int M, n0;
   const float* lo;
   const float* hi;
@@ -479,6 +484,7 @@ struct EpiPlanes {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 4;
   static constexpr bool UNGUARDED_INSIDE = false;
+  static constexpr bool FENCE_GROUPS = false;
   int U, Nh;
   const double* cP;
   const double* eP;
@@ -529,9 +535,12 @@ template <bool FULL>
 struct EpiAdjT {
   static constexpr int NSUM = 0;
   static constexpr int VGROUP = 2;
-  // the unguarded form takes 16 more VGPRs here (5 -> 4 waves per SIMD) and
-  // was measured slower (0.624 -> 0.663 ms at the 784-256x6 shapes)
-  static constexpr bool UNGUARDED_INSIDE = false;
+  // unguarded only with the groups fenced: the compiler otherwise hoists the
+  // later groups' loads and takes 16 more VGPRs (5 -> 4 waves per SIMD;
+  // measured 0.624 -> 0.663 ms at the 784-256x6 shapes, 0.607 -> 0.587 ms
+  // fenced)
+  static constexpr bool UNGUARDED_INSIDE = true;
+  static constexpr bool FENCE_GROUPS = true;
   int M, Nh, off;
   const float* bias;
   const float* lz;
